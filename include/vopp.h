@@ -1,0 +1,181 @@
+/*
+ * vopp.h -- C ABI of the MI355X planner for Vectorized Online POMDP Planning
+ * (VOPP: Hoerger, Sudrajat, Kurniawati).
+ *
+ * One call of vopp_plan() is one planning step of Alg. 1: K iterations, each
+ * sampling n_p root states from the belief particles, running the
+ * level-by-level forward search of Alg. 2 (softmax action draw of Eq. 6,
+ * generative model G, AppendActions, FilterTerminals, AppendBeliefs) to the
+ * iteration's depth, and the bottom-up preference backup of Alg. 3 (Q = C/N +
+ * gamma W, Psi <- Psi - L_eta Psi + Q from Eq. 5, V = L_eta Psi from Eq. 3);
+ * then the root action with the largest preference.  The tree is the tensor
+ * store of Sec. III-C (belief rows, action-node rows, preference rows), kept
+ * in HBM in structure-of-arrays form.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a vopp_status; nothing throws across the ABI.
+ *     On failure vopp_last_error() returns a message (per thread, valid until
+ *     the next call on that thread).
+ *   - "host" pointers are read during the call and not retained; "device"
+ *     pointers must point to memory of the current HIP device.
+ *   - Inputs are validated before any device work.  HIP failures map to
+ *     VOPP_E_DEVICE.  Handles are not thread-safe: use one stream per handle.
+ *   - Random numbers are Philox4x32-10 streams keyed by the 64-bit seed with
+ *     counter (episode, tag<<24 | level, iteration, real step), so the same
+ *     inputs give the same tree on every run and in every batch.
+ */
+#ifndef VOPP_H
+#define VOPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VOPP_OK = 0,
+  VOPP_E_INVALID = -1,   /* bad argument; nothing was launched            */
+  VOPP_E_NOMEM = -2,     /* footprint exceeds free HBM or a given budget  */
+  VOPP_E_DEVICE = -3,    /* a HIP call failed                             */
+  VOPP_E_BUSY = -4,      /* server: no slot or memory free right now      */
+  VOPP_E_INTERNAL = -5   /* an internal consistency check failed          */
+} vopp_status;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* vopp_last_error(void);
+
+/* Library version string. */
+const char* vopp_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* POMDP models: the generative model G(s, a) -> (s', o, r) of Sec. III-B.   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct vopp_pomdp vopp_pomdp;
+
+/* Tabular POMDP <S, A, O, T, Z, R, gamma> (Sec. II-A).  All pointers are host
+ * pointers, copied to the device at creation; the handle owns the copy.
+ *   rowptr [nS*nA+1], col/tprob [rowptr[nS*nA]]: transition rows T(s, a, .) in
+ *     CSR form, row index s*nA + a; probabilities fp32, non-negative, each row
+ *     summing to 1 within 1e-5.
+ *   zprob [nS*nA*nO]: observation rows Z(s', a, .) indexed [s'][a][o].
+ *   reward [nS*nA]: R(s, a).   heur [nS] or NULL: leaf value heuristic.
+ * Limits: 1 <= nA <= 64, 1 <= nO <= 2^24, 1 <= nS < 2^31, 0 < gamma < 1.
+ * Sampling uses integer thresholds rint(cum/total * 2^31) per row. */
+typedef struct {
+  int32_t nS, nA, nO;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const float* tprob;
+  const float* zprob;
+  const float* reward;
+  const float* heur;
+  double gamma;
+} vopp_tabular_desc;
+
+/* Continuous 2-D navigation POMDP (continuous spaces represented by a fixed
+ * finite set chosen a priori, Sec. III-B): state (x, y) fp32 in [lo, hi]^2;
+ * actions 0..3 move by +y, +x, -y, -x of length `step` with N(0, sigma_move^2)
+ * noise per axis; observation = next position + N(0, sd^2) noise per axis with
+ * sd = sigma_obs0 + sigma_obs_slope*|x' - obs_center_x|, keyed by its grid
+ * cell floor(v*inv_bin) clamped to [key_lo, key_lo+key_n-1] per axis; reward
+ * r_step, plus r_goal inside the goal disk (terminal), plus r_hit inside any
+ * obstacle disk.  Noise comes from `gauss`, a host table of 4096 standard
+ * normal quantiles indexed by 12 random bits.  disks [2*n_disks] holds the
+ * centres.  heuristic: 0 = zero leaf value, 1 = -(|x-goal_x| + |y-goal_y|).
+ * All arithmetic is single precision without contraction. */
+typedef struct {
+  float lo, hi, step, sigma_move, sigma_obs0, sigma_obs_slope, obs_center_x,
+      inv_bin;
+  int32_t key_lo, key_n;
+  float goal_x, goal_y, goal_r2, disk_r2, r_step, r_goal, r_hit;
+  int32_t heuristic;
+  int32_t n_disks;
+  const float* disks;
+  const float* gauss;
+  double gamma;
+} vopp_nav2d_desc;
+
+vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* desc, vopp_pomdp** out);
+vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* desc, vopp_pomdp** out);
+/* Number of actions |A| of a model (0 for NULL). */
+int32_t vopp_pomdp_num_actions(const vopp_pomdp* pomdp);
+void vopp_pomdp_free(vopp_pomdp* pomdp);
+
+/* ------------------------------------------------------------------------ */
+/* Planning (Alg. 1-3).                                                      */
+/* ------------------------------------------------------------------------ */
+
+enum { VOPP_SCHEDULE_DEEPEN = 0, VOPP_SCHEDULE_FIXED = 1 };
+
+/* n_particles: episodes per iteration (n_p of Alg. 1), 1 .. 2^24.
+ * eta: the multiplier of the preferences in the softmax (Eq. 3, 6), > 0.
+ * schedule: DEEPEN grows the search depth as D_k = min(k, depth) (D_max of
+ *   Alg. 1 starts at 1 and grows by one per iteration); FIXED uses depth.
+ * seed: Philox key.  step: real step index t (a counter word). */
+typedef struct {
+  int32_t n_particles;
+  int32_t schedule;
+  double eta;
+  uint64_t seed;
+  uint32_t step;
+} vopp_params;
+
+typedef struct {
+  int64_t particle_steps;   /* generative-model calls made by the plan     */
+  int64_t n_beliefs;        /* rows of the belief table (root included)    */
+  int64_t n_actions;        /* rows of the action-node table               */
+  double device_ms;         /* device time of the plan, HIP events          */
+} vopp_stats;
+
+/* A workspace holds one plan's tree and per-episode arrays in HBM, sized for
+ * the worst case (beliefs <= 1 + n_p * sum_k D_k), so no plan can overflow it. */
+typedef struct vopp_workspace vopp_workspace;
+
+/* Bytes of device memory a workspace for (pomdp, params, budget, depth) needs. */
+size_t vopp_plan_footprint(const vopp_pomdp* pomdp, const vopp_params* params,
+                           int32_t budget, int32_t depth);
+
+vopp_status vopp_workspace_create(const vopp_pomdp* pomdp,
+                                  const vopp_params* params, int32_t budget,
+                                  int32_t depth, vopp_workspace** out);
+void vopp_workspace_free(vopp_workspace* ws);
+
+/* One planning step.
+ *   pomdp: the model.  belief_particles: DEVICE pointer to n_belief particles
+ *     (tabular: int32 states [n_belief]; navigation: fp32 x[n_belief] followed
+ *     by fp32 y[n_belief]).  Root states are drawn with replacement, index =
+ *     (x0 * n_belief) >> 32.
+ *   budget: iterations K >= 1.  depth: maximum leaf depth, 1 .. 64.
+ *   ws: a workspace created for at least these sizes, or NULL to use one
+ *     owned by the pomdp handle (grown on demand).
+ *   stream: hipStream_t (NULL = default stream).
+ *   action (host, out): argmax_a Psi(root, a), lowest index on ties.
+ *   values (host, out, may be NULL): the root preferences Psi(root, .) [nA],
+ *     kept in double precision.  v_root (host, may be NULL): L_eta Psi(root).
+ *   stats (host, may be NULL).
+ * The call returns after the result has reached the host. */
+vopp_status vopp_plan(const vopp_pomdp* pomdp, const void* belief_particles,
+                      int32_t n_belief, int32_t budget, int32_t depth,
+                      const vopp_params* params, vopp_workspace* ws,
+                      void* stream, int32_t* action, double* values,
+                      double* v_root, vopp_stats* stats);
+
+/* Copy the tree of the last plan run in `ws` to host arrays (any may be
+ * NULL).  Sizes come from vopp_stats.  Belief arrays [n_beliefs]: parent
+ * action row (-1 for the root), observation key (-1 for the root), depth,
+ * value V, visit count N_b; psi [n_beliefs*nA] (fp32; row 0 is the root,
+ * whose double values are in vopp_plan's `values`).  Action arrays
+ * [n_actions]: parent belief row, action, cumulative reward C, visits N. */
+vopp_status vopp_tree_dump(vopp_workspace* ws, int32_t* b_parent, int32_t* b_obs,
+                           int32_t* b_depth, float* psi, float* b_V,
+                           int32_t* b_N, int32_t* a_parent, int32_t* a_act,
+                           double* a_C, int32_t* a_N);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOPP_H */

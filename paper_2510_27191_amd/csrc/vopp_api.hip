@@ -1,0 +1,631 @@
+// vopp_api.hip -- host side of the C ABI declared in include/vopp.h.
+//
+// Model handles own a device copy of the POMDP (with integer sampling
+// thresholds derived here), workspaces own one plan's tree arena, and
+// vopp_plan() drives the launches of one planning step (Alg. 1) on a stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vopp.h"
+#include "vopp_device.hpp"
+#include "vopp_launch.hpp"
+#include "vopp_internal.hpp"
+
+using namespace vopp;
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace vopp {
+
+vopp_status fail(vopp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+vopp_status hip_fail(hipError_t e, const char* what) {
+  return fail(VOPP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Sampling thresholds of a categorical row: thr_j = rint(cum_j / total * 2^31)
+// with cum the running double sum of the fp32 probabilities; last = 2^31.
+static void row_thresholds(const float* p, int n, uint32_t* out) {
+  const double two31 = 2147483648.0;
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) total += (double)p[j];
+  double cum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    cum += (double)p[j];
+    double v = std::rint(cum / total * two31);
+    v = std::min(std::max(v, 0.0), two31);
+    out[j] = (uint32_t)v;
+  }
+  out[n - 1] = (uint32_t)two31;
+}
+
+static bool valid_row(const float* p, int n) {
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (!(p[j] >= 0.0f) || !std::isfinite(p[j])) return false;
+    s += (double)p[j];
+  }
+  return std::fabs(s - 1.0) <= 1e-5;
+}
+
+// Carves aligned sub-buffers out of one device allocation.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t n) {
+    off = align_up(off, 256);
+    T* p = (T*)(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace vopp
+
+extern "C" const char* vopp_last_error(void) { return g_err.c_str(); }
+extern "C" const char* vopp_version(void) { return "vopp-mi355x 0.1"; }
+
+// ---------------------------------------------------------------------------
+// Models.
+// ---------------------------------------------------------------------------
+extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp** out) {
+  clear_error();
+  if (!d || !out) return fail(VOPP_E_INVALID, "null argument");
+  *out = nullptr;
+  if (d->nS < 1 || d->nA < 1 || d->nA > kMaxA || d->nO < 1 || d->nO > (1 << 24))
+    return fail(VOPP_E_INVALID, "sizes out of range (nS=%d nA=%d nO=%d)", d->nS, d->nA, d->nO);
+  if (!(d->gamma > 0.0 && d->gamma < 1.0)) return fail(VOPP_E_INVALID, "gamma must be in (0,1)");
+  if (!d->rowptr || !d->col || !d->tprob || !d->zprob || !d->reward)
+    return fail(VOPP_E_INVALID, "null model array");
+  const long long rows = (long long)d->nS * d->nA;
+  if (rows > INT32_MAX / 2 || rows * d->nO > (long long)1 << 40)
+    return fail(VOPP_E_INVALID, "model too large");
+  if (d->rowptr[0] != 0) return fail(VOPP_E_INVALID, "rowptr[0] must be 0");
+  for (long long r = 0; r < rows; ++r) {
+    if (d->rowptr[r + 1] <= d->rowptr[r])
+      return fail(VOPP_E_INVALID, "transition row %lld is empty or rowptr decreases", r);
+  }
+  const int nnz = d->rowptr[rows];
+  for (int i = 0; i < nnz; ++i)
+    if (d->col[i] < 0 || d->col[i] >= d->nS)
+      return fail(VOPP_E_INVALID, "successor index %d out of range at %d", d->col[i], i);
+  for (long long r = 0; r < rows; ++r) {
+    int lo = d->rowptr[r], n = d->rowptr[r + 1] - lo;
+    if (!valid_row(d->tprob + lo, n))
+      return fail(VOPP_E_INVALID, "transition row %lld does not sum to 1", r);
+    if (!valid_row(d->zprob + r * d->nO, d->nO))
+      return fail(VOPP_E_INVALID, "observation row %lld does not sum to 1", r);
+  }
+  double rmax = 0.0, hmax = 0.0;
+  for (long long i = 0; i < rows; ++i) {
+    if (!std::isfinite(d->reward[i])) return fail(VOPP_E_INVALID, "non-finite reward");
+    rmax = std::max(rmax, (double)std::fabs(d->reward[i]));
+  }
+  if (d->heur)
+    for (int i = 0; i < d->nS; ++i) {
+      if (!std::isfinite(d->heur[i])) return fail(VOPP_E_INVALID, "non-finite heuristic");
+      hmax = std::max(hmax, (double)std::fabs(d->heur[i]));
+    }
+
+  std::vector<uint32_t> thrT(nnz), thrZ((size_t)rows * d->nO);
+  for (long long r = 0; r < rows; ++r) {
+    int lo = d->rowptr[r], n = d->rowptr[r + 1] - lo;
+    row_thresholds(d->tprob + lo, n, thrT.data() + lo);
+    row_thresholds(d->zprob + r * d->nO, d->nO, thrZ.data() + r * d->nO);
+  }
+
+  vopp_pomdp* p = new vopp_pomdp();
+  p->kind = kTabular;
+  p->nA = d->nA;
+  p->r_max = rmax;
+  p->h_max = hmax;
+  p->gamma = d->gamma;
+  p->branch = (double)d->nA * d->nO;
+  hipGetDevice(&p->device);
+  size_t bytes = 0;
+  bytes += align_up((rows + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) * 2;
+  bytes += align_up(thrZ.size() * 4, 256) + align_up(rows * 4, 256) +
+           align_up((size_t)d->nS * 4, 256) + 1024;
+  hipError_t e = hipMalloc(&p->arena, bytes);
+  if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
+  p->bytes = bytes;
+  Carver c(p->arena);
+  int* rowptr = c.take<int>(rows + 1);
+  int* col = c.take<int>(nnz);
+  uint32_t* tT = c.take<uint32_t>(nnz);
+  uint32_t* tZ = c.take<uint32_t>(thrZ.size());
+  float* R = c.take<float>(rows);
+  float* H = d->heur ? c.take<float>(d->nS) : nullptr;
+  e = hipMemcpy(rowptr, d->rowptr, (rows + 1) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(col, d->col, (size_t)nnz * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(tT, thrT.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(tZ, thrZ.data(), thrZ.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(R, d->reward, rows * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && H) e = hipMemcpy(H, d->heur, (size_t)d->nS * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
+  ModelView& m = p->view;
+  std::memset(&m, 0, sizeof(m));
+  m.kind = kTabular;
+  m.nS = d->nS; m.nA = d->nA; m.nO = d->nO;
+  m.Apad = (d->nA + 3) / 4 * 4;
+  m.rowptr = rowptr; m.col = col; m.thrT = tT; m.thrZ = tZ; m.R = R; m.H = H;
+  m.gamma = (float)d->gamma;
+  m.gamma64 = d->gamma;
+  *out = p;
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** out) {
+  clear_error();
+  if (!d || !out) return fail(VOPP_E_INVALID, "null argument");
+  *out = nullptr;
+  if (!(d->gamma > 0.0 && d->gamma < 1.0)) return fail(VOPP_E_INVALID, "gamma must be in (0,1)");
+  if (!d->gauss) return fail(VOPP_E_INVALID, "null Gaussian table");
+  if (d->n_disks < 0 || d->n_disks > 4096 || (d->n_disks > 0 && !d->disks))
+    return fail(VOPP_E_INVALID, "bad obstacle list");
+  if (!(d->hi > d->lo) || d->key_n < 1 || d->key_n > 4096 || !(d->inv_bin > 0.0f))
+    return fail(VOPP_E_INVALID, "bad navigation geometry");
+  for (int i = 0; i < 4096; ++i)
+    if (!std::isfinite(d->gauss[i])) return fail(VOPP_E_INVALID, "non-finite Gaussian table");
+  vopp_pomdp* p = new vopp_pomdp();
+  p->kind = kNav;
+  p->nA = 4;
+  p->gamma = d->gamma;
+  double rs = d->r_step, rg = d->r_goal, rh = d->r_hit;
+  p->r_max = std::max({std::fabs(rs), std::fabs(rs + rg), std::fabs(rs + rh),
+                       std::fabs(rs + rg + rh)});
+  p->h_max = d->heuristic ? 2.0 * (double)(d->hi - d->lo) + 1.0 : 0.0;
+  p->branch = 4.0 * (double)d->key_n * d->key_n;
+  hipGetDevice(&p->device);
+  size_t bytes = align_up(4096 * 4, 256) + align_up((size_t)2 * d->n_disks * 4 + 4, 256) + 512;
+  hipError_t e = hipMalloc(&p->arena, bytes);
+  if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
+  p->bytes = bytes;
+  Carver c(p->arena);
+  float* g = c.take<float>(4096);
+  float* disks = c.take<float>(2 * (size_t)d->n_disks + 1);
+  e = hipMemcpy(g, d->gauss, 4096 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && d->n_disks)
+    e = hipMemcpy(disks, d->disks, 2 * (size_t)d->n_disks * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
+  ModelView& m = p->view;
+  std::memset(&m, 0, sizeof(m));
+  m.kind = kNav;
+  m.nS = 0; m.nA = 4; m.nO = d->key_n * d->key_n; m.Apad = 4;
+  NavParams& np = m.nav;
+  np.lo = d->lo; np.hi = d->hi; np.step = d->step; np.sigma_move = d->sigma_move;
+  np.sigma_obs0 = d->sigma_obs0; np.sigma_obs_slope = d->sigma_obs_slope;
+  np.obs_center_x = d->obs_center_x; np.inv_bin = d->inv_bin;
+  np.key_lo = d->key_lo; np.key_n = d->key_n;
+  np.goal_x = d->goal_x; np.goal_y = d->goal_y; np.goal_r2 = d->goal_r2;
+  np.disk_r2 = d->disk_r2; np.r_step = d->r_step; np.r_goal = d->r_goal;
+  np.r_hit = d->r_hit; np.heuristic = d->heuristic; np.n_disks = d->n_disks;
+  m.gauss = g; m.disks = disks;
+  m.gamma = (float)d->gamma;
+  m.gamma64 = d->gamma;
+  *out = p;
+  return VOPP_OK;
+}
+
+extern "C" int32_t vopp_pomdp_num_actions(const vopp_pomdp* p) { return p ? p->nA : 0; }
+
+extern "C" void vopp_pomdp_free(vopp_pomdp* p) {
+  if (!p) return;
+  if (p->own_ws) vopp_workspace_free(p->own_ws);
+  if (p->arena) hipFree(p->arena);
+  delete p;
+}
+
+// ---------------------------------------------------------------------------
+// Workspaces.
+// ---------------------------------------------------------------------------
+namespace vopp {
+
+int sum_depths(int K, int depth, int schedule) {
+  long long s = 0;
+  for (int k = 1; k <= K; ++k) s += schedule == VOPP_SCHEDULE_FIXED ? depth : std::min(k, depth);
+  return (int)s;
+}
+
+static WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) {
+  WsSizes z;
+  z.n_p = n_p;
+  z.steps = sum_depths(K, depth, schedule);
+  z.K = K;
+  z.Apad = p->view.Apad;
+  z.cap_b = 1 + (long long)n_p * z.steps;
+  z.cap_a = (long long)n_p * z.steps;
+  uint64_t h = 1024;
+  while (h < 2 * (uint64_t)z.cap_b) h <<= 1;
+  z.hcap = h;
+  z.res_tiles = (n_p + kResTile - 1) / kResTile;
+  return z;
+}
+
+static size_t bytes_for(const WsSizes& z) {
+  size_t b = 0;
+  auto add = [&](size_t n) { b += align_up(n, 256); };
+  const size_t cb = (size_t)z.cap_b, ca = (size_t)z.cap_a;
+  add(cb * 4); add(cb * 4); add(cb * z.Apad * 4); add(cb * z.Apad * 4);
+  add(cb * 4); add(cb * 4); add(cb * 4); add(cb * 8); add(cb * 4);
+  add(ca * 4); add(ca * 4); add(ca * 8); add(ca * 4); add(ca * 8);
+  add(kMaxA * 8); add(8);
+  add(z.hcap * 8); add(z.hcap * 4);
+  add((z.steps + 1) * 4); add((z.steps + 1) * 4);
+  add((size_t)z.steps * z.res_tiles * 8); add((size_t)z.steps * 4);
+  add(64); add((z.K + 1) * 4);
+  add((size_t)z.n_p * 4 * 6);
+  add(256 * 8);
+  return b + 4096;
+}
+
+static bool fits(const WsSizes& have, const WsSizes& need) {
+  return have.n_p >= need.n_p && have.cap_b >= need.cap_b && have.steps >= need.steps &&
+         have.K >= need.K && have.Apad >= need.Apad && have.res_tiles >= need.res_tiles &&
+         have.hcap >= need.hcap;
+}
+
+vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
+  vopp_workspace* w = new vopp_workspace();
+  w->z = z;
+  w->bytes = bytes_for(z);
+  hipGetDevice(&w->device);
+  hipError_t e = hipMalloc(&w->arena, w->bytes);
+  if (e != hipSuccess) {
+    delete w;
+    return fail(VOPP_E_NOMEM, "hipMalloc(%zu bytes) for the workspace: %s", bytes_for(z),
+                hipGetErrorString(e));
+  }
+  Carver c(w->arena);
+  const size_t cb = (size_t)z.cap_b, ca = (size_t)z.cap_a;
+  TreeView& t = w->tree;
+  t.b_parent = c.take<int>(cb);
+  t.b_obs = c.take<int>(cb);
+  t.psi = c.take<float>(cb * z.Apad);
+  t.b_child = c.take<int>(cb * z.Apad);
+  t.b_V = c.take<float>(cb);
+  t.b_N = c.take<int>(cb);
+  t.leaf_cnt = c.take<int>(cb);
+  t.leaf_h = c.take<unsigned long long>(cb);
+  t.b_hslot = c.take<int>(cb);
+  t.a_parent = c.take<int>(ca);
+  t.a_act = c.take<int>(ca);
+  t.a_C = c.take<unsigned long long>(ca);
+  t.a_N = c.take<int>(ca);
+  t.a_W = c.take<unsigned long long>(ca);
+  t.psi_root = c.take<double>(kMaxA);
+  t.v_root = c.take<double>(1);
+  t.h_key = c.take<unsigned long long>(z.hcap);
+  t.h_val = c.take<int>(z.hcap);
+  t.h_mask = (uint32_t)(z.hcap - 1);
+  t.bel_base = c.take<int>(z.steps + 1);
+  t.act_base = c.take<int>(z.steps + 1);
+  t.lookback = c.take<unsigned long long>((size_t)z.steps * z.res_tiles);
+  t.tickets = c.take<int>(z.steps);
+  t.counters = c.take<unsigned long long>(8);
+  int* step_base = c.take<int>(z.K + 1);
+  t.step_base = step_base;
+  w->step_base_dev = step_base;
+  t.res_tiles = z.res_tiles;
+  EpisodeView& ev = w->ep;
+  ev.s_i = c.take<int>(z.n_p);
+  ev.s_x = c.take<float>(z.n_p);
+  ev.s_y = c.take<float>(z.n_p);
+  ev.aslot = c.take<int>(z.n_p);
+  ev.hslot = c.take<int>(z.n_p);
+  ev.r = c.take<float>(z.n_p);
+  w->out_dev = c.take<double>(256);
+  e = hipHostMalloc((void**)&w->out_host, 256 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 1) * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&w->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&w->ev1);
+  if (e != hipSuccess) {
+    vopp_workspace_free(w);
+    return hip_fail(e, "workspace set-up");
+  }
+  w->hash_dirty = true;
+  *out = w;
+  return VOPP_OK;
+}
+
+vopp_status check_params(const vopp_pomdp* p, const vopp_params* prm, int32_t budget,
+                         int32_t depth) {
+  if (!p) return fail(VOPP_E_INVALID, "null pomdp");
+  if (!prm) return fail(VOPP_E_INVALID, "null params");
+  if (prm->n_particles < 1 || prm->n_particles > (1 << 24))
+    return fail(VOPP_E_INVALID, "n_particles must be in [1, 2^24]");
+  if (budget < 1 || budget > kMaxBudget)
+    return fail(VOPP_E_INVALID, "budget must be in [1, %d]", kMaxBudget);
+  if (depth < 1 || depth > 64) return fail(VOPP_E_INVALID, "depth must be in [1, 64]");
+  if (!(prm->eta > 0.0) || !std::isfinite(prm->eta)) return fail(VOPP_E_INVALID, "eta must be > 0");
+  if (prm->schedule != VOPP_SCHEDULE_DEEPEN && prm->schedule != VOPP_SCHEDULE_FIXED)
+    return fail(VOPP_E_INVALID, "unknown schedule");
+  const long long steps = sum_depths(budget, depth, prm->schedule);
+  if ((long long)prm->n_particles * steps + 1 > (1ll << 30))
+    return fail(VOPP_E_INVALID, "n_particles * sum of depths exceeds 2^30 nodes");
+  return VOPP_OK;
+}
+
+}  // namespace vopp
+
+extern "C" size_t vopp_plan_footprint(const vopp_pomdp* p, const vopp_params* prm,
+                                      int32_t budget, int32_t depth) {
+  if (check_params(p, prm, budget, depth) != VOPP_OK) return 0;
+  return bytes_for(sizes_for(p, prm->n_particles, budget, depth, prm->schedule));
+}
+
+extern "C" vopp_status vopp_workspace_create(const vopp_pomdp* p, const vopp_params* prm,
+                                             int32_t budget, int32_t depth,
+                                             vopp_workspace** out) {
+  clear_error();
+  if (!out) return fail(VOPP_E_INVALID, "null out");
+  *out = nullptr;
+  vopp_status st = check_params(p, prm, budget, depth);
+  if (st != VOPP_OK) return st;
+  return ws_alloc(sizes_for(p, prm->n_particles, budget, depth, prm->schedule), out);
+}
+
+extern "C" void vopp_workspace_free(vopp_workspace* w) {
+  if (!w) return;
+  if (w->arena) hipFree(w->arena);
+  if (w->out_host) hipHostFree(w->out_host);
+  if (w->step_host) hipHostFree(w->step_host);
+  if (w->ev0) hipEventDestroy(w->ev0);
+  if (w->ev1) hipEventDestroy(w->ev1);
+  delete w;
+}
+
+// ---------------------------------------------------------------------------
+// One planning step.
+// ---------------------------------------------------------------------------
+namespace vopp {
+
+// Fixed-point scale 2^S for the cross-episode sums: every partial sum is
+// bounded by n_p * K * vmax with vmax >= |V| = R_max/(1-gamma) + H_max, and S
+// keeps that bound below 2^61.
+static int fixed_shift(const vopp_pomdp* p, int n_p, int K) {
+  const double vmax = p->r_max / (1.0 - p->gamma) + p->h_max + 1.0;
+  const double lg = std::log2((double)n_p * (double)K * vmax);
+  int S = (int)std::floor(61.0 - lg);
+  return std::min(std::max(S, 4), 40);
+}
+
+PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
+                   int n_belief, int K, int depth, const vopp_params* prm) {
+  PlanView P;
+  std::memset(&P, 0, sizeof(P));
+  P.m = p->view;
+  P.t = w->tree;
+  P.t.res_tiles = (prm->n_particles + kResTile - 1) / kResTile;
+  P.e = w->ep;
+  P.e.belief = belief;
+  P.e.n_belief = n_belief;
+  P.n_p = prm->n_particles;
+  P.eta = (float)prm->eta;
+  P.eta64 = prm->eta;
+  P.seed_lo = (uint32_t)prm->seed;
+  P.seed_hi = (uint32_t)(prm->seed >> 32);
+  P.step = prm->step;
+  const int S = fixed_shift(p, prm->n_particles, K);
+  P.fix_scale = std::ldexp(1.0f, S);
+  P.fix_inv = std::ldexp(1.0f, -S);
+  P.fix_inv64 = std::ldexp(1.0, -S);
+  P.psi0_64 = -std::log((double)p->nA) / prm->eta;
+  P.psi0 = (float)P.psi0_64;
+  P.K = K;
+  P.depth = depth;
+  P.schedule = prm->schedule;
+  return P;
+}
+
+// Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
+static int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k) {
+  int iters = 0;
+  for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
+  double bound = (double)n_p * iters;
+  const double tree = std::pow(p->branch, (double)dep);
+  if (tree < bound) bound = tree;
+  long long g = (long long)std::ceil(bound / kBlock);
+  return (int)std::max(1ll, std::min(g, 2048ll));
+}
+
+// Enqueue one planning step on stream s.  Returns the level-step count.
+vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
+                         hipStream_t s, int* n_steps_out) {
+  const int K = P.K;
+  std::vector<int> D(K + 1, 0);
+  int steps = 0;
+  w->step_host[0] = 0;
+  for (int k = 1; k <= K; ++k) {
+    D[k] = P.schedule == VOPP_SCHEDULE_FIXED ? P.depth : std::min(k, P.depth);
+    steps += D[k];
+    w->step_host[k] = steps;
+  }
+  hipError_t e = hipMemcpyAsync(w->step_base_dev, w->step_host, (K + 1) * sizeof(int),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload schedule");
+  const WsSizes& z = w->z;
+  if (w->hash_dirty) {
+    e = launch_fill32((uint32_t*)w->tree.h_key, z.hcap * 2, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_fill32((uint32_t*)w->tree.h_val, z.hcap, 0xFFFFFFFFu, s);
+  } else {
+    e = launch_clear_slots(P, w->n_prev_beliefs, s);
+  }
+  if (e == hipSuccess)
+    e = launch_fill32((uint32_t*)w->tree.lookback, (size_t)steps * P.t.res_tiles * 2, 0u, s);
+  if (e == hipSuccess) e = launch_fill32((uint32_t*)w->tree.tickets, (size_t)steps, 0u, s);
+  if (e == hipSuccess) e = launch_init_root(P, s);
+  if (e != hipSuccess) return hip_fail(e, "plan set-up launch");
+  w->hash_dirty = true;   // until the plan's belief count is known
+  int t = 0;
+  for (int k = 1; k <= K; ++k) {
+    for (int d = 0; d < D[k]; ++d) {
+      e = launch_expand(P, k, d, s);
+      if (e == hipSuccess) e = launch_resolve(P, t, s);
+      if (e != hipSuccess) return hip_fail(e, "forward-search launch");
+      ++t;
+    }
+    e = launch_finish(P, s);
+    if (e == hipSuccess) e = launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k), s);
+    for (int dep = D[k]; dep >= 2 && e == hipSuccess; --dep)
+      e = launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k), s);
+    if (e == hipSuccess) e = launch_backup_root(P, s);
+    if (e != hipSuccess) return hip_fail(e, "backup launch");
+  }
+  e = launch_select(P, t, w->out_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  *n_steps_out = t;
+  return VOPP_OK;
+}
+
+vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_params* prm,
+                      int K, int depth) {
+  const WsSizes need = sizes_for(p, prm->n_particles, K, depth, prm->schedule);
+  vopp_workspace* w = *ws;
+  if (w && fits(w->z, need)) return VOPP_OK;
+  if (w) {
+    vopp_workspace_free(w);
+    *ws = nullptr;
+  }
+  return ws_alloc(need, ws);
+}
+
+}  // namespace vopp
+
+extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_t n_belief,
+                                 int32_t budget, int32_t depth, const vopp_params* prm,
+                                 vopp_workspace* ws, void* stream, int32_t* action,
+                                 double* values, double* v_root, vopp_stats* stats) {
+  clear_error();
+  vopp_status st = check_params(p, prm, budget, depth);
+  if (st != VOPP_OK) return st;
+  if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
+  if (!action) return fail(VOPP_E_INVALID, "null action pointer");
+  int dev = -1;
+  hipGetDevice(&dev);
+  if (dev != p->device) return fail(VOPP_E_INVALID, "model lives on device %d, current is %d", p->device, dev);
+  if (ws) {
+    if (!fits(ws->z, sizes_for(p, prm->n_particles, budget, depth, prm->schedule)))
+      return fail(VOPP_E_INVALID, "workspace too small for this plan");
+  } else {
+    vopp_pomdp* mp = const_cast<vopp_pomdp*>(p);
+    st = ensure_ws(p, &mp->own_ws, prm, budget, depth);
+    if (st != VOPP_OK) return st;
+    ws = mp->own_ws;
+  }
+  if (ws->z.Apad < p->view.Apad) return fail(VOPP_E_INVALID, "workspace built for fewer actions");
+  hipStream_t s = (hipStream_t)stream;
+  PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm);
+  hipError_t e = hipEventRecord(ws->ev0, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  int steps = 0;
+  st = enqueue_plan(p, ws, P, s, &steps);
+  if (st != VOPP_OK) return st;
+  const int A = p->nA;
+  e = hipMemcpyAsync(ws->out_host, ws->out_dev, (A + 6) * sizeof(double),
+                     hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(ws->ev1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "plan execution");
+  const double* o = ws->out_host;
+  ws->n_prev_beliefs = (int)o[A + 3];
+  ws->hash_dirty = false;
+  if (o[A + 5] != 0.0)
+    return fail(VOPP_E_INVALID, "a belief particle holds a state outside [0, nS)");
+  *action = (int32_t)o[0];
+  if (values) for (int j = 0; j < A; ++j) values[j] = o[1 + j];
+  if (v_root) *v_root = o[A + 1];
+  ws->n_prev_beliefs = (int)o[A + 3];
+  ws->n_prev_actions = (int)o[A + 4];
+  ws->hash_dirty = false;
+  ws->last_A = A;
+  ws->last_apad = p->view.Apad;
+  ws->last_steps = steps;
+  ws->last_n_p = prm->n_particles;
+  ws->last_K = budget;
+  ws->last_depth = depth;
+  ws->last_schedule = prm->schedule;
+  ws->last_fix_inv64 = P.fix_inv64;
+  if (stats) {
+    stats->particle_steps = (int64_t)o[A + 2];
+    stats->n_beliefs = (int64_t)o[A + 3];
+    stats->n_actions = (int64_t)o[A + 4];
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
+    stats->device_ms = ms;
+  }
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int32_t* b_obs,
+                                      int32_t* b_depth, float* psi, float* b_V, int32_t* b_N,
+                                      int32_t* a_parent, int32_t* a_act, double* a_C,
+                                      int32_t* a_N) {
+  clear_error();
+  if (!w) return fail(VOPP_E_INVALID, "null workspace");
+  if (w->n_prev_beliefs <= 0) return fail(VOPP_E_INVALID, "no plan has run in this workspace");
+  const size_t nb = (size_t)w->n_prev_beliefs, na = (size_t)w->n_prev_actions;
+  const int A = w->last_A, Apad = w->last_apad;
+  hipError_t e = hipDeviceSynchronize();
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && dst && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+  };
+  cp(b_parent, w->tree.b_parent, nb * 4);
+  cp(b_obs, w->tree.b_obs, nb * 4);
+  cp(b_V, w->tree.b_V, nb * 4);
+  cp(b_N, w->tree.b_N, nb * 4);
+  cp(a_parent, w->tree.a_parent, na * 4);
+  cp(a_act, w->tree.a_act, na * 4);
+  cp(a_N, w->tree.a_N, na * 4);
+  if (psi) {
+    std::vector<float> tmp(nb * Apad);
+    cp(tmp.data(), w->tree.psi, nb * Apad * 4);
+    for (size_t b = 0; b < nb; ++b)
+      for (int j = 0; j < A; ++j) psi[b * A + j] = tmp[b * Apad + j];
+  }
+  if (a_C) {
+    std::vector<long long> tmp(na);
+    cp(tmp.data(), w->tree.a_C, na * 8);
+    const double inv = w->last_fix_inv64;
+    for (size_t i = 0; i < na; ++i) a_C[i] = (double)tmp[i] * inv;
+  }
+  if (b_depth) {
+    // Depth of each belief from the level-step ranges: level d makes depth d+1.
+    std::vector<int> base(w->last_steps + 1);
+    cp(base.data(), w->tree.bel_base, base.size() * 4);
+    std::vector<int> level_of_step;
+    for (int k = 1; k <= w->last_K; ++k) {
+      const int D = w->last_schedule == VOPP_SCHEDULE_FIXED ? w->last_depth
+                                                           : std::min(k, w->last_depth);
+      for (int d = 0; d < D; ++d) level_of_step.push_back(d);
+    }
+    b_depth[0] = 0;
+    for (size_t t = 0; t < level_of_step.size(); ++t)
+      for (int b = base[t]; b < base[t + 1]; ++b) b_depth[b] = level_of_step[t] + 1;
+  }
+  if (e != hipSuccess) return hip_fail(e, "tree dump");
+  return VOPP_OK;
+}

@@ -1,0 +1,298 @@
+// vopp_device.hpp -- device-side data views and per-episode building blocks
+// of the VOPP planning step on CDNA4 (gfx950).
+//
+// Everything here runs in registers: the Philox4x32-10 counter-based
+// generator, the tabular and navigation generative models G (Sec. III-B),
+// the softmax action draw of Eq. (6) and the log-sum-exp value of Eq. (3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vopp {
+
+constexpr int kBlock = 256;                 // threads per block (4 wavefronts)
+constexpr int kResItems = 8;                // episodes per thread in resolve
+constexpr int kResTile = kBlock * kResItems;
+constexpr int kMaxA = 64;
+constexpr int kMaxBudget = 256;             // iterations per plan
+constexpr int kMaxRanges = kMaxBudget;
+constexpr int32_t kClaimBase = INT32_MIN;   // claim value = kClaimBase + episode
+constexpr int32_t kWinBit = 1 << 30;        // flags the claim winner's hash slot
+constexpr int32_t kSlotMask = kWinBit - 1;
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+enum : uint32_t { kTagRoot = 1, kTagStep = 2, kTagEnv = 4, kTagPF = 5, kTagResample = 6 };
+enum : int { kTabular = 0, kNav = 1 };
+
+struct NavParams {
+  float lo, hi, step, sigma_move, sigma_obs0, sigma_obs_slope, obs_center_x,
+      inv_bin;
+  int key_lo, key_n;
+  float goal_x, goal_y, goal_r2, disk_r2, r_step, r_goal, r_hit;
+  int heuristic;
+  int n_disks;
+};
+
+// Device copy of a model (owned by the pomdp handle).
+struct ModelView {
+  int kind;
+  int nS, nA, nO, Apad;                    // Apad: row stride, multiple of 4
+  const int* rowptr;                       // [nS*nA+1]
+  const int* col;                          // [nnz]
+  const uint32_t* thrT;                    // [nnz]
+  const uint32_t* thrZ;                    // [nS*nA*nO]
+  const float* R;                          // [nS*nA]
+  const float* H;                          // [nS] or null
+  NavParams nav;
+  const float* disks;                      // [2*n_disks]
+  const float* gauss;                      // [4096]
+  float gamma;
+  double gamma64;
+};
+
+// The tree store in HBM (structure of arrays).  Beliefs and action nodes are
+// numbered in creation order; the root is belief 0, whose preference row is
+// kept in double precision in psi_root.
+struct TreeView {
+  int* b_parent;           // parent action node
+  int* b_obs;              // observation key
+  float* psi;              // [cap_b * Apad] preferences
+  int* b_child;            // [cap_b * Apad] action node per action, -1 none
+  float* b_V;              // value L_eta Psi (internal) or mean heuristic (leaf)
+  int* b_N;                // visit count
+  int* leaf_cnt;           // this iteration's leaf visits (0 between iterations)
+  unsigned long long* leaf_h;   // this iteration's heuristic sum (fixed point)
+  int* b_hslot;            // hash slot that maps to the belief
+  int* a_parent;           // parent belief
+  int* a_act;              // action
+  unsigned long long* a_C; // cumulative reward (fixed point, two's complement)
+  int* a_N;                // visit count
+  unsigned long long* a_W; // sum over child beliefs of V*N_b (fixed point)
+  double* psi_root;        // [nA]
+  double* v_root;          // [1]
+  unsigned long long* h_key;   // open-addressing table (belief, action, obs)
+  int* h_val;                  // -> belief, -1 free, < -1 claim
+  uint32_t h_mask;
+  int* bel_base;           // [max_steps+1] beliefs before each level step
+  int* act_base;           // [max_steps+1] action nodes before each step
+  unsigned long long* lookback;  // [max_steps * res_tiles] scan state
+  int* tickets;            // [max_steps] dynamic tile counters
+  unsigned long long* counters;  // [0] particle steps
+  const int* step_base;    // [K+1] first level step of each iteration
+  int res_tiles;
+};
+
+// Per-episode arrays, indexed by episode id (length n_p).
+struct EpisodeView {
+  int* s_i;                // tabular state
+  float* s_x;              // navigation state
+  float* s_y;
+  int* aslot;              // belief*Apad + action, -1 when not running
+  int* hslot;              // hash slot (| kWinBit for the creator), -1 if terminal
+  float* r;                // reward of the last step
+  const void* belief;      // root belief particles
+  int n_belief;
+};
+
+struct PlanView {
+  ModelView m;
+  TreeView t;
+  EpisodeView e;
+  int n_p;
+  float eta;
+  double eta64;
+  uint32_t seed_lo, seed_hi, step;
+  float fix_scale;         // 2^S: fixed-point scale of the deterministic sums
+  float fix_inv;           // 2^-S
+  double fix_inv64;
+  float psi0;              // -ln|A| / eta
+  double psi0_64;
+  int K, depth, schedule;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds; each multiplies words 0
+// and 2 by the two round constants, mixes the high halves with the key and the
+// other two words, and the key advances by the two Weyl constants.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                     uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
+    const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(const PlanView& P, uint32_t ep, uint32_t tag,
+                                   uint32_t level, uint32_t iter) {
+  return philox(ep, (tag << 24) | level, iter, P.step, P.seed_lo, P.seed_hi);
+}
+
+// splitmix64 finaliser for the open-addressing table.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Count of thresholds <= u among n monotone thresholds = first j with u < thr_j.
+__device__ __forceinline__ int count_le(const uint32_t* __restrict__ thr, int n,
+                                        uint32_t u) {
+  int c = 0;
+  for (int j = 0; j < n; ++j) c += (thr[j] <= u) ? 1 : 0;
+  return c;
+}
+
+// Tabular G: successor from word y, observation from word z, R(s, a).
+__device__ __forceinline__ void tabular_step(const ModelView& m, int s, int a,
+                                             const U4& x, int& sn, int& obs,
+                                             float& r) {
+  const int row = s * m.nA + a;
+  const int lo = m.rowptr[row];
+  const int n = m.rowptr[row + 1] - lo;
+  int j = count_le(m.thrT + lo, n, x.y >> 1);
+  j = j < n ? j : n - 1;
+  sn = m.col[lo + j];
+  const uint32_t* zr = m.thrZ + ((size_t)sn * m.nA + a) * m.nO;
+  int o = count_le(zr, m.nO, x.z >> 1);
+  obs = o < m.nO ? o : m.nO - 1;
+  r = m.R[row];
+}
+
+__device__ __forceinline__ int nav_axis(const NavParams& p, float v) {
+  float c = floorf(v * p.inv_bin);
+  c = fmaxf(fminf(c, (float)(p.key_lo + p.key_n - 1)), (float)p.key_lo);
+  return (int)c - p.key_lo;
+}
+
+// Navigation G.  Built without contraction: each operation rounds once.
+__device__ __forceinline__ void nav_step(const ModelView& m, float x, float y,
+                                         int a, const U4& w, float& nx,
+                                         float& ny, int& key, float& r,
+                                         bool& term) {
+  const NavParams& p = m.nav;
+  float dx = 0.0f, dy = 0.0f;
+  if (a == 0) dy = p.step;
+  else if (a == 1) dx = p.step;
+  else if (a == 2) dy = -p.step;
+  else dx = -p.step;
+  const float zx = m.gauss[w.y >> 20];
+  const float zy = m.gauss[(w.y >> 8) & 4095u];
+  const float mx = x + dx;
+  const float my = y + dy;
+  nx = fminf(fmaxf(mx + p.sigma_move * zx, p.lo), p.hi);
+  ny = fminf(fmaxf(my + p.sigma_move * zy, p.lo), p.hi);
+  const float sd = p.sigma_obs0 + p.sigma_obs_slope * fabsf(nx - p.obs_center_x);
+  const float ox = nx + sd * m.gauss[w.z >> 20];
+  const float oy = ny + sd * m.gauss[(w.z >> 8) & 4095u];
+  key = nav_axis(p, ox) * p.key_n + nav_axis(p, oy);
+  const float gx = nx - p.goal_x, gy = ny - p.goal_y;
+  const bool goal = (gx * gx + gy * gy) <= p.goal_r2;
+  bool hit = false;
+  for (int i = 0; i < p.n_disks; ++i) {
+    const float ex = nx - m.disks[2 * i], ey = ny - m.disks[2 * i + 1];
+    hit = hit || ((ex * ex + ey * ey) <= p.disk_r2);
+  }
+  float rr = p.r_step;
+  if (goal) rr = rr + p.r_goal;
+  if (hit) rr = rr + p.r_hit;
+  r = rr;
+  term = goal;
+}
+
+__device__ __forceinline__ float nav_heuristic(const NavParams& p, float x, float y) {
+  if (p.heuristic == 0) return 0.0f;
+  return -(fabsf(x - p.goal_x) + fabsf(y - p.goal_y));
+}
+
+// Softmax draw of Eq. (6) in single precision: weights exp(eta (psi_j - max)),
+// running sums P_j, t = u * P_last, first j with t < P_j.  AM >= A is a
+// compile-time bound so the row stays in registers.
+template <int AM>
+__device__ __forceinline__ int draw_action32(const float* __restrict__ row, int A,
+                                             float eta, uint32_t x0) {
+  float v[AM];
+#pragma unroll
+  for (int j = 0; j < AM; j += 4) {
+    // Rows are padded to a multiple of 4, so j < A keeps the load in the row.
+    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j < A) q = *reinterpret_cast<const float4*>(row + j);
+    v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
+  }
+  float m = v[0];
+#pragma unroll
+  for (int j = 1; j < AM; ++j)
+    if (j < A) m = fmaxf(m, v[j]);
+  float total = 0.0f;
+#pragma unroll
+  for (int j = 0; j < AM; ++j)
+    if (j < A) { v[j] = expf(eta * (v[j] - m)); total = total + v[j]; }
+  const float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
+  const float t = u * total;
+  float run = 0.0f;
+  int a = A - 1;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < AM; ++j) {
+    if (j < A && !found) {
+      run = run + v[j];
+      if (t < run) { a = j; found = true; }
+    }
+  }
+  return a;
+}
+
+// The same draw in double precision (root row).
+__device__ __forceinline__ int draw_action64(const double* __restrict__ row, int A,
+                                             double eta, uint32_t x0) {
+  double m = row[0];
+  for (int j = 1; j < A; ++j) m = fmax(m, row[j]);
+  double total = 0.0;
+  for (int j = 0; j < A; ++j) total = total + exp(eta * (row[j] - m));
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double t = u * total;
+  double run = 0.0;
+  for (int j = 0; j < A; ++j) {
+    run = run + exp(eta * (row[j] - m));
+    if (t < run) return j;
+  }
+  return A - 1;
+}
+
+// L_eta x = max + (1/eta) ln sum_j exp(eta (x_j - max))   (Eq. 3).
+__device__ __forceinline__ float lse32(const float* x, int A, float eta) {
+  float m = x[0];
+  for (int j = 1; j < A; ++j) m = fmaxf(m, x[j]);
+  float s = 0.0f;
+  for (int j = 0; j < A; ++j) s = s + expf(eta * (x[j] - m));
+  return m + logf(s) / eta;
+}
+
+__device__ __forceinline__ double lse64(const double* x, int A, double eta) {
+  double m = x[0];
+  for (int j = 1; j < A; ++j) m = fmax(m, x[j]);
+  double s = 0.0;
+  for (int j = 0; j < A; ++j) s = s + exp(eta * (x[j] - m));
+  return m + log(s) / eta;
+}
+
+// Fixed-point conversion of a value for the order-independent sums.
+__device__ __forceinline__ unsigned long long to_fix(float v, float scale) {
+  return (unsigned long long)__float2ll_rn(v * scale);
+}
+__device__ __forceinline__ float from_fix(unsigned long long v, float inv) {
+  return (float)(long long)v * inv;
+}
+
+}  // namespace vopp

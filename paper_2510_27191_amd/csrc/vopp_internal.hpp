@@ -1,0 +1,63 @@
+// vopp_internal.hpp -- host-side handle types shared by the library's
+// translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/vopp.h"
+#include "vopp_device.hpp"
+
+struct vopp_pomdp {
+  int kind = 0;
+  int nA = 0;
+  int device = 0;
+  double r_max = 0.0, h_max = 0.0, gamma = 0.0;
+  double branch = 1.0;           // |A| * |O| (observation keys per action)
+  void* arena = nullptr;
+  size_t bytes = 0;
+  vopp::ModelView view{};
+  vopp_workspace* own_ws = nullptr;
+};
+
+namespace vopp {
+struct WsSizes {
+  int n_p = 0, steps = 0, K = 0, Apad = 0, res_tiles = 0;
+  long long cap_b = 0, cap_a = 0;
+  uint64_t hcap = 0;
+};
+}  // namespace vopp
+
+struct vopp_workspace {
+  vopp::WsSizes z;
+  int device = 0;
+  void* arena = nullptr;
+  size_t bytes = 0;
+  vopp::TreeView tree{};
+  vopp::EpisodeView ep{};
+  int* step_base_dev = nullptr;
+  int* step_host = nullptr;       // pinned
+  double* out_dev = nullptr;
+  double* out_host = nullptr;     // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool hash_dirty = true;
+  int n_prev_beliefs = 0, n_prev_actions = 0;
+  int last_A = 0, last_apad = 0, last_steps = 0, last_n_p = 0, last_K = 0,
+      last_depth = 0, last_schedule = 0;
+  double last_fix_inv64 = 0.0;
+};
+
+namespace vopp {
+vopp_status fail(vopp_status st, const char* fmt, ...);
+vopp_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+int sum_depths(int K, int depth, int schedule);
+vopp_status check_params(const vopp_pomdp* p, const vopp_params* prm, int32_t budget,
+                         int32_t depth);
+vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out);
+vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_params* prm,
+                      int K, int depth);
+PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
+                   int n_belief, int K, int depth, const vopp_params* prm);
+vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
+                         hipStream_t s, int* n_steps_out);
+}  // namespace vopp

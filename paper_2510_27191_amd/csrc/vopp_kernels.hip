@@ -1,0 +1,605 @@
+// vopp_kernels.hip -- HIP kernels of one VOPP planning step for gfx950.
+//
+// One level of the vectorized forward search (Alg. 2) is two launches:
+//
+//   expand   one thread per episode: close the previous level (visit count and
+//            reward sum of the action node, parent of a new belief), draw the
+//            action from the softmax of the belief's preferences (Eq. 6), call
+//            G, and claim the (belief, action) slot of the dense child table
+//            and the (belief, action, observation) slot of the open-addressing
+//            table with atomicMin(kClaimBase + episode).
+//   resolve  the smallest claiming episode of each new pair is its creator;
+//            creators are ranked in episode order by a single-pass
+//            decoupled look-back scan (dynamic tile tickets), which numbers new
+//            action nodes and beliefs in first-visitor order, initialises
+//            their rows and publishes the indices in the tables.
+//
+// After the deepest level, `finish` closes it and accumulates this
+// iteration's leaf visits and heuristic sums.  The backup of Alg. 3 is one
+// launch per depth over every belief of that depth in the tree: leaves take
+// their mean heuristic, internal beliefs update their preference row with
+// Q = C/N + gamma W and V = L_eta Psi, and each belief pushes V*N_b into its
+// parent action's W accumulator.  The root level runs in double precision.
+//
+// All cross-episode sums (rewards, heuristics, V*N_b) are 64-bit fixed-point
+// integer atomics, so the results do not depend on thread order.
+#include "vopp_device.hpp"
+#include "vopp_launch.hpp"
+
+namespace vopp {
+
+// ---------------------------------------------------------------------------
+// Open-addressing table: find or insert the key, return its slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int hash_slot(const TreeView& t, unsigned long long key) {
+  uint32_t h = (uint32_t)mix64(key) & t.h_mask;
+  while (true) {
+    unsigned long long cur = __hip_atomic_load(&t.h_key[h], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == key) return (int)h;
+    if (cur == kEmptyKey) {
+      unsigned long long prev = atomicCAS(&t.h_key[h], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) return (int)h;
+    }
+    h = (h + 1) & t.h_mask;
+  }
+}
+
+__device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) {
+  return ((unsigned long long)(uint32_t)b << 32) |
+         ((unsigned long long)(uint32_t)a << 24) | (uint32_t)obs;
+}
+
+// Close the previous level for one episode: returns the belief the episode
+// now sits at, or -1 if it stopped (terminal or not running).
+__device__ __forceinline__ int close_level(const PlanView& P, int ep) {
+  const int as = P.e.aslot[ep];
+  if (as < 0) return -1;
+  const int an = P.t.b_child[as];
+  atomicAdd(&P.t.a_N[an], 1);
+  atomicAdd(&P.t.a_C[an], to_fix(P.e.r[ep], P.fix_scale));
+  const int hs = P.e.hslot[ep];
+  if (hs < 0) return -1;
+  const int b = P.t.h_val[hs & kSlotMask];
+  if (hs & kWinBit) P.t.b_parent[b] = an;
+  return b;
+}
+
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
+  const int ep = blockIdx.x * kBlock + threadIdx.x;
+  bool alive = false;
+  int b = -1, s = 0;
+  float x = 0.0f, y = 0.0f;
+  if (ep < P.n_p) {
+    if (d == 0) {
+      const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
+      const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
+      if (P.m.kind == kTabular) {
+        s = ((const int*)P.e.belief)[idx];
+        if ((unsigned)s >= (unsigned)P.m.nS) {   // caller's particle out of range
+          atomicOr((unsigned int*)&P.t.counters[1], 1u);
+          s = 0;
+        }
+      } else {
+        const float* bf = (const float*)P.e.belief;
+        x = bf[idx];
+        y = bf[P.e.n_belief + idx];
+      }
+      b = 0;
+      alive = true;
+    } else {
+      b = close_level(P, ep);
+      alive = b >= 0;
+      if (alive) {
+        if (P.m.kind == kTabular) s = P.e.s_i[ep];
+        else { x = P.e.s_x[ep]; y = P.e.s_y[ep]; }
+      }
+    }
+  }
+  int as = -1, hs = -1;
+  if (alive) {
+    const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
+    const int A = P.m.nA;
+    int a;
+    if (b == 0) {
+      a = draw_action64(P.t.psi_root, A, P.eta64, w.x);
+    } else {
+      a = draw_action32<AM>(P.t.psi + (size_t)b * P.m.Apad, A, P.eta, w.x);
+    }
+    int obs;
+    float r;
+    bool term = false;
+    if (P.m.kind == kTabular) {
+      int sn;
+      tabular_step(P.m, s, a, w, sn, obs, r);
+      P.e.s_i[ep] = sn;
+    } else {
+      float nx, ny;
+      nav_step(P.m, x, y, a, w, nx, ny, obs, r, term);
+      P.e.s_x[ep] = nx;
+      P.e.s_y[ep] = ny;
+    }
+    P.e.r[ep] = r;
+    as = b * P.m.Apad + a;
+    if (P.t.b_child[as] < 0) atomicMin(&P.t.b_child[as], kClaimBase + ep);
+    if (!term) {
+      hs = hash_slot(P.t, belief_key(b, a, obs));
+      if (P.t.h_val[hs] < 0) atomicMin(&P.t.h_val[hs], kClaimBase + ep);
+    }
+  }
+  if (ep < P.n_p) {
+    P.e.aslot[ep] = as;
+    P.e.hslot[ep] = hs;
+  }
+  // Particle-step count: one generative-model call per running episode.
+  const unsigned long long ballot = __ballot(alive);
+  if ((threadIdx.x & 63) == 0 && ballot)
+    atomicAdd(&P.t.counters[0], (unsigned long long)__popcll(ballot));
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of two packed counters.
+// Packed word: (count_a << 31) | count_b, both < 2^31.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    unsigned long long n = __shfl_up(v, off, 64);
+    if (lane >= off) v += n;
+  }
+  return v;
+}
+
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagIncl = 2ull << 62;
+constexpr unsigned long long kPayload = (1ull << 62) - 1;
+
+__global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
+  __shared__ int s_tile;
+  __shared__ unsigned long long s_wave[kBlock / 64];
+  __shared__ unsigned long long s_prefix;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&P.t.tickets[t], 1);
+  __syncthreads();
+  const int tile = s_tile;
+  const int base_ep = tile * kResTile + threadIdx.x * kResItems;
+
+  int aslot[kResItems], hslot[kResItems];
+  unsigned flags = 0;   // bit i: action creator, bit 16+i: belief creator
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int i = 0; i < kResItems; ++i) {
+    const int ep = base_ep + i;
+    aslot[i] = -1;
+    hslot[i] = -1;
+    if (ep < P.n_p) {
+      aslot[i] = P.e.aslot[ep];
+      hslot[i] = P.e.hslot[ep];
+      if (aslot[i] >= 0 && P.t.b_child[aslot[i]] == kClaimBase + ep) {
+        flags |= 1u << i;
+        mine += 1ull << 31;
+      }
+      if (hslot[i] >= 0 && P.t.h_val[hslot[i]] == kClaimBase + ep) {
+        flags |= 1u << (16 + i);
+        mine += 1ull;
+      }
+    }
+  }
+  // Block scan.
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned long long incl = wave_incl_scan(mine);
+  if (lane == 63) s_wave[wid] = incl;
+  __syncthreads();
+  unsigned long long wave_off = 0, block_total = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < wid) wave_off += s_wave[i];
+    block_total += s_wave[i];
+  }
+  const unsigned long long local_excl = wave_off + incl - mine;
+
+  // Decoupled look-back across tiles.
+  if (threadIdx.x == 0) {
+    unsigned long long* st = P.t.lookback + (size_t)t * P.t.res_tiles;
+    unsigned long long excl = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&st[0], kFlagIncl | block_total, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&st[tile], kFlagAgg | block_total, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      int j = tile - 1;
+      while (true) {
+        unsigned long long v;
+        do {
+          v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if ((v >> 62) == 0) __builtin_amdgcn_s_sleep(1);
+        } while ((v >> 62) == 0);
+        excl += v & kPayload;
+        if ((v >> 62) == 2) break;
+        --j;
+      }
+      __hip_atomic_store(&st[tile], kFlagIncl | (excl + block_total),
+                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_prefix = excl;
+    if (tile == P.t.res_tiles - 1) {
+      const unsigned long long tot = excl + block_total;
+      P.t.act_base[t + 1] = P.t.act_base[t] + (int)(tot >> 31);
+      P.t.bel_base[t + 1] = P.t.bel_base[t] + (int)(tot & 0x7FFFFFFFull);
+    }
+  }
+  __syncthreads();
+  if (!flags) return;
+  const unsigned long long pre = s_prefix + local_excl;
+  int na = P.t.act_base[t] + (int)(pre >> 31);
+  int nb = P.t.bel_base[t] + (int)(pre & 0x7FFFFFFFull);
+  const int Apad = P.m.Apad, A = P.m.nA;
+#pragma unroll
+  for (int i = 0; i < kResItems; ++i) {
+    if (flags & (1u << i)) {
+      const int as = aslot[i];
+      P.t.b_child[as] = na;
+      P.t.a_parent[na] = as / Apad;
+      P.t.a_act[na] = as % Apad;
+      P.t.a_C[na] = 0ull;
+      P.t.a_N[na] = 0;
+      P.t.a_W[na] = 0ull;
+      ++na;
+    }
+    if (flags & (1u << (16 + i))) {
+      const int hs = hslot[i];
+      const unsigned long long key = P.t.h_key[hs];
+      P.t.h_val[hs] = nb;
+      P.t.b_obs[nb] = (int)(key & 0xFFFFFFull);
+      P.t.b_hslot[nb] = hs;
+      P.t.b_V[nb] = 0.0f;
+      P.t.b_N[nb] = 0;
+      P.t.leaf_cnt[nb] = 0;
+      P.t.leaf_h[nb] = 0ull;
+      float* row = P.t.psi + (size_t)nb * Apad;
+      int* crow = P.t.b_child + (size_t)nb * Apad;
+      for (int j = 0; j < Apad; ++j) {
+        row[j] = j < A ? P.psi0 : 0.0f;
+        crow[j] = -1;
+      }
+      P.e.hslot[base_ep + i] = hs | kWinBit;
+      ++nb;
+    }
+  }
+}
+
+// Close the deepest level and accumulate this iteration's leaves.
+__global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
+  const int ep = blockIdx.x * kBlock + threadIdx.x;
+  if (ep >= P.n_p) return;
+  const int b = close_level(P, ep);
+  if (b < 0) return;
+  atomicAdd(&P.t.leaf_cnt[b], 1);
+  float h = 0.0f;
+  if (P.m.kind == kTabular) {
+    if (P.m.H) h = P.m.H[P.e.s_i[ep]];
+  } else {
+    h = nav_heuristic(P.m.nav, P.e.s_x[ep], P.e.s_y[ep]);
+  }
+  if (h != 0.0f) atomicAdd(&P.t.leaf_h[b], to_fix(h, P.fix_scale));
+}
+
+// ---------------------------------------------------------------------------
+// Backup.  Beliefs of depth `dep` were created by level dep-1 of every
+// iteration k' <= k whose depth D_k' >= dep; each such level step is one
+// contiguous row range.
+// ---------------------------------------------------------------------------
+struct Ranges {
+  int n;
+  int lo[kMaxRanges];
+  int len[kMaxRanges];
+  int off[kMaxRanges + 1];
+};
+
+__device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
+                                            Ranges& R) {
+  if (threadIdx.x == 0) {
+    int n = 0, off = 0;
+    for (int kk = 1; kk <= k; ++kk) {
+      const int s0 = P.t.step_base[kk - 1];
+      const int Dk = P.t.step_base[kk] - s0;
+      if (Dk >= dep) {
+        const int t = s0 + dep - 1;
+        const int lo = P.t.bel_base[t];
+        const int len = P.t.bel_base[t + 1] - lo;
+        R.lo[n] = lo;
+        R.len[n] = len;
+        R.off[n] = off;
+        off += len;
+        ++n;
+      }
+    }
+    R.off[n] = off;
+    R.n = n;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int range_row(const Ranges& R, int i) {
+  int lo = 0, hi = R.n - 1;          // last r with off[r] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (R.off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return R.lo[lo] + (i - R.off[lo]);
+}
+
+__device__ __forceinline__ void push_value(const PlanView& P, int b, float V, int N) {
+  if (N > 0) {
+    const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
+    if (f) atomicAdd(&P.t.a_W[P.t.b_parent[b]], f);
+  }
+}
+
+// Leaves of this iteration take count and mean heuristic; every belief of
+// depth D pushes V*N_b to its parent action.
+__global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
+  __shared__ Ranges R;
+  load_ranges(P, dep, k, R);
+  const int total = R.off[R.n];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    const int b = range_row(R, i);
+    const int c = P.t.leaf_cnt[b];
+    float V;
+    int N;
+    if (c > 0) {
+      const unsigned long long hs = P.t.leaf_h[b];
+      V = from_fix(hs, P.fix_inv) / (float)c;
+      N = c;
+      P.t.b_V[b] = V;
+      P.t.b_N[b] = N;
+      P.t.leaf_cnt[b] = 0;
+      if (hs) P.t.leaf_h[b] = 0ull;
+    } else {
+      V = P.t.b_V[b];
+      N = P.t.b_N[b];
+    }
+    push_value(P, b, V, N);
+  }
+}
+
+// Internal beliefs of depth dep-1 >= 1.  AM >= |A| keeps the row in registers.
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, int k) {
+  __shared__ Ranges R;
+  load_ranges(P, dep - 1, k, R);
+  const int total = R.off[R.n];
+  const int A = P.m.nA, Apad = P.m.Apad;
+  const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    const int b = range_row(R, i);
+    const int* crow = P.t.b_child + (size_t)b * Apad;
+    float* prow = P.t.psi + (size_t)b * Apad;
+    int child[AM];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < AM; j += 4) {
+      int4 c = make_int4(-1, -1, -1, -1);
+      if (j < A) c = *reinterpret_cast<const int4*>(crow + j);
+      child[j] = c.x; child[j + 1] = c.y; child[j + 2] = c.z; child[j + 3] = c.w;
+    }
+#pragma unroll
+    for (int j = 0; j < AM; ++j) any = any || (j < A && child[j] >= 0);
+    float V;
+    int N;
+    if (any) {
+      float psi[AM];
+#pragma unroll
+      for (int j = 0; j < AM; j += 4) {
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < A) q = *reinterpret_cast<const float4*>(prow + j);
+        psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
+      }
+      float m = psi[0];
+#pragma unroll
+      for (int j = 1; j < AM; ++j)
+        if (j < A) m = fmaxf(m, psi[j]);
+      float se = 0.0f;
+#pragma unroll
+      for (int j = 0; j < AM; ++j)
+        if (j < A) se = se + expf(eta * (psi[j] - m));
+      const float vc = m + logf(se) / eta;
+      int nsum = 0;
+#pragma unroll
+      for (int j = 0; j < AM; ++j) {
+        const int an = child[j];
+        if (j < A && an >= 0) {
+          const int n = P.t.a_N[an];
+          const float c = from_fix(P.t.a_C[an], inv);
+          const unsigned long long wf = P.t.a_W[an];
+          const float w = from_fix(wf, inv);
+          if (wf) P.t.a_W[an] = 0ull;
+          const float fn = (float)n;
+          const float q = c / fn + gamma * (w / fn);
+          psi[j] = (psi[j] - vc) + q;
+          nsum += n;
+        }
+      }
+      float m2 = psi[0];
+#pragma unroll
+      for (int j = 1; j < AM; ++j)
+        if (j < A) m2 = fmaxf(m2, psi[j]);
+      float se2 = 0.0f;
+#pragma unroll
+      for (int j = 0; j < AM; ++j)
+        if (j < A) se2 = se2 + expf(eta * (psi[j] - m2));
+      V = m2 + logf(se2) / eta;
+      N = nsum;
+#pragma unroll
+      for (int j = 0; j < AM; j += 4)
+        if (j < A)
+          *reinterpret_cast<float4*>(prow + j) =
+              make_float4(psi[j], psi[j + 1], psi[j + 2], psi[j + 3]);
+      P.t.b_V[b] = V;
+      P.t.b_N[b] = N;
+    } else {
+      V = P.t.b_V[b];
+      N = P.t.b_N[b];
+    }
+    push_value(P, b, V, N);
+  }
+}
+
+// The root row in double precision.
+__global__ void k_backup_root(PlanView P) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int A = P.m.nA;
+  double psi[kMaxA];
+  for (int j = 0; j < A; ++j) psi[j] = P.t.psi_root[j];
+  const double vc = lse64(psi, A, P.eta64);
+  long long nsum = 0;
+  bool any = false;
+  for (int j = 0; j < A; ++j) {
+    const int an = P.t.b_child[j];
+    if (an < 0) continue;
+    any = true;
+    const int n = P.t.a_N[an];
+    const double c = (double)(long long)P.t.a_C[an] * P.fix_inv64;
+    const double w = (double)(long long)P.t.a_W[an] * P.fix_inv64;
+    P.t.a_W[an] = 0ull;
+    const double q = c / (double)n + P.m.gamma64 * (w / (double)n);
+    psi[j] = (psi[j] - vc) + q;
+    nsum += n;
+  }
+  if (!any) return;
+  for (int j = 0; j < A; ++j) P.t.psi_root[j] = psi[j];
+  const double v = lse64(psi, A, P.eta64);
+  P.t.v_root[0] = v;
+  P.t.b_V[0] = (float)v;
+  P.t.b_N[0] = (int)nsum;
+}
+
+// ---------------------------------------------------------------------------
+// Plan set-up and result.
+// ---------------------------------------------------------------------------
+
+// Clear the table slots used by the previous plan (its beliefs' slots).
+__global__ __launch_bounds__(kBlock) void k_clear_slots(PlanView P, int n_prev) {
+  for (int b = 1 + blockIdx.x * kBlock + threadIdx.x; b < n_prev;
+       b += gridDim.x * kBlock) {
+    const int hs = P.t.b_hslot[b];
+    P.t.h_key[hs] = kEmptyKey;
+    P.t.h_val[hs] = -1;
+  }
+}
+
+// Fill 32-bit words with a value (a plain kernel, safe inside graph capture).
+__global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, size_t n, uint32_t v) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+__global__ void k_init_root(PlanView P) {
+  const int j = threadIdx.x;
+  const int A = P.m.nA, Apad = P.m.Apad;
+  if (j < Apad) {
+    P.t.b_child[j] = -1;
+    P.t.psi[j] = j < A ? P.psi0 : 0.0f;
+    if (j < A) P.t.psi_root[j] = P.psi0_64;
+  }
+  if (j == 0) {
+    P.t.b_parent[0] = -1;
+    P.t.b_obs[0] = -1;
+    P.t.b_V[0] = 0.0f;
+    P.t.b_N[0] = 0;
+    P.t.leaf_cnt[0] = 0;
+    P.t.leaf_h[0] = 0ull;
+    P.t.b_hslot[0] = 0;
+    P.t.v_root[0] = 0.0;
+    P.t.bel_base[0] = 1;
+    P.t.act_base[0] = 0;
+    P.t.counters[0] = 0ull;
+    P.t.counters[1] = 0ull;
+  }
+}
+
+// out: [0] action, [1..A] psi_root, [A+1] v_root, [A+2] particle steps,
+//      [A+3] beliefs, [A+4] action nodes, [A+5] input-error flags (doubles).
+__global__ void k_select(PlanView P, int last_step, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int A = P.m.nA;
+  int best = 0;
+  for (int j = 1; j < A; ++j)
+    if (P.t.psi_root[j] > P.t.psi_root[best]) best = j;
+  out[0] = (double)best;
+  for (int j = 0; j < A; ++j) out[1 + j] = P.t.psi_root[j];
+  out[A + 1] = P.t.v_root[0];
+  out[A + 2] = (double)P.t.counters[0];
+  out[A + 3] = (double)P.t.bel_base[last_step];
+  out[A + 4] = (double)P.t.act_base[last_step];
+  out[A + 5] = (double)P.t.counters[1];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side).
+// ---------------------------------------------------------------------------
+static inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_expand(const PlanView& P, int k, int d, hipStream_t s) {
+  const dim3 g(blocks_for(P.n_p)), b(kBlock);
+  const int Ap = P.m.Apad;
+  if (Ap <= 4) hipLaunchKernelGGL(k_expand<4>, g, b, 0, s, P, k, d);
+  else if (Ap <= 8) hipLaunchKernelGGL(k_expand<8>, g, b, 0, s, P, k, d);
+  else if (Ap <= 16) hipLaunchKernelGGL(k_expand<16>, g, b, 0, s, P, k, d);
+  else if (Ap <= 32) hipLaunchKernelGGL(k_expand<32>, g, b, 0, s, P, k, d);
+  else hipLaunchKernelGGL(k_expand<64>, g, b, 0, s, P, k, d);
+  return hipGetLastError();
+}
+hipError_t launch_resolve(const PlanView& P, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_resolve, dim3(P.t.res_tiles), dim3(kBlock), 0, s, P, t);
+  return hipGetLastError();
+}
+hipError_t launch_finish(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(blocks_for(P.n_p)), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_backup_leaf, dim3(grid), dim3(kBlock), 0, s, P, dep, k);
+  return hipGetLastError();
+}
+hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
+  const dim3 g(grid), b(kBlock);
+  const int Ap = P.m.Apad;
+  if (Ap <= 4) hipLaunchKernelGGL(k_backup_level<4>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 8) hipLaunchKernelGGL(k_backup_level<8>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, P, dep, k);
+  else hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
+  return hipGetLastError();
+}
+hipError_t launch_backup_root(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_clear_slots(const PlanView& P, int n_prev, hipStream_t s) {
+  if (n_prev <= 1) return hipSuccess;
+  int grid = blocks_for(n_prev);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(kBlock), 0, s, P, n_prev);
+  return hipGetLastError();
+}
+hipError_t launch_fill32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t g = (n + kBlock - 1) / kBlock;
+  int grid = (int)(g > 8192 ? 8192 : g);
+  hipLaunchKernelGGL(k_fill32, dim3(grid), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_init_root(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, s, P);
+  return hipGetLastError();
+}
+hipError_t launch_select(const PlanView& P, int last_step, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P, last_step, out);
+  return hipGetLastError();
+}
+
+}  // namespace vopp

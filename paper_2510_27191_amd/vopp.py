@@ -1,0 +1,247 @@
+"""Thin ctypes binding of the C ABI in ``include/vopp.h``.
+
+Argument marshalling only: every step of a plan runs in the HIP library
+``libvopp.so``.  PyTorch provides device memory (belief particles) and
+streams.  Importing this module raises if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvopp.so")
+
+VOPP_OK = 0
+VOPP_E_INVALID = -1
+VOPP_E_NOMEM = -2
+VOPP_E_DEVICE = -3
+VOPP_E_BUSY = -4
+VOPP_E_INTERNAL = -5
+SCHEDULE_DEEPEN = 0
+SCHEDULE_FIXED = 1
+
+EXPORTS = (
+    "vopp_last_error", "vopp_version", "vopp_pomdp_tabular", "vopp_pomdp_nav2d",
+    "vopp_pomdp_num_actions", "vopp_pomdp_free", "vopp_plan_footprint",
+    "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
+    "vopp_tree_dump",
+)
+
+
+class VoppError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"vopp status {status}: {msg}")
+        self.status = status
+
+
+class vopp_tabular_desc(C.Structure):
+    _fields_ = [("nS", C.c_int32), ("nA", C.c_int32), ("nO", C.c_int32),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("tprob", C.c_void_p), ("zprob", C.c_void_p),
+                ("reward", C.c_void_p), ("heur", C.c_void_p),
+                ("gamma", C.c_double)]
+
+
+class vopp_nav2d_desc(C.Structure):
+    _fields_ = [(n, C.c_float) for n in (
+        "lo", "hi", "step", "sigma_move", "sigma_obs0", "sigma_obs_slope",
+        "obs_center_x", "inv_bin")] + [
+        ("key_lo", C.c_int32), ("key_n", C.c_int32)] + [
+        (n, C.c_float) for n in ("goal_x", "goal_y", "goal_r2", "disk_r2",
+                                 "r_step", "r_goal", "r_hit")] + [
+        ("heuristic", C.c_int32), ("n_disks", C.c_int32),
+        ("disks", C.c_void_p), ("gauss", C.c_void_p), ("gamma", C.c_double)]
+
+
+class vopp_params(C.Structure):
+    _fields_ = [("n_particles", C.c_int32), ("schedule", C.c_int32),
+                ("eta", C.c_double), ("seed", C.c_uint64), ("step", C.c_uint32)]
+
+
+class vopp_stats(C.Structure):
+    _fields_ = [("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
+                ("n_actions", C.c_int64), ("device_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvopp.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run python -m paper_2510_27191_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, st = C.c_void_p, C.c_int32, C.c_int
+    L.vopp_last_error.restype = C.c_char_p
+    L.vopp_version.restype = C.c_char_p
+    L.vopp_pomdp_tabular.argtypes = [C.POINTER(vopp_tabular_desc), C.POINTER(vp)]
+    L.vopp_pomdp_tabular.restype = st
+    L.vopp_pomdp_nav2d.argtypes = [C.POINTER(vopp_nav2d_desc), C.POINTER(vp)]
+    L.vopp_pomdp_nav2d.restype = st
+    L.vopp_pomdp_num_actions.argtypes = [vp]
+    L.vopp_pomdp_num_actions.restype = i32
+    L.vopp_pomdp_free.argtypes = [vp]
+    L.vopp_pomdp_free.restype = None
+    L.vopp_plan_footprint.argtypes = [vp, C.POINTER(vopp_params), i32, i32]
+    L.vopp_plan_footprint.restype = C.c_size_t
+    L.vopp_workspace_create.argtypes = [vp, C.POINTER(vopp_params), i32, i32,
+                                        C.POINTER(vp)]
+    L.vopp_workspace_create.restype = st
+    L.vopp_workspace_free.argtypes = [vp]
+    L.vopp_workspace_free.restype = None
+    L.vopp_plan.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vopp_params), vp, vp,
+                            C.POINTER(i32), vp, vp, C.POINTER(vopp_stats)]
+    L.vopp_plan.restype = st
+    L.vopp_tree_dump.argtypes = [vp] * 11
+    L.vopp_tree_dump.restype = st
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != VOPP_OK:
+        raise VoppError(status, lib().vopp_last_error().decode())
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _arr(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Pomdp:
+    """A model handle (vopp_pomdp_tabular / vopp_pomdp_nav2d)."""
+
+    def __init__(self, handle, kind, nA):
+        self.handle = C.c_void_p(handle)
+        self.kind = kind
+        self.nA = nA
+
+    @classmethod
+    def from_instance(cls, inst):
+        L = lib()
+        h = C.c_void_p()
+        if inst["kind"] == "tabular":
+            keep = [_arr(inst["rowptr"], np.int32), _arr(inst["col"], np.int32),
+                    _arr(inst["tprob"], np.float32), _arr(inst["zprob"], np.float32),
+                    _arr(inst["reward"], np.float32)]
+            heur = inst.get("heur")
+            heur = None if heur is None else _arr(heur, np.float32)
+            d = vopp_tabular_desc(inst["nS"], inst["nA"], inst["nO"],
+                                  *[_p(a) for a in keep], _p(heur), inst["gamma"])
+            _check(L.vopp_pomdp_tabular(C.byref(d), C.byref(h)))
+            return cls(h.value, "tabular", inst["nA"])
+        disks = _arr(inst["disks"], np.float32).reshape(-1)
+        gauss = _arr(inst["gauss"], np.float32)
+        d = vopp_nav2d_desc(inst["lo"], inst["hi"], inst["step"], inst["sigma_move"],
+                            inst["sigma_obs0"], inst["sigma_obs_slope"],
+                            inst["obs_center_x"], inst["inv_bin"], inst["key_lo"],
+                            inst["key_n"], inst["goal_x"], inst["goal_y"],
+                            inst["goal_r2"], inst["disk_r2"], inst["r_step"],
+                            inst["r_goal"], inst["r_hit"], inst["heuristic"],
+                            disks.size // 2, _p(disks), _p(gauss), inst["gamma"])
+        _check(L.vopp_pomdp_nav2d(C.byref(d), C.byref(h)))
+        return cls(h.value, "nav", 4)
+
+    def close(self):
+        if self.handle:
+            lib().vopp_pomdp_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params(n_particles, eta=1.0, seed=1, schedule=SCHEDULE_DEEPEN, step=0):
+    return vopp_params(int(n_particles), int(schedule), float(eta),
+                       int(seed) & (2 ** 64 - 1), int(step) & 0xFFFFFFFF)
+
+
+class Workspace:
+    def __init__(self, pomdp, prm, budget, depth):
+        h = C.c_void_p()
+        _check(lib().vopp_workspace_create(pomdp.handle, C.byref(prm), int(budget),
+                                           int(depth), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().vopp_workspace_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint(pomdp, prm, budget, depth):
+    return int(lib().vopp_plan_footprint(pomdp.handle, C.byref(prm), int(budget),
+                                         int(depth)))
+
+
+@dataclass
+class PlanResult:
+    action: int
+    values: np.ndarray
+    v_root: float
+    particle_steps: int
+    n_beliefs: int
+    n_actions: int
+    device_ms: float
+
+
+def belief_tensor(inst, belief, device="cuda"):
+    """Device tensor of belief particles in the layout vopp_plan expects."""
+    import torch
+    if inst["kind"] == "tabular":
+        return torch.as_tensor(_arr(belief, np.int32), device=device)
+    x, y = belief
+    return torch.as_tensor(np.concatenate([_arr(x, np.float32), _arr(y, np.float32)]),
+                           device=device)
+
+
+def plan(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None):
+    """vopp_plan on a device tensor of belief particles."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    act = C.c_int32(-1)
+    vals = np.zeros(pomdp.nA, np.float64)
+    vroot = np.zeros(1, np.float64)
+    st = vopp_stats()
+    _check(lib().vopp_plan(pomdp.handle, C.c_void_p(belief_dev.data_ptr()),
+                           int(n_belief), int(budget), int(depth), C.byref(prm),
+                           ws.handle if ws is not None else None,
+                           C.c_void_p(stream.cuda_stream), C.byref(act), _p(vals),
+                           _p(vroot), C.byref(st)))
+    return PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
+                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
+
+
+def tree_dump(ws, nA, n_beliefs, n_actions):
+    out = dict(b_parent=np.zeros(n_beliefs, np.int32), b_obs=np.zeros(n_beliefs, np.int32),
+               b_depth=np.zeros(n_beliefs, np.int32),
+               psi=np.zeros((n_beliefs, nA), np.float32),
+               b_V=np.zeros(n_beliefs, np.float32), b_N=np.zeros(n_beliefs, np.int32),
+               a_parent=np.zeros(n_actions, np.int32), a_act=np.zeros(n_actions, np.int32),
+               a_C=np.zeros(n_actions, np.float64), a_N=np.zeros(n_actions, np.int32))
+    _check(lib().vopp_tree_dump(ws.handle, *[_p(out[k]) for k in (
+        "b_parent", "b_obs", "b_depth", "psi", "b_V", "b_N", "a_parent", "a_act",
+        "a_C", "a_N")]))
+    return out
