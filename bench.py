@@ -1,0 +1,198 @@
+#!/usr/bin/env python
+"""Benchmark of one VOPP planning step on one MI355X.
+
+A "step" is one full planning step (Alg. 1: K iterations of sampling,
+level-by-level forward search and bottom-up backup, then the root argmax) on
+the continuous 2-D navigation POMDP: n_p = 65,536 episodes, depth 10, budget
+K = 10 iterations, 8 obstacle disks, observations keyed on a 0.5 grid.  Inputs
+(model tables and belief particles) are resident in HBM before timing starts.
+
+Prints one JSON line:
+  value        particle-steps/s (generative-model calls per second, whole job)
+  latency_ms   p50 / p99 of the per-plan wall time (host call to result)
+  roofline     achieved algorithmic GB/s of the dominant kernel (HIP events on
+               the plan's stream) against the 8 TB/s HBM peak
+  cpu_baseline the serial CPU oracle timed on a bounded sample of the workload
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit of work, per kernel kind.  Counted once per field
+# the kernel must touch in HBM-resident tree or episode arrays (model tables
+# are cache resident and not counted).  See the kernel table in the design doc.
+#   expand: per particle-step, levels >= 1:
+#     close the previous level: aslot 4 + child slot 4 + N atomic 8 + C atomic 16
+#       + hslot 4 + belief index 4 + reward 4                      = 44
+#     state read + write                                         = 2*state
+#     preference row                                             = 4*|A|
+#     child-table probe 4, hash key 8, hash value 4              = 16
+#     reward, aslot, hslot writes                                = 12
+def expand_bytes_per_step(nA: int, state_bytes: int) -> int:
+    return 44 + 2 * state_bytes + 4 * nA + 16 + 12
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, np.float64), q))
+
+
+def cpu_baseline(inst, bel, p, budget_s=12.0, max_plans=4):
+    """Time the serial oracle on whole plans of the same workload."""
+    from oracle import oracle as orc
+    steps = 0
+    t_total = 0.0
+    plans = 0
+    while plans < max_plans and (t_total < budget_s or plans == 0):
+        t0 = time.perf_counter()
+        r = orc.plan(inst, bel, p["n_particles"], p["budget"], p["depth"],
+                     eta=p["eta"], seed=7 + plans)
+        t_total += time.perf_counter() - t0
+        steps += r.particle_steps
+        plans += 1
+    return {"value": steps / t_total, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{plans} full plan(s) of the same workload "
+                      f"(n_p={p['n_particles']}, K={p['budget']}, depth={p['depth']}), "
+                      f"serial, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nav2d",
+                    choices=["nav2d", "sparse4096", "tabular16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-event-profile", action="store_true",
+                    help="skip the per-kernel event brackets in the timed region")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the "
+                          "planner has no multi-GPU path (see DESIGN.md)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(3)
+    from paper_2510_27191_amd import instances as I
+    from paper_2510_27191_amd import vopp as V
+
+    inst, bel, p = I.workload(args.workload, seed=0)
+    n_p, K, depth, eta = p["n_particles"], p["budget"], p["depth"], p["eta"]
+    pom = V.Pomdp.from_instance(inst)
+    prm = V.params(n_p, eta=eta, seed=1)
+    ws = V.Workspace(pom, prm, K, depth)
+    belt = V.belief_tensor(inst, bel)
+    n_bel = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
+    stream = torch.cuda.current_stream()
+
+    # Warm-up plans; the last ones bracket every kernel kind with events to
+    # find the kind that dominates device time.
+    dom = None
+    for i in range(args.warmup):
+        if not args.no_event_profile and i == args.warmup - 1:
+            V.profile_reset(ws)
+            V.profile_enable(ws, None)
+        V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=100 + i),
+               ws=ws, stream=stream)
+    if not args.no_event_profile and args.warmup > 0:
+        warm = V.profile_read(ws)
+        dom = max((k for k in warm if k != "setup"), key=lambda k: warm[k][0])
+        warm_total = sum(v[0] for v in warm.values())
+        warm_share = {k: v[0] / warm_total for k, v in warm.items() if v[1]}
+
+    # Timed region: only the dominant kind is bracketed (each bracket costs
+    # device time).
+    if dom is not None:
+        V.profile_enable(ws, [])
+        V.profile_reset(ws)
+        V.profile_enable(ws, [dom])
+    torch.cuda.synchronize()
+    lat = []
+    dev_ms = []
+    steps = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        r = V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
+                   ws=ws, stream=stream)
+        lat.append((time.perf_counter() - a) * 1e3)
+        dev_ms.append(r.device_ms)
+        steps += r.particle_steps
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = V.profile_read(ws) if dom is not None else None
+    V.profile_enable(ws, [])
+
+    out = {
+        "metric": "particle-steps/s at fixed budget; p50/p99 plan latency, batched vs plain",
+        "value": steps / elapsed,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded instance generators; no dataset)",
+        "config": {"workload": f"{args.workload}: " + {
+            "nav2d": "continuous 2-D navigation POMDP, 8 obstacle disks, 0.5-grid "
+                     "observation keys, n_p=65536, depth 10, budget 10 iterations",
+            "sparse4096": "sparse tabular POMDP |S|=4096 |A|=8 |O|=32, 8 successors, "
+                          "n_p=262144, depth 8, budget 8 iterations",
+            "tabular16": "tabular POMDP |S|=16 |A|=3 |O|=4, n_p=1024, depth 4, budget 4",
+        }[args.workload], "n_particles": n_p, "budget": K, "depth": depth,
+            "eta": eta, "gamma": inst["gamma"], "schedule": "deepening",
+            "parallelism": "single GPU"},
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "device_p50": percentile(dev_ms, 50)},
+        "particle_steps_per_plan": steps / args.steps,
+    }
+    if prof is not None:
+        kinds = {k: v for k, v in prof.items() if v[1] > 0}
+        out["kernel_share_warmup"] = warm_share
+        roof = {"kernel": dom, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": None}
+        if dom == "expand":
+            sb = 4 if inst["kind"] == "tabular" else 8
+            bps = expand_bytes_per_step(pom.nA, sb)
+            ms, launches = kinds["expand"]
+            achieved = bps * steps / (ms * 1e-3) / 1e9
+            roof.update(achieved=achieved, frac=achieved / HBM_PEAK_GBS,
+                        bytes_per_unit=bps, unit_of_work="particle-step",
+                        avg_launch_us=ms * 1e3 / launches,
+                        bytes_per_launch=bps * steps / launches)
+        else:
+            roof.update(achieved=None, frac=None,
+                        note=f"dominant kernel {dom} has no byte model yet")
+        out["roofline"] = roof
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, bel, p)
+    print(json.dumps(out), flush=True)
+    ws.close()
+    pom.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,35 @@ vopp_status vopp_tree_dump(vopp_workspace* ws, int32_t* b_parent, int32_t* b_obs
                            int32_t* b_N, int32_t* a_parent, int32_t* a_act,
                            double* a_C, int32_t* a_N);
 
+/* ------------------------------------------------------------------------ */
+/* Per-kernel timing (HIP events on the plan's stream).                      */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel kinds of a plan, in the order of vopp_profile_read's arrays. */
+enum {
+  VOPP_KERNEL_EXPAND = 0,       /* draw, G, claims: one launch per level     */
+  VOPP_KERNEL_RESOLVE = 1,      /* first-visitor numbering: one per level    */
+  VOPP_KERNEL_FINISH = 2,       /* deepest level closed, leaves accumulated  */
+  VOPP_KERNEL_BACKUP_LEAF = 3,  /* leaf values (Alg. 3, leaves)              */
+  VOPP_KERNEL_BACKUP_LEVEL = 4, /* one depth of the backup (Alg. 3 loop)     */
+  VOPP_KERNEL_BACKUP_ROOT = 5,  /* root backup in double precision           */
+  VOPP_KERNEL_SETUP = 6,        /* table clearing and root initialisation    */
+  VOPP_KERNEL_SELECT = 7,       /* argmax of the root preferences            */
+  VOPP_KERNEL_KINDS = 8
+};
+
+/* kind_mask != 0: every later vopp_plan in `ws` brackets each launch of the
+ * kernel kinds whose bit (1 << kind) is set with a pair of HIP events on its
+ * stream and adds the elapsed time to per-kind totals (-1 = all kinds).
+ * kind_mask == 0 stops it.  Totals are kept until vopp_profile_reset.  Each
+ * bracket costs a few microseconds of device time, so bracket only the kinds
+ * being measured. */
+vopp_status vopp_profile_enable(vopp_workspace* ws, int32_t kind_mask);
+vopp_status vopp_profile_reset(vopp_workspace* ws);
+/* ms[VOPP_KERNEL_KINDS] (host, out): summed kernel milliseconds per kind;
+ * launches[VOPP_KERNEL_KINDS] (host, out, may be NULL): launch counts. */
+vopp_status vopp_profile_read(const vopp_workspace* ws, double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -261,7 +261,10 @@ static WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int sch
   uint64_t h = 1024;
   while (h < 2 * (uint64_t)z.cap_b) h <<= 1;
   z.hcap = h;
-  z.res_tiles = (n_p + kResTile - 1) / kResTile;
+  // Largest resolve tile count of any plan with n_p or fewer episodes (the
+  // count is not monotone in n_p: it drops when the items per thread grow).
+  z.res_tiles = std::max(res_tiles_for(n_p), std::min((n_p + kBlock - 1) / kBlock,
+                                                      kResTargetTiles));
   return z;
 }
 
@@ -395,6 +398,7 @@ extern "C" void vopp_workspace_free(vopp_workspace* w) {
   if (w->step_host) hipHostFree(w->step_host);
   if (w->ev0) hipEventDestroy(w->ev0);
   if (w->ev1) hipEventDestroy(w->ev1);
+  for (hipEvent_t ev : w->prof_events) hipEventDestroy(ev);
   delete w;
 }
 
@@ -419,7 +423,8 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
   std::memset(&P, 0, sizeof(P));
   P.m = p->view;
   P.t = w->tree;
-  P.t.res_tiles = (prm->n_particles + kResTile - 1) / kResTile;
+  P.t.res_tiles = res_tiles_for(prm->n_particles);
+  P.t.res_items = res_items_for(prm->n_particles);
   P.e = w->ep;
   P.e.belief = belief;
   P.e.n_belief = n_belief;
@@ -468,37 +473,86 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "upload schedule");
   const WsSizes& z = w->z;
-  if (w->hash_dirty) {
-    e = launch_fill32((uint32_t*)w->tree.h_key, z.hcap * 2, 0xFFFFFFFFu, s);
-    if (e == hipSuccess) e = launch_fill32((uint32_t*)w->tree.h_val, z.hcap, 0xFFFFFFFFu, s);
+  w->prof_used = 0;
+  // Each launch below is bracketed by prof_begin/prof_end (no-ops unless
+  // profiling is enabled on the workspace).
+#define VOPP_TIMED(kind, call)                              \
+  do {                                                      \
+    if (e == hipSuccess) e = prof_begin(w, kind, s);        \
+    if (e == hipSuccess) e = (call);                        \
+    if (e == hipSuccess) e = prof_end(w, s);                \
+  } while (0)
+  // Clearing the previous plan's slots one by one costs a line per belief;
+  // a full fill streams 12 bytes per slot.  Take the cheaper one.
+  if (w->hash_dirty || (uint64_t)w->n_prev_beliefs * 10 >= z.hcap) {
+    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.h_key, z.hcap * 2, 0xFFFFFFFFu, s));
+    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.h_val, z.hcap, 0xFFFFFFFFu, s));
   } else {
-    e = launch_clear_slots(P, w->n_prev_beliefs, s);
+    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_clear_slots(P, w->n_prev_beliefs, s));
   }
-  if (e == hipSuccess)
-    e = launch_fill32((uint32_t*)w->tree.lookback, (size_t)steps * P.t.res_tiles * 2, 0u, s);
-  if (e == hipSuccess) e = launch_fill32((uint32_t*)w->tree.tickets, (size_t)steps, 0u, s);
-  if (e == hipSuccess) e = launch_init_root(P, s);
+  VOPP_TIMED(VOPP_KERNEL_SETUP,
+             launch_fill32((uint32_t*)w->tree.lookback, (size_t)steps * P.t.res_tiles * 2, 0u, s));
+  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.tickets, (size_t)steps, 0u, s));
+  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_init_root(P, s));
   if (e != hipSuccess) return hip_fail(e, "plan set-up launch");
   w->hash_dirty = true;   // until the plan's belief count is known
   int t = 0;
   for (int k = 1; k <= K; ++k) {
     for (int d = 0; d < D[k]; ++d) {
-      e = launch_expand(P, k, d, s);
-      if (e == hipSuccess) e = launch_resolve(P, t, s);
+      VOPP_TIMED(VOPP_KERNEL_EXPAND, launch_expand(P, k, d, s));
+      VOPP_TIMED(VOPP_KERNEL_RESOLVE, launch_resolve(P, t, s));
       if (e != hipSuccess) return hip_fail(e, "forward-search launch");
       ++t;
     }
-    e = launch_finish(P, s);
-    if (e == hipSuccess) e = launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k), s);
-    for (int dep = D[k]; dep >= 2 && e == hipSuccess; --dep)
-      e = launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k), s);
-    if (e == hipSuccess) e = launch_backup_root(P, s);
+    VOPP_TIMED(VOPP_KERNEL_FINISH, launch_finish(P, s));
+    VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
+               launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k), s));
+    for (int dep = D[k]; dep >= 2; --dep)
+      VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
+                 launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k), s));
+    VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, s));
     if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
-  e = launch_select(P, t, w->out_dev, s);
+  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, t, w->out_dev, s));
+#undef VOPP_TIMED
   if (e != hipSuccess) return hip_fail(e, "select launch");
   *n_steps_out = t;
   return VOPP_OK;
+}
+
+hipError_t prof_begin(vopp_workspace* w, int kind, hipStream_t s) {
+  w->prof_open = w->prof_on && ((w->prof_mask >> kind) & 1u);
+  if (!w->prof_open) return hipSuccess;
+  while (w->prof_events.size() < w->prof_used + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    w->prof_events.push_back(ev);
+  }
+  if (w->prof_kinds.size() < w->prof_used / 2 + 1) w->prof_kinds.resize(w->prof_used / 2 + 1);
+  w->prof_kinds[w->prof_used / 2] = kind;
+  return hipEventRecord(w->prof_events[w->prof_used], s);
+}
+
+hipError_t prof_end(vopp_workspace* w, hipStream_t s) {
+  if (!w->prof_open) return hipSuccess;
+  w->prof_open = false;
+  hipError_t e = hipEventRecord(w->prof_events[w->prof_used + 1], s);
+  w->prof_used += 2;
+  return e;
+}
+
+void prof_collect(vopp_workspace* w) {
+  if (!w->prof_on) return;
+  for (size_t i = 0; i + 1 < w->prof_used; i += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, w->prof_events[i], w->prof_events[i + 1]) == hipSuccess) {
+      const int kind = w->prof_kinds[i / 2];
+      w->prof_ms[kind] += ms;
+      w->prof_count[kind] += 1;
+    }
+  }
+  w->prof_used = 0;
 }
 
 vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_params* prm,
@@ -550,6 +604,7 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   if (e == hipSuccess) e = hipEventRecord(ws->ev1, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "plan execution");
+  prof_collect(ws);
   const double* o = ws->out_host;
   ws->n_prev_beliefs = (int)o[A + 3];
   ws->hash_dirty = false;
@@ -627,5 +682,31 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
       for (int b = base[t]; b < base[t + 1]; ++b) b_depth[b] = level_of_step[t] + 1;
   }
   if (e != hipSuccess) return hip_fail(e, "tree dump");
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_profile_enable(vopp_workspace* w, int32_t kind_mask) {
+  clear_error();
+  if (!w) return fail(VOPP_E_INVALID, "null workspace");
+  w->prof_on = kind_mask != 0;
+  w->prof_mask = (uint32_t)kind_mask;
+  w->prof_used = 0;
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_profile_reset(vopp_workspace* w) {
+  clear_error();
+  if (!w) return fail(VOPP_E_INVALID, "null workspace");
+  for (int i = 0; i < VOPP_KERNEL_KINDS; ++i) { w->prof_ms[i] = 0.0; w->prof_count[i] = 0; }
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_profile_read(const vopp_workspace* w, double* ms, int64_t* launches) {
+  clear_error();
+  if (!w || !ms) return fail(VOPP_E_INVALID, "null argument");
+  for (int i = 0; i < VOPP_KERNEL_KINDS; ++i) {
+    ms[i] = w->prof_ms[i];
+    if (launches) launches[i] = w->prof_count[i];
+  }
   return VOPP_OK;
 }

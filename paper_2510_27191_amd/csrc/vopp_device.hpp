@@ -12,8 +12,8 @@
 namespace vopp {
 
 constexpr int kBlock = 256;                 // threads per block (4 wavefronts)
-constexpr int kResItems = 8;                // episodes per thread in resolve
-constexpr int kResTile = kBlock * kResItems;
+constexpr int kResItemsMax = 8;             // episodes per thread in resolve (max)
+constexpr int kResTargetTiles = 256;        // resolve tiles per launch (about)
 constexpr int kMaxA = 64;
 constexpr int kMaxBudget = 256;             // iterations per plan
 constexpr int kMaxRanges = kMaxBudget;
@@ -80,7 +80,8 @@ struct TreeView {
   int* tickets;            // [max_steps] dynamic tile counters
   unsigned long long* counters;  // [0] particle steps
   const int* step_base;    // [K+1] first level step of each iteration
-  int res_tiles;
+  int res_tiles;           // resolve tiles of this plan
+  int res_items;           // episodes per thread in resolve (1..kResItemsMax)
 };
 
 // Per-episode arrays, indexed by episode id (length n_p).
@@ -94,6 +95,17 @@ struct EpisodeView {
   const void* belief;      // root belief particles
   int n_belief;
 };
+
+// Resolve tiling: enough episodes per thread that a launch has about
+// kResTargetTiles tiles (short look-back chains), at most kResItemsMax.
+__host__ __device__ inline int res_items_for(int n_p) {
+  int items = (n_p + kBlock * kResTargetTiles - 1) / (kBlock * kResTargetTiles);
+  return items < 1 ? 1 : (items > kResItemsMax ? kResItemsMax : items);
+}
+__host__ __device__ inline int res_tiles_for(int n_p) {
+  const int tile = kBlock * res_items_for(n_p);
+  return (n_p + tile - 1) / tile;
+}
 
 struct PlanView {
   ModelView m;
@@ -147,10 +159,18 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // Count of thresholds <= u among n monotone thresholds = first j with u < thr_j.
+// Rows are read as 16-byte vectors when 16-byte aligned.
 __device__ __forceinline__ int count_le(const uint32_t* __restrict__ thr, int n,
                                         uint32_t u) {
   int c = 0;
-  for (int j = 0; j < n; ++j) c += (thr[j] <= u) ? 1 : 0;
+  int j = 0;
+  if ((((uintptr_t)thr) & 15) == 0) {
+    for (; j + 4 <= n; j += 4) {
+      const uint4 q = *reinterpret_cast<const uint4*>(thr + j);
+      c += (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
+    }
+  }
+  for (; j < n; ++j) c += (thr[j] <= u) ? 1 : 0;
   return c;
 }
 
@@ -161,13 +181,13 @@ __device__ __forceinline__ void tabular_step(const ModelView& m, int s, int a,
   const int row = s * m.nA + a;
   const int lo = m.rowptr[row];
   const int n = m.rowptr[row + 1] - lo;
+  r = m.R[row];
   int j = count_le(m.thrT + lo, n, x.y >> 1);
   j = j < n ? j : n - 1;
   sn = m.col[lo + j];
   const uint32_t* zr = m.thrZ + ((size_t)sn * m.nA + a) * m.nO;
   int o = count_le(zr, m.nO, x.z >> 1);
   obs = o < m.nO ? o : m.nO - 1;
-  r = m.R[row];
 }
 
 __device__ __forceinline__ int nav_axis(const NavParams& p, float v) {

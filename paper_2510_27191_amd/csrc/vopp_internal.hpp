@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/vopp.h"
 #include "vopp_device.hpp"
 
@@ -44,6 +46,15 @@ struct vopp_workspace {
   int last_A = 0, last_apad = 0, last_steps = 0, last_n_p = 0, last_K = 0,
       last_depth = 0, last_schedule = 0;
   double last_fix_inv64 = 0.0;
+  // Per-kernel event timing (vopp_profile_enable).
+  bool prof_on = false;
+  uint32_t prof_mask = 0;                // kinds bracketed with events
+  bool prof_open = false;                // current launch is bracketed
+  std::vector<hipEvent_t> prof_events;   // pool, two per bracketed launch
+  std::vector<int> prof_kinds;           // kind of each bracketed launch
+  size_t prof_used = 0;                  // events used by the current plan
+  double prof_ms[VOPP_KERNEL_KINDS] = {0};
+  int64_t prof_count[VOPP_KERNEL_KINDS] = {0};
 };
 
 namespace vopp {
@@ -60,4 +71,9 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
                    int n_belief, int K, int depth, const vopp_params* prm);
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
                          hipStream_t s, int* n_steps_out);
+// Event brackets around one launch when profiling is on.
+hipError_t prof_begin(vopp_workspace* w, int kind, hipStream_t s);
+hipError_t prof_end(vopp_workspace* w, hipStream_t s);
+// Fold the current plan's event pairs into the totals (after a sync).
+void prof_collect(vopp_workspace* w);
 }  // namespace vopp

@@ -50,29 +50,104 @@ __device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) 
          ((unsigned long long)(uint32_t)a << 24) | (uint32_t)obs;
 }
 
-// Close the previous level for one episode: returns the belief the episode
-// now sits at, or -1 if it stopped (terminal or not running).
-__device__ __forceinline__ int close_level(const PlanView& P, int ep) {
-  const int as = P.e.aslot[ep];
-  if (as < 0) return -1;
-  const int an = P.t.b_child[as];
-  atomicAdd(&P.t.a_N[an], 1);
-  atomicAdd(&P.t.a_C[an], to_fix(P.e.r[ep], P.fix_scale));
-  const int hs = P.e.hslot[ep];
-  if (hs < 0) return -1;
-  const int b = P.t.h_val[hs & kSlotMask];
-  if (hs & kWinBit) P.t.b_parent[b] = an;
+// ---------------------------------------------------------------------------
+// Block-level pre-aggregation.  Shallow tree levels funnel many episodes into
+// few nodes (every episode of an iteration passes through one of the |A| root
+// action nodes), so same-address global atomics would serialise.  Each block
+// first combines its contributions per key in an LDS hash table and then
+// issues one global atomic per distinct key.  Integer adds and min are
+// order-independent, so results stay bit-identical.
+// ---------------------------------------------------------------------------
+constexpr int kAggSlots = 2 * kBlock;      // at most kBlock keys per block
+
+struct AggTable {
+  int key[kAggSlots];
+  unsigned long long a[kAggSlots];
+  unsigned long long b[kAggSlots];
+};
+
+__device__ __forceinline__ void agg_clear(AggTable& T, unsigned long long init) {
+  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    T.key[i] = -1;
+    T.a[i] = init;
+    T.b[i] = 0ull;
+  }
+}
+
+__device__ __forceinline__ int agg_slot(AggTable& T, int key) {
+  uint32_t h = ((uint32_t)key * 2654435761u) >> 23;   // 9 bits
+  while (true) {
+    const int prev = atomicCAS(&T.key[h], -1, key);
+    if (prev == -1 || prev == key) return (int)h;
+    h = (h + 1) & (kAggSlots - 1);
+  }
+}
+
+// Visit count and reward sum of the previous level's action nodes, then the
+// belief the episode now sits at (-1 if it stopped).  Called by every thread
+// of the block (it contains barriers); `ep_ok` marks threads with an episode.
+__device__ __forceinline__ int close_level(const PlanView& P, int ep, bool ep_ok,
+                                           AggTable& T) {
+  int an = -1, b = -1;
+  unsigned long long rf = 0ull;
+  if (ep_ok) {
+    const int as = P.e.aslot[ep];
+    if (as >= 0) {
+      an = P.t.b_child[as];
+      rf = to_fix(P.e.r[ep], P.fix_scale);
+      const int hs = P.e.hslot[ep];
+      if (hs >= 0) {
+        b = P.t.h_val[hs & kSlotMask];
+        if (hs & kWinBit) P.t.b_parent[b] = an;
+      }
+    }
+  }
+  agg_clear(T, 0ull);
+  __syncthreads();
+  if (an >= 0) {
+    const int sl = agg_slot(T, an);
+    atomicAdd(&T.a[sl], 1ull);
+    if (rf) atomicAdd(&T.b[sl], rf);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    const int k = T.key[i];
+    if (k >= 0) {
+      atomicAdd(&P.t.a_N[k], (int)T.a[i]);
+      if (T.b[i]) atomicAdd(&P.t.a_C[k], T.b[i]);
+    }
+  }
+  __syncthreads();
   return b;
+}
+
+// First-visitor claim: table[key] = min(table[key], kClaimBase + ep), with the
+// per-block minimum episode taken in LDS first.
+__device__ __forceinline__ void claim_min(AggTable& T, int* table, int key, int ep) {
+  agg_clear(T, 0x7FFFFFFFull);
+  __syncthreads();
+  if (key >= 0) {
+    const int sl = agg_slot(T, key);
+    atomicMin(&T.a[sl], (unsigned long long)ep);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    const int k = T.key[i];
+    if (k >= 0) atomicMin(&table[k], kClaimBase + (int)T.a[i]);
+  }
+  __syncthreads();
 }
 
 template <int AM>
 __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
+  __shared__ AggTable T;
   const int ep = blockIdx.x * kBlock + threadIdx.x;
+  const bool ep_ok = ep < P.n_p;
   bool alive = false;
   int b = -1, s = 0;
   float x = 0.0f, y = 0.0f;
-  if (ep < P.n_p) {
-    if (d == 0) {
+  if (d == 0) {
+    if (ep_ok) {
       const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
       const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
       if (P.m.kind == kTabular) {
@@ -88,16 +163,18 @@ __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
       }
       b = 0;
       alive = true;
-    } else {
-      b = close_level(P, ep);
-      alive = b >= 0;
-      if (alive) {
-        if (P.m.kind == kTabular) s = P.e.s_i[ep];
-        else { x = P.e.s_x[ep]; y = P.e.s_y[ep]; }
-      }
     }
+  } else {
+    // The state load does not depend on the previous level's tables.
+    if (ep_ok) {
+      if (P.m.kind == kTabular) s = P.e.s_i[ep];
+      else { x = P.e.s_x[ep]; y = P.e.s_y[ep]; }
+    }
+    b = close_level(P, ep, ep_ok, T);
+    alive = b >= 0;
   }
   int as = -1, hs = -1;
+  bool claim_a = false, claim_b = false;
   if (alive) {
     const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
     const int A = P.m.nA;
@@ -122,16 +199,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
     }
     P.e.r[ep] = r;
     as = b * P.m.Apad + a;
-    if (P.t.b_child[as] < 0) atomicMin(&P.t.b_child[as], kClaimBase + ep);
+    claim_a = P.t.b_child[as] < 0;
     if (!term) {
       hs = hash_slot(P.t, belief_key(b, a, obs));
-      if (P.t.h_val[hs] < 0) atomicMin(&P.t.h_val[hs], kClaimBase + ep);
+      claim_b = P.t.h_val[hs] < 0;
     }
   }
-  if (ep < P.n_p) {
+  if (ep_ok) {
     P.e.aslot[ep] = as;
     P.e.hslot[ep] = hs;
   }
+  // First-visitor claims: the smallest episode id per new pair wins.
+  if (__syncthreads_or(claim_a)) claim_min(T, P.t.b_child, claim_a ? as : -1, ep);
+  if (__syncthreads_or(claim_b)) claim_min(T, P.t.h_val, claim_b ? hs : -1, ep);
   // Particle-step count: one generative-model call per running episode.
   const unsigned long long ballot = __ballot(alive);
   if ((threadIdx.x & 63) == 0 && ballot)
@@ -163,17 +243,18 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   if (threadIdx.x == 0) s_tile = atomicAdd(&P.t.tickets[t], 1);
   __syncthreads();
   const int tile = s_tile;
-  const int base_ep = tile * kResTile + threadIdx.x * kResItems;
+  const int items = P.t.res_items;
+  const int base_ep = (tile * kBlock + threadIdx.x) * items;
 
-  int aslot[kResItems], hslot[kResItems];
+  int aslot[kResItemsMax], hslot[kResItemsMax];
   unsigned flags = 0;   // bit i: action creator, bit 16+i: belief creator
   unsigned long long mine = 0;
 #pragma unroll
-  for (int i = 0; i < kResItems; ++i) {
+  for (int i = 0; i < kResItemsMax; ++i) {
     const int ep = base_ep + i;
     aslot[i] = -1;
     hslot[i] = -1;
-    if (ep < P.n_p) {
+    if (i < items && ep < P.n_p) {
       aslot[i] = P.e.aslot[ep];
       hslot[i] = P.e.hslot[ep];
       if (aslot[i] >= 0 && P.t.b_child[aslot[i]] == kClaimBase + ep) {
@@ -199,35 +280,49 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   }
   const unsigned long long local_excl = wave_off + incl - mine;
 
-  // Decoupled look-back across tiles.
-  if (threadIdx.x == 0) {
+  // Decoupled look-back across tiles, one wavefront probing 64 predecessors
+  // at a time.
+  if (wid == 0) {
     unsigned long long* st = P.t.lookback + (size_t)t * P.t.res_tiles;
-    unsigned long long excl = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&st[0], kFlagIncl | block_total, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&st[tile], kFlagAgg | block_total, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int j = tile - 1;
-      while (true) {
-        unsigned long long v;
-        do {
-          v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          if ((v >> 62) == 0) __builtin_amdgcn_s_sleep(1);
-        } while ((v >> 62) == 0);
-        excl += v & kPayload;
-        if ((v >> 62) == 2) break;
-        --j;
-      }
-      __hip_atomic_store(&st[tile], kFlagIncl | (excl + block_total),
+    if (lane == 0)
+      __hip_atomic_store(&st[tile], (tile == 0 ? kFlagIncl : kFlagAgg) | block_total,
                          __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long excl = 0;
+    int hi = tile - 1;
+    while (hi >= 0) {
+      const int j = hi - lane;
+      unsigned long long v = kFlagIncl;          // before tile 0: inclusive 0
+      if (j >= 0) {
+        v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        while ((v >> 62) == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      const unsigned long long incl_mask = __ballot((v >> 62) == 2);
+      unsigned long long part;
+      if (incl_mask) {
+        const int first = __ffsll((long long)incl_mask) - 1;   // nearest inclusive
+        part = lane <= first ? (v & kPayload) : 0ull;
+      } else {
+        part = v & kPayload;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      excl += part;
+      if (incl_mask) break;
+      hi -= 64;
     }
-    s_prefix = excl;
-    if (tile == P.t.res_tiles - 1) {
-      const unsigned long long tot = excl + block_total;
-      P.t.act_base[t + 1] = P.t.act_base[t] + (int)(tot >> 31);
-      P.t.bel_base[t + 1] = P.t.bel_base[t] + (int)(tot & 0x7FFFFFFFull);
+    if (lane == 0) {
+      if (tile > 0)
+        __hip_atomic_store(&st[tile], kFlagIncl | (excl + block_total),
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      s_prefix = excl;
+      if (tile == P.t.res_tiles - 1) {
+        const unsigned long long tot = excl + block_total;
+        P.t.act_base[t + 1] = P.t.act_base[t] + (int)(tot >> 31);
+        P.t.bel_base[t + 1] = P.t.bel_base[t] + (int)(tot & 0x7FFFFFFFull);
+      }
     }
   }
   __syncthreads();
@@ -237,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   int nb = P.t.bel_base[t] + (int)(pre & 0x7FFFFFFFull);
   const int Apad = P.m.Apad, A = P.m.nA;
 #pragma unroll
-  for (int i = 0; i < kResItems; ++i) {
+  for (int i = 0; i < kResItemsMax; ++i) {
     if (flags & (1u << i)) {
       const int as = aslot[i];
       P.t.b_child[as] = na;
@@ -258,11 +353,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
       P.t.b_N[nb] = 0;
       P.t.leaf_cnt[nb] = 0;
       P.t.leaf_h[nb] = 0ull;
-      float* row = P.t.psi + (size_t)nb * Apad;
-      int* crow = P.t.b_child + (size_t)nb * Apad;
-      for (int j = 0; j < Apad; ++j) {
-        row[j] = j < A ? P.psi0 : 0.0f;
-        crow[j] = -1;
+      float4* row = reinterpret_cast<float4*>(P.t.psi + (size_t)nb * Apad);
+      int4* crow = reinterpret_cast<int4*>(P.t.b_child + (size_t)nb * Apad);
+      for (int j = 0; j < Apad; j += 4) {
+        const float p0 = P.psi0;
+        row[j >> 2] = make_float4(j < A ? p0 : 0.0f, j + 1 < A ? p0 : 0.0f,
+                                  j + 2 < A ? p0 : 0.0f, j + 3 < A ? p0 : 0.0f);
+        crow[j >> 2] = make_int4(-1, -1, -1, -1);
       }
       P.e.hslot[base_ep + i] = hs | kWinBit;
       ++nb;
@@ -272,18 +369,35 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
 
 // Close the deepest level and accumulate this iteration's leaves.
 __global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
+  __shared__ AggTable T;
   const int ep = blockIdx.x * kBlock + threadIdx.x;
-  if (ep >= P.n_p) return;
-  const int b = close_level(P, ep);
-  if (b < 0) return;
-  atomicAdd(&P.t.leaf_cnt[b], 1);
-  float h = 0.0f;
-  if (P.m.kind == kTabular) {
-    if (P.m.H) h = P.m.H[P.e.s_i[ep]];
-  } else {
-    h = nav_heuristic(P.m.nav, P.e.s_x[ep], P.e.s_y[ep]);
+  const bool ep_ok = ep < P.n_p;
+  const int b = close_level(P, ep, ep_ok, T);
+  unsigned long long hf = 0ull;
+  if (b >= 0) {
+    float h = 0.0f;
+    if (P.m.kind == kTabular) {
+      if (P.m.H) h = P.m.H[P.e.s_i[ep]];
+    } else {
+      h = nav_heuristic(P.m.nav, P.e.s_x[ep], P.e.s_y[ep]);
+    }
+    hf = to_fix(h, P.fix_scale);
   }
-  if (h != 0.0f) atomicAdd(&P.t.leaf_h[b], to_fix(h, P.fix_scale));
+  agg_clear(T, 0ull);
+  __syncthreads();
+  if (b >= 0) {
+    const int sl = agg_slot(T, b);
+    atomicAdd(&T.a[sl], 1ull);
+    if (hf) atomicAdd(&T.b[sl], hf);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    const int key = T.key[i];
+    if (key >= 0) {
+      atomicAdd(&P.t.leaf_cnt[key], (int)T.a[i]);
+      if (T.b[i]) atomicAdd(&P.t.leaf_h[key], T.b[i]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -331,37 +445,55 @@ __device__ __forceinline__ int range_row(const Ranges& R, int i) {
   return R.lo[lo] + (i - R.off[lo]);
 }
 
-__device__ __forceinline__ void push_value(const PlanView& P, int b, float V, int N) {
-  if (N > 0) {
-    const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
-    if (f) atomicAdd(&P.t.a_W[P.t.b_parent[b]], f);
+// Push V*N_b of belief b (or nothing if b < 0) into its parent action's W
+// accumulator, aggregated per block.  Called by every thread of the block.
+__device__ __forceinline__ void push_values(const PlanView& P, AggTable& T, int b,
+                                            float V, int N) {
+  int par = -1;
+  unsigned long long f = 0ull;
+  if (b >= 0 && N > 0) {
+    f = to_fix(V * (float)N, P.fix_scale);
+    if (f) par = P.t.b_parent[b];
   }
+  agg_clear(T, 0ull);
+  __syncthreads();
+  if (par >= 0) atomicAdd(&T.a[agg_slot(T, par)], f);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
+    const int key = T.key[i];
+    if (key >= 0 && T.a[i]) atomicAdd(&P.t.a_W[key], T.a[i]);
+  }
+  __syncthreads();
 }
 
 // Leaves of this iteration take count and mean heuristic; every belief of
 // depth D pushes V*N_b to its parent action.
 __global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
   __shared__ Ranges R;
+  __shared__ AggTable T;
   load_ranges(P, dep, k, R);
   const int total = R.off[R.n];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-    const int b = range_row(R, i);
-    const int c = P.t.leaf_cnt[b];
-    float V;
-    int N;
-    if (c > 0) {
-      const unsigned long long hs = P.t.leaf_h[b];
-      V = from_fix(hs, P.fix_inv) / (float)c;
-      N = c;
-      P.t.b_V[b] = V;
-      P.t.b_N[b] = N;
-      P.t.leaf_cnt[b] = 0;
-      if (hs) P.t.leaf_h[b] = 0ull;
-    } else {
-      V = P.t.b_V[b];
-      N = P.t.b_N[b];
+  for (int base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {
+    const int i = base + threadIdx.x;
+    int b = -1, N = 0;
+    float V = 0.0f;
+    if (i < total) {
+      b = range_row(R, i);
+      const int c = P.t.leaf_cnt[b];
+      if (c > 0) {
+        const unsigned long long hs = P.t.leaf_h[b];
+        V = from_fix(hs, P.fix_inv) / (float)c;
+        N = c;
+        P.t.b_V[b] = V;
+        P.t.b_N[b] = N;
+        P.t.leaf_cnt[b] = 0;
+        if (hs) P.t.leaf_h[b] = 0ull;
+      } else {
+        V = P.t.b_V[b];
+        N = P.t.b_N[b];
+      }
     }
-    push_value(P, b, V, N);
+    push_values(P, T, b, V, N);
   }
 }
 
@@ -373,8 +505,13 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
   const int total = R.off[R.n];
   const int A = P.m.nA, Apad = P.m.Apad;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-    const int b = range_row(R, i);
+  __shared__ AggTable T;
+  for (int base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {
+    const int i = base + threadIdx.x;
+    int b = -1, N = 0;
+    float V = 0.0f;
+    if (i < total) {
+    b = range_row(R, i);
     const int* crow = P.t.b_child + (size_t)b * Apad;
     float* prow = P.t.psi + (size_t)b * Apad;
     int child[AM];
@@ -387,8 +524,6 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
     }
 #pragma unroll
     for (int j = 0; j < AM; ++j) any = any || (j < A && child[j] >= 0);
-    float V;
-    int N;
     if (any) {
       float psi[AM];
 #pragma unroll
@@ -443,7 +578,8 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
       V = P.t.b_V[b];
       N = P.t.b_N[b];
     }
-    push_value(P, b, V, N);
+    }
+    push_values(P, T, b, V, N);
   }
 }
 

@@ -29,8 +29,12 @@ EXPORTS = (
     "vopp_last_error", "vopp_version", "vopp_pomdp_tabular", "vopp_pomdp_nav2d",
     "vopp_pomdp_num_actions", "vopp_pomdp_free", "vopp_plan_footprint",
     "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
-    "vopp_tree_dump",
+    "vopp_tree_dump", "vopp_profile_enable", "vopp_profile_reset",
+    "vopp_profile_read",
 )
+
+KERNEL_KINDS = ("expand", "resolve", "finish", "backup_leaf", "backup_level",
+                "backup_root", "setup", "select")
 
 
 class VoppError(RuntimeError):
@@ -103,6 +107,12 @@ def lib():
     L.vopp_plan.restype = st
     L.vopp_tree_dump.argtypes = [vp] * 11
     L.vopp_tree_dump.restype = st
+    L.vopp_profile_enable.argtypes = [vp, i32]
+    L.vopp_profile_enable.restype = st
+    L.vopp_profile_reset.argtypes = [vp]
+    L.vopp_profile_reset.restype = st
+    L.vopp_profile_read.argtypes = [vp, vp, vp]
+    L.vopp_profile_read.restype = st
     _lib = L
     return L
 
@@ -245,3 +255,26 @@ def tree_dump(ws, nA, n_beliefs, n_actions):
         "b_parent", "b_obs", "b_depth", "psi", "b_V", "b_N", "a_parent", "a_act",
         "a_C", "a_N")]))
     return out
+
+
+def profile_enable(ws, kinds=None):
+    """Bracket launches of the given kernel kinds (None: all; []: stop)."""
+    if kinds is None:
+        mask = -1
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KERNEL_KINDS.index(k)
+    _check(lib().vopp_profile_enable(ws.handle, mask))
+
+
+def profile_reset(ws):
+    _check(lib().vopp_profile_reset(ws.handle))
+
+
+def profile_read(ws):
+    """{kind: (total_ms, launches)} accumulated by the event profiler."""
+    ms = np.zeros(len(KERNEL_KINDS), np.float64)
+    n = np.zeros(len(KERNEL_KINDS), np.int64)
+    _check(lib().vopp_profile_read(ws.handle, _p(ms), _p(n)))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
