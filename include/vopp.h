@@ -175,6 +175,76 @@ vopp_status vopp_tree_dump(vopp_workspace* ws, int32_t* b_parent, int32_t* b_obs
                            double* a_C, int32_t* a_N);
 
 /* ------------------------------------------------------------------------ */
+/* Batched planning: many independent instances (models of any kind, uneven */
+/* n_p, budget and depth) advanced together.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* One planning request: the arguments of vopp_plan.  belief_particles is a
+ * DEVICE pointer in the layout vopp_plan documents. */
+typedef struct {
+  const vopp_pomdp* pomdp;
+  const void* belief_particles;
+  int32_t n_belief;
+  int32_t budget;
+  int32_t depth;
+  vopp_params params;
+} vopp_request;
+
+#define VOPP_MAX_ACTIONS 64
+
+/* Result of one request.  values[0 .. nA-1] are the root preferences. */
+typedef struct {
+  int32_t action;
+  int32_t status;           /* vopp_status of this request */
+  double v_root;
+  int64_t particle_steps;
+  int64_t n_beliefs;
+  int64_t n_actions;
+  double values[VOPP_MAX_ACTIONS];
+} vopp_result;
+
+/* Launch-shape knobs of a batch.  res_target_tiles: resolve tiles per level
+ * step that a plan aims at (the episodes per thread follow from it, 1..8);
+ * backup_cap: most blocks of one backup sweep of one instance. */
+typedef struct {
+  int32_t res_target_tiles;
+  int32_t backup_cap;
+} vopp_tuning;
+
+typedef struct vopp_batch vopp_batch;
+
+/* Create a batch of n requests: one workspace per request (owned by the
+ * batch), a per-phase schedule in which launch g runs the g-th phase of every
+ * instance that has one (each block of the launch serves one phase of one
+ * instance), and that launch sequence captured in one hipGraph.  All models
+ * must have |A| <= 16.  tuning may be NULL (defaults). */
+vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
+                              const vopp_tuning* tuning, vopp_batch** out);
+/* Bytes of device memory the batch's workspaces need. */
+size_t vopp_batch_footprint(const vopp_request* reqs, int32_t n);
+/* Replace request i's belief particles, seed and real step (same sizes). */
+vopp_status vopp_batch_set_request(vopp_batch* b, int32_t i, const void* belief_particles,
+                                   int32_t n_belief, uint64_t seed, uint32_t step);
+/* Run every request once.  use_graph != 0 replays the captured hipGraph;
+ * 0 issues the same launches one by one.  The batch runs on its own stream,
+ * ordered after the work already queued on `stream`.  results[n] (host, out);
+ * device_ms (host, out, may be NULL): device time of the batch. */
+vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_graph,
+                           vopp_result* results, double* device_ms);
+/* Try launch shapes on this batch (reps timed runs each), keep the fastest,
+ * re-capture the graph, and report it in chosen (may be NULL).  Every tried
+ * shape must give bit-identical results, else VOPP_E_INTERNAL. */
+vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t reps,
+                                vopp_tuning* chosen);
+/* Number of batched launches (phases of the longest instance). */
+int32_t vopp_batch_num_launches(const vopp_batch* b);
+void vopp_batch_free(vopp_batch* b);
+
+/* One-shot form: create, run once, free. */
+vopp_status vopp_plan_batch(const vopp_request* reqs, int32_t n, void* stream,
+                            vopp_result* results);
+
+/* ------------------------------------------------------------------------ */
 /* Per-kernel timing (HIP events on the plan's stream).                      */
 /* ------------------------------------------------------------------------ */
 

@@ -250,7 +250,7 @@ int sum_depths(int K, int depth, int schedule) {
   return (int)s;
 }
 
-static WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) {
+WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) {
   WsSizes z;
   z.n_p = n_p;
   z.steps = sum_depths(K, depth, schedule);
@@ -261,14 +261,13 @@ static WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int sch
   uint64_t h = 1024;
   while (h < 2 * (uint64_t)z.cap_b) h <<= 1;
   z.hcap = h;
-  // Largest resolve tile count of any plan with n_p or fewer episodes (the
-  // count is not monotone in n_p: it drops when the items per thread grow).
-  z.res_tiles = std::max(res_tiles_for(n_p), std::min((n_p + kBlock - 1) / kBlock,
-                                                      kResTargetTiles));
+  // Largest resolve tile count of any plan with n_p or fewer episodes at any
+  // tiling (one episode per thread gives the most tiles).
+  z.res_tiles = (n_p + kBlock - 1) / kBlock;
   return z;
 }
 
-static size_t bytes_for(const WsSizes& z) {
+size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
   auto add = [&](size_t n) { b += align_up(n, 256); };
   const size_t cb = (size_t)z.cap_b, ca = (size_t)z.cap_a;
@@ -285,7 +284,7 @@ static size_t bytes_for(const WsSizes& z) {
   return b + 4096;
 }
 
-static bool fits(const WsSizes& have, const WsSizes& need) {
+bool fits(const WsSizes& have, const WsSizes& need) {
   return have.n_p >= need.n_p && have.cap_b >= need.cap_b && have.steps >= need.steps &&
          have.K >= need.K && have.Apad >= need.Apad && have.res_tiles >= need.res_tiles &&
          have.hcap >= need.hcap;
@@ -342,14 +341,28 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   ev.r = c.take<float>(z.n_p);
   w->out_dev = c.take<double>(256);
   e = hipHostMalloc((void**)&w->out_host, 256 * sizeof(double), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 1) * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 8) * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) {
+    // step_host[kMaxBudget + 1 ..] holds the 64-bit constant 1 (dirty flag).
+    const unsigned long long one = 1ull;
+    std::memcpy(&w->step_host[kMaxBudget + 1], &one, sizeof(one));
+  }
   if (e == hipSuccess) e = hipEventCreate(&w->ev0);
   if (e == hipSuccess) e = hipEventCreate(&w->ev1);
   if (e != hipSuccess) {
     vopp_workspace_free(w);
     return hip_fail(e, "workspace set-up");
   }
-  w->hash_dirty = true;
+  // Counters: [3] = 1 marks the belief table as dirty (fully cleared by the
+  // next plan's set-up).
+  unsigned long long init[8] = {0, 0, 0, 1, 0, 0, 0, 0};
+  e = hipMemcpy(t.counters, init, sizeof(init), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    vopp_workspace_free(w);
+    return hip_fail(e, "workspace counters");
+  }
+  w->hash_dirty = false;
   *out = w;
   return VOPP_OK;
 }
@@ -418,13 +431,14 @@ static int fixed_shift(const vopp_pomdp* p, int n_p, int K) {
 }
 
 PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
-                   int n_belief, int K, int depth, const vopp_params* prm) {
+                   int n_belief, int K, int depth, const vopp_params* prm,
+                   int res_target) {
   PlanView P;
   std::memset(&P, 0, sizeof(P));
   P.m = p->view;
   P.t = w->tree;
-  P.t.res_tiles = res_tiles_for(prm->n_particles);
-  P.t.res_items = res_items_for(prm->n_particles);
+  P.t.res_items = res_items_for(prm->n_particles, res_target);
+  P.t.res_tiles = res_tiles_for(prm->n_particles, res_target);
   P.e = w->ep;
   P.e.belief = belief;
   P.e.n_belief = n_belief;
@@ -443,18 +457,21 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
   P.K = K;
   P.depth = depth;
   P.schedule = prm->schedule;
+  P.steps = sum_depths(K, depth, prm->schedule);
+  P.out = w->out_dev;
   return P;
 }
 
 // Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
-static int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k) {
+int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
+                int cap) {
   int iters = 0;
   for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
   double bound = (double)n_p * iters;
   const double tree = std::pow(p->branch, (double)dep);
   if (tree < bound) bound = tree;
   long long g = (long long)std::ceil(bound / kBlock);
-  return (int)std::max(1ll, std::min(g, 2048ll));
+  return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 
 // Enqueue one planning step on stream s.  Returns the level-step count.
@@ -482,20 +499,14 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     if (e == hipSuccess) e = (call);                        \
     if (e == hipSuccess) e = prof_end(w, s);                \
   } while (0)
-  // Clearing the previous plan's slots one by one costs a line per belief;
-  // a full fill streams 12 bytes per slot.  Take the cheaper one.
-  if (w->hash_dirty || (uint64_t)w->n_prev_beliefs * 10 >= z.hcap) {
-    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.h_key, z.hcap * 2, 0xFFFFFFFFu, s));
-    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.h_val, z.hcap, 0xFFFFFFFFu, s));
-  } else {
-    VOPP_TIMED(VOPP_KERNEL_SETUP, launch_clear_slots(P, w->n_prev_beliefs, s));
+  if (w->hash_dirty) {
+    // A plan did not finish: the table state is unknown, clear it fully.
+    e = hipMemcpyAsync(&w->tree.counters[3], &w->step_host[kMaxBudget + 1],
+                       sizeof(unsigned long long), hipMemcpyHostToDevice, s);
   }
-  VOPP_TIMED(VOPP_KERNEL_SETUP,
-             launch_fill32((uint32_t*)w->tree.lookback, (size_t)steps * P.t.res_tiles * 2, 0u, s));
-  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_fill32((uint32_t*)w->tree.tickets, (size_t)steps, 0u, s));
-  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_init_root(P, s));
+  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_setup(P, s));
   if (e != hipSuccess) return hip_fail(e, "plan set-up launch");
-  w->hash_dirty = true;   // until the plan's belief count is known
+  w->hash_dirty = true;   // until the plan has finished
   int t = 0;
   for (int k = 1; k <= K; ++k) {
     for (int d = 0; d < D[k]; ++d) {
@@ -506,14 +517,14 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     }
     VOPP_TIMED(VOPP_KERNEL_FINISH, launch_finish(P, s));
     VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
-               launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k), s));
+               launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k, kBackupCap), s));
     for (int dep = D[k]; dep >= 2; --dep)
       VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
-                 launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k), s));
+                 launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap), s));
     VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, s));
     if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
-  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, t, w->out_dev, s));
+  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, t, s));
 #undef VOPP_TIMED
   if (e != hipSuccess) return hip_fail(e, "select launch");
   *n_steps_out = t;
@@ -592,14 +603,14 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   }
   if (ws->z.Apad < p->view.Apad) return fail(VOPP_E_INVALID, "workspace built for fewer actions");
   hipStream_t s = (hipStream_t)stream;
-  PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm);
+  PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm, kResTargetTiles);
   hipError_t e = hipEventRecord(ws->ev0, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   int steps = 0;
   st = enqueue_plan(p, ws, P, s, &steps);
   if (st != VOPP_OK) return st;
   const int A = p->nA;
-  e = hipMemcpyAsync(ws->out_host, ws->out_dev, (A + 6) * sizeof(double),
+  e = hipMemcpyAsync(ws->out_host, ws->out_dev, kOutStride * sizeof(double),
                      hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(ws->ev1, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -1,0 +1,393 @@
+// vopp_batch.hip -- batched planning: many independent instances advanced
+// together, one phase per launch, the launch sequence captured in a hipGraph.
+//
+// Each instance's plan is a fixed list of phases (set-up; per iteration the
+// expand/resolve pair of every level, finish, the leaf sweep, one sweep per
+// depth, the root; finally select).  Launch g of the batch runs the g-th
+// phase of every instance that still has one: the launch's blocks are split
+// into BatchItems, each block serving one phase of one instance.  Instances
+// share no state, so each result is the same as that of a plain vopp_plan
+// call with the same inputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/vopp.h"
+#include "vopp_device.hpp"
+#include "vopp_internal.hpp"
+#include "vopp_launch.hpp"
+
+using namespace vopp;
+
+struct vopp_batch {
+  int n = 0;
+  int device = 0;
+  std::vector<vopp_request> reqs;
+  std::vector<vopp_workspace*> ws;
+  std::vector<PlanView> views;
+  PlanView* views_dev = nullptr;
+  std::vector<BatchItem> items;          // all launches, concatenated
+  std::vector<int> launch_off, launch_items, launch_blocks;
+  BatchItem* items_dev = nullptr;
+  double* out_dev = nullptr;
+  double* out_host = nullptr;            // pinned
+  int amax = 4;
+  vopp_tuning tuning{kResTargetTiles, kBackupCap};
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Phase list of one plan, in execution order.
+struct Phase {
+  int kind, a0, a1, nblk;
+};
+
+std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, const vopp_tuning& tu) {
+  std::vector<Phase> ph;
+  const int K = P.K;
+  std::vector<int> D(K + 1, 0);
+  for (int k = 1; k <= K; ++k)
+    D[k] = P.schedule == VOPP_SCHEDULE_FIXED ? P.depth : std::min(k, P.depth);
+  const int eblocks = (P.n_p + kBlock - 1) / kBlock;
+  ph.push_back({kPhaseSetup, 0, 0, setup_blocks(P)});
+  int t = 0;
+  for (int k = 1; k <= K; ++k) {
+    for (int d = 0; d < D[k]; ++d) {
+      ph.push_back({kPhaseExpand, k, d, eblocks});
+      ph.push_back({kPhaseResolve, t, 0, P.t.res_tiles});
+      ++t;
+    }
+    ph.push_back({kPhaseFinish, 0, 0, eblocks});
+    ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D, D[k], k, tu.backup_cap)});
+    for (int dep = D[k]; dep >= 2; --dep)
+      ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, tu.backup_cap)});
+    ph.push_back({kPhaseRoot, 0, 0, 1});
+  }
+  ph.push_back({kPhaseSelect, t, 0, 1});
+  return ph;
+}
+
+void release_graph(vopp_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Build views and the launch schedule for the current tuning; upload them.
+vopp_status build_schedule(vopp_batch* b) {
+  const int n = b->n;
+  b->views.assign(n, PlanView{});
+  std::vector<std::vector<Phase>> phases(n);
+  size_t longest = 0;
+  for (int i = 0; i < n; ++i) {
+    const vopp_request& r = b->reqs[i];
+    PlanView P = make_view(r.pomdp, b->ws[i], r.belief_particles, r.n_belief, r.budget,
+                           r.depth, &r.params, b->tuning.res_target_tiles);
+    P.out = b->out_dev + (size_t)i * kOutStride;
+    b->views[i] = P;
+    phases[i] = plan_phases(r.pomdp, P, b->tuning);
+    longest = std::max(longest, phases[i].size());
+  }
+  b->items.clear();
+  b->launch_off.clear();
+  b->launch_items.clear();
+  b->launch_blocks.clear();
+  for (size_t g = 0; g < longest; ++g) {
+    int blocks = 0, cnt = 0;
+    b->launch_off.push_back((int)b->items.size());
+    for (int i = 0; i < n; ++i) {
+      if (g >= phases[i].size()) continue;
+      const Phase& f = phases[i][g];
+      BatchItem it;
+      it.inst = i;
+      it.kind = f.kind;
+      it.a0 = f.a0;
+      it.a1 = f.a1;
+      it.blk0 = blocks;
+      it.nblk = f.nblk;
+      blocks += f.nblk;
+      b->items.push_back(it);
+      ++cnt;
+    }
+    b->launch_items.push_back(cnt);
+    b->launch_blocks.push_back(blocks);
+  }
+  hipError_t e = hipSuccess;
+  if (b->items_dev) hipFree(b->items_dev);
+  b->items_dev = nullptr;
+  e = hipMalloc(&b->items_dev, b->items.size() * sizeof(BatchItem));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->items_dev, b->items.data(), b->items.size() * sizeof(BatchItem),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->views_dev, b->views.data(), n * sizeof(PlanView), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch schedule upload");
+  return VOPP_OK;
+}
+
+hipError_t enqueue_launches(vopp_batch* b, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (size_t g = 0; g < b->launch_items.size() && e == hipSuccess; ++g)
+    e = launch_batch(b->views_dev, b->items_dev + b->launch_off[g], b->launch_items[g],
+                     b->launch_blocks[g], b->amax, s);
+  return e;
+}
+
+vopp_status capture(vopp_batch* b) {
+  release_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t e2 = enqueue_launches(b, b->stream);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (e2 != hipSuccess) return hip_fail(e2, "batched launch during capture");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return VOPP_OK;
+}
+
+void parse_results(const vopp_batch* b, vopp_result* res) {
+  for (int i = 0; i < b->n; ++i) {
+    const double* o = b->out_host + (size_t)i * kOutStride;
+    const int A = b->reqs[i].pomdp->nA;
+    vopp_result& r = res[i];
+    std::memset(&r, 0, sizeof(r));
+    r.action = (int32_t)o[0];
+    for (int j = 0; j < A; ++j) r.values[j] = o[1 + j];
+    r.v_root = o[A + 1];
+    r.particle_steps = (int64_t)o[A + 2];
+    r.n_beliefs = (int64_t)o[A + 3];
+    r.n_actions = (int64_t)o[A + 4];
+    r.status = o[A + 5] != 0.0 ? VOPP_E_INVALID : VOPP_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" size_t vopp_batch_footprint(const vopp_request* reqs, int32_t n) {
+  if (!reqs || n < 1) return 0;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const size_t f = vopp_plan_footprint(reqs[i].pomdp, &reqs[i].params, reqs[i].budget,
+                                         reqs[i].depth);
+    if (f == 0) return 0;
+    total += f;
+  }
+  return total;
+}
+
+extern "C" void vopp_batch_free(vopp_batch* b) {
+  if (!b) return;
+  release_graph(b);
+  for (vopp_workspace* w : b->ws) vopp_workspace_free(w);
+  if (b->views_dev) hipFree(b->views_dev);
+  if (b->items_dev) hipFree(b->items_dev);
+  if (b->out_dev) hipFree(b->out_dev);
+  if (b->out_host) hipHostFree(b->out_host);
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+}
+
+extern "C" vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
+                                         const vopp_tuning* tuning, vopp_batch** out) {
+  clear_error();
+  if (!out) return fail(VOPP_E_INVALID, "null out");
+  *out = nullptr;
+  if (!reqs || n < 1) return fail(VOPP_E_INVALID, "empty batch");
+  int dev = 0;
+  hipGetDevice(&dev);
+  int amax = 4;
+  for (int i = 0; i < n; ++i) {
+    const vopp_request& r = reqs[i];
+    vopp_status st = check_params(r.pomdp, &r.params, r.budget, r.depth);
+    if (st != VOPP_OK) return fail(st, "request %d: %s", i, vopp_last_error());
+    if (!r.belief_particles || r.n_belief < 1)
+      return fail(VOPP_E_INVALID, "request %d: empty belief", i);
+    if (r.pomdp->device != dev)
+      return fail(VOPP_E_INVALID, "request %d: model lives on another device", i);
+    if (r.pomdp->view.Apad > 16)
+      return fail(VOPP_E_INVALID, "request %d: batched plans support |A| <= 16", i);
+    amax = std::max(amax, r.pomdp->view.Apad);
+  }
+  if (tuning && (tuning->res_target_tiles < 1 || tuning->backup_cap < 1))
+    return fail(VOPP_E_INVALID, "bad tuning");
+  vopp_batch* b = new vopp_batch();
+  b->n = n;
+  b->device = dev;
+  b->amax = amax;
+  b->reqs.assign(reqs, reqs + n);
+  if (tuning) b->tuning = *tuning;
+  b->ws.assign(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    vopp_status st = vopp_workspace_create(reqs[i].pomdp, &reqs[i].params, reqs[i].budget,
+                                           reqs[i].depth, &b->ws[i]);
+    if (st != VOPP_OK) {
+      vopp_batch_free(b);
+      return st;
+    }
+    // Upload the instance's iteration schedule once.
+    int* sb = b->ws[i]->step_host;
+    sb[0] = 0;
+    for (int k = 1; k <= reqs[i].budget; ++k)
+      sb[k] = sb[k - 1] + (reqs[i].params.schedule == VOPP_SCHEDULE_FIXED
+                               ? reqs[i].depth
+                               : std::min(k, reqs[i].depth));
+    hipError_t e = hipMemcpy(b->ws[i]->step_base_dev, sb, (reqs[i].budget + 1) * sizeof(int),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      vopp_batch_free(b);
+      return hip_fail(e, "batch schedule");
+    }
+  }
+  hipError_t e = hipMalloc(&b->views_dev, n * sizeof(PlanView));
+  if (e == hipSuccess) e = hipMalloc(&b->out_dev, (size_t)n * kOutStride * sizeof(double));
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->out_host, (size_t)n * kOutStride * sizeof(double),
+                      hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreate(&b->stream);   // default priority
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev_in);
+  if (e != hipSuccess) {
+    vopp_batch_free(b);
+    return hip_fail(e, "batch set-up");
+  }
+  vopp_status st = build_schedule(b);
+  if (st == VOPP_OK) st = capture(b);
+  if (st != VOPP_OK) {
+    vopp_batch_free(b);
+    return st;
+  }
+  *out = b;
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_batch_set_request(vopp_batch* b, int32_t i, const void* belief,
+                                              int32_t n_belief, uint64_t seed, uint32_t step) {
+  clear_error();
+  if (!b || i < 0 || i >= b->n) return fail(VOPP_E_INVALID, "bad batch index");
+  if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
+  vopp_request& r = b->reqs[i];
+  r.belief_particles = belief;
+  r.n_belief = n_belief;
+  r.params.seed = seed;
+  r.params.step = step;
+  PlanView& P = b->views[i];
+  P.e.belief = belief;
+  P.e.n_belief = n_belief;
+  P.seed_lo = (uint32_t)seed;
+  P.seed_hi = (uint32_t)(seed >> 32);
+  P.step = step;
+  hipError_t e = hipMemcpy(b->views_dev + i, &P, sizeof(PlanView), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch request update");
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_graph,
+                                      vopp_result* results, double* device_ms) {
+  clear_error();
+  if (!b || !results) return fail(VOPP_E_INVALID, "null argument");
+  hipError_t e = hipEventRecord(b->ev_in, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+  if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
+  if (e == hipSuccess) {
+    if (use_graph && b->exec) e = hipGraphLaunch(b->exec, b->stream);
+    else e = enqueue_launches(b, b->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->out_host, b->out_dev, (size_t)b->n * kOutStride * sizeof(double),
+                       hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    // The tables of every instance are in an unknown state now.
+    const unsigned long long one = 1ull;
+    for (vopp_workspace* w : b->ws) hipMemcpy(&w->tree.counters[3], &one, 8, hipMemcpyHostToDevice);
+    return hip_fail(e, "batch execution");
+  }
+  if (device_ms) {
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, b->ev0, b->ev1);
+    *device_ms = ms;
+  }
+  parse_results(b, results);
+  for (int i = 0; i < b->n; ++i)
+    if (results[i].status != VOPP_OK)
+      return fail(VOPP_E_INVALID, "request %d: a belief particle holds a state outside [0, nS)", i);
+  return VOPP_OK;
+}
+
+extern "C" int32_t vopp_batch_num_launches(const vopp_batch* b) {
+  return b ? (int32_t)b->launch_items.size() : 0;
+}
+
+extern "C" vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t reps,
+                                           vopp_tuning* chosen) {
+  clear_error();
+  if (!b) return fail(VOPP_E_INVALID, "null batch");
+  if (reps < 1) reps = 1;
+  const int res_cands[] = {64, 256, 1024};
+  const int cap_cands[] = {256, 1024, 4096};
+  std::vector<vopp_result> ref(b->n), cur(b->n);
+  bool have_ref = false;
+  double best_ms = 1e30;
+  vopp_tuning best = b->tuning;
+  for (int rc : res_cands) {
+    for (int cc : cap_cands) {
+      b->tuning.res_target_tiles = rc;
+      b->tuning.backup_cap = cc;
+      vopp_status st = build_schedule(b);
+      if (st == VOPP_OK) st = capture(b);
+      if (st != VOPP_OK) return st;
+      double ms_min = 1e30;
+      for (int r = 0; r < reps + 1; ++r) {
+        double ms = 0.0;
+        st = vopp_batch_run(b, stream, 1, cur.data(), &ms);
+        if (st != VOPP_OK) return st;
+        if (r > 0) ms_min = std::min(ms_min, ms);      // the first run warms up
+      }
+      // The launch shape must not change any result.
+      if (!have_ref) {
+        ref = cur;
+        have_ref = true;
+      } else {
+        for (int i = 0; i < b->n; ++i)
+          if (std::memcmp(&ref[i], &cur[i], sizeof(vopp_result)) != 0)
+            return fail(VOPP_E_INTERNAL, "tuning (%d, %d) changed the result of request %d",
+                        rc, cc, i);
+      }
+      if (ms_min < best_ms) {
+        best_ms = ms_min;
+        best = b->tuning;
+      }
+    }
+  }
+  b->tuning = best;
+  vopp_status st = build_schedule(b);
+  if (st == VOPP_OK) st = capture(b);
+  if (st != VOPP_OK) return st;
+  if (chosen) *chosen = best;
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_plan_batch(const vopp_request* reqs, int32_t n, void* stream,
+                                       vopp_result* results) {
+  vopp_batch* b = nullptr;
+  vopp_status st = vopp_batch_create(reqs, n, nullptr, &b);
+  if (st != VOPP_OK) return st;
+  st = vopp_batch_run(b, stream, 1, results, nullptr);
+  vopp_batch_free(b);
+  return st;
+}

@@ -78,7 +78,8 @@ struct TreeView {
   int* act_base;           // [max_steps+1] action nodes before each step
   unsigned long long* lookback;  // [max_steps * res_tiles] scan state
   int* tickets;            // [max_steps] dynamic tile counters
-  unsigned long long* counters;  // [0] particle steps
+  unsigned long long* counters;  // [0] particle steps [1] input errors
+                                 // [2] beliefs of the last plan [3] table dirty
   const int* step_base;    // [K+1] first level step of each iteration
   int res_tiles;           // resolve tiles of this plan
   int res_items;           // episodes per thread in resolve (1..kResItemsMax)
@@ -98,14 +99,17 @@ struct EpisodeView {
 
 // Resolve tiling: enough episodes per thread that a launch has about
 // kResTargetTiles tiles (short look-back chains), at most kResItemsMax.
-__host__ __device__ inline int res_items_for(int n_p) {
-  int items = (n_p + kBlock * kResTargetTiles - 1) / (kBlock * kResTargetTiles);
+__host__ __device__ inline int res_items_for(int n_p, int target_tiles) {
+  const long long per = (long long)kBlock * target_tiles;
+  int items = (int)((n_p + per - 1) / per);
   return items < 1 ? 1 : (items > kResItemsMax ? kResItemsMax : items);
 }
-__host__ __device__ inline int res_tiles_for(int n_p) {
-  const int tile = kBlock * res_items_for(n_p);
+__host__ __device__ inline int res_tiles_for(int n_p, int target_tiles) {
+  const int tile = kBlock * res_items_for(n_p, target_tiles);
   return (n_p + tile - 1) / tile;
 }
+
+constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
 
 struct PlanView {
   ModelView m;
@@ -121,6 +125,25 @@ struct PlanView {
   float psi0;              // -ln|A| / eta
   double psi0_64;
   int K, depth, schedule;
+  int steps;               // level steps of the plan (sum of D_k)
+  double* out;             // kOutStride doubles: the plan's result
+};
+
+// Result record written by the select phase (doubles): [0] action,
+// [1..A] root preferences, [A+1] V(root), [A+2] particle steps, [A+3] beliefs,
+// [A+4] action nodes, [A+5] input-error flags.
+constexpr int kOutStride = kMaxA + 8;
+
+// Phase kinds (same numbering as the ABI's VOPP_KERNEL_* kinds).
+enum : int {
+  kPhaseExpand = 0, kPhaseResolve = 1, kPhaseFinish = 2, kPhaseLeaf = 3,
+  kPhaseLevel = 4, kPhaseRoot = 5, kPhaseSetup = 6, kPhaseSelect = 7
+};
+
+// One phase of one instance inside a batched launch: blocks
+// [blk0, blk0 + nblk) of the launch run phase `kind` of instance `inst`.
+struct BatchItem {
+  int inst, kind, a0, a1, blk0, nblk;
 };
 
 // ---------------------------------------------------------------------------

@@ -68,7 +68,13 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out);
 vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_params* prm,
                       int K, int depth);
 PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
-                   int n_belief, int K, int depth, const vopp_params* prm);
+                   int n_belief, int K, int depth, const vopp_params* prm,
+                   int res_target);
+int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
+                int cap);
+WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule);
+bool fits(const WsSizes& have, const WsSizes& need);
+size_t bytes_for(const WsSizes& z);
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
                          hipStream_t s, int* n_steps_out);
 // Event brackets around one launch when profiling is on.

@@ -1,6 +1,6 @@
 // vopp_kernels.hip -- HIP kernels of one VOPP planning step for gfx950.
 //
-// One level of the vectorized forward search (Alg. 2) is two launches:
+// One level of the vectorized forward search (Alg. 2) is two phases:
 //
 //   expand   one thread per episode: close the previous level (visit count and
 //            reward sum of the action node, parent of a new belief), draw the
@@ -16,13 +16,21 @@
 //
 // After the deepest level, `finish` closes it and accumulates this
 // iteration's leaf visits and heuristic sums.  The backup of Alg. 3 is one
-// launch per depth over every belief of that depth in the tree: leaves take
+// phase per depth over every belief of that depth in the tree: leaves take
 // their mean heuristic, internal beliefs update their preference row with
 // Q = C/N + gamma W and V = L_eta Psi, and each belief pushes V*N_b into its
 // parent action's W accumulator.  The root level runs in double precision.
 //
 // All cross-episode sums (rewards, heuristics, V*N_b) are 64-bit fixed-point
 // integer atomics, so the results do not depend on thread order.
+//
+// Every phase is a __device__ function of (plan view, block index within the
+// phase, block count of the phase).  The single-plan path launches one kernel
+// per phase; the batched path launches k_batch, whose blocks each run one
+// phase of one instance of a batch (BatchItem), so one launch advances every
+// instance of the batch by one phase.
+#include <algorithm>
+
 #include "vopp_device.hpp"
 #include "vopp_launch.hpp"
 
@@ -51,19 +59,37 @@ __device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) 
 }
 
 // ---------------------------------------------------------------------------
+// Shared memory of every phase (one static allocation per kernel).
+// ---------------------------------------------------------------------------
+
 // Block-level pre-aggregation.  Shallow tree levels funnel many episodes into
 // few nodes (every episode of an iteration passes through one of the |A| root
 // action nodes), so same-address global atomics would serialise.  Each block
 // first combines its contributions per key in an LDS hash table and then
 // issues one global atomic per distinct key.  Integer adds and min are
 // order-independent, so results stay bit-identical.
-// ---------------------------------------------------------------------------
 constexpr int kAggSlots = 2 * kBlock;      // at most kBlock keys per block
 
 struct AggTable {
   int key[kAggSlots];
   unsigned long long a[kAggSlots];
   unsigned long long b[kAggSlots];
+};
+
+// Row ranges of the beliefs of one depth: level step t of every iteration
+// that reached that depth created one contiguous range.
+struct Ranges {
+  int n;
+  int lo[kMaxRanges];
+  int off[kMaxRanges + 1];
+};
+
+struct Smem {
+  AggTable agg;
+  Ranges ranges;
+  int tile;
+  unsigned long long wave[kBlock / 64];
+  unsigned long long prefix;
 };
 
 __device__ __forceinline__ void agg_clear(AggTable& T, unsigned long long init) {
@@ -138,16 +164,75 @@ __device__ __forceinline__ void claim_min(AggTable& T, int* table, int key, int 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Phase: set-up of a plan.  Clears the belief table (a full fill, or only the
+// slots the previous plan used when that is cheaper), the scan state and the
+// root row.  The previous plan's belief count is read on the device, so the
+// phase is identical on every replay of a captured launch sequence.
+// ---------------------------------------------------------------------------
+__device__ void dev_setup(const PlanView& P, int blk, int nblk) {
+  const unsigned long long n_prev = P.t.counters[2];
+  const bool full = P.t.counters[3] != 0ull ||
+                    n_prev * 10ull >= (unsigned long long)P.t.h_mask + 1ull;
+  const size_t tid = (size_t)blk * kBlock + threadIdx.x;
+  const size_t stride = (size_t)nblk * kBlock;
+  const size_t hcap = (size_t)P.t.h_mask + 1;
+  if (full) {
+    uint4* hk = reinterpret_cast<uint4*>(P.t.h_key);
+    uint4* hv = reinterpret_cast<uint4*>(P.t.h_val);
+    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (size_t i = tid; i < hcap / 2; i += stride) hk[i] = ones;
+    for (size_t i = tid; i < hcap / 4; i += stride) hv[i] = ones;
+  } else {
+    for (size_t b = 1 + tid; b < n_prev; b += stride) {
+      const int hs = P.t.b_hslot[b];
+      P.t.h_key[hs] = kEmptyKey;
+      P.t.h_val[hs] = -1;
+    }
+  }
+  const size_t nlb = (size_t)P.steps * P.t.res_tiles;
+  for (size_t i = tid; i < nlb; i += stride) P.t.lookback[i] = 0ull;
+  for (size_t i = tid; i < (size_t)P.steps; i += stride) P.t.tickets[i] = 0;
+  if (blk == 0) {
+    const int j = threadIdx.x;
+    const int A = P.m.nA, Apad = P.m.Apad;
+    if (j < Apad) {
+      P.t.b_child[j] = -1;
+      P.t.psi[j] = j < A ? P.psi0 : 0.0f;
+      if (j < A) P.t.psi_root[j] = P.psi0_64;
+    }
+    if (j == 0) {
+      P.t.b_parent[0] = -1;
+      P.t.b_obs[0] = -1;
+      P.t.b_V[0] = 0.0f;
+      P.t.b_N[0] = 0;
+      P.t.leaf_cnt[0] = 0;
+      P.t.leaf_h[0] = 0ull;
+      P.t.b_hslot[0] = 0;
+      P.t.v_root[0] = 0.0;
+      P.t.bel_base[0] = 1;
+      P.t.act_base[0] = 0;
+      P.t.counters[0] = 0ull;
+      P.t.counters[1] = 0ull;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase: expand one level (Alg. 2, one recursion step).
+// ---------------------------------------------------------------------------
 template <int AM>
-__global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
-  __shared__ AggTable T;
-  const int ep = blockIdx.x * kBlock + threadIdx.x;
+__device__ void dev_expand(const PlanView& P, int k, int d, int blk, Smem& sm) {
+  AggTable& T = sm.agg;
+  const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
   bool alive = false;
   int b = -1, s = 0;
   float x = 0.0f, y = 0.0f;
   if (d == 0) {
     if (ep_ok) {
+      // Alg. 1: the episode starts at the root with a state drawn from the
+      // belief particles.
       const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
       const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
       if (P.m.kind == kTabular) {
@@ -200,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
     P.e.r[ep] = r;
     as = b * P.m.Apad + a;
     claim_a = P.t.b_child[as] < 0;
-    if (!term) {
+    if (!term) {                              // FilterTerminals
       hs = hash_slot(P.t, belief_key(b, a, obs));
       claim_b = P.t.h_val[hs] < 0;
     }
@@ -209,7 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
     P.e.aslot[ep] = as;
     P.e.hslot[ep] = hs;
   }
-  // First-visitor claims: the smallest episode id per new pair wins.
+  // AppendActions / AppendBeliefs claims: the smallest episode id per new
+  // pair wins.
   if (__syncthreads_or(claim_a)) claim_min(T, P.t.b_child, claim_a ? as : -1, ep);
   if (__syncthreads_or(claim_b)) claim_min(T, P.t.h_val, claim_b ? hs : -1, ep);
   // Particle-step count: one generative-model call per running episode.
@@ -219,8 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of two packed counters.
-// Packed word: (count_a << 31) | count_b, both < 2^31.
+// Phase: resolve the claims of level step t (first-visitor numbering).
+// Packed scan word: (count_a << 31) | count_b, both < 2^31.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
   const int lane = threadIdx.x & 63;
@@ -236,13 +322,10 @@ constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagIncl = 2ull << 62;
 constexpr unsigned long long kPayload = (1ull << 62) - 1;
 
-__global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
-  __shared__ int s_tile;
-  __shared__ unsigned long long s_wave[kBlock / 64];
-  __shared__ unsigned long long s_prefix;
-  if (threadIdx.x == 0) s_tile = atomicAdd(&P.t.tickets[t], 1);
+__device__ void dev_resolve(const PlanView& P, int t, Smem& sm) {
+  if (threadIdx.x == 0) sm.tile = atomicAdd(&P.t.tickets[t], 1);
   __syncthreads();
-  const int tile = s_tile;
+  const int tile = sm.tile;
   const int items = P.t.res_items;
   const int base_ep = (tile * kBlock + threadIdx.x) * items;
 
@@ -270,13 +353,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   // Block scan.
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const unsigned long long incl = wave_incl_scan(mine);
-  if (lane == 63) s_wave[wid] = incl;
+  if (lane == 63) sm.wave[wid] = incl;
   __syncthreads();
   unsigned long long wave_off = 0, block_total = 0;
 #pragma unroll
   for (int i = 0; i < kBlock / 64; ++i) {
-    if (i < wid) wave_off += s_wave[i];
-    block_total += s_wave[i];
+    if (i < wid) wave_off += sm.wave[i];
+    block_total += sm.wave[i];
   }
   const unsigned long long local_excl = wave_off + incl - mine;
 
@@ -317,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
       if (tile > 0)
         __hip_atomic_store(&st[tile], kFlagIncl | (excl + block_total),
                            __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      s_prefix = excl;
+      sm.prefix = excl;
       if (tile == P.t.res_tiles - 1) {
         const unsigned long long tot = excl + block_total;
         P.t.act_base[t + 1] = P.t.act_base[t] + (int)(tot >> 31);
@@ -327,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   }
   __syncthreads();
   if (!flags) return;
-  const unsigned long long pre = s_prefix + local_excl;
+  const unsigned long long pre = sm.prefix + local_excl;
   int na = P.t.act_base[t] + (int)(pre >> 31);
   int nb = P.t.bel_base[t] + (int)(pre & 0x7FFFFFFFull);
   const int Apad = P.m.Apad, A = P.m.nA;
@@ -367,15 +450,17 @@ __global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
   }
 }
 
-// Close the deepest level and accumulate this iteration's leaves.
-__global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
-  __shared__ AggTable T;
-  const int ep = blockIdx.x * kBlock + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Phase: close the deepest level and accumulate this iteration's leaves.
+// ---------------------------------------------------------------------------
+__device__ void dev_finish(const PlanView& P, int blk, Smem& sm) {
+  AggTable& T = sm.agg;
+  const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
   const int b = close_level(P, ep, ep_ok, T);
   unsigned long long hf = 0ull;
   if (b >= 0) {
-    float h = 0.0f;
+    float h = 0.0f;                           // ValueHeuristic
     if (P.m.kind == kTabular) {
       if (P.m.H) h = P.m.H[P.e.s_i[ep]];
     } else {
@@ -401,17 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
 }
 
 // ---------------------------------------------------------------------------
-// Backup.  Beliefs of depth `dep` were created by level dep-1 of every
-// iteration k' <= k whose depth D_k' >= dep; each such level step is one
-// contiguous row range.
+// Backup (Alg. 3).  Beliefs of depth `dep` were created by level dep-1 of
+// every iteration k' <= k whose depth D_k' >= dep.
 // ---------------------------------------------------------------------------
-struct Ranges {
-  int n;
-  int lo[kMaxRanges];
-  int len[kMaxRanges];
-  int off[kMaxRanges + 1];
-};
-
 __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
                                             Ranges& R) {
   if (threadIdx.x == 0) {
@@ -424,7 +501,6 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
         const int lo = P.t.bel_base[t];
         const int len = P.t.bel_base[t + 1] - lo;
         R.lo[n] = lo;
-        R.len[n] = len;
         R.off[n] = off;
         off += len;
         ++n;
@@ -468,12 +544,12 @@ __device__ __forceinline__ void push_values(const PlanView& P, AggTable& T, int 
 
 // Leaves of this iteration take count and mean heuristic; every belief of
 // depth D pushes V*N_b to its parent action.
-__global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
-  __shared__ Ranges R;
-  __shared__ AggTable T;
+__device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int nblk,
+                                Smem& sm) {
+  Ranges& R = sm.ranges;
   load_ranges(P, dep, k, R);
   const int total = R.off[R.n];
-  for (int base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {
+  for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
     const int i = base + threadIdx.x;
     int b = -1, N = 0;
     float V = 0.0f;
@@ -493,102 +569,104 @@ __global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int
         N = P.t.b_N[b];
       }
     }
-    push_values(P, T, b, V, N);
+    push_values(P, sm.agg, b, V, N);
   }
 }
 
 // Internal beliefs of depth dep-1 >= 1.  AM >= |A| keeps the row in registers.
 template <int AM>
-__global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, int k) {
-  __shared__ Ranges R;
+__device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int nblk,
+                                 Smem& sm) {
+  Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
   const int total = R.off[R.n];
   const int A = P.m.nA, Apad = P.m.Apad;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
-  __shared__ AggTable T;
-  for (int base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {
+  for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
     const int i = base + threadIdx.x;
     int b = -1, N = 0;
     float V = 0.0f;
     if (i < total) {
-    b = range_row(R, i);
-    const int* crow = P.t.b_child + (size_t)b * Apad;
-    float* prow = P.t.psi + (size_t)b * Apad;
-    int child[AM];
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < AM; j += 4) {
-      int4 c = make_int4(-1, -1, -1, -1);
-      if (j < A) c = *reinterpret_cast<const int4*>(crow + j);
-      child[j] = c.x; child[j + 1] = c.y; child[j + 2] = c.z; child[j + 3] = c.w;
-    }
-#pragma unroll
-    for (int j = 0; j < AM; ++j) any = any || (j < A && child[j] >= 0);
-    if (any) {
-      float psi[AM];
+      b = range_row(R, i);
+      const int* crow = P.t.b_child + (size_t)b * Apad;
+      float* prow = P.t.psi + (size_t)b * Apad;
+      int child[AM];
+      bool any = false;
 #pragma unroll
       for (int j = 0; j < AM; j += 4) {
-        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (j < A) q = *reinterpret_cast<const float4*>(prow + j);
-        psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
+        int4 c = make_int4(-1, -1, -1, -1);
+        if (j < A) c = *reinterpret_cast<const int4*>(crow + j);
+        child[j] = c.x; child[j + 1] = c.y; child[j + 2] = c.z; child[j + 3] = c.w;
       }
-      float m = psi[0];
 #pragma unroll
-      for (int j = 1; j < AM; ++j)
-        if (j < A) m = fmaxf(m, psi[j]);
-      float se = 0.0f;
+      for (int j = 0; j < AM; ++j) any = any || (j < A && child[j] >= 0);
+      if (any) {
+        float psi[AM];
 #pragma unroll
-      for (int j = 0; j < AM; ++j)
-        if (j < A) se = se + expf(eta * (psi[j] - m));
-      const float vc = m + logf(se) / eta;
-      int nsum = 0;
-#pragma unroll
-      for (int j = 0; j < AM; ++j) {
-        const int an = child[j];
-        if (j < A && an >= 0) {
-          const int n = P.t.a_N[an];
-          const float c = from_fix(P.t.a_C[an], inv);
-          const unsigned long long wf = P.t.a_W[an];
-          const float w = from_fix(wf, inv);
-          if (wf) P.t.a_W[an] = 0ull;
-          const float fn = (float)n;
-          const float q = c / fn + gamma * (w / fn);
-          psi[j] = (psi[j] - vc) + q;
-          nsum += n;
+        for (int j = 0; j < AM; j += 4) {
+          float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          if (j < A) q = *reinterpret_cast<const float4*>(prow + j);
+          psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
         }
+        // V_curr = L_eta Psi (Eq. 3) before the update.
+        float m = psi[0];
+#pragma unroll
+        for (int j = 1; j < AM; ++j)
+          if (j < A) m = fmaxf(m, psi[j]);
+        float se = 0.0f;
+#pragma unroll
+        for (int j = 0; j < AM; ++j)
+          if (j < A) se = se + expf(eta * (psi[j] - m));
+        const float vc = m + logf(se) / eta;
+        // Q = C/N + gamma W with W = sum_children V N_b / N; Psi <- Psi - V_curr + Q.
+        int nsum = 0;
+#pragma unroll
+        for (int j = 0; j < AM; ++j) {
+          const int an = child[j];
+          if (j < A && an >= 0) {
+            const int n = P.t.a_N[an];
+            const float c = from_fix(P.t.a_C[an], inv);
+            const unsigned long long wf = P.t.a_W[an];
+            const float w = from_fix(wf, inv);
+            if (wf) P.t.a_W[an] = 0ull;
+            const float fn = (float)n;
+            const float q = c / fn + gamma * (w / fn);
+            psi[j] = (psi[j] - vc) + q;
+            nsum += n;
+          }
+        }
+        // V = L_eta Psi after the update; N_b = sum_a N(b, a).
+        float m2 = psi[0];
+#pragma unroll
+        for (int j = 1; j < AM; ++j)
+          if (j < A) m2 = fmaxf(m2, psi[j]);
+        float se2 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < AM; ++j)
+          if (j < A) se2 = se2 + expf(eta * (psi[j] - m2));
+        V = m2 + logf(se2) / eta;
+        N = nsum;
+#pragma unroll
+        for (int j = 0; j < AM; j += 4)
+          if (j < A)
+            *reinterpret_cast<float4*>(prow + j) =
+                make_float4(psi[j], psi[j + 1], psi[j + 2], psi[j + 3]);
+        P.t.b_V[b] = V;
+        P.t.b_N[b] = N;
+      } else {
+        V = P.t.b_V[b];
+        N = P.t.b_N[b];
       }
-      float m2 = psi[0];
-#pragma unroll
-      for (int j = 1; j < AM; ++j)
-        if (j < A) m2 = fmaxf(m2, psi[j]);
-      float se2 = 0.0f;
-#pragma unroll
-      for (int j = 0; j < AM; ++j)
-        if (j < A) se2 = se2 + expf(eta * (psi[j] - m2));
-      V = m2 + logf(se2) / eta;
-      N = nsum;
-#pragma unroll
-      for (int j = 0; j < AM; j += 4)
-        if (j < A)
-          *reinterpret_cast<float4*>(prow + j) =
-              make_float4(psi[j], psi[j + 1], psi[j + 2], psi[j + 3]);
-      P.t.b_V[b] = V;
-      P.t.b_N[b] = N;
-    } else {
-      V = P.t.b_V[b];
-      N = P.t.b_N[b];
     }
-    }
-    push_values(P, T, b, V, N);
+    push_values(P, sm.agg, b, V, N);
   }
 }
 
-// The root row in double precision.
-__global__ void k_backup_root(PlanView P) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The root row in double precision, updated in place (one thread).
+__device__ void dev_backup_root(const PlanView& P) {
+  if (threadIdx.x != 0) return;
   const int A = P.m.nA;
-  double psi[kMaxA];
-  for (int j = 0; j < A; ++j) psi[j] = P.t.psi_root[j];
+  double* psi = P.t.psi_root;
   const double vc = lse64(psi, A, P.eta64);
   long long nsum = 0;
   bool any = false;
@@ -605,66 +683,21 @@ __global__ void k_backup_root(PlanView P) {
     nsum += n;
   }
   if (!any) return;
-  for (int j = 0; j < A; ++j) P.t.psi_root[j] = psi[j];
   const double v = lse64(psi, A, P.eta64);
   P.t.v_root[0] = v;
   P.t.b_V[0] = (float)v;
   P.t.b_N[0] = (int)nsum;
 }
 
-// ---------------------------------------------------------------------------
-// Plan set-up and result.
-// ---------------------------------------------------------------------------
-
-// Clear the table slots used by the previous plan (its beliefs' slots).
-__global__ __launch_bounds__(kBlock) void k_clear_slots(PlanView P, int n_prev) {
-  for (int b = 1 + blockIdx.x * kBlock + threadIdx.x; b < n_prev;
-       b += gridDim.x * kBlock) {
-    const int hs = P.t.b_hslot[b];
-    P.t.h_key[hs] = kEmptyKey;
-    P.t.h_val[hs] = -1;
-  }
-}
-
-// Fill 32-bit words with a value (a plain kernel, safe inside graph capture).
-__global__ __launch_bounds__(kBlock) void k_fill32(uint32_t* p, size_t n, uint32_t v) {
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * kBlock)
-    p[i] = v;
-}
-
-__global__ void k_init_root(PlanView P) {
-  const int j = threadIdx.x;
-  const int A = P.m.nA, Apad = P.m.Apad;
-  if (j < Apad) {
-    P.t.b_child[j] = -1;
-    P.t.psi[j] = j < A ? P.psi0 : 0.0f;
-    if (j < A) P.t.psi_root[j] = P.psi0_64;
-  }
-  if (j == 0) {
-    P.t.b_parent[0] = -1;
-    P.t.b_obs[0] = -1;
-    P.t.b_V[0] = 0.0f;
-    P.t.b_N[0] = 0;
-    P.t.leaf_cnt[0] = 0;
-    P.t.leaf_h[0] = 0ull;
-    P.t.b_hslot[0] = 0;
-    P.t.v_root[0] = 0.0;
-    P.t.bel_base[0] = 1;
-    P.t.act_base[0] = 0;
-    P.t.counters[0] = 0ull;
-    P.t.counters[1] = 0ull;
-  }
-}
-
-// out: [0] action, [1..A] psi_root, [A+1] v_root, [A+2] particle steps,
-//      [A+3] beliefs, [A+4] action nodes, [A+5] input-error flags (doubles).
-__global__ void k_select(PlanView P, int last_step, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Alg. 1: argmax of the root preferences (lowest index on ties) and the
+// result record; also records the belief count for the next plan's set-up.
+__device__ void dev_select(const PlanView& P, int last_step) {
+  if (threadIdx.x != 0) return;
   const int A = P.m.nA;
   int best = 0;
   for (int j = 1; j < A; ++j)
     if (P.t.psi_root[j] > P.t.psi_root[best]) best = j;
+  double* out = P.out;
   out[0] = (double)best;
   for (int j = 0; j < A; ++j) out[1 + j] = P.t.psi_root[j];
   out[A + 1] = P.t.v_root[0];
@@ -672,6 +705,86 @@ __global__ void k_select(PlanView P, int last_step, double* out) {
   out[A + 3] = (double)P.t.bel_base[last_step];
   out[A + 4] = (double)P.t.act_base[last_step];
   out[A + 5] = (double)P.t.counters[1];
+  P.t.counters[2] = (unsigned long long)P.t.bel_base[last_step];
+  P.t.counters[3] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Single-plan kernels (one launch per phase).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
+  dev_setup(P, blockIdx.x, gridDim.x);
+}
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
+  __shared__ Smem sm;
+  dev_expand<AM>(P, k, d, blockIdx.x, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
+  __shared__ Smem sm;
+  dev_resolve(P, t, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
+  __shared__ Smem sm;
+  dev_finish(P, blockIdx.x, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
+  __shared__ Smem sm;
+  dev_backup_leaf(P, dep, k, blockIdx.x, gridDim.x, sm);
+}
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, int k) {
+  __shared__ Smem sm;
+  dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
+}
+__global__ void k_backup_root(PlanView P) { dev_backup_root(P); }
+__global__ void k_select(PlanView P, int last_step) { dev_select(P, last_step); }
+
+// ---------------------------------------------------------------------------
+// Batched kernel: block -> (instance, phase) through the item list, sorted by
+// first block.  AMAX bounds the padded action count of the batch.
+// ---------------------------------------------------------------------------
+template <int AMAX>
+__global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ views,
+                                                  const BatchItem* __restrict__ items,
+                                                  int n_items) {
+  __shared__ Smem sm;
+  const int g = blockIdx.x;
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].blk0 <= g) lo = mid; else hi = mid - 1;
+  }
+  const BatchItem it = items[lo];
+  const int blk = g - it.blk0;
+  if (blk >= it.nblk) return;          // uniform per block
+  const PlanView& P = views[it.inst];
+  const int Apad = P.m.Apad;
+  switch (it.kind) {
+    case kPhaseSetup: dev_setup(P, blk, it.nblk); break;
+    case kPhaseExpand:
+      if (Apad <= 4) {
+        dev_expand<4>(P, it.a0, it.a1, blk, sm);
+      } else if constexpr (AMAX >= 8) {
+        if (Apad <= 8) dev_expand<8>(P, it.a0, it.a1, blk, sm);
+        else if constexpr (AMAX >= 16) dev_expand<16>(P, it.a0, it.a1, blk, sm);
+      }
+      break;
+    case kPhaseResolve: dev_resolve(P, it.a0, sm); break;
+    case kPhaseFinish: dev_finish(P, blk, sm); break;
+    case kPhaseLeaf: dev_backup_leaf(P, it.a0, it.a1, blk, it.nblk, sm); break;
+    case kPhaseLevel:
+      if (Apad <= 4) {
+        dev_backup_level<4>(P, it.a0, it.a1, blk, it.nblk, sm);
+      } else if constexpr (AMAX >= 8) {
+        if (Apad <= 8) dev_backup_level<8>(P, it.a0, it.a1, blk, it.nblk, sm);
+        else if constexpr (AMAX >= 16) dev_backup_level<16>(P, it.a0, it.a1, blk, it.nblk, sm);
+      }
+      break;
+    case kPhaseRoot: dev_backup_root(P); break;
+    case kPhaseSelect: dev_select(P, it.a0); break;
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -679,6 +792,16 @@ __global__ void k_select(PlanView P, int last_step, double* out) {
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
+int setup_blocks(const PlanView& P) {
+  const long long work = ((long long)P.t.h_mask + 1) / 2;   // 16-byte stores
+  long long g = (work + kBlock * 8 - 1) / (kBlock * 8);
+  return (int)std::max(1ll, std::min(g, 1024ll));
+}
+
+hipError_t launch_setup(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
 hipError_t launch_expand(const PlanView& P, int k, int d, hipStream_t s) {
   const dim3 g(blocks_for(P.n_p)), b(kBlock);
   const int Ap = P.m.Apad;
@@ -715,26 +838,17 @@ hipError_t launch_backup_root(const PlanView& P, hipStream_t s) {
   hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }
-hipError_t launch_clear_slots(const PlanView& P, int n_prev, hipStream_t s) {
-  if (n_prev <= 1) return hipSuccess;
-  int grid = blocks_for(n_prev);
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_clear_slots, dim3(grid), dim3(kBlock), 0, s, P, n_prev);
+hipError_t launch_select(const PlanView& P, int last_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P, last_step);
   return hipGetLastError();
 }
-hipError_t launch_fill32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  size_t g = (n + kBlock - 1) / kBlock;
-  int grid = (int)(g > 8192 ? 8192 : g);
-  hipLaunchKernelGGL(k_fill32, dim3(grid), dim3(kBlock), 0, s, p, n, v);
-  return hipGetLastError();
-}
-hipError_t launch_init_root(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, s, P);
-  return hipGetLastError();
-}
-hipError_t launch_select(const PlanView& P, int last_step, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P, last_step, out);
+hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
+                        int n_blocks, int amax, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  const dim3 g(n_blocks), b(kBlock);
+  if (amax <= 4) hipLaunchKernelGGL(k_batch<4>, g, b, 0, s, views, items, n_items);
+  else if (amax <= 8) hipLaunchKernelGGL(k_batch<8>, g, b, 0, s, views, items, n_items);
+  else hipLaunchKernelGGL(k_batch<16>, g, b, 0, s, views, items, n_items);
   return hipGetLastError();
 }
 

@@ -30,8 +30,11 @@ EXPORTS = (
     "vopp_pomdp_num_actions", "vopp_pomdp_free", "vopp_plan_footprint",
     "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
     "vopp_tree_dump", "vopp_profile_enable", "vopp_profile_reset",
-    "vopp_profile_read",
+    "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
+    "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
+    "vopp_batch_num_launches", "vopp_batch_free", "vopp_plan_batch",
 )
+MAX_ACTIONS = 64
 
 KERNEL_KINDS = ("expand", "resolve", "finish", "backup_leaf", "backup_level",
                 "backup_root", "setup", "select")
@@ -70,6 +73,22 @@ class vopp_params(C.Structure):
 class vopp_stats(C.Structure):
     _fields_ = [("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
                 ("n_actions", C.c_int64), ("device_ms", C.c_double)]
+
+
+class vopp_request(C.Structure):
+    _fields_ = [("pomdp", C.c_void_p), ("belief_particles", C.c_void_p),
+                ("n_belief", C.c_int32), ("budget", C.c_int32), ("depth", C.c_int32),
+                ("params", vopp_params)]
+
+
+class vopp_result(C.Structure):
+    _fields_ = [("action", C.c_int32), ("status", C.c_int32), ("v_root", C.c_double),
+                ("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
+                ("n_actions", C.c_int64), ("values", C.c_double * MAX_ACTIONS)]
+
+
+class vopp_tuning(C.Structure):
+    _fields_ = [("res_target_tiles", C.c_int32), ("backup_cap", C.c_int32)]
 
 
 _lib = None
@@ -113,6 +132,22 @@ def lib():
     L.vopp_profile_reset.restype = st
     L.vopp_profile_read.argtypes = [vp, vp, vp]
     L.vopp_profile_read.restype = st
+    L.vopp_batch_create.argtypes = [vp, i32, C.POINTER(vopp_tuning), C.POINTER(vp)]
+    L.vopp_batch_create.restype = st
+    L.vopp_batch_footprint.argtypes = [vp, i32]
+    L.vopp_batch_footprint.restype = C.c_size_t
+    L.vopp_batch_set_request.argtypes = [vp, i32, vp, i32, C.c_uint64, C.c_uint32]
+    L.vopp_batch_set_request.restype = st
+    L.vopp_batch_run.argtypes = [vp, vp, i32, vp, vp]
+    L.vopp_batch_run.restype = st
+    L.vopp_batch_autotune.argtypes = [vp, vp, i32, C.POINTER(vopp_tuning)]
+    L.vopp_batch_autotune.restype = st
+    L.vopp_batch_num_launches.argtypes = [vp]
+    L.vopp_batch_num_launches.restype = i32
+    L.vopp_batch_free.argtypes = [vp]
+    L.vopp_batch_free.restype = None
+    L.vopp_plan_batch.argtypes = [vp, i32, vp, vp]
+    L.vopp_plan_batch.restype = st
     _lib = L
     return L
 
@@ -278,3 +313,78 @@ def profile_read(ws):
     n = np.zeros(len(KERNEL_KINDS), np.int64)
     _check(lib().vopp_profile_read(ws.handle, _p(ms), _p(n)))
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def make_requests(items):
+    """items: list of (Pomdp, belief device tensor, n_belief, budget, depth, params)."""
+    arr = (vopp_request * len(items))()
+    for i, (pom, bel, nb, K, depth, prm) in enumerate(items):
+        arr[i] = vopp_request(pom.handle.value, bel.data_ptr(), int(nb), int(K),
+                              int(depth), prm)
+    return arr
+
+
+def _results(arr, nAs):
+    out = []
+    for r, nA in zip(arr, nAs):
+        out.append(PlanResult(int(r.action), np.array(r.values[:nA], np.float64),
+                              float(r.v_root), int(r.particle_steps), int(r.n_beliefs),
+                              int(r.n_actions), float("nan")))
+    return out
+
+
+class Batch:
+    """vopp_batch: many requests advanced together, replayed as one hipGraph."""
+
+    def __init__(self, items, tuning=None):
+        self.items = list(items)
+        self.reqs = make_requests(self.items)
+        self.nAs = [it[0].nA for it in self.items]
+        h = C.c_void_p()
+        tu = None if tuning is None else C.byref(vopp_tuning(*tuning))
+        _check(lib().vopp_batch_create(C.cast(self.reqs, C.c_void_p), len(self.items), tu,
+                                       C.byref(h)))
+        self.handle = h
+
+    def __len__(self):
+        return len(self.items)
+
+    @property
+    def num_launches(self):
+        return int(lib().vopp_batch_num_launches(self.handle))
+
+    def set_request(self, i, belief_dev, n_belief, seed, step=0):
+        _check(lib().vopp_batch_set_request(self.handle, int(i),
+                                            C.c_void_p(belief_dev.data_ptr()),
+                                            int(n_belief), int(seed) & (2 ** 64 - 1),
+                                            int(step) & 0xFFFFFFFF))
+
+    def run(self, use_graph=True, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        arr = (vopp_result * len(self.items))()
+        ms = np.zeros(1, np.float64)
+        _check(lib().vopp_batch_run(self.handle, C.c_void_p(stream.cuda_stream),
+                                    1 if use_graph else 0, C.cast(arr, C.c_void_p), _p(ms)))
+        return _results(arr, self.nAs), float(ms[0])
+
+    def autotune(self, reps=2, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        tu = vopp_tuning()
+        _check(lib().vopp_batch_autotune(self.handle, C.c_void_p(stream.cuda_stream),
+                                         int(reps), C.byref(tu)))
+        return (int(tu.res_target_tiles), int(tu.backup_cap))
+
+    def close(self):
+        if self.handle:
+            lib().vopp_batch_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,151 @@
+"""Batched planning (vopp_batch_*): every instance's result must be bit-identical
+to a plain vopp_plan call with the same inputs, whether the batch is replayed
+from its captured hipGraph or issued launch by launch, on every replay, and
+for every launch shape the autotuner tries."""
+
+import numpy as np
+import pytest
+
+from paper_2510_27191_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_27191_amd import vopp
+    vopp.lib()
+    return vopp
+
+
+def small_mix(seed, n):
+    """A reduced mix: tabular and navigation, uneven n_p / depth / budget."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        depth = int(rng.integers(2, 7))
+        K = int(rng.integers(1, depth + 1))
+        n_p = int(rng.integers(100, 3000))
+        sched = int(rng.integers(0, 2))
+        if i % 2 == 0:
+            inst = I.tabular_sparse(int(rng.integers(0, 1000)), int(rng.integers(20, 200)),
+                                    int(rng.integers(2, 9)), int(rng.integers(2, 12)), 4,
+                                    with_heuristic=bool(i % 4 == 0))
+            bel = I.tabular_belief(inst)
+        else:
+            inst = I.nav2d(int(rng.integers(0, 1000)), int(rng.integers(4, 12)),
+                           heuristic=int(i % 3 == 0))
+            bel = I.nav_belief(int(rng.integers(0, 1000)), 500,
+                               *( (7.0, 8.5) if i % 5 == 1 else (0.5, 1.5) ))
+        out.append((inst, bel, dict(n_particles=n_p, budget=K, depth=depth, eta=1.0,
+                                    seed=int(rng.integers(1, 2 ** 40)), schedule=sched)))
+    return out
+
+
+def build(V, mix):
+    items, keep = [], []
+    for inst, bel, p in mix:
+        pom = V.Pomdp.from_instance(inst)
+        belt = V.belief_tensor(inst, bel)
+        nb = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
+        prm = V.params(p["n_particles"], eta=p["eta"], seed=p["seed"],
+                       schedule=p["schedule"])
+        items.append((pom, belt, nb, p["budget"], p["depth"], prm))
+        keep.append((pom, belt))
+    return items, keep
+
+
+def plain(V, items):
+    out = []
+    for pom, belt, nb, K, depth, prm in items:
+        out.append(V.plan(pom, belt, nb, K, depth, prm))
+    return out
+
+
+def same(a, b):
+    assert a.action == b.action
+    assert np.array_equal(a.values, b.values)
+    assert a.v_root == b.v_root
+    assert (a.particle_steps, a.n_beliefs, a.n_actions) == (b.particle_steps, b.n_beliefs,
+                                                            b.n_actions)
+
+
+def test_batch_equals_plain_plans(V):
+    items, keep = build(V, small_mix(1, 14))
+    ref = plain(V, items)
+    batch = V.Batch(items)
+    assert batch.num_launches > 10
+    for use_graph in (True, False, True):
+        res, ms = batch.run(use_graph=use_graph)
+        assert ms > 0
+        for a, b in zip(res, ref):
+            same(a, b)
+    batch.close()
+
+
+def test_graph_replays_with_new_requests(V):
+    import torch
+    mix = small_mix(2, 10)
+    items, keep = build(V, mix)
+    batch = V.Batch(items)
+    for rep in range(3):
+        # Eager work and synchronisation between replays.
+        x = torch.randn(1000, device="cuda")
+        _ = (x * 2).sum().item()
+        new_items = []
+        for i, (pom, belt, nb, K, depth, prm) in enumerate(items):
+            seed = 1000 * rep + 17 * i + 3
+            batch.set_request(i, belt, nb, seed, step=rep)
+            new_items.append((pom, belt, nb, K, depth,
+                              V.params(prm.n_particles, eta=prm.eta, seed=seed,
+                                       schedule=prm.schedule, step=rep)))
+        res, _ = batch.run(use_graph=True)
+        eager, _ = batch.run(use_graph=False)
+        ref = plain(V, new_items)
+        for a, b, c in zip(res, eager, ref):
+            same(a, c)
+            same(b, c)
+    batch.close()
+
+
+def test_batch_instance_matches_oracle(V, orc):
+    inst = I.tabular_dense(0, 16, 3, 4)
+    bel = I.tabular_belief(inst)
+    o = orc.plan(inst, bel, 1024, 4, 4, eta=1.0, seed=1)
+    assert o.near_ties == 0
+    mix = small_mix(3, 5)
+    items, keep = build(V, mix)
+    pom = V.Pomdp.from_instance(inst)
+    belt = V.belief_tensor(inst, bel)
+    items.insert(2, (pom, belt, bel.size, 4, 4, V.params(1024, seed=1)))
+    batch = V.Batch(items)
+    res, _ = batch.run()
+    r = res[2]
+    assert r.action == o.action
+    assert r.n_beliefs == len(o.b_parent) and r.particle_steps == o.particle_steps
+    assert np.all(np.abs(r.values - o.psi_root) <= 1e-4 * np.maximum(np.abs(o.psi_root), 1))
+    batch.close()
+
+
+def test_autotune_keeps_results(V):
+    items, keep = build(V, small_mix(4, 8))
+    ref = plain(V, items)
+    batch = V.Batch(items)
+    chosen = batch.autotune(reps=1)
+    assert chosen[0] in (64, 256, 1024) and chosen[1] in (256, 1024, 4096)
+    res, _ = batch.run()
+    for a, b in zip(res, ref):
+        same(a, b)
+    batch.close()
+
+
+def test_batch_rejects_large_action_sets(V):
+    inst = I.tabular_dense(0, 4, 20, 2)
+    pom = V.Pomdp.from_instance(inst)
+    belt = V.belief_tensor(inst, I.tabular_belief(inst))
+    with pytest.raises(V.VoppError) as e:
+        V.Batch([(pom, belt, 4, 2, 2, V.params(64))])
+    assert e.value.status == V.VOPP_E_INVALID
