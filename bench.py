@@ -70,6 +70,74 @@ def cpu_baseline(inst, bel, p, budget_s=12.0, max_plans=4):
                       f"serial, {t_total:.1f} s"}
 
 
+def bench_batch(V, I, reps=3, autotune=True):
+    """256 mixed instances: one batched hipGraph replay vs 256 plain calls."""
+    import torch
+    mix = I.batch_mix(0)
+    items = []
+    for inst, bel, p in mix:
+        pom = V.Pomdp.from_instance(inst)
+        belt = V.belief_tensor(inst, bel)
+        nb = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
+        items.append((pom, belt, nb, p["budget"], p["depth"],
+                      V.params(p["n_particles"], eta=p["eta"], seed=p["seed"])))
+    stream = torch.cuda.current_stream()
+    # Plain: one vopp_plan per instance, back to back (each returns its result).
+    for pom, belt, nb, K, depth, prm in items:          # warm-up, allocates
+        V.plan(pom, belt, nb, K, depth, prm, stream=stream)
+    torch.cuda.synchronize()
+    plain_s, plain_lat = [], []
+    steps = 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        steps = 0
+        for pom, belt, nb, K, depth, prm in items:
+            a = time.perf_counter()
+            r = V.plan(pom, belt, nb, K, depth, prm, stream=stream)
+            plain_lat.append((time.perf_counter() - a) * 1e3)
+            steps += r.particle_steps
+        plain_s.append(time.perf_counter() - t0)
+    plain_ref = [V.plan(pom, belt, nb, K, depth, prm, stream=stream)
+                 for pom, belt, nb, K, depth, prm in items]
+    # Batched: the whole batch as one graph launch.
+    batch = V.Batch(items)
+    tuning = batch.autotune(reps=1) if autotune else None
+    batch.run()
+    batch_s, batch_dev = [], []
+    res = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, ms = batch.run(use_graph=True)
+        batch_s.append(time.perf_counter() - t0)
+        batch_dev.append(ms)
+    identical = all(a.action == b.action and np.array_equal(a.values, b.values)
+                    and a.n_beliefs == b.n_beliefs for a, b in zip(res, plain_ref))
+    bsteps = sum(r.particle_steps for r in res)
+    out = {
+        "workload": "256 mixed instances: tabular (|S| log-uniform 64-4096, |A| 3-8, "
+                    "|O| 4-32, 8 successors) and 2-D navigation (4-16 obstacles), "
+                    "depth 4-12, budget = depth, n_p log-uniform 2^10-2^16",
+        "instances": len(items),
+        "particle_steps_per_batch": bsteps,
+        "plain_sequential": {"value": steps / min(plain_s), "unit": "particle-steps/s",
+                             "ms_per_batch": min(plain_s) * 1e3,
+                             "plan_latency_ms": {"p50": percentile(plain_lat, 50),
+                                                 "p99": percentile(plain_lat, 99)}},
+        "batched_graph": {"value": bsteps / min(batch_s), "unit": "particle-steps/s",
+                          "ms_per_batch": min(batch_s) * 1e3,
+                          "device_ms_per_batch": min(batch_dev),
+                          "launches": batch.num_launches},
+        "speedup": min(plain_s) / min(batch_s),
+        "results_identical_to_plain": bool(identical),
+        "tuning": {"res_target_tiles": tuning[0], "backup_cap": tuning[1]} if tuning else None,
+    }
+    batch.close()
+    for it in items:
+        it[0].close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +148,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-event-profile", action="store_true",
                     help="skip the per-kernel event brackets in the timed region")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 256-instance batched vs plain comparison")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -187,11 +257,13 @@ def main():
             roof.update(achieved=None, frac=None,
                         note=f"dominant kernel {dom} has no byte model yet")
         out["roofline"] = roof
+    ws.close()
+    pom.close()
+    if not args.no_batch:
+        out["batched_vs_plain"] = bench_batch(V, I)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, bel, p)
     print(json.dumps(out), flush=True)
-    ws.close()
-    pom.close()
 
 
 if __name__ == "__main__":

@@ -88,9 +88,7 @@ def tabular_sparse(seed: int, nS: int = 4096, nA: int = 8, nO: int = 32,
     rng = np.random.default_rng(seed)
     k = min(n_succ, nS)
     rows = nS * nA
-    col = np.empty((rows, k), dtype=np.int32)
-    for r in range(rows):
-        col[r] = np.sort(rng.choice(nS, size=k, replace=False))
+    col = _distinct_rows(rng, rows, nS, k)
     tp = rng.dirichlet(alpha * np.ones(k), size=rows).astype(np.float32)
     Z = rng.dirichlet(alpha * np.ones(nO), size=(nS, nA)).astype(np.float32)
     R = rng.uniform(-1.0, 1.0, size=(nS, nA)).astype(np.float32)
@@ -101,6 +99,21 @@ def tabular_sparse(seed: int, nS: int = 4096, nA: int = 8, nO: int = 32,
                 col=col.reshape(-1).copy(), tprob=tp.reshape(-1).copy(),
                 zprob=Z.reshape(-1).copy(), reward=R.reshape(-1).copy(),
                 heur=heur, gamma=float(gamma))
+
+
+def _distinct_rows(rng, rows: int, n: int, k: int) -> np.ndarray:
+    """rows x k distinct integers from [0, n) per row, sorted; uniform over
+    k-subsets (rows with a repeated value are drawn again)."""
+    if k == n:
+        return np.tile(np.arange(n, dtype=np.int32), (rows, 1))
+    out = np.sort(rng.integers(0, n, size=(rows, k)), axis=1)
+    bad = np.nonzero((np.diff(out, axis=1) == 0).any(axis=1))[0]
+    while bad.size:
+        redo = np.sort(rng.integers(0, n, size=(bad.size, k)), axis=1)
+        out[bad] = redo
+        ok = ~(np.diff(redo, axis=1) == 0).any(axis=1)
+        bad = bad[~ok]
+    return out.astype(np.int32)
 
 
 def nav2d(seed: int, n_disks: int = 8, gamma: float = 0.95,
