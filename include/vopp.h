@@ -175,6 +175,34 @@ vopp_status vopp_tree_dump(vopp_workspace* ws, int32_t* b_parent, int32_t* b_obs
                            double* a_C, int32_t* a_N);
 
 /* ------------------------------------------------------------------------ */
+/* Between real steps: the true environment and the belief update.          */
+/* ------------------------------------------------------------------------ */
+
+/* One step of a simulated true environment (Alg. 1, "execute action a and
+ * perceive o"): the generative model G with its own Philox stream, counter
+ * (0, 4<<24, 0, step) under env_seed.  state: DEVICE pointer, in/out
+ * (tabular: int32[1]; navigation: fp32 x, y).  obs, reward, terminal: host
+ * outputs (any may be NULL).  Synchronous. */
+vopp_status vopp_env_step(const vopp_pomdp* pomdp, void* state, int32_t action,
+                          uint64_t env_seed, uint32_t step, void* stream,
+                          int32_t* obs, float* reward, int32_t* terminal);
+
+/* Sequential importance resampling belief update b <- tau(b, a, o) (Alg. 1,
+ * belief update; SIR particle filter of Sec. III-B), in place on n DEVICE
+ * particles (layout of vopp_plan's belief_particles).  Each particle moves
+ * under a (transition part of G, Philox counter (i, 5<<24, 0, step)); its
+ * weight is the exact integer likelihood of o (tabular: the observation
+ * threshold difference; navigation: the count of noise indices per axis that
+ * land in o's grid cell, multiplied); n new particles are drawn
+ * multinomially (counter (j, 6<<24, 0, step)).  If every weight is zero the
+ * moved particles are kept.  total_weight (host, may be NULL): the weight
+ * sum (tabular in units of 2^-31, navigation in units of 2^-24).
+ * Synchronous. */
+vopp_status vopp_belief_update(const vopp_pomdp* pomdp, void* particles, int32_t n,
+                               int32_t action, int32_t obs, uint64_t seed,
+                               uint32_t step, void* stream, uint64_t* total_weight);
+
+/* ------------------------------------------------------------------------ */
 /* Batched planning: many independent instances (models of any kind, uneven */
 /* n_p, budget and depth) advanced together.                                 */
 /* ------------------------------------------------------------------------ */

@@ -87,6 +87,16 @@ def load():
     lib.orc_sample_action.restype = C.c_int32
     lib.orc_nav_step.argtypes = [C.POINTER(OrcNav), C.c_float, C.c_float,
                                  C.c_int32, C.c_uint32, C.c_uint32] + [vp] * 5
+    lib.orc_env_step_tabular.argtypes = [C.POINTER(OrcTabular), vp, C.c_int32,
+                                         C.c_uint64, C.c_uint32, vp, vp, vp]
+    lib.orc_env_step_nav.argtypes = [C.POINTER(OrcNav), vp, vp, C.c_int32,
+                                     C.c_uint64, C.c_uint32, vp, vp, vp]
+    lib.orc_pf_update_tabular.argtypes = [C.POINTER(OrcTabular), vp, C.c_int32,
+                                          C.c_int32, C.c_int32, C.c_uint64, C.c_uint32]
+    lib.orc_pf_update_tabular.restype = C.c_uint64
+    lib.orc_pf_update_nav.argtypes = [C.POINTER(OrcNav), vp, vp, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_uint64, C.c_uint32]
+    lib.orc_pf_update_nav.restype = C.c_uint64
     _lib = lib
     return lib
 
@@ -253,3 +263,43 @@ def nav_step(inst, x, y, a, w1, w2):
     lib.orc_nav_step(C.byref(m), float(x), float(y), int(a), int(w1), int(w2),
                      _ptr(nx), _ptr(ny), _ptr(key), _ptr(r), _ptr(term))
     return float(nx[0]), float(ny[0]), int(key[0]), float(r[0]), int(term[0])
+
+
+def env_step(inst, state, a, seed, step):
+    """One true-environment step.  state: int (tabular) or (x, y)."""
+    lib = load()
+    keep = _Keep()
+    obs = np.zeros(1, np.int32)
+    r = np.zeros(1, np.float32)
+    term = np.zeros(1, np.int32)
+    if inst["kind"] == "tabular":
+        m = tabular_struct(inst, keep)
+        s = np.array([state], np.int32)
+        lib.orc_env_step_tabular(C.byref(m), _ptr(s), int(a), int(seed), int(step),
+                                 _ptr(obs), _ptr(r), _ptr(term))
+        return int(s[0]), int(obs[0]), float(r[0]), int(term[0])
+    m = nav_struct(inst, keep)
+    x = np.array([state[0]], np.float32)
+    y = np.array([state[1]], np.float32)
+    lib.orc_env_step_nav(C.byref(m), _ptr(x), _ptr(y), int(a), int(seed), int(step),
+                         _ptr(obs), _ptr(r), _ptr(term))
+    return (float(x[0]), float(y[0])), int(obs[0]), float(r[0]), int(term[0])
+
+
+def belief_update(inst, particles, a, o, seed, step):
+    """SIR update.  particles: int32 array (tabular) or (x, y) float32 arrays.
+    Returns (new particles, integer weight total)."""
+    lib = load()
+    keep = _Keep()
+    if inst["kind"] == "tabular":
+        m = tabular_struct(inst, keep)
+        p = np.array(particles, np.int32)
+        tot = lib.orc_pf_update_tabular(C.byref(m), _ptr(p), p.size, int(a), int(o),
+                                        int(seed), int(step))
+        return p, int(tot)
+    m = nav_struct(inst, keep)
+    x = np.array(particles[0], np.float32)
+    y = np.array(particles[1], np.float32)
+    tot = lib.orc_pf_update_nav(C.byref(m), _ptr(x), _ptr(y), x.size, int(a), int(o),
+                                int(seed), int(step))
+    return (x, y), int(tot)

@@ -58,6 +58,12 @@
  *     sequential double sum of the fp32 row (last = 2^31); outcome = first j
  *     with (x >> 1) < thr_j.  Successor from word 1, observation from word 2
  *     using the row Z[s', a, .]; reward R[s, a]; never terminal.
+ *   - Between real steps (Alg. 1): the true environment is G with its own
+ *     stream (tag ENV = 4); the belief update is sequential importance
+ *     resampling with exact integer likelihoods (tabular: the observation
+ *     threshold difference; navigation: the count of noise-table index pairs
+ *     whose observation lands in the observed cell) and multinomial draws
+ *     (tags PF = 5, RESAMPLE = 6).
  *   - Navigation G: single-precision arithmetic with no contraction, noise
  *     from the instance's 4096-entry Gaussian quantile table; observation
  *     key from the 0.5 grid cell of the noisy position; reward -1 per step,
@@ -101,7 +107,7 @@ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
   return out;
 }
 
-const uint32_t TAG_ROOT = 1, TAG_STEP = 2;
+const uint32_t TAG_ROOT = 1, TAG_STEP = 2, TAG_ENV = 4, TAG_PF = 5, TAG_RESAMPLE = 6;
 
 Words draw(uint64_t seed, uint32_t ep, uint32_t tag, uint32_t level,
            uint32_t iter, uint32_t step) {
@@ -223,12 +229,21 @@ struct TabularModel {
     for (float v : R) r_max = std::max(r_max, (double)std::fabs(v));
   }
 
+  int successor(int s, int a, uint32_t word) const {
+    int row = s * nA + a;
+    int lo = rowptr[row], n = rowptr[row + 1] - lo;
+    return col[lo + pick(&thrT[lo], n, word)];
+  }
+  // Probability of observation o after (a, s'), in units of 2^-31.
+  uint64_t obs_weight(int sn, int a, int o) const {
+    const uint32_t* t = &thrZ[((size_t)sn * nA + a) * nO];
+    return (uint64_t)t[o] - (o > 0 ? (uint64_t)t[o - 1] : 0ull);
+  }
+
   Outcome step(const State& st, int a, const Words& x) const {
     Outcome o;
     int row = st.s * nA + a;
-    int lo = rowptr[row], n = rowptr[row + 1] - lo;
-    int j = pick(&thrT[lo], n, x.w[1]);
-    int sn = col[lo + j];
+    int sn = successor(st.s, a, x.w[1]);
     int ob = pick(&thrZ[((size_t)sn * nA + a) * nO], nO, x.w[2]);
     o.next.s = sn; o.next.x = 0.0f; o.next.y = 0.0f;
     o.obs = ob;
@@ -266,20 +281,40 @@ struct NavModel {
     return i - p.key_lo;
   }
 
-  Outcome step(const State& st, int a, const Words& x) const {
-    // Moves: 0 = +y, 1 = +x, 2 = -y, 3 = -x.
+  // Motion part of G: moves 0 = +y, 1 = +x, 2 = -y, 3 = -x, plus noise.
+  void move(float x, float y, int a, uint32_t word, float* nx, float* ny) const {
     float dx = 0.0f, dy = 0.0f;
     if (a == 0) dy = p.step;
     else if (a == 1) dx = p.step;
     else if (a == 2) dy = -p.step;
     else dx = -p.step;
-    float zx = gauss[x.w[1] >> 20];
-    float zy = gauss[(x.w[1] >> 8) & 4095u];
-    float mx = st.x + dx;
-    float my = st.y + dy;
-    float nx = clampf(mx + p.sigma_move * zx, p.lo, p.hi);
-    float ny = clampf(my + p.sigma_move * zy, p.lo, p.hi);
-    float sd = p.sigma_obs0 + p.sigma_obs_slope * std::fabs(nx - p.obs_center_x);
+    float zx = gauss[word >> 20];
+    float zy = gauss[(word >> 8) & 4095u];
+    float mx = x + dx;
+    float my = y + dy;
+    *nx = clampf(mx + p.sigma_move * zx, p.lo, p.hi);
+    *ny = clampf(my + p.sigma_move * zy, p.lo, p.hi);
+  }
+  float obs_sd(float nx) const {
+    return p.sigma_obs0 + p.sigma_obs_slope * std::fabs(nx - p.obs_center_x);
+  }
+  // Likelihood of observation key o at (nx, ny), in units of 2^-24: the number
+  // of (12-bit, 12-bit) noise index pairs whose observation lands in o's cell.
+  uint64_t obs_weight(float nx, float ny, int o) const {
+    const float sd = obs_sd(nx);
+    const int kx = o / p.key_n, ky = o % p.key_n;
+    uint64_t cx = 0, cy = 0;
+    for (int j = 0; j < 4096; ++j) {
+      if (key_axis(nx + sd * gauss[j]) == kx) ++cx;
+      if (key_axis(ny + sd * gauss[j]) == ky) ++cy;
+    }
+    return cx * cy;
+  }
+
+  Outcome step(const State& st, int a, const Words& x) const {
+    float nx, ny;
+    move(st.x, st.y, a, x.w[1], &nx, &ny);
+    float sd = obs_sd(nx);
     float ox = nx + sd * gauss[x.w[2] >> 20];
     float oy = ny + sd * gauss[(x.w[2] >> 8) & 4095u];
     int key = key_axis(ox) * p.key_n + key_axis(oy);
@@ -649,6 +684,99 @@ void orc_nav_step(const orc_nav* m, float x, float y, int32_t a, uint32_t w1,
   Words w = {{0u, w1, w2, 0u}};
   Outcome o = model.step(s, a, w);
   *nx = o.next.x; *ny = o.next.y; *key = o.obs; *r = o.r; *term = o.term ? 1 : 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Between real steps (Alg. 1: execute, perceive, update the belief).
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class Model>
+Outcome env_step(const Model& model, const State& st, int a, uint64_t seed, uint32_t step) {
+  Words x = philox4x32_10(0u, TAG_ENV << 24, 0u, step, (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+  return model.step(st, a, x);
+}
+
+// SIR update: move every particle under a, weight it by the exact integer
+// likelihood of o, draw n new particles multinomially.
+template <class Model, class Move, class Weight>
+uint64_t pf_update(const Model& model, std::vector<State>& parts, int a, int o, uint64_t seed,
+                   uint32_t step, Move mv, Weight wt) {
+  const int n = (int)parts.size();
+  std::vector<State> moved(n);
+  std::vector<uint64_t> cum(n);
+  uint64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    Words x = philox4x32_10((uint32_t)i, TAG_PF << 24, 0u, step, (uint32_t)seed,
+                            (uint32_t)(seed >> 32));
+    moved[i] = mv(parts[i], x.w[1]);
+    total += wt(moved[i]);
+    cum[i] = total;
+  }
+  if (total == 0) {
+    parts = moved;
+    return 0;
+  }
+  for (int j = 0; j < n; ++j) {
+    Words y = philox4x32_10((uint32_t)j, TAG_RESAMPLE << 24, 0u, step, (uint32_t)seed,
+                            (uint32_t)(seed >> 32));
+    const uint64_t u = ((uint64_t)y.w[0] << 32) | y.w[1];
+    const uint64_t target = (uint64_t)(((unsigned __int128)u * total) >> 64);
+    const int i = (int)(std::upper_bound(cum.begin(), cum.end(), target) - cum.begin());
+    parts[j] = moved[i];
+  }
+  return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+void orc_env_step_tabular(const orc_tabular* m, int32_t* s, int32_t a, uint64_t seed,
+                          uint32_t step, int32_t* obs, float* r, int32_t* term) {
+  TabularModel model(m);
+  State st; st.s = *s; st.x = st.y = 0.0f;
+  Outcome o = env_step(model, st, a, seed, step);
+  *s = o.next.s; *obs = o.obs; *r = o.r; *term = o.term ? 1 : 0;
+}
+
+void orc_env_step_nav(const orc_nav* m, float* x, float* y, int32_t a, uint64_t seed,
+                      uint32_t step, int32_t* obs, float* r, int32_t* term) {
+  NavModel model(m);
+  State st; st.s = 0; st.x = *x; st.y = *y;
+  Outcome o = env_step(model, st, a, seed, step);
+  *x = o.next.x; *y = o.next.y; *obs = o.obs; *r = o.r; *term = o.term ? 1 : 0;
+}
+
+uint64_t orc_pf_update_tabular(const orc_tabular* m, int32_t* parts, int32_t n, int32_t a,
+                               int32_t o, uint64_t seed, uint32_t step) {
+  TabularModel model(m);
+  std::vector<State> P(n);
+  for (int i = 0; i < n; ++i) { P[i].s = parts[i]; P[i].x = P[i].y = 0.0f; }
+  uint64_t tot = pf_update(model, P, a, o, seed, step,
+      [&](const State& s, uint32_t w) { State r = s; r.s = model.successor(s.s, a, w); return r; },
+      [&](const State& s) { return model.obs_weight(s.s, a, o); });
+  for (int i = 0; i < n; ++i) parts[i] = P[i].s;
+  return tot;
+}
+
+uint64_t orc_pf_update_nav(const orc_nav* m, float* px, float* py, int32_t n, int32_t a,
+                           int32_t o, uint64_t seed, uint32_t step) {
+  NavModel model(m);
+  std::vector<State> P(n);
+  for (int i = 0; i < n; ++i) { P[i].s = 0; P[i].x = px[i]; P[i].y = py[i]; }
+  uint64_t tot = pf_update(model, P, a, o, seed, step,
+      [&](const State& s, uint32_t w) {
+        State r = s;
+        model.move(s.x, s.y, a, w, &r.x, &r.y);
+        return r;
+      },
+      [&](const State& s) { return model.obs_weight(s.x, s.y, o); });
+  for (int i = 0; i < n; ++i) { px[i] = P[i].x; py[i] = P[i].y; }
+  return tot;
 }
 
 }  // extern "C"

@@ -235,6 +235,7 @@ extern "C" int32_t vopp_pomdp_num_actions(const vopp_pomdp* p) { return p ? p->n
 extern "C" void vopp_pomdp_free(vopp_pomdp* p) {
   if (!p) return;
   if (p->own_ws) vopp_workspace_free(p->own_ws);
+  if (p->filt) hipFree(p->filt);
   if (p->arena) hipFree(p->arena);
   delete p;
 }
@@ -719,5 +720,118 @@ extern "C" vopp_status vopp_profile_read(const vopp_workspace* w, double* ms, in
     ms[i] = w->prof_ms[i];
     if (launches) launches[i] = w->prof_count[i];
   }
+  return VOPP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// True environment and belief update (single episode).
+// ---------------------------------------------------------------------------
+namespace {
+
+// Scratch layout: out record | env words | weights | propagated particles.
+vopp_status filter_scratch(vopp_pomdp* p, int n, double** out, int** env,
+                           unsigned long long** w, void** prop) {
+  const size_t need = 4096 + (size_t)n * 8 + (size_t)n * 8 + 512;
+  if (p->filt_bytes < need) {
+    if (p->filt) hipFree(p->filt);
+    p->filt = nullptr;
+    p->filt_bytes = 0;
+    hipError_t e = hipMalloc(&p->filt, need);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(filter scratch)");
+    p->filt_bytes = need;
+  }
+  char* base = (char*)p->filt;
+  *out = (double*)base;
+  *env = (int*)(base + 2048);
+  *w = (unsigned long long*)(base + 4096);
+  *prop = (void*)(base + 4096 + (size_t)n * 8);
+  return VOPP_OK;
+}
+
+PlanView filter_view(const vopp_pomdp* p, double* out, int* env, unsigned long long* w,
+                     void* prop, void* part, int n, uint64_t seed) {
+  PlanView P;
+  std::memset(&P, 0, sizeof(P));
+  P.m = p->view;
+  P.out = out;
+  P.seed_lo = (uint32_t)seed;
+  P.seed_hi = (uint32_t)(seed >> 32);
+  P.f.part = part;
+  P.f.prop = prop;
+  P.f.w = w;
+  P.f.M = n;
+  P.f.env = env;
+  P.f.env_seed_lo = (uint32_t)seed;
+  P.f.env_seed_hi = (uint32_t)(seed >> 32);
+  return P;
+}
+
+}  // namespace
+
+extern "C" vopp_status vopp_env_step(const vopp_pomdp* p, void* state, int32_t action,
+                                     uint64_t env_seed, uint32_t step, void* stream,
+                                     int32_t* obs, float* reward, int32_t* terminal) {
+  clear_error();
+  if (!p || !state) return fail(VOPP_E_INVALID, "null argument");
+  if (action < 0 || action >= p->nA) return fail(VOPP_E_INVALID, "action out of range");
+  vopp_pomdp* mp = const_cast<vopp_pomdp*>(p);
+  double* out;
+  int* env;
+  unsigned long long* w;
+  void* prop;
+  vopp_status st = filter_scratch(mp, 1, &out, &env, &w, &prop);
+  if (st != VOPP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int words = p->kind == kTabular ? 1 : 2;
+  int host_env[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double act = (double)action;
+  hipError_t e = hipMemcpyAsync(env, state, words * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, &act, sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "env step set-up");
+  if (p->kind == kTabular) {
+    int sv = 0;
+    e = hipMemcpy(&sv, env, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && (sv < 0 || sv >= p->view.nS))
+      return fail(VOPP_E_INVALID, "state outside [0, nS)");
+  }
+  PlanView P = filter_view(p, out, env, w, prop, state, 1, env_seed);
+  e = launch_env(P, (int)step, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(state, env, words * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_env, env, sizeof(host_env), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "env step");
+  if (obs) *obs = host_env[2];
+  if (reward) std::memcpy(reward, &host_env[4], 4);
+  if (terminal) *terminal = host_env[5];
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_belief_update(const vopp_pomdp* p, void* particles, int32_t n,
+                                          int32_t action, int32_t obs, uint64_t seed,
+                                          uint32_t step, void* stream,
+                                          uint64_t* total_weight) {
+  clear_error();
+  if (!p || !particles) return fail(VOPP_E_INVALID, "null argument");
+  if (n < 1 || n > (1 << 24)) return fail(VOPP_E_INVALID, "n must be in [1, 2^24]");
+  if (action < 0 || action >= p->nA) return fail(VOPP_E_INVALID, "action out of range");
+  if (obs < 0 || obs >= p->view.nO) return fail(VOPP_E_INVALID, "observation out of range");
+  vopp_pomdp* mp = const_cast<vopp_pomdp*>(p);
+  double* out;
+  int* env;
+  unsigned long long* w;
+  void* prop;
+  vopp_status st = filter_scratch(mp, n, &out, &env, &w, &prop);
+  if (st != VOPP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int host_env[8] = {0, 0, obs, action, 0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(env, host_env, sizeof(host_env), hipMemcpyHostToDevice, s);
+  PlanView P = filter_view(p, out, env, w, prop, particles, n, seed);
+  if (e == hipSuccess) e = launch_pf(P, (int)step, s);
+  unsigned long long tot = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&tot, w + (n - 1), 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "belief update");
+  if (total_weight) *total_weight = tot;
   return VOPP_OK;
 }

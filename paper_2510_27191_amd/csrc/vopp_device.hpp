@@ -111,6 +111,18 @@ __host__ __device__ inline int res_tiles_for(int n_p, int target_tiles) {
 
 constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
 
+// Particle-filter belief and true-environment state of a served episode.
+struct FilterView {
+  void* part;              // M belief particles (the plan's root belief)
+  void* prop;              // M propagated particles, same layout
+  unsigned long long* w;   // [M] integer weights, then their inclusive sums
+  int M;
+  int* env;                // [0] state (tabular) or x bits, [1] y bits,
+                           // [2] last observation, [3] last action,
+                           // [4] last reward bits, [5] terminal flag
+  uint32_t env_seed_lo, env_seed_hi;
+};
+
 struct PlanView {
   ModelView m;
   TreeView t;
@@ -127,6 +139,7 @@ struct PlanView {
   int K, depth, schedule;
   int steps;               // level steps of the plan (sum of D_k)
   double* out;             // kOutStride doubles: the plan's result
+  FilterView f;            // served episodes only
 };
 
 // Result record written by the select phase (doubles): [0] action,
@@ -137,7 +150,9 @@ constexpr int kOutStride = kMaxA + 8;
 // Phase kinds (same numbering as the ABI's VOPP_KERNEL_* kinds).
 enum : int {
   kPhaseExpand = 0, kPhaseResolve = 1, kPhaseFinish = 2, kPhaseLeaf = 3,
-  kPhaseLevel = 4, kPhaseRoot = 5, kPhaseSetup = 6, kPhaseSelect = 7
+  kPhaseLevel = 4, kPhaseRoot = 5, kPhaseSetup = 6, kPhaseSelect = 7,
+  // Served episodes: true-environment step and SIR belief update.
+  kPhaseEnv = 8, kPhasePFWeight = 9, kPhasePFScan = 10, kPhasePFResample = 11
 };
 
 // One phase of one instance inside a batched launch: blocks
@@ -197,17 +212,22 @@ __device__ __forceinline__ int count_le(const uint32_t* __restrict__ thr, int n,
   return c;
 }
 
+// Tabular transition: successor of (s, a) from a 32-bit random word.
+__device__ __forceinline__ int tabular_next(const ModelView& m, int s, int a, uint32_t word) {
+  const int row = s * m.nA + a;
+  const int lo = m.rowptr[row];
+  const int n = m.rowptr[row + 1] - lo;
+  int j = count_le(m.thrT + lo, n, word >> 1);
+  j = j < n ? j : n - 1;
+  return m.col[lo + j];
+}
+
 // Tabular G: successor from word y, observation from word z, R(s, a).
 __device__ __forceinline__ void tabular_step(const ModelView& m, int s, int a,
                                              const U4& x, int& sn, int& obs,
                                              float& r) {
-  const int row = s * m.nA + a;
-  const int lo = m.rowptr[row];
-  const int n = m.rowptr[row + 1] - lo;
-  r = m.R[row];
-  int j = count_le(m.thrT + lo, n, x.y >> 1);
-  j = j < n ? j : n - 1;
-  sn = m.col[lo + j];
+  r = m.R[s * m.nA + a];
+  sn = tabular_next(m, s, a, x.y);
   const uint32_t* zr = m.thrZ + ((size_t)sn * m.nA + a) * m.nO;
   int o = count_le(zr, m.nO, x.z >> 1);
   obs = o < m.nO ? o : m.nO - 1;
@@ -219,24 +239,35 @@ __device__ __forceinline__ int nav_axis(const NavParams& p, float v) {
   return (int)c - p.key_lo;
 }
 
-// Navigation G.  Built without contraction: each operation rounds once.
-__device__ __forceinline__ void nav_step(const ModelView& m, float x, float y,
-                                         int a, const U4& w, float& nx,
-                                         float& ny, int& key, float& r,
-                                         bool& term) {
+// Navigation motion: next position of (x, y) under move a, noise from word y.
+__device__ __forceinline__ void nav_move(const ModelView& m, float x, float y, int a,
+                                         uint32_t word, float& nx, float& ny) {
   const NavParams& p = m.nav;
   float dx = 0.0f, dy = 0.0f;
   if (a == 0) dy = p.step;
   else if (a == 1) dx = p.step;
   else if (a == 2) dy = -p.step;
   else dx = -p.step;
-  const float zx = m.gauss[w.y >> 20];
-  const float zy = m.gauss[(w.y >> 8) & 4095u];
+  const float zx = m.gauss[word >> 20];
+  const float zy = m.gauss[(word >> 8) & 4095u];
   const float mx = x + dx;
   const float my = y + dy;
   nx = fminf(fmaxf(mx + p.sigma_move * zx, p.lo), p.hi);
   ny = fminf(fmaxf(my + p.sigma_move * zy, p.lo), p.hi);
-  const float sd = p.sigma_obs0 + p.sigma_obs_slope * fabsf(nx - p.obs_center_x);
+}
+
+__device__ __forceinline__ float nav_obs_sd(const NavParams& p, float nx) {
+  return p.sigma_obs0 + p.sigma_obs_slope * fabsf(nx - p.obs_center_x);
+}
+
+// Navigation G.  Built without contraction: each operation rounds once.
+__device__ __forceinline__ void nav_step(const ModelView& m, float x, float y,
+                                         int a, const U4& w, float& nx,
+                                         float& ny, int& key, float& r,
+                                         bool& term) {
+  const NavParams& p = m.nav;
+  nav_move(m, x, y, a, w.y, nx, ny);
+  const float sd = nav_obs_sd(p, nx);
   const float ox = nx + sd * m.gauss[w.z >> 20];
   const float oy = ny + sd * m.gauss[(w.z >> 8) & 4095u];
   key = nav_axis(p, ox) * p.key_n + nav_axis(p, oy);

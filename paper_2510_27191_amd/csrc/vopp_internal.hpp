@@ -19,6 +19,9 @@ struct vopp_pomdp {
   size_t bytes = 0;
   vopp::ModelView view{};
   vopp_workspace* own_ws = nullptr;
+  // Scratch of vopp_env_step / vopp_belief_update (grown on demand).
+  void* filt = nullptr;
+  size_t filt_bytes = 0;
 };
 
 namespace vopp {

@@ -710,8 +710,165 @@ __device__ void dev_select(const PlanView& P, int last_step) {
 }
 
 // ---------------------------------------------------------------------------
+// Served episodes: one step of the true environment, then the sequential
+// importance resampling belief update tau(b, a, o) (Alg. 1, belief update).
+// Likelihoods are exact integers, so every side draws the same particles:
+//   tabular: thr_o - thr_{o-1} of the observation row Z(s', a, .);
+//   navigation: the number of 12-bit noise indices per axis whose observation
+//   falls in the observed grid cell (the cell is monotone in the index, so two
+//   binary searches over the 4096-entry table count them), multiplied.
+// Resampling is multinomial: a 64-bit Philox word u per new particle picks
+// the particle whose inclusive weight sum first exceeds (u * total) >> 64.
+// ---------------------------------------------------------------------------
+__device__ void dev_env(const PlanView& P, int t) {
+  if (threadIdx.x != 0) return;
+  const int a = (int)P.out[0];                 // the action the last plan chose
+  const U4 w = philox(0u, kTagEnv << 24, 0u, (uint32_t)t, P.f.env_seed_lo, P.f.env_seed_hi);
+  int* env = P.f.env;
+  int obs;
+  float r;
+  bool term = false;
+  if (P.m.kind == kTabular) {
+    int sn;
+    tabular_step(P.m, env[0], a, w, sn, obs, r);
+    env[0] = sn;
+  } else {
+    float nx, ny;
+    nav_step(P.m, __int_as_float(env[0]), __int_as_float(env[1]), a, w, nx, ny, obs, r,
+             term);
+    env[0] = __float_as_int(nx);
+    env[1] = __float_as_int(ny);
+  }
+  env[2] = obs;
+  env[3] = a;
+  env[4] = __float_as_int(r);
+  env[5] = term ? 1 : 0;
+}
+
+// Number of table indices j whose observation nx + sd*G[j] falls in cell kx.
+__device__ __forceinline__ unsigned nav_cell_count(const ModelView& m, float nx, float sd,
+                                                   int kx) {
+  // first j with cell(j) >= kx, and first j with cell(j) > kx
+  int lo = 0, hi = 4096;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (nav_axis(m.nav, nx + sd * m.gauss[mid]) >= kx) hi = mid; else lo = mid + 1;
+  }
+  const int first = lo;
+  hi = 4096;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (nav_axis(m.nav, nx + sd * m.gauss[mid]) > kx) hi = mid; else lo = mid + 1;
+  }
+  return (unsigned)(lo - first);
+}
+
+__device__ void dev_pf_weight(const PlanView& P, int t, int blk) {
+  const int i = blk * kBlock + threadIdx.x;
+  const int M = P.f.M;
+  if (i >= M) return;
+  const int a = P.f.env[3], o = P.f.env[2];
+  const U4 x = philox((uint32_t)i, kTagPF << 24, 0u, (uint32_t)t, P.seed_lo, P.seed_hi);
+  unsigned long long wt;
+  if (P.m.kind == kTabular) {
+    const int s = ((const int*)P.f.part)[i];
+    const int sn = tabular_next(P.m, s, a, x.y);
+    ((int*)P.f.prop)[i] = sn;
+    const uint32_t* zr = P.m.thrZ + ((size_t)sn * P.m.nA + a) * P.m.nO;
+    wt = (unsigned long long)(zr[o] - (o > 0 ? zr[o - 1] : 0u));
+  } else {
+    const float* pf = (const float*)P.f.part;
+    float nx, ny;
+    nav_move(P.m, pf[i], pf[M + i], a, x.y, nx, ny);
+    float* q = (float*)P.f.prop;
+    q[i] = nx;
+    q[M + i] = ny;
+    const float sd = nav_obs_sd(P.m.nav, nx);
+    const int kn = P.m.nav.key_n;
+    wt = (unsigned long long)nav_cell_count(P.m, nx, sd, o / kn) *
+         (unsigned long long)nav_cell_count(P.m, ny, sd, o % kn);
+  }
+  P.f.w[i] = wt;
+}
+
+// In-place inclusive scan of the M weights by one block.
+__device__ void dev_pf_scan(const PlanView& P, Smem& sm) {
+  const int M = P.f.M;
+  unsigned long long* w = P.f.w;
+  unsigned long long carry = 0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int base = 0; base < M; base += kBlock * 4) {
+    unsigned long long v[4];
+    unsigned long long mine = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + threadIdx.x * 4 + q;
+      v[q] = i < M ? w[i] : 0ull;
+      mine += v[q];
+    }
+    const unsigned long long incl = wave_incl_scan(mine);
+    if (lane == 63) sm.wave[wid] = incl;
+    __syncthreads();
+    unsigned long long off = carry, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+      if (q < wid) off += sm.wave[q];
+      tot += sm.wave[q];
+    }
+    unsigned long long run = off + incl - mine;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + threadIdx.x * 4 + q;
+      run += v[q];
+      if (i < M) w[i] = run;
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__device__ void dev_pf_resample(const PlanView& P, int t, int blk) {
+  const int j = blk * kBlock + threadIdx.x;
+  const int M = P.f.M;
+  if (j >= M) return;
+  const unsigned long long total = P.f.w[M - 1];
+  int src = j;                                   // zero total: keep propagation
+  if (total > 0ull) {
+    const U4 y = philox((uint32_t)j, kTagResample << 24, 0u, (uint32_t)t, P.seed_lo,
+                        P.seed_hi);
+    const unsigned long long u = ((unsigned long long)y.x << 32) | y.y;
+    const unsigned long long target = __umul64hi(u, total);
+    int lo = 0, hi = M - 1;                      // first i with w[i] > target
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.f.w[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    src = lo;
+  }
+  if (P.m.kind == kTabular) {
+    ((int*)P.f.part)[j] = ((const int*)P.f.prop)[src];
+  } else {
+    const float* q = (const float*)P.f.prop;
+    float* pf = (float*)P.f.part;
+    pf[j] = q[src];
+    pf[M + j] = q[M + src];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Single-plan kernels (one launch per phase).
 // ---------------------------------------------------------------------------
+__global__ void k_env(PlanView P, int t) { dev_env(P, t); }
+__global__ __launch_bounds__(kBlock) void k_pf_weight(PlanView P, int t) {
+  dev_pf_weight(P, t, blockIdx.x);
+}
+__global__ __launch_bounds__(kBlock) void k_pf_scan(PlanView P) {
+  __shared__ Smem sm;
+  dev_pf_scan(P, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_pf_resample(PlanView P, int t) {
+  dev_pf_resample(P, t, blockIdx.x);
+}
 __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
   dev_setup(P, blockIdx.x, gridDim.x);
 }
@@ -783,6 +940,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
       break;
     case kPhaseRoot: dev_backup_root(P); break;
     case kPhaseSelect: dev_select(P, it.a0); break;
+    case kPhaseEnv: dev_env(P, it.a0); break;
+    case kPhasePFWeight: dev_pf_weight(P, it.a0, blk); break;
+    case kPhasePFScan: dev_pf_scan(P, sm); break;
+    case kPhasePFResample: dev_pf_resample(P, it.a0, blk); break;
     default: break;
   }
 }
@@ -840,6 +1001,21 @@ hipError_t launch_backup_root(const PlanView& P, hipStream_t s) {
 }
 hipError_t launch_select(const PlanView& P, int last_step, hipStream_t s) {
   hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P, last_step);
+  return hipGetLastError();
+}
+hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_env, dim3(1), dim3(64), 0, s, P, t);
+  return hipGetLastError();
+}
+hipError_t launch_pf(const PlanView& P, int t, hipStream_t s) {
+  const dim3 g(blocks_for(P.f.M)), b(kBlock);
+  hipLaunchKernelGGL(k_pf_weight, g, b, 0, s, P, t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pf_scan, dim3(1), b, 0, s, P);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pf_resample, g, b, 0, s, P, t);
   return hipGetLastError();
 }
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,

@@ -15,6 +15,9 @@ hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipSt
 hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s);
 hipError_t launch_backup_root(const PlanView& P, hipStream_t s);
 hipError_t launch_select(const PlanView& P, int last_step, hipStream_t s);
+hipError_t launch_env(const PlanView& P, int t, hipStream_t s);
+// SIR update of P.f: weight, scan, resample (three launches).
+hipError_t launch_pf(const PlanView& P, int t, hipStream_t s);
 // One batched launch: n_blocks blocks over n_items phase items (device arrays).
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
                         int n_blocks, int amax, hipStream_t s);

@@ -33,6 +33,7 @@ EXPORTS = (
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
     "vopp_batch_num_launches", "vopp_batch_free", "vopp_plan_batch",
+    "vopp_env_step", "vopp_belief_update",
 )
 MAX_ACTIONS = 64
 
@@ -148,6 +149,10 @@ def lib():
     L.vopp_batch_free.restype = None
     L.vopp_plan_batch.argtypes = [vp, i32, vp, vp]
     L.vopp_plan_batch.restype = st
+    L.vopp_env_step.argtypes = [vp, vp, i32, C.c_uint64, C.c_uint32, vp, vp, vp, vp]
+    L.vopp_env_step.restype = st
+    L.vopp_belief_update.argtypes = [vp, vp, i32, i32, i32, C.c_uint64, C.c_uint32, vp, vp]
+    L.vopp_belief_update.restype = st
     _lib = L
     return L
 
@@ -388,3 +393,32 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def env_step(pomdp, state_dev, action, seed, step, stream=None):
+    """vopp_env_step on a device state tensor (int32[1] or float32[2]), in place."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    obs = C.c_int32()
+    r = C.c_float()
+    term = C.c_int32()
+    _check(lib().vopp_env_step(pomdp.handle, C.c_void_p(state_dev.data_ptr()), int(action),
+                               int(seed) & (2 ** 64 - 1), int(step) & 0xFFFFFFFF,
+                               C.c_void_p(stream.cuda_stream), C.byref(obs), C.byref(r),
+                               C.byref(term)))
+    return int(obs.value), float(r.value), int(term.value)
+
+
+def belief_update(pomdp, particles_dev, n, action, obs, seed, step, stream=None):
+    """vopp_belief_update in place on a device particle tensor; returns the
+    integer weight total."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    tot = C.c_uint64()
+    _check(lib().vopp_belief_update(pomdp.handle, C.c_void_p(particles_dev.data_ptr()),
+                                    int(n), int(action), int(obs),
+                                    int(seed) & (2 ** 64 - 1), int(step) & 0xFFFFFFFF,
+                                    C.c_void_p(stream.cuda_stream), C.byref(tot)))
+    return int(tot.value)

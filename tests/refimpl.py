@@ -397,3 +397,59 @@ def fluid_plan(inst, b0, K, depth, eta, schedule=0):
                 node["V"] = lse(node["psi"], eta)
     root = bel[()]
     return root["psi"].copy(), root["V"]
+
+
+# ---------------------------------------------------------------------------
+# Between real steps: true environment and SIR belief update.
+# ---------------------------------------------------------------------------
+
+def env_step(inst, state, a, seed, step):
+    mdl = model_of(inst)
+    w = philox((0, 4 << 24, 0, step), (seed & MASK, (seed >> 32) & MASK))
+    return mdl.step(state, a, w)
+
+
+def nav_cell_count(mdl, v, sd, k):
+    f = np.float32
+    g = mdl.g
+    return sum(1 for j in range(4096) if mdl._axis(f(f(v) + f(f(sd) * g[j]))) == k)
+
+
+def pf_update(inst, particles, a, o, seed, step):
+    """Propagate, weight by the exact integer likelihood, resample
+    multinomially with 64-bit uniforms."""
+    mdl = model_of(inst)
+    key = (seed & MASK, (seed >> 32) & MASK)
+    n = len(particles)
+    moved, cum = [], []
+    total = 0
+    for i in range(n):
+        w = philox((i, 5 << 24, 0, step), key)
+        if inst["kind"] == "tabular":
+            s = int(particles[i])
+            cols, thr, _ = mdl.rows[s * mdl.nA + a]
+            sn = int(cols[pick(thr, w[1])])
+            zt = mdl.zthr[sn][a]
+            wt = int(zt[o]) - (int(zt[o - 1]) if o > 0 else 0)
+            moved.append(sn)
+        else:
+            (nx, ny), _, _, _ = mdl.step(particles[i], a, (0, w[1], 0, 0))
+            f = np.float32
+            p = mdl.p
+            sd = f(f(p["sigma_obs0"]) + f(f(p["sigma_obs_slope"]) *
+                                          abs(f(nx - f(p["obs_center_x"])))))
+            kn = p["key_n"]
+            wt = nav_cell_count(mdl, nx, sd, o // kn) * nav_cell_count(mdl, ny, sd, o % kn)
+            moved.append((nx, ny))
+        total += wt
+        cum.append(total)
+    if total == 0:
+        return moved, 0
+    out = []
+    for j in range(n):
+        y = philox((j, 6 << 24, 0, step), key)
+        u = (y[0] << 32) | y[1]
+        target = (u * total) >> 64
+        i = next(k for k, c in enumerate(cum) if c > target)
+        out.append(moved[i])
+    return out, total
