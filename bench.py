@@ -46,6 +46,26 @@ def expand_bytes_per_step(nA: int, state_bytes: int) -> int:
     return 44 + 2 * state_bytes + 4 * nA + 16 + 12
 
 
+# Measured HBM traffic of the expand kernel per launch (bytes), from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
+# profiles/planning_step_hbm_traffic.md, scaled by a plain-copy calibration
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it
+# was taken on (hash below); otherwise `traffic` is reported as null.
+MEASURED_TRAFFIC = {
+    "sources_sha256_16": "bbf28ea10f164ab7",
+    "expand": {"nav2d": 35.47e6, "sparse4096": 165.76e6},
+}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("vopp_kernels.hip", "vopp_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2510_27191_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q))
 
@@ -268,6 +288,10 @@ def main():
                         bytes_per_unit=bps, unit_of_work="particle-step",
                         avg_launch_us=ms * 1e3 / launches,
                         bytes_per_launch=bps * steps / launches)
+            tr = MEASURED_TRAFFIC["expand"].get(args.workload)
+            if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
+                roof["traffic"] = tr
+                roof["traffic_GBs"] = tr / (ms * 1e-3 / launches) / 1e9
         else:
             roof.update(achieved=None, frac=None,
                         note=f"dominant kernel {dom} has no byte model yet")
