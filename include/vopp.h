@@ -273,6 +273,71 @@ vopp_status vopp_plan_batch(const vopp_request* reqs, int32_t n, void* stream,
                             vopp_result* results);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of episodes' planning steps.                 */
+/* ------------------------------------------------------------------------ */
+
+/* hbm_budget_bytes: admission limit on the summed footprint (workspace and
+ * particle buffers) of the active episodes.  max_active: most episodes
+ * resident at once (<= 4096).  max_inflight: launches queued ahead on the
+ * device (1..8). */
+typedef struct {
+  uint64_t hbm_budget_bytes;
+  int32_t max_active;
+  int32_t max_inflight;
+} vopp_server_config;
+
+/* One episode: a model, its initial belief particles (HOST array, n_particles
+ * of them, in vopp_plan's belief layout), the planner settings of every step,
+ * the true initial state (HOST: tabular int32[1]; navigation fp32[2]), the
+ * environment's seed and the number of real steps.  Every step plans with
+ * params (step index t as the Philox counter word), executes the chosen
+ * action in the simulated environment and updates the belief particles with
+ * vopp_belief_update's filter -- all on the device.  Models need |A| <= 16. */
+typedef struct {
+  const vopp_pomdp* pomdp;
+  const void* init_particles;
+  int32_t n_particles;
+  int32_t budget;
+  int32_t depth;
+  vopp_params params;
+  const void* true_state;
+  uint64_t env_seed;
+  int32_t n_steps;
+} vopp_episode_desc;
+
+/* A finished planning request (one real step of one episode).  Times are
+ * seconds on the server's steady clock: arrival = when the request was
+ * issued (episode submission for step 0, completion of the previous step
+ * otherwise), done = when the server saw its result. */
+typedef struct {
+  int32_t episode;
+  int32_t step;
+  int32_t action;
+  int32_t status;
+  double v_root;
+  int64_t particle_steps;
+  double arrival_s;
+  double done_s;
+} vopp_served;
+
+typedef struct vopp_server vopp_server;
+
+vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_server** out);
+/* Queue an episode for admission; its id is returned in *episode. */
+vopp_status vopp_server_submit(vopp_server* s, const vopp_episode_desc* ep, int32_t* episode);
+/* Admit what fits, issue at most one batched launch that advances every
+ * active request by one phase, and collect finished requests.  *pending
+ * (may be NULL) = queued + active episodes after the call. */
+vopp_status vopp_server_tick(vopp_server* s, int32_t* pending);
+/* Move up to max finished requests into out; returns how many. */
+int32_t vopp_server_poll(vopp_server* s, vopp_served* out, int32_t max);
+/* Current true state (host out, as in vopp_episode_desc) and step of an
+ * episode that is active or finished. */
+vopp_status vopp_server_episode_state(vopp_server* s, int32_t episode, void* true_state,
+                                      int32_t* steps_done);
+void vopp_server_free(vopp_server* s);
+
+/* ------------------------------------------------------------------------ */
 /* Per-kernel timing (HIP events on the plan's stream).                      */
 /* ------------------------------------------------------------------------ */
 

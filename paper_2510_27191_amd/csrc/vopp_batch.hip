@@ -43,14 +43,9 @@ struct vopp_batch {
   hipGraphExec_t exec = nullptr;
 };
 
-namespace {
+namespace vopp {
 
-// Phase list of one plan, in execution order.
-struct Phase {
-  int kind, a0, a1, nblk;
-};
-
-std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, const vopp_tuning& tu) {
+std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int backup_cap) {
   std::vector<Phase> ph;
   const int K = P.K;
   std::vector<int> D(K + 1, 0);
@@ -66,14 +61,18 @@ std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, const vop
       ++t;
     }
     ph.push_back({kPhaseFinish, 0, 0, eblocks});
-    ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D, D[k], k, tu.backup_cap)});
+    ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D, D[k], k, backup_cap)});
     for (int dep = D[k]; dep >= 2; --dep)
-      ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, tu.backup_cap)});
+      ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, backup_cap)});
     ph.push_back({kPhaseRoot, 0, 0, 1});
   }
   ph.push_back({kPhaseSelect, t, 0, 1});
   return ph;
 }
+
+}  // namespace vopp
+
+namespace {
 
 void release_graph(vopp_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
@@ -94,7 +93,7 @@ vopp_status build_schedule(vopp_batch* b) {
                            r.depth, &r.params, b->tuning.res_target_tiles);
     P.out = b->out_dev + (size_t)i * kOutStride;
     b->views[i] = P;
-    phases[i] = plan_phases(r.pomdp, P, b->tuning);
+    phases[i] = plan_phases(r.pomdp, P, b->tuning.backup_cap);
     longest = std::max(longest, phases[i].size());
   }
   b->items.clear();

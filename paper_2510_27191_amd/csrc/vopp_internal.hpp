@@ -61,6 +61,14 @@ struct vopp_workspace {
 };
 
 namespace vopp {
+// One phase of one plan or served request, in execution order.
+struct Phase {
+  int kind, a0, a1, nblk;
+};
+// The planning phases of a plan (set-up ... select) for the launch shapes
+// given by res tiling already stored in P and the backup block cap.
+std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int backup_cap);
+
 vopp_status fail(vopp_status st, const char* fmt, ...);
 vopp_status hip_fail(hipError_t e, const char* what);
 void clear_error();

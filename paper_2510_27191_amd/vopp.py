@@ -33,7 +33,9 @@ EXPORTS = (
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
     "vopp_batch_num_launches", "vopp_batch_free", "vopp_plan_batch",
-    "vopp_env_step", "vopp_belief_update",
+    "vopp_env_step", "vopp_belief_update", "vopp_server_create",
+    "vopp_server_submit", "vopp_server_tick", "vopp_server_poll",
+    "vopp_server_episode_state", "vopp_server_free",
 )
 MAX_ACTIONS = 64
 
@@ -90,6 +92,25 @@ class vopp_result(C.Structure):
 
 class vopp_tuning(C.Structure):
     _fields_ = [("res_target_tiles", C.c_int32), ("backup_cap", C.c_int32)]
+
+
+class vopp_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_active", C.c_int32),
+                ("max_inflight", C.c_int32)]
+
+
+class vopp_episode_desc(C.Structure):
+    _fields_ = [("pomdp", C.c_void_p), ("init_particles", C.c_void_p),
+                ("n_particles", C.c_int32), ("budget", C.c_int32), ("depth", C.c_int32),
+                ("params", vopp_params), ("true_state", C.c_void_p),
+                ("env_seed", C.c_uint64), ("n_steps", C.c_int32)]
+
+
+class vopp_served(C.Structure):
+    _fields_ = [("episode", C.c_int32), ("step", C.c_int32), ("action", C.c_int32),
+                ("status", C.c_int32), ("v_root", C.c_double),
+                ("particle_steps", C.c_int64), ("arrival_s", C.c_double),
+                ("done_s", C.c_double)]
 
 
 _lib = None
@@ -153,6 +174,18 @@ def lib():
     L.vopp_env_step.restype = st
     L.vopp_belief_update.argtypes = [vp, vp, i32, i32, i32, C.c_uint64, C.c_uint32, vp, vp]
     L.vopp_belief_update.restype = st
+    L.vopp_server_create.argtypes = [C.POINTER(vopp_server_config), C.POINTER(vp)]
+    L.vopp_server_create.restype = st
+    L.vopp_server_submit.argtypes = [vp, C.POINTER(vopp_episode_desc), C.POINTER(i32)]
+    L.vopp_server_submit.restype = st
+    L.vopp_server_tick.argtypes = [vp, C.POINTER(i32)]
+    L.vopp_server_tick.restype = st
+    L.vopp_server_poll.argtypes = [vp, vp, i32]
+    L.vopp_server_poll.restype = i32
+    L.vopp_server_episode_state.argtypes = [vp, i32, vp, C.POINTER(i32)]
+    L.vopp_server_episode_state.restype = st
+    L.vopp_server_free.argtypes = [vp]
+    L.vopp_server_free.restype = None
     _lib = L
     return L
 
@@ -422,3 +455,79 @@ def belief_update(pomdp, particles_dev, n, action, obs, seed, step, stream=None)
                                     int(seed) & (2 ** 64 - 1), int(step) & 0xFFFFFFFF,
                                     C.c_void_p(stream.cuda_stream), C.byref(tot)))
     return int(tot.value)
+
+
+def particles_host(inst, belief):
+    """Host array in vopp_plan's belief layout (tabular int32; nav x then y)."""
+    if inst["kind"] == "tabular":
+        return _arr(belief, np.int32)
+    return np.concatenate([_arr(belief[0], np.float32), _arr(belief[1], np.float32)])
+
+
+class Server:
+    """vopp_server: continuous batching of many episodes' planning steps."""
+
+    def __init__(self, hbm_budget_bytes=64 << 30, max_active=256, max_inflight=3):
+        h = C.c_void_p()
+        cfg = vopp_server_config(int(hbm_budget_bytes), int(max_active), int(max_inflight))
+        _check(lib().vopp_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.kinds = {}
+
+    def submit(self, pomdp, particles, budget, depth, prm, true_state, env_seed, n_steps):
+        """particles: host array from particles_host(); true_state: int or (x, y)."""
+        parts = np.ascontiguousarray(particles)
+        n = parts.size if pomdp.kind == "tabular" else parts.size // 2
+        st = (np.array([true_state], np.int32) if pomdp.kind == "tabular"
+              else np.array(true_state, np.float32))
+        d = vopp_episode_desc(pomdp.handle.value, _p(parts), int(n), int(budget), int(depth),
+                              prm, _p(st), int(env_seed) & (2 ** 64 - 1), int(n_steps))
+        eid = C.c_int32()
+        _check(lib().vopp_server_submit(self.handle, C.byref(d), C.byref(eid)))
+        self.kinds[eid.value] = pomdp.kind
+        return int(eid.value)
+
+    def tick(self):
+        pending = C.c_int32()
+        _check(lib().vopp_server_tick(self.handle, C.byref(pending)))
+        return int(pending.value)
+
+    def poll(self, max_n=4096):
+        arr = (vopp_served * max_n)()
+        n = lib().vopp_server_poll(self.handle, C.cast(arr, C.c_void_p), max_n)
+        return [dict(episode=a.episode, step=a.step, action=a.action, status=a.status,
+                     v_root=a.v_root, particle_steps=a.particle_steps,
+                     arrival_s=a.arrival_s, done_s=a.done_s) for a in arr[:n]]
+
+    def episode_state(self, eid):
+        buf = np.zeros(2, np.int32)
+        steps = C.c_int32()
+        _check(lib().vopp_server_episode_state(self.handle, int(eid), _p(buf), C.byref(steps)))
+        if self.kinds.get(eid) == "tabular":
+            return int(buf[0]), int(steps.value)
+        f = buf.view(np.float32)
+        return (float(f[0]), float(f[1])), int(steps.value)
+
+    def run_until_idle(self, timeout_s=120.0):
+        import time
+        out = []
+        t0 = time.time()
+        while True:
+            pending = self.tick()
+            out += self.poll()
+            if pending == 0:
+                break
+            if time.time() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().vopp_server_free(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
