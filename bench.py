@@ -158,6 +158,130 @@ def bench_batch(V, I, reps=3, autotune=True):
     return out
 
 
+def serve_trace(seed, qps, seconds, steps_per_episode):
+    """Poisson episode starts at rate qps / steps (each episode then issues
+    its requests back to back, so the offered load is about qps requests/s)."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    rate = qps / steps_per_episode
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            return out
+        out.append(t)
+
+
+def bench_serve(V, I, qps_list=(250, 1000, 2500), seconds=5.0, steps_per_episode=50,
+                deadline_ms=50.0, plain_max_qps=1000):
+    """Continuous-batching server vs plain one-request-at-a-time planning on
+    the same arrival trace of episodes drawn from the 256-instance mix."""
+    import torch
+    mix = I.batch_mix(0)
+    poms = [V.Pomdp.from_instance(inst) for inst, _, _ in mix]
+
+    def episode(j):
+        inst, bel, p = mix[j % len(mix)]
+        n_p = p["n_particles"]
+        if inst["kind"] == "tabular":
+            parts = (np.arange(n_p) % inst["nS"]).astype(np.int32)
+            state = int((j * 7919) % inst["nS"])
+            host = parts
+        else:
+            x, y = I.nav_belief(p["seed"] + j, n_p)
+            host = np.concatenate([x, y])
+            state = (1.0, 1.0)
+        return dict(pom=poms[j % len(mix)], host=host, n_p=n_p, budget=p["budget"],
+                    depth=p["depth"], seed=p["seed"] + 1000003 * j, env_seed=j + 1,
+                    state=state, kind=inst["kind"])
+
+    def stats(lat, steps, wall):
+        lat = np.asarray(lat)
+        return {"requests": int(lat.size), "p50_ms": percentile(lat, 50),
+                "p99_ms": percentile(lat, 99),
+                "deadline_miss_frac": float((lat > deadline_ms).mean()) if lat.size else None,
+                "particle_steps_per_s": steps / wall}
+
+    results = []
+    for qps in qps_list:
+        starts = serve_trace(17, qps, seconds, steps_per_episode)
+        eps = [episode(j) for j in range(len(starts))]
+        # Served: continuous batching.
+        srv = V.Server(hbm_budget_bytes=64 << 30, max_active=512, max_inflight=3)
+        lat, steps = [], 0
+        t0 = time.perf_counter()
+        nxt = 0
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(starts) and starts[nxt] <= now:
+                e = eps[nxt]
+                srv.submit(e["pom"], e["host"], e["budget"], e["depth"],
+                           V.params(e["n_p"], seed=e["seed"]), e["state"], e["env_seed"],
+                           steps_per_episode)
+                nxt += 1
+            pending = srv.tick()
+            for r in srv.poll():
+                lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
+                steps += r["particle_steps"]
+            if pending == 0 and nxt >= len(starts):
+                break
+            if pending == 0:
+                time.sleep(max(0.0, min(starts[nxt] - (time.perf_counter() - t0), 0.01)))
+        served = stats(lat, steps, time.perf_counter() - t0)
+        srv.close()
+        if qps > plain_max_qps:
+            # The plain path saturates below this load (its queue only grows),
+            # so it is not run here.
+            results.append({"offered_qps": qps, "episodes": len(starts),
+                            "served_continuous_batching": served,
+                            "plain_one_at_a_time": None})
+            continue
+        # Plain: one request at a time (plan, then environment step and belief
+        # update), first come first served over the same trace.
+        import heapq
+        t0 = time.perf_counter()
+        heap = [(starts[j], j, 0) for j in range(len(starts))]
+        heapq.heapify(heap)
+        dev = {}
+        lat, steps = [], 0
+        while heap:
+            arr, j, t = heapq.heappop(heap)
+            now = time.perf_counter() - t0
+            if arr > now:
+                time.sleep(arr - now)
+            e = eps[j]
+            if j not in dev:
+                parts = torch.as_tensor(e["host"], device="cuda")
+                st = (torch.tensor([e["state"]], dtype=torch.int32, device="cuda")
+                      if e["kind"] == "tabular" else
+                      torch.tensor(e["state"], dtype=torch.float32, device="cuda"))
+                dev[j] = (parts, st)
+            parts, st = dev[j]
+            if t > 0:
+                obs, _, _ = V.env_step(e["pom"], st, e["last"], e["env_seed"], t - 1)
+                V.belief_update(e["pom"], parts, e["n_p"], e["last"], obs, e["seed"], t - 1)
+            r = V.plan(e["pom"], parts, e["n_p"], e["budget"], e["depth"],
+                       V.params(e["n_p"], seed=e["seed"], step=t))
+            e["last"] = r.action
+            done = time.perf_counter() - t0
+            lat.append((done - arr) * 1e3)
+            steps += r.particle_steps
+            if t + 1 < steps_per_episode:
+                heapq.heappush(heap, (done, j, t + 1))
+            else:
+                del dev[j]
+        plain = stats(lat, steps, time.perf_counter() - t0)
+        results.append({"offered_qps": qps, "episodes": len(starts),
+                        "served_continuous_batching": served,
+                        "plain_one_at_a_time": plain})
+    for p in poms:
+        p.close()
+    return {"workload": f"episodes drawn from the 256-instance mix, {steps_per_episode} "
+                        f"steps each, Poisson episode starts for {seconds:.0f} s, belief "
+                        "particles and trees resident, 64 GiB HBM admission budget, "
+                        f"{deadline_ms:.0f} ms per-step deadline",
+            "sweep": results}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +294,9 @@ def main():
                     help="skip the per-kernel event brackets in the timed region")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-instance batched vs plain comparison")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served (continuous batching) vs plain comparison")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to "
                          "calibrate HBM traffic counters, then exit")
@@ -300,6 +427,8 @@ def main():
     pom.close()
     if not args.no_batch:
         out["batched_vs_plain"] = bench_batch(V, I)
+    if not args.no_serve:
+        out["served_vs_plain"] = bench_serve(V, I, seconds=args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, bel, p)
     print(json.dumps(out), flush=True)
