@@ -32,28 +32,51 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per unit of work, per kernel kind.  Counted once per field
-# the kernel must touch in HBM-resident tree or episode arrays (model tables
-# are cache resident and not counted).  See the kernel table in the design doc.
-#   expand: per particle-step, levels >= 1:
-#     close the previous level: aslot 4 + child slot 4 + N atomic 8 + C atomic 16
-#       + hslot 4 + belief index 4 + reward 4                      = 44
-#     state read + write                                         = 2*state
-#     preference row                                             = 4*|A|
-#     child-table probe 4, hash key 8, hash value 4              = 16
-#     reward, aslot, hslot writes                                = 12
-def expand_bytes_per_step(nA: int, state_bytes: int) -> int:
-    return 44 + 2 * state_bytes + 4 * nA + 16 + 12
+# Algorithmic bytes of each kernel kind over one plan: every field the kernel
+# must touch in HBM-resident tree or trace arrays, counted once (model tables
+# are cache resident and not counted).  ra = |A| rounded up to a multiple of
+# 4; a belief record holds 24*ra + 32 used bytes.  The kernel table of
+# the design doc derives each term.
+#   forward, per particle-step: preference row 4|A| + table probe 8 + trace
+#     word and value 12; per new belief: key insert 8 + record 24*ra + 32;
+#     per episode and iteration: leaf trace 12.
+#   accumulate, per trace item: 12 read; per particle-step: N 8 + C 16
+#     (atomic read + write); per leaf (bounded by n_p per iteration): 24;
+#     per new belief: list entry 4.
+#   backup_level, per belief of the swept depth: record 24*ra + 32 read, row
+#     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16,
+#     list entry 4.
+#   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
+#     written, push 16, list entry 4.
+def plan_bytes(nA, n_p, K, depth, counts, particle_steps):
+    ra = (nA + 3) // 4 * 4
+    rec = 24 * ra + 32
+    D = [min(k, depth) for k in range(1, K + 1)]
+    t0 = np.concatenate([[0], np.cumsum(D)[:-1]]).astype(int)
+    new_b = int(np.sum(counts))
+
+    def beliefs_at(k, dep):       # beliefs of depth dep after iteration k (1-based)
+        return sum(int(counts[t0[kk] + dep - 1]) for kk in range(k) if D[kk] >= dep)
+
+    level = sum(beliefs_at(k, dep - 1) for k in range(1, K + 1)
+                for dep in range(2, D[k - 1] + 1))
+    leaf = sum(beliefs_at(k, D[k - 1]) for k in range(1, K + 1))
+    return {
+        "forward": particle_steps * (4 * nA + 8 + 12) + new_b * (8 + rec) + K * n_p * 12,
+        "accumulate": sum((d + 1) * n_p * 12 for d in D) + particle_steps * 24
+                      + K * n_p * 24 + new_b * 4,
+        "backup_level": level * (rec + 4 * ra + 8 + 8 * nA + 16 + 4),
+        "backup_leaf": leaf * (32 + 24 + 16 + 4),
+    }
 
 
-# Measured HBM traffic of the expand kernel per launch (bytes), from the
+# Measured HBM traffic of the dominant kernel per launch (bytes), from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
 # profiles/planning_step_hbm_traffic.md, scaled by a plain-copy calibration
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it
 # was taken on (hash below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "bbf28ea10f164ab7",
-    "expand": {"nav2d": 35.47e6, "sparse4096": 165.76e6},
+    "sources_sha256_16": None,
 }
 
 
@@ -150,7 +173,7 @@ def bench_batch(V, I, reps=3, autotune=True):
                           "launches": batch.num_launches},
         "speedup": min(plain_s) / min(batch_s),
         "results_identical_to_plain": bool(identical),
-        "tuning": {"res_target_tiles": tuning[0], "backup_cap": tuning[1]} if tuning else None,
+        "tuning": {"accum_cap": tuning[0], "backup_cap": tuning[1]} if tuning else None,
     }
     batch.close()
     for it in items:
@@ -406,22 +429,24 @@ def main():
         out["kernel_share_warmup"] = warm_share
         roof = {"kernel": dom, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "traffic": None}
-        if dom == "expand":
-            sb = 4 if inst["kind"] == "tabular" else 8
-            bps = expand_bytes_per_step(pom.nA, sb)
-            ms, launches = kinds["expand"]
-            achieved = bps * steps / (ms * 1e-3) / 1e9
+        model = plan_bytes(pom.nA, n_p, K, depth, V.level_counts(ws), r.particle_steps)
+        if dom in model:
+            ms, launches = kinds[dom]
+            per_plan_ms = ms / args.steps
+            achieved = model[dom] / (per_plan_ms * 1e-3) / 1e9
             roof.update(achieved=achieved, frac=achieved / HBM_PEAK_GBS,
-                        bytes_per_unit=bps, unit_of_work="particle-step",
+                        launches_per_plan=launches // args.steps,
                         avg_launch_us=ms * 1e3 / launches,
-                        bytes_per_launch=bps * steps / launches)
-            tr = MEASURED_TRAFFIC["expand"].get(args.workload)
+                        bytes_per_launch=model[dom] * args.steps / launches,
+                        bytes_per_plan=model[dom],
+                        byte_model="algorithmic bytes of the last timed plan's tree")
+            tr = MEASURED_TRAFFIC.get(dom, {}).get(args.workload)
             if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
                 roof["traffic"] = tr
                 roof["traffic_GBs"] = tr / (ms * 1e-3 / launches) / 1e9
         else:
             roof.update(achieved=None, frac=None,
-                        note=f"dominant kernel {dom} has no byte model yet")
+                        note=f"dominant kernel {dom} has no byte model")
         out["roofline"] = roof
     ws.close()
     pom.close()

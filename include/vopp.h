@@ -62,7 +62,7 @@ typedef struct vopp_pomdp vopp_pomdp;
  *     summing to 1 within 1e-5.
  *   zprob [nS*nA*nO]: observation rows Z(s', a, .) indexed [s'][a][o].
  *   reward [nS*nA]: R(s, a).   heur [nS] or NULL: leaf value heuristic.
- * Limits: 1 <= nA <= 64, 1 <= nO <= 2^24, 1 <= nS < 2^31, 0 < gamma < 1.
+ * Limits: 1 <= nA <= 64, 1 <= nO <= 2^20, 1 <= nS < 2^31, 0 < gamma < 1.
  * Sampling uses integer thresholds rint(cum/total * 2^31) per row. */
 typedef struct {
   int32_t nS, nA, nO;
@@ -80,7 +80,8 @@ typedef struct {
  * actions 0..3 move by +y, +x, -y, -x of length `step` with N(0, sigma_move^2)
  * noise per axis; observation = next position + N(0, sd^2) noise per axis with
  * sd = sigma_obs0 + sigma_obs_slope*|x' - obs_center_x|, keyed by its grid
- * cell floor(v*inv_bin) clamped to [key_lo, key_lo+key_n-1] per axis; reward
+ * cell floor(v*inv_bin) clamped to [key_lo, key_lo+key_n-1] per axis
+ * (1 <= key_n <= 1024, key = cell_x * key_n + cell_y); reward
  * r_step, plus r_goal inside the goal disk (terminal), plus r_hit inside any
  * obstacle disk.  Noise comes from `gauss`, a host table of 4096 standard
  * normal quantiles indexed by 12 random bits.  disks [2*n_disks] holds the
@@ -125,13 +126,17 @@ typedef struct {
 
 typedef struct {
   int64_t particle_steps;   /* generative-model calls made by the plan     */
-  int64_t n_beliefs;        /* rows of the belief table (root included)    */
-  int64_t n_actions;        /* rows of the action-node table               */
+  int64_t n_beliefs;        /* beliefs of the tree (root included)         */
+  int64_t n_actions;        /* action nodes (b, a) visited at least once   */
   double device_ms;         /* device time of the plan, HIP events          */
 } vopp_stats;
 
-/* A workspace holds one plan's tree and per-episode arrays in HBM, sized for
- * the worst case (beliefs <= 1 + n_p * sum_k D_k), so no plan can overflow it. */
+/* A workspace holds one plan's tree and per-episode trace in HBM, sized for
+ * the worst case (beliefs <= 1 + n_p * sum_k D_k <= 2^28), so no plan can
+ * overflow it.  Each belief owns a record of 24*ra + 32 bytes rounded up to a
+ * multiple of 128 (ra = |A| rounded up to a multiple of 4), addressed by its
+ * slot in an open-addressing table of 2^ceil(log2(2*(1 + n_p*sum_k D_k)))
+ * slots (load <= 1/2). */
 typedef struct vopp_workspace vopp_workspace;
 
 /* Bytes of device memory a workspace for (pomdp, params, budget, depth) needs. */
@@ -168,11 +173,22 @@ vopp_status vopp_plan(const vopp_pomdp* pomdp, const void* belief_particles,
  * action row (-1 for the root), observation key (-1 for the root), depth,
  * value V, visit count N_b; psi [n_beliefs*nA] (fp32; row 0 is the root,
  * whose double values are in vopp_plan's `values`).  Action arrays
- * [n_actions]: parent belief row, action, cumulative reward C, visits N. */
+ * [n_actions]: parent belief row, action, cumulative reward C, visits N.
+ * Rows are in canonical order, which depends only on the tree: beliefs by
+ * depth, then by (parent belief row, action, observation key); action nodes
+ * by (parent belief row, action).  The root is belief row 0.  The dump
+ * allocates temporary device memory and synchronizes the device. */
 vopp_status vopp_tree_dump(vopp_workspace* ws, int32_t* b_parent, int32_t* b_obs,
                            int32_t* b_depth, float* psi, float* b_V,
                            int32_t* b_N, int32_t* a_parent, int32_t* a_act,
                            double* a_C, int32_t* a_N);
+
+/* Beliefs created by each level step of the last plan run in `ws`.  Level
+ * step t = D_1 + ... + D_{k-1} + d is level d of iteration k; it creates
+ * beliefs of depth d + 1.  counts (host, out, may be NULL) receives the first
+ * min(cap, n_steps) counts; n_steps (host, out) the number of level steps. */
+vopp_status vopp_level_counts(const vopp_workspace* ws, int32_t* counts, int32_t cap,
+                              int32_t* n_steps);
 
 /* ------------------------------------------------------------------------ */
 /* Between real steps: the true environment and the belief update.          */
@@ -231,11 +247,11 @@ typedef struct {
   double values[VOPP_MAX_ACTIONS];
 } vopp_result;
 
-/* Launch-shape knobs of a batch.  res_target_tiles: resolve tiles per level
- * step that a plan aims at (the episodes per thread follow from it, 1..8);
- * backup_cap: most blocks of one backup sweep of one instance. */
+/* Launch-shape knobs of a batch.  accum_cap: most blocks of one instance's
+ * accumulate sweep (the sweep loops over the trace when capped); backup_cap:
+ * most blocks of one backup sweep of one instance. */
 typedef struct {
-  int32_t res_target_tiles;
+  int32_t accum_cap;
   int32_t backup_cap;
 } vopp_tuning;
 
@@ -343,15 +359,14 @@ void vopp_server_free(vopp_server* s);
 
 /* Kernel kinds of a plan, in the order of vopp_profile_read's arrays. */
 enum {
-  VOPP_KERNEL_EXPAND = 0,       /* draw, G, claims: one launch per level     */
-  VOPP_KERNEL_RESOLVE = 1,      /* first-visitor numbering: one per level    */
-  VOPP_KERNEL_FINISH = 2,       /* deepest level closed, leaves accumulated  */
-  VOPP_KERNEL_BACKUP_LEAF = 3,  /* leaf values (Alg. 3, leaves)              */
-  VOPP_KERNEL_BACKUP_LEVEL = 4, /* one depth of the backup (Alg. 3 loop)     */
-  VOPP_KERNEL_BACKUP_ROOT = 5,  /* root backup in double precision           */
-  VOPP_KERNEL_SETUP = 6,        /* table clearing and root initialisation    */
-  VOPP_KERNEL_SELECT = 7,       /* argmax of the root preferences            */
-  VOPP_KERNEL_KINDS = 8
+  VOPP_KERNEL_FORWARD = 0,      /* all levels of one iteration's search      */
+  VOPP_KERNEL_ACCUMULATE = 1,   /* trace -> action nodes, leaves, lists      */
+  VOPP_KERNEL_BACKUP_LEAF = 2,  /* leaf values (Alg. 3, leaves)              */
+  VOPP_KERNEL_BACKUP_LEVEL = 3, /* one depth of the backup (Alg. 3 loop)     */
+  VOPP_KERNEL_BACKUP_ROOT = 4,  /* root backup in double precision           */
+  VOPP_KERNEL_SETUP = 5,        /* table clearing and root initialisation    */
+  VOPP_KERNEL_SELECT = 6,       /* argmax of the root preferences            */
+  VOPP_KERNEL_KINDS = 7
 };
 
 /* kind_mask != 0: every later vopp_plan in `ws` brackets each launch of the

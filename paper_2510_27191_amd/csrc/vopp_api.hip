@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/vopp.h"
@@ -95,7 +96,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   clear_error();
   if (!d || !out) return fail(VOPP_E_INVALID, "null argument");
   *out = nullptr;
-  if (d->nS < 1 || d->nA < 1 || d->nA > kMaxA || d->nO < 1 || d->nO > (1 << 24))
+  if (d->nS < 1 || d->nA < 1 || d->nA > kMaxA || d->nO < 1 || d->nO > kMaxObs)
     return fail(VOPP_E_INVALID, "sizes out of range (nS=%d nA=%d nO=%d)", d->nS, d->nA, d->nO);
   if (!(d->gamma > 0.0 && d->gamma < 1.0)) return fail(VOPP_E_INVALID, "gamma must be in (0,1)");
   if (!d->rowptr || !d->col || !d->tprob || !d->zprob || !d->reward)
@@ -186,7 +187,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   if (!d->gauss) return fail(VOPP_E_INVALID, "null Gaussian table");
   if (d->n_disks < 0 || d->n_disks > 4096 || (d->n_disks > 0 && !d->disks))
     return fail(VOPP_E_INVALID, "bad obstacle list");
-  if (!(d->hi > d->lo) || d->key_n < 1 || d->key_n > 4096 || !(d->inv_bin > 0.0f))
+  if (!(d->hi > d->lo) || d->key_n < 1 || d->key_n > 1024 || !(d->inv_bin > 0.0f))
     return fail(VOPP_E_INVALID, "bad navigation geometry");
   for (int i = 0; i < 4096; ++i)
     if (!std::isfinite(d->gauss[i])) return fail(VOPP_E_INVALID, "non-finite Gaussian table");
@@ -256,38 +257,34 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) 
   z.n_p = n_p;
   z.steps = sum_depths(K, depth, schedule);
   z.K = K;
+  z.depth = depth;
   z.Apad = p->view.Apad;
+  z.rs = rec_bytes(z.Apad);
   z.cap_b = 1 + (long long)n_p * z.steps;
-  z.cap_a = (long long)n_p * z.steps;
   uint64_t h = 1024;
   while (h < 2 * (uint64_t)z.cap_b) h <<= 1;
   z.hcap = h;
-  // Largest resolve tile count of any plan with n_p or fewer episodes at any
-  // tiling (one episode per thread gives the most tiles).
-  z.res_tiles = (n_p + kBlock - 1) / kBlock;
   return z;
 }
 
 size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
   auto add = [&](size_t n) { b += align_up(n, 256); };
-  const size_t cb = (size_t)z.cap_b, ca = (size_t)z.cap_a;
-  add(cb * 4); add(cb * 4); add(cb * z.Apad * 4); add(cb * z.Apad * 4);
-  add(cb * 4); add(cb * 4); add(cb * 4); add(cb * 8); add(cb * 4);
-  add(ca * 4); add(ca * 4); add(ca * 8); add(ca * 4); add(ca * 8);
-  add(kMaxA * 8); add(8);
-  add(z.hcap * 8); add(z.hcap * 4);
-  add((z.steps + 1) * 4); add((z.steps + 1) * 4);
-  add((size_t)z.steps * z.res_tiles * 8); add((size_t)z.steps * 4);
+  add((z.hcap + 1) * (size_t)z.rs);                  // belief records
+  add(z.hcap * 8);                                   // table keys
+  add(kMaxA * 8); add(8);                            // root row, V(root)
+  add((size_t)z.steps * z.n_p * 4);                  // level-step lists
+  add((size_t)z.steps * 4); add((size_t)z.steps * 4);
   add(64); add((z.K + 1) * 4);
-  add((size_t)z.n_p * 4 * 6);
+  add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
+  add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
   add(256 * 8);
   return b + 4096;
 }
 
 bool fits(const WsSizes& have, const WsSizes& need) {
   return have.n_p >= need.n_p && have.cap_b >= need.cap_b && have.steps >= need.steps &&
-         have.K >= need.K && have.Apad >= need.Apad && have.res_tiles >= need.res_tiles &&
+         have.K >= need.K && have.Apad >= need.Apad && have.depth >= need.depth &&
          have.hcap >= need.hcap;
 }
 
@@ -303,43 +300,23 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
                 hipGetErrorString(e));
   }
   Carver c(w->arena);
-  const size_t cb = (size_t)z.cap_b, ca = (size_t)z.cap_a;
   TreeView& t = w->tree;
-  t.b_parent = c.take<int>(cb);
-  t.b_obs = c.take<int>(cb);
-  t.psi = c.take<float>(cb * z.Apad);
-  t.b_child = c.take<int>(cb * z.Apad);
-  t.b_V = c.take<float>(cb);
-  t.b_N = c.take<int>(cb);
-  t.leaf_cnt = c.take<int>(cb);
-  t.leaf_h = c.take<unsigned long long>(cb);
-  t.b_hslot = c.take<int>(cb);
-  t.a_parent = c.take<int>(ca);
-  t.a_act = c.take<int>(ca);
-  t.a_C = c.take<unsigned long long>(ca);
-  t.a_N = c.take<int>(ca);
-  t.a_W = c.take<unsigned long long>(ca);
+  t.rec = c.take<unsigned char>((z.hcap + 1) * (size_t)z.rs);
+  t.rs = z.rs;
+  t.ra = z.Apad;
+  t.h_key = c.take<unsigned long long>(z.hcap);
+  t.h_mask = (uint32_t)(z.hcap - 1);
   t.psi_root = c.take<double>(kMaxA);
   t.v_root = c.take<double>(1);
-  t.h_key = c.take<unsigned long long>(z.hcap);
-  t.h_val = c.take<int>(z.hcap);
-  t.h_mask = (uint32_t)(z.hcap - 1);
-  t.bel_base = c.take<int>(z.steps + 1);
-  t.act_base = c.take<int>(z.steps + 1);
-  t.lookback = c.take<unsigned long long>((size_t)z.steps * z.res_tiles);
-  t.tickets = c.take<int>(z.steps);
+  t.list = c.take<int>((size_t)z.steps * z.n_p);
+  t.cnt = c.take<int>(z.steps);
+  t.cnt_prev = c.take<int>(z.steps);
   t.counters = c.take<unsigned long long>(8);
   int* step_base = c.take<int>(z.K + 1);
   t.step_base = step_base;
   w->step_base_dev = step_base;
-  t.res_tiles = z.res_tiles;
-  EpisodeView& ev = w->ep;
-  ev.s_i = c.take<int>(z.n_p);
-  ev.s_x = c.take<float>(z.n_p);
-  ev.s_y = c.take<float>(z.n_p);
-  ev.aslot = c.take<int>(z.n_p);
-  ev.hslot = c.take<int>(z.n_p);
-  ev.r = c.take<float>(z.n_p);
+  t.tr_key = c.take<unsigned long long>((size_t)(z.depth + 1) * z.n_p);
+  t.tr_val = c.take<float>((size_t)(z.depth + 1) * z.n_p);
   w->out_dev = c.take<double>(256);
   e = hipHostMalloc((void**)&w->out_host, 256 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess)
@@ -381,8 +358,8 @@ vopp_status check_params(const vopp_pomdp* p, const vopp_params* prm, int32_t bu
   if (prm->schedule != VOPP_SCHEDULE_DEEPEN && prm->schedule != VOPP_SCHEDULE_FIXED)
     return fail(VOPP_E_INVALID, "unknown schedule");
   const long long steps = sum_depths(budget, depth, prm->schedule);
-  if ((long long)prm->n_particles * steps + 1 > (1ll << 30))
-    return fail(VOPP_E_INVALID, "n_particles * sum of depths exceeds 2^30 nodes");
+  if ((long long)prm->n_particles * steps + 1 > kMaxBeliefs)
+    return fail(VOPP_E_INVALID, "n_particles * sum of depths exceeds 2^28 beliefs");
   return VOPP_OK;
 }
 
@@ -432,15 +409,11 @@ static int fixed_shift(const vopp_pomdp* p, int n_p, int K) {
 }
 
 PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
-                   int n_belief, int K, int depth, const vopp_params* prm,
-                   int res_target) {
+                   int n_belief, int K, int depth, const vopp_params* prm) {
   PlanView P;
   std::memset(&P, 0, sizeof(P));
   P.m = p->view;
   P.t = w->tree;
-  P.t.res_items = res_items_for(prm->n_particles, res_target);
-  P.t.res_tiles = res_tiles_for(prm->n_particles, res_target);
-  P.e = w->ep;
   P.e.belief = belief;
   P.e.n_belief = n_belief;
   P.n_p = prm->n_particles;
@@ -510,13 +483,11 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   w->hash_dirty = true;   // until the plan has finished
   int t = 0;
   for (int k = 1; k <= K; ++k) {
-    for (int d = 0; d < D[k]; ++d) {
-      VOPP_TIMED(VOPP_KERNEL_EXPAND, launch_expand(P, k, d, s));
-      VOPP_TIMED(VOPP_KERNEL_RESOLVE, launch_resolve(P, t, s));
-      if (e != hipSuccess) return hip_fail(e, "forward-search launch");
-      ++t;
-    }
-    VOPP_TIMED(VOPP_KERNEL_FINISH, launch_finish(P, s));
+    VOPP_TIMED(VOPP_KERNEL_FORWARD, launch_forward(P, k, D[k], s));
+    VOPP_TIMED(VOPP_KERNEL_ACCUMULATE,
+               launch_accum(P, D[k], t, accum_blocks(P, D[k], kAccumCap), s));
+    if (e != hipSuccess) return hip_fail(e, "forward-search launch");
+    t += D[k];
     VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
                launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k, kBackupCap), s));
     for (int dep = D[k]; dep >= 2; --dep)
@@ -525,7 +496,7 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, s));
     if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
-  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, t, s));
+  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, s));
 #undef VOPP_TIMED
   if (e != hipSuccess) return hip_fail(e, "select launch");
   *n_steps_out = t;
@@ -604,7 +575,7 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   }
   if (ws->z.Apad < p->view.Apad) return fail(VOPP_E_INVALID, "workspace built for fewer actions");
   hipStream_t s = (hipStream_t)stream;
-  PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm, kResTargetTiles);
+  PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm);
   hipError_t e = hipEventRecord(ws->ev0, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   int steps = 0;
@@ -620,8 +591,9 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   const double* o = ws->out_host;
   ws->n_prev_beliefs = (int)o[A + 3];
   ws->hash_dirty = false;
-  if (o[A + 5] != 0.0)
-    return fail(VOPP_E_INVALID, "a belief particle holds a state outside [0, nS)");
+  const int flags = (int)o[A + 5];
+  if (flags & 1) return fail(VOPP_E_INVALID, "a belief particle holds a state outside [0, nS)");
+  if (flags & 2) return fail(VOPP_E_INTERNAL, "belief table overflow");
   *action = (int32_t)o[0];
   if (values) for (int j = 0; j < A; ++j) values[j] = o[1 + j];
   if (v_root) *v_root = o[A + 1];
@@ -654,46 +626,131 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   clear_error();
   if (!w) return fail(VOPP_E_INVALID, "null workspace");
   if (w->n_prev_beliefs <= 0) return fail(VOPP_E_INVALID, "no plan has run in this workspace");
-  const size_t nb = (size_t)w->n_prev_beliefs, na = (size_t)w->n_prev_actions;
-  const int A = w->last_A, Apad = w->last_apad;
+  const int A = w->last_A, ra = w->tree.ra, rs = w->tree.rs;
+  const int steps = w->last_steps, n_p = w->last_n_p;
   hipError_t e = hipDeviceSynchronize();
   auto cp = [&](void* dst, const void* src, size_t bytes) {
-    if (e == hipSuccess && dst && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
   };
-  cp(b_parent, w->tree.b_parent, nb * 4);
-  cp(b_obs, w->tree.b_obs, nb * 4);
-  cp(b_V, w->tree.b_V, nb * 4);
-  cp(b_N, w->tree.b_N, nb * 4);
-  cp(a_parent, w->tree.a_parent, na * 4);
-  cp(a_act, w->tree.a_act, na * 4);
-  cp(a_N, w->tree.a_N, na * 4);
-  if (psi) {
-    std::vector<float> tmp(nb * Apad);
-    cp(tmp.data(), w->tree.psi, nb * Apad * 4);
-    for (size_t b = 0; b < nb; ++b)
-      for (int j = 0; j < A; ++j) psi[b * A + j] = tmp[b * Apad + j];
-  }
-  if (a_C) {
-    std::vector<long long> tmp(na);
-    cp(tmp.data(), w->tree.a_C, na * 8);
-    const double inv = w->last_fix_inv64;
-    for (size_t i = 0; i < na; ++i) a_C[i] = (double)tmp[i] * inv;
-  }
-  if (b_depth) {
-    // Depth of each belief from the level-step ranges: level d makes depth d+1.
-    std::vector<int> base(w->last_steps + 1);
-    cp(base.data(), w->tree.bel_base, base.size() * 4);
-    std::vector<int> level_of_step;
+  // Beliefs with their depth: the root, then each level step's list (level d
+  // creates depth d + 1).
+  std::vector<int> cnt(steps);
+  cp(cnt.data(), w->tree.cnt, cnt.size() * 4);
+  std::vector<int> ids{0}, depth{0};
+  {
+    int t = 0;
     for (int k = 1; k <= w->last_K; ++k) {
       const int D = w->last_schedule == VOPP_SCHEDULE_FIXED ? w->last_depth
                                                            : std::min(k, w->last_depth);
-      for (int d = 0; d < D; ++d) level_of_step.push_back(d);
+      for (int d = 0; d < D; ++d, ++t) {
+        const size_t at = ids.size();
+        ids.resize(at + cnt[t]);
+        cp(ids.data() + at, w->tree.list + (size_t)t * n_p, (size_t)cnt[t] * 4);
+        depth.resize(ids.size(), d + 1);
+      }
     }
-    b_depth[0] = 0;
-    for (size_t t = 0; t < level_of_step.size(); ++t)
-      for (int b = base[t]; b < base[t + 1]; ++b) b_depth[b] = level_of_step[t] + 1;
   }
   if (e != hipSuccess) return hip_fail(e, "tree dump");
+  const size_t nb = ids.size();
+  if ((long long)nb != w->n_prev_beliefs)
+    return fail(VOPP_E_INTERNAL, "tree dump: %zu listed beliefs, %d counted", nb,
+                w->n_prev_beliefs);
+  // Gather the records on the device, then copy them.
+  std::vector<unsigned char> rec(nb * (size_t)rs);
+  int* ids_dev = nullptr;
+  unsigned char* rec_dev = nullptr;
+  e = hipMalloc(&ids_dev, nb * 4);
+  if (e == hipSuccess) e = hipMalloc(&rec_dev, nb * (size_t)rs);
+  if (e == hipSuccess) e = hipMemcpy(ids_dev, ids.data(), nb * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_gather(w->tree, ids_dev, (int)nb, rec_dev, nullptr);
+  cp(rec.data(), rec_dev, nb * (size_t)rs);
+  if (ids_dev) hipFree(ids_dev);
+  if (rec_dev) hipFree(rec_dev);
+  if (e != hipSuccess) return hip_fail(e, "tree dump");
+  auto meta = [&](size_t i) {
+    return reinterpret_cast<const RecMeta*>(rec.data() + i * rs + 24 * ra);
+  };
+  auto nrow = [&](size_t i) { return reinterpret_cast<const int*>(rec.data() + i * rs + 4 * ra); };
+  auto crow = [&](size_t i) {
+    return reinterpret_cast<const long long*>(rec.data() + i * rs + 8 * ra);
+  };
+  auto prow = [&](size_t i) { return reinterpret_cast<const float*>(rec.data() + i * rs); };
+  // Canonical order: by depth, then (parent's position, action, observation);
+  // action nodes by (parent's position, action).  It depends only on the
+  // tree, not on the order in which episodes inserted it.
+  int max_id = 0;
+  for (int id : ids) max_id = std::max(max_id, id);
+  std::vector<int> pos_of(max_id + 1, -1);
+  std::vector<size_t> order(nb);
+  for (size_t i = 0; i < nb; ++i) order[i] = i;
+  pos_of[0] = 0;
+  size_t lo = 1;
+  for (int d = 1; lo < nb; ++d) {
+    // Lists are per level step, so one depth is spread over several of them.
+    std::vector<size_t> grp;
+    for (size_t i = 0; i < nb; ++i)
+      if (depth[i] == d) grp.push_back(i);
+    auto key = [&](size_t i) {
+      const unsigned long long par = meta(i)->parent;
+      return std::make_tuple(pos_of[(int)(par >> 6)], (int)(par & 63ull), meta(i)->obs);
+    };
+    std::sort(grp.begin(), grp.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
+    for (size_t j = 0; j < grp.size(); ++j) {
+      order[lo + j] = grp[j];
+      pos_of[ids[grp[j]]] = (int)(lo + j);
+    }
+    lo += grp.size();
+    if (grp.empty()) return fail(VOPP_E_INTERNAL, "tree dump: depth %d is empty", d);
+  }
+  std::vector<int> act_of(nb * (size_t)A, -1);
+  size_t na = 0;
+  for (size_t q = 0; q < nb; ++q) {
+    const size_t i = order[q];
+    for (int a = 0; a < A; ++a) {
+      const int n = nrow(i)[a];
+      if (n <= 0) continue;
+      act_of[q * A + a] = (int)na;
+      if (a_parent) a_parent[na] = (int32_t)q;
+      if (a_act) a_act[na] = a;
+      if (a_N) a_N[na] = n;
+      if (a_C) a_C[na] = (double)crow(i)[a] * w->last_fix_inv64;
+      ++na;
+    }
+  }
+  if ((long long)na != w->n_prev_actions)
+    return fail(VOPP_E_INTERNAL, "tree dump: %zu action nodes, %d counted", na,
+                w->n_prev_actions);
+  for (size_t q = 0; q < nb; ++q) {
+    const size_t i = order[q];
+    const RecMeta* m = meta(i);
+    int par = -1;
+    if (q > 0) {
+      const int pq = pos_of[(int)(m->parent >> 6)];
+      par = act_of[(size_t)pq * A + (int)(m->parent & 63ull)];
+    }
+    if (b_parent) b_parent[q] = par;
+    if (b_obs) b_obs[q] = q > 0 ? m->obs : -1;
+    if (b_depth) b_depth[q] = depth[i];
+    if (b_V) b_V[q] = m->V;
+    if (b_N) b_N[q] = m->Nb;
+    if (psi)
+      for (int j = 0; j < A; ++j) psi[q * A + j] = prow(i)[j];
+  }
+  return VOPP_OK;
+}
+
+extern "C" vopp_status vopp_level_counts(const vopp_workspace* w, int32_t* counts, int32_t cap,
+                                         int32_t* n_steps) {
+  clear_error();
+  if (!w || !n_steps) return fail(VOPP_E_INVALID, "null argument");
+  if (w->n_prev_beliefs <= 0) return fail(VOPP_E_INVALID, "no plan has run in this workspace");
+  *n_steps = w->last_steps;
+  const int n = std::min(cap, w->last_steps);
+  if (counts && n > 0) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(counts, w->tree.cnt, (size_t)n * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "level counts");
+  }
   return VOPP_OK;
 }
 

@@ -2,8 +2,8 @@
 // together, one phase per launch, the launch sequence captured in a hipGraph.
 //
 // Each instance's plan is a fixed list of phases (set-up; per iteration the
-// expand/resolve pair of every level, finish, the leaf sweep, one sweep per
-// depth, the root; finally select).  Launch g of the batch runs the g-th
+// forward search, the accumulate sweep, the leaf sweep, one sweep per depth,
+// the root; finally select).  Launch g of the batch runs the g-th
 // phase of every instance that still has one: the launch's blocks are split
 // into BatchItems, each block serving one phase of one instance.  Instances
 // share no state, so each result is the same as that of a plain vopp_plan
@@ -36,7 +36,7 @@ struct vopp_batch {
   double* out_dev = nullptr;
   double* out_host = nullptr;            // pinned
   int amax = 4;
-  vopp_tuning tuning{kResTargetTiles, kBackupCap};
+  vopp_tuning tuning{kAccumCap, kBackupCap};
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr;
   hipGraph_t graph = nullptr;
@@ -45,28 +45,25 @@ struct vopp_batch {
 
 namespace vopp {
 
-std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int backup_cap) {
+std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int accum_cap,
+                               int backup_cap) {
   std::vector<Phase> ph;
   const int K = P.K;
   std::vector<int> D(K + 1, 0);
   for (int k = 1; k <= K; ++k)
     D[k] = P.schedule == VOPP_SCHEDULE_FIXED ? P.depth : std::min(k, P.depth);
-  const int eblocks = (P.n_p + kBlock - 1) / kBlock;
   ph.push_back({kPhaseSetup, 0, 0, setup_blocks(P)});
   int t = 0;
   for (int k = 1; k <= K; ++k) {
-    for (int d = 0; d < D[k]; ++d) {
-      ph.push_back({kPhaseExpand, k, d, eblocks});
-      ph.push_back({kPhaseResolve, t, 0, P.t.res_tiles});
-      ++t;
-    }
-    ph.push_back({kPhaseFinish, 0, 0, eblocks});
+    ph.push_back({kPhaseForward, k, D[k], forward_blocks(P)});
+    ph.push_back({kPhaseAccum, D[k], t, accum_blocks(P, D[k], accum_cap)});
+    t += D[k];
     ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D, D[k], k, backup_cap)});
     for (int dep = D[k]; dep >= 2; --dep)
       ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, backup_cap)});
     ph.push_back({kPhaseRoot, 0, 0, 1});
   }
-  ph.push_back({kPhaseSelect, t, 0, 1});
+  ph.push_back({kPhaseSelect, 0, 0, 1});
   return ph;
 }
 
@@ -90,10 +87,10 @@ vopp_status build_schedule(vopp_batch* b) {
   for (int i = 0; i < n; ++i) {
     const vopp_request& r = b->reqs[i];
     PlanView P = make_view(r.pomdp, b->ws[i], r.belief_particles, r.n_belief, r.budget,
-                           r.depth, &r.params, b->tuning.res_target_tiles);
+                           r.depth, &r.params);
     P.out = b->out_dev + (size_t)i * kOutStride;
     b->views[i] = P;
-    phases[i] = plan_phases(r.pomdp, P, b->tuning.backup_cap);
+    phases[i] = plan_phases(r.pomdp, P, b->tuning.accum_cap, b->tuning.backup_cap);
     longest = std::max(longest, phases[i].size());
   }
   b->items.clear();
@@ -166,7 +163,8 @@ void parse_results(const vopp_batch* b, vopp_result* res) {
     r.particle_steps = (int64_t)o[A + 2];
     r.n_beliefs = (int64_t)o[A + 3];
     r.n_actions = (int64_t)o[A + 4];
-    r.status = o[A + 5] != 0.0 ? VOPP_E_INVALID : VOPP_OK;
+    const int flags = (int)o[A + 5];
+    r.status = (flags & 2) ? VOPP_E_INTERNAL : (flags & 1) ? VOPP_E_INVALID : VOPP_OK;
   }
 }
 
@@ -220,7 +218,7 @@ extern "C" vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
       return fail(VOPP_E_INVALID, "request %d: batched plans support |A| <= 16", i);
     amax = std::max(amax, r.pomdp->view.Apad);
   }
-  if (tuning && (tuning->res_target_tiles < 1 || tuning->backup_cap < 1))
+  if (tuning && (tuning->accum_cap < 1 || tuning->backup_cap < 1))
     return fail(VOPP_E_INVALID, "bad tuning");
   vopp_batch* b = new vopp_batch();
   b->n = n;
@@ -323,7 +321,9 @@ extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_g
   }
   parse_results(b, results);
   for (int i = 0; i < b->n; ++i)
-    if (results[i].status != VOPP_OK)
+    if (results[i].status == VOPP_E_INTERNAL)
+      return fail(VOPP_E_INTERNAL, "request %d: belief table overflow", i);
+    else if (results[i].status != VOPP_OK)
       return fail(VOPP_E_INVALID, "request %d: a belief particle holds a state outside [0, nS)", i);
   return VOPP_OK;
 }
@@ -337,15 +337,15 @@ extern "C" vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t 
   clear_error();
   if (!b) return fail(VOPP_E_INVALID, "null batch");
   if (reps < 1) reps = 1;
-  const int res_cands[] = {64, 256, 1024};
+  const int acc_cands[] = {256, 1024, 4096};
   const int cap_cands[] = {256, 1024, 4096};
   std::vector<vopp_result> ref(b->n), cur(b->n);
   bool have_ref = false;
   double best_ms = 1e30;
   vopp_tuning best = b->tuning;
-  for (int rc : res_cands) {
+  for (int rc : acc_cands) {
     for (int cc : cap_cands) {
-      b->tuning.res_target_tiles = rc;
+      b->tuning.accum_cap = rc;
       b->tuning.backup_cap = cc;
       vopp_status st = build_schedule(b);
       if (st == VOPP_OK) st = capture(b);

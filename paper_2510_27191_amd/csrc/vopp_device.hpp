@@ -12,15 +12,29 @@
 namespace vopp {
 
 constexpr int kBlock = 256;                 // threads per block (4 wavefronts)
-constexpr int kResItemsMax = 8;             // episodes per thread in resolve (max)
-constexpr int kResTargetTiles = 256;        // resolve tiles per launch (about)
 constexpr int kMaxA = 64;
 constexpr int kMaxBudget = 256;             // iterations per plan
 constexpr int kMaxRanges = kMaxBudget;
-constexpr int32_t kClaimBase = INT32_MIN;   // claim value = kClaimBase + episode
-constexpr int32_t kWinBit = 1 << 30;        // flags the claim winner's hash slot
-constexpr int32_t kSlotMask = kWinBit - 1;
 constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Belief keys of the open-addressing table (AppendBeliefs):
+//   bits  0..19  observation key      bits 20..25  action
+//   bits 26..55  parent belief id     bits 56..63  iteration that inserted it
+// A belief's id is its table slot + 1 (the root is id 0), so every episode
+// that reaches a belief knows its id as soon as its probe ends, without
+// waiting for a numbering pass.  The iteration stamp tells whether the
+// belief's record was written by an earlier kernel (then its preference row
+// may be read) or is being created by this one (then the row is psi0).
+constexpr int kObsBits = 20;
+constexpr int kMaxObs = 1 << kObsBits;
+constexpr int kStampShift = 56;
+constexpr unsigned long long kStampMask = 0xFFull << kStampShift;
+constexpr long long kMaxBeliefs = 1ll << 28;   // ids stay below 2^29 + 1
+
+// Trace words written by the forward kernel, one per (level, episode):
+//   level d < D: (belief id << 6) | action;  leaf (d = D): belief id;
+//   kTraceNew: this episode inserted that belief;  kEmptyKey: no step.
+constexpr unsigned long long kTraceNew = 1ull << 61;
 
 enum : uint32_t { kTagRoot = 1, kTagStep = 2, kTagEnv = 4, kTagPF = 5, kTagResample = 6 };
 enum : int { kTabular = 0, kNav = 1 };
@@ -51,65 +65,74 @@ struct ModelView {
   double gamma64;
 };
 
-// The tree store in HBM (structure of arrays).  Beliefs and action nodes are
-// numbered in creation order; the root is belief 0, whose preference row is
-// kept in double precision in psi_root.
-struct TreeView {
-  int* b_parent;           // parent action node
-  int* b_obs;              // observation key
-  float* psi;              // [cap_b * Apad] preferences
-  int* b_child;            // [cap_b * Apad] action node per action, -1 none
-  float* b_V;              // value L_eta Psi (internal) or mean heuristic (leaf)
-  int* b_N;                // visit count
-  int* leaf_cnt;           // this iteration's leaf visits (0 between iterations)
-  unsigned long long* leaf_h;   // this iteration's heuristic sum (fixed point)
-  int* b_hslot;            // hash slot that maps to the belief
-  int* a_parent;           // parent belief
-  int* a_act;              // action
-  unsigned long long* a_C; // cumulative reward (fixed point, two's complement)
-  int* a_N;                // visit count
-  unsigned long long* a_W; // sum over child beliefs of V*N_b (fixed point)
-  double* psi_root;        // [nA]
-  double* v_root;          // [1]
-  unsigned long long* h_key;   // open-addressing table (belief, action, obs)
-  int* h_val;                  // -> belief, -1 free, < -1 claim
-  uint32_t h_mask;
-  int* bel_base;           // [max_steps+1] beliefs before each level step
-  int* act_base;           // [max_steps+1] action nodes before each step
-  unsigned long long* lookback;  // [max_steps * res_tiles] scan state
-  int* tickets;            // [max_steps] dynamic tile counters
-  unsigned long long* counters;  // [0] particle steps [1] input errors
-                                 // [2] beliefs of the last plan [3] table dirty
-  const int* step_base;    // [K+1] first level step of each iteration
-  int res_tiles;           // resolve tiles of this plan
-  int res_items;           // episodes per thread in resolve (1..kResItemsMax)
+// Tail of a belief record.
+struct RecMeta {
+  float V;                   // L_eta Psi (internal) or mean heuristic (leaf)
+  int Nb;                    // visit count N_b
+  int leaf_cnt;              // this iteration's leaf visits (0 between iterations)
+  int obs;                   // observation key (-1 for the root)
+  unsigned long long leaf_h; // this iteration's heuristic sum (fixed point)
+  unsigned long long parent; // (parent id << 6) | action; ~0 for the root
 };
 
-// Per-episode arrays, indexed by episode id (length n_p).
+// The tree store in HBM.  Each belief owns one record of rs bytes (a multiple
+// of the 128-byte cache line), addressed by its id; with ra = |A| rounded up
+// to a multiple of 4 the record holds
+//   Psi[ra] f32 | N[ra] i32 | C[ra] i64 | W[ra] i64 | RecMeta
+// where N, C (cumulative reward) and W (sum of V*N_b over the child beliefs)
+// are the action nodes (b, a) of tensor A, stored with their parent belief.
+// C, W and the leaf sums are 64-bit two's-complement fixed point.  The root
+// (id 0) keeps its preference row in double precision in psi_root.
+struct TreeView {
+  unsigned char* rec;            // [(h_mask + 2) * rs]
+  int rs, ra;
+  unsigned long long* h_key;     // [h_mask + 1] open-addressing table
+  uint32_t h_mask;
+  double* psi_root;              // [nA]
+  double* v_root;                // [1]
+  int* list;                     // [steps * n_p]: ids created by each level step
+  int* cnt;                      // [steps] lengths of this plan's lists
+  int* cnt_prev;                 // [steps] lengths of the previous plan's lists
+  unsigned long long* counters;  // [0] particle steps [1] input errors
+                                 // [2] beliefs of the last plan [3] table dirty
+                                 // [4] action nodes [5] last plan's level steps
+                                 // [6] last plan's list stride
+  const int* step_base;          // [K+1] first level step of each iteration
+  unsigned long long* tr_key;    // [(depth + 1) * n_p] trace words
+  float* tr_val;                 // reward (levels) or heuristic (leaf)
+};
+
+__host__ __device__ inline int rec_bytes(int ra) {
+  const int used = 24 * ra + (int)sizeof(RecMeta);
+  return (used + 127) / 128 * 128;
+}
+__device__ __forceinline__ unsigned char* rec_at(const TreeView& t, int id) {
+  return t.rec + (size_t)id * (size_t)t.rs;
+}
+__device__ __forceinline__ float* rec_psi(const TreeView& t, int id) {
+  return reinterpret_cast<float*>(rec_at(t, id));
+}
+__device__ __forceinline__ int* rec_n(const TreeView& t, int id) {
+  return reinterpret_cast<int*>(rec_at(t, id) + 4 * t.ra);
+}
+__device__ __forceinline__ unsigned long long* rec_c(const TreeView& t, int id) {
+  return reinterpret_cast<unsigned long long*>(rec_at(t, id) + 8 * t.ra);
+}
+__device__ __forceinline__ unsigned long long* rec_w(const TreeView& t, int id) {
+  return reinterpret_cast<unsigned long long*>(rec_at(t, id) + 16 * t.ra);
+}
+__device__ __forceinline__ RecMeta* rec_meta(const TreeView& t, int id) {
+  return reinterpret_cast<RecMeta*>(rec_at(t, id) + 24 * t.ra);
+}
+
+// The root belief of a plan.
 struct EpisodeView {
-  int* s_i;                // tabular state
-  float* s_x;              // navigation state
-  float* s_y;
-  int* aslot;              // belief*Apad + action, -1 when not running
-  int* hslot;              // hash slot (| kWinBit for the creator), -1 if terminal
-  float* r;                // reward of the last step
   const void* belief;      // root belief particles
   int n_belief;
 };
 
-// Resolve tiling: enough episodes per thread that a launch has about
-// kResTargetTiles tiles (short look-back chains), at most kResItemsMax.
-__host__ __device__ inline int res_items_for(int n_p, int target_tiles) {
-  const long long per = (long long)kBlock * target_tiles;
-  int items = (int)((n_p + per - 1) / per);
-  return items < 1 ? 1 : (items > kResItemsMax ? kResItemsMax : items);
-}
-__host__ __device__ inline int res_tiles_for(int n_p, int target_tiles) {
-  const int tile = kBlock * res_items_for(n_p, target_tiles);
-  return (n_p + tile - 1) / tile;
-}
-
 constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
+constexpr int kAccumCap = 4096;             // default block cap of the accumulate sweep
 
 // Particle-filter belief and true-environment state of a served episode.
 struct FilterView {
@@ -149,10 +172,10 @@ constexpr int kOutStride = kMaxA + 8;
 
 // Phase kinds (same numbering as the ABI's VOPP_KERNEL_* kinds).
 enum : int {
-  kPhaseExpand = 0, kPhaseResolve = 1, kPhaseFinish = 2, kPhaseLeaf = 3,
-  kPhaseLevel = 4, kPhaseRoot = 5, kPhaseSetup = 6, kPhaseSelect = 7,
+  kPhaseForward = 0, kPhaseAccum = 1, kPhaseLeaf = 2, kPhaseLevel = 3,
+  kPhaseRoot = 4, kPhaseSetup = 5, kPhaseSelect = 6,
   // Served episodes: true-environment step and SIR belief update.
-  kPhaseEnv = 8, kPhasePFWeight = 9, kPhasePFScan = 10, kPhasePFResample = 11
+  kPhaseEnv = 7, kPhasePFWeight = 8, kPhasePFScan = 9, kPhasePFResample = 10
 };
 
 // One phase of one instance inside a batched launch: blocks
@@ -290,20 +313,11 @@ __device__ __forceinline__ float nav_heuristic(const NavParams& p, float x, floa
   return -(fabsf(x - p.goal_x) + fabsf(y - p.goal_y));
 }
 
-// Softmax draw of Eq. (6) in single precision: weights exp(eta (psi_j - max)),
-// running sums P_j, t = u * P_last, first j with t < P_j.  AM >= A is a
-// compile-time bound so the row stays in registers.
+// Softmax draw of Eq. (6) in single precision over a row held in registers:
+// weights exp(eta (psi_j - max)), running sums P_j, t = u * P_last, first j
+// with t < P_j.  AM >= A is a compile-time bound so the row stays in registers.
 template <int AM>
-__device__ __forceinline__ int draw_action32(const float* __restrict__ row, int A,
-                                             float eta, uint32_t x0) {
-  float v[AM];
-#pragma unroll
-  for (int j = 0; j < AM; j += 4) {
-    // Rows are padded to a multiple of 4, so j < A keeps the load in the row.
-    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (j < A) q = *reinterpret_cast<const float4*>(row + j);
-    v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
-  }
+__device__ __forceinline__ int draw_row32(float (&v)[AM], int A, float eta, uint32_t x0) {
   float m = v[0];
 #pragma unroll
   for (int j = 1; j < AM; ++j)
@@ -325,6 +339,29 @@ __device__ __forceinline__ int draw_action32(const float* __restrict__ row, int 
     }
   }
   return a;
+}
+
+// The same draw from a preference row in memory (padded to a multiple of 4).
+template <int AM>
+__device__ __forceinline__ int draw_action32(const float* __restrict__ row, int A,
+                                             float eta, uint32_t x0) {
+  float v[AM];
+#pragma unroll
+  for (int j = 0; j < AM; j += 4) {
+    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j < A) q = *reinterpret_cast<const float4*>(row + j);
+    v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
+  }
+  return draw_row32<AM>(v, A, eta, x0);
+}
+
+// The draw from a row that still holds its initial value psi0 everywhere.
+template <int AM>
+__device__ __forceinline__ int draw_initial32(float psi0, int A, float eta, uint32_t x0) {
+  float v[AM];
+#pragma unroll
+  for (int j = 0; j < AM; ++j) v[j] = psi0;
+  return draw_row32<AM>(v, A, eta, x0);
 }
 
 // The same draw in double precision (root row).

@@ -26,8 +26,8 @@ struct vopp_pomdp {
 
 namespace vopp {
 struct WsSizes {
-  int n_p = 0, steps = 0, K = 0, Apad = 0, res_tiles = 0;
-  long long cap_b = 0, cap_a = 0;
+  int n_p = 0, steps = 0, K = 0, depth = 0, Apad = 0, rs = 0;
+  long long cap_b = 0;
   uint64_t hcap = 0;
 };
 }  // namespace vopp
@@ -38,7 +38,6 @@ struct vopp_workspace {
   void* arena = nullptr;
   size_t bytes = 0;
   vopp::TreeView tree{};
-  vopp::EpisodeView ep{};
   int* step_base_dev = nullptr;
   int* step_host = nullptr;       // pinned
   double* out_dev = nullptr;
@@ -65,9 +64,10 @@ namespace vopp {
 struct Phase {
   int kind, a0, a1, nblk;
 };
-// The planning phases of a plan (set-up ... select) for the launch shapes
-// given by res tiling already stored in P and the backup block cap.
-std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int backup_cap);
+// The planning phases of a plan (set-up ... select) for the given block caps
+// of the accumulate and backup sweeps.
+std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int accum_cap,
+                               int backup_cap);
 
 vopp_status fail(vopp_status st, const char* fmt, ...);
 vopp_status hip_fail(hipError_t e, const char* what);
@@ -79,8 +79,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out);
 vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_params* prm,
                       int K, int depth);
 PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
-                   int n_belief, int K, int depth, const vopp_params* prm,
-                   int res_target);
+                   int n_belief, int K, int depth, const vopp_params* prm);
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
                 int cap);
 WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule);

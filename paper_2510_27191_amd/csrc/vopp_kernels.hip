@@ -1,28 +1,27 @@
 // vopp_kernels.hip -- HIP kernels of one VOPP planning step for gfx950.
 //
-// One level of the vectorized forward search (Alg. 2) is two phases:
+// One iteration of Alg. 1 is a short, fixed sequence of phases:
 //
-//   expand   one thread per episode: close the previous level (visit count and
-//            reward sum of the action node, parent of a new belief), draw the
-//            action from the softmax of the belief's preferences (Eq. 6), call
-//            G, and claim the (belief, action) slot of the dense child table
-//            and the (belief, action, observation) slot of the open-addressing
-//            table with atomicMin(kClaimBase + episode).
-//   resolve  the smallest claiming episode of each new pair is its creator;
-//            creators are ranked in episode order by a single-pass
-//            decoupled look-back scan (dynamic tile tickets), which numbers new
-//            action nodes and beliefs in first-visitor order, initialises
-//            their rows and publishes the indices in the tables.
-//
-// After the deepest level, `finish` closes it and accumulates this
-// iteration's leaf visits and heuristic sums.  The backup of Alg. 3 is one
-// phase per depth over every belief of that depth in the tree: leaves take
-// their mean heuristic, internal beliefs update their preference row with
-// Q = C/N + gamma W and V = L_eta Psi, and each belief pushes V*N_b into its
-// parent action's W accumulator.  The root level runs in double precision.
+//   forward     one thread per episode runs every level of the vectorized
+//               forward search (Alg. 2) with its state in registers: draw the
+//               action from the softmax of the belief's preferences (Eq. 6),
+//               call G, and find or insert the child belief (belief, action,
+//               observation) in the open-addressing table.  A belief's id is
+//               its table slot, so no episode ever waits for another, and one
+//               launch covers all D_k levels.  Each step goes to a trace.
+//   accumulate  folds the trace into the tree: visit counts and reward sums of
+//               the action nodes (AppendActions), this iteration's leaf visits
+//               and heuristic sums, and the new beliefs into per-level-step
+//               lists (AppendBeliefs) that the backup sweeps.
+//   backup      Alg. 3, one phase per depth over every belief of that depth:
+//               leaves take their mean heuristic, internal beliefs update their
+//               preference row with Q = C/N + gamma W and V = L_eta Psi, and
+//               each belief pushes V*N_b into its parent action's W
+//               accumulator.  The root runs in double precision.
 //
 // All cross-episode sums (rewards, heuristics, V*N_b) are 64-bit fixed-point
-// integer atomics, so the results do not depend on thread order.
+// integer atomics, so the results do not depend on thread order; the tree's
+// ids depend on the order of insertions, its content does not.
 //
 // Every phase is a __device__ function of (plan view, block index within the
 // phase, block count of the phase).  The single-plan path launches one kernel
@@ -37,25 +36,40 @@
 namespace vopp {
 
 // ---------------------------------------------------------------------------
-// Open-addressing table: find or insert the key, return its slot.
+// Open-addressing table (linear probing, load <= 1/2).  Finds or inserts key;
+// the inserting thread writes key | stamp.  Returns the slot, or ~0u if the
+// table has no free slot left (an internal error, reported by the plan).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int hash_slot(const TreeView& t, unsigned long long key) {
+__device__ __forceinline__ uint32_t probe(const TreeView& t, unsigned long long key,
+                                          unsigned long long stamp, bool& won,
+                                          bool& fresh) {
   uint32_t h = (uint32_t)mix64(key) & t.h_mask;
-  while (true) {
+  for (uint32_t n = 0; n <= t.h_mask; ++n) {
     unsigned long long cur = __hip_atomic_load(&t.h_key[h], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == key) return (int)h;
     if (cur == kEmptyKey) {
-      unsigned long long prev = atomicCAS(&t.h_key[h], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) return (int)h;
+      cur = atomicCAS(&t.h_key[h], kEmptyKey, key | stamp);
+      if (cur == kEmptyKey) {
+        won = true;
+        fresh = true;
+        return h;
+      }
+    }
+    if ((cur & ~kStampMask) == key) {
+      won = false;
+      fresh = (cur & kStampMask) == stamp;
+      return h;
     }
     h = (h + 1) & t.h_mask;
   }
+  won = false;
+  fresh = false;
+  return ~0u;
 }
 
 __device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) {
-  return ((unsigned long long)(uint32_t)b << 32) |
-         ((unsigned long long)(uint32_t)a << 24) | (uint32_t)obs;
+  return ((unsigned long long)(uint32_t)b << 26) | ((unsigned long long)(uint32_t)a << 20) |
+         (uint32_t)obs;
 }
 
 // ---------------------------------------------------------------------------
@@ -66,431 +80,300 @@ __device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) 
 // few nodes (every episode of an iteration passes through one of the |A| root
 // action nodes), so same-address global atomics would serialise.  Each block
 // first combines its contributions per key in an LDS hash table and then
-// issues one global atomic per distinct key.  Integer adds and min are
+// issues one global atomic per distinct key.  Integer adds are
 // order-independent, so results stay bit-identical.
 constexpr int kAggSlots = 2 * kBlock;      // at most kBlock keys per block
 
 struct AggTable {
-  int key[kAggSlots];
+  unsigned long long key[kAggSlots];
   unsigned long long a[kAggSlots];
   unsigned long long b[kAggSlots];
 };
 
-// Row ranges of the beliefs of one depth: level step t of every iteration
-// that reached that depth created one contiguous range.
+// Level-step lists holding the beliefs of one depth: level dep-1 of every
+// iteration that reached depth dep created one list.
 struct Ranges {
   int n;
-  int lo[kMaxRanges];
+  int step[kMaxRanges];
   int off[kMaxRanges + 1];
 };
 
 struct Smem {
   AggTable agg;
   Ranges ranges;
-  int tile;
   unsigned long long wave[kBlock / 64];
-  unsigned long long prefix;
 };
 
-__device__ __forceinline__ void agg_clear(AggTable& T, unsigned long long init) {
+__device__ __forceinline__ void agg_clear(AggTable& T) {
   for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-    T.key[i] = -1;
-    T.a[i] = init;
+    T.key[i] = kEmptyKey;
+    T.a[i] = 0ull;
     T.b[i] = 0ull;
   }
 }
 
-__device__ __forceinline__ int agg_slot(AggTable& T, int key) {
-  uint32_t h = ((uint32_t)key * 2654435761u) >> 23;   // 9 bits
+__device__ __forceinline__ int agg_slot(AggTable& T, unsigned long long key) {
+  uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 55);   // 9 bits
   while (true) {
-    const int prev = atomicCAS(&T.key[h], -1, key);
-    if (prev == -1 || prev == key) return (int)h;
+    const unsigned long long prev = atomicCAS(&T.key[h], kEmptyKey, key);
+    if (prev == kEmptyKey || prev == key) return (int)h;
     h = (h + 1) & (kAggSlots - 1);
   }
 }
 
-// Visit count and reward sum of the previous level's action nodes, then the
-// belief the episode now sits at (-1 if it stopped).  Called by every thread
-// of the block (it contains barriers); `ep_ok` marks threads with an episode.
-__device__ __forceinline__ int close_level(const PlanView& P, int ep, bool ep_ok,
-                                           AggTable& T) {
-  int an = -1, b = -1;
-  unsigned long long rf = 0ull;
-  if (ep_ok) {
-    const int as = P.e.aslot[ep];
-    if (as >= 0) {
-      an = P.t.b_child[as];
-      rf = to_fix(P.e.r[ep], P.fix_scale);
-      const int hs = P.e.hslot[ep];
-      if (hs >= 0) {
-        b = P.t.h_val[hs & kSlotMask];
-        if (hs & kWinBit) P.t.b_parent[b] = an;
-      }
-    }
-  }
-  agg_clear(T, 0ull);
-  __syncthreads();
-  if (an >= 0) {
-    const int sl = agg_slot(T, an);
-    atomicAdd(&T.a[sl], 1ull);
-    if (rf) atomicAdd(&T.b[sl], rf);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-    const int k = T.key[i];
-    if (k >= 0) {
-      atomicAdd(&P.t.a_N[k], (int)T.a[i]);
-      if (T.b[i]) atomicAdd(&P.t.a_C[k], T.b[i]);
-    }
-  }
-  __syncthreads();
-  return b;
-}
-
-// First-visitor claim: table[key] = min(table[key], kClaimBase + ep), with the
-// per-block minimum episode taken in LDS first.
-__device__ __forceinline__ void claim_min(AggTable& T, int* table, int key, int ep) {
-  agg_clear(T, 0x7FFFFFFFull);
-  __syncthreads();
-  if (key >= 0) {
-    const int sl = agg_slot(T, key);
-    atomicMin(&T.a[sl], (unsigned long long)ep);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-    const int k = T.key[i];
-    if (k >= 0) atomicMin(&table[k], kClaimBase + (int)T.a[i]);
-  }
-  __syncthreads();
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
 // Phase: set-up of a plan.  Clears the belief table (a full fill, or only the
-// slots the previous plan used when that is cheaper), the scan state and the
-// root row.  The previous plan's belief count is read on the device, so the
+// slots the previous plan used when that is cheaper), the list lengths and
+// the root record.  The previous plan's sizes are read on the device, so the
 // phase is identical on every replay of a captured launch sequence.
 // ---------------------------------------------------------------------------
 __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
-  const unsigned long long n_prev = P.t.counters[2];
-  const bool full = P.t.counters[3] != 0ull ||
-                    n_prev * 10ull >= (unsigned long long)P.t.h_mask + 1ull;
+  const TreeView& T = P.t;
+  const unsigned long long n_prev = T.counters[2];
+  const size_t hcap = (size_t)T.h_mask + 1;
+  const bool full = T.counters[3] != 0ull || n_prev * 10ull >= (unsigned long long)hcap;
   const size_t tid = (size_t)blk * kBlock + threadIdx.x;
   const size_t stride = (size_t)nblk * kBlock;
-  const size_t hcap = (size_t)P.t.h_mask + 1;
   if (full) {
-    uint4* hk = reinterpret_cast<uint4*>(P.t.h_key);
-    uint4* hv = reinterpret_cast<uint4*>(P.t.h_val);
+    uint4* hk = reinterpret_cast<uint4*>(T.h_key);
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (size_t i = tid; i < hcap / 2; i += stride) hk[i] = ones;
-    for (size_t i = tid; i < hcap / 4; i += stride) hv[i] = ones;
   } else {
-    for (size_t b = 1 + tid; b < n_prev; b += stride) {
-      const int hs = P.t.b_hslot[b];
-      P.t.h_key[hs] = kEmptyKey;
-      P.t.h_val[hs] = -1;
+    const int prev_steps = (int)T.counters[5];
+    const size_t lstride = (size_t)T.counters[6];
+    for (int t = 0; t < prev_steps; ++t) {
+      const size_t n = (size_t)T.cnt_prev[t];
+      for (size_t i = tid; i < n; i += stride) T.h_key[T.list[t * lstride + i] - 1] = kEmptyKey;
     }
   }
-  const size_t nlb = (size_t)P.steps * P.t.res_tiles;
-  for (size_t i = tid; i < nlb; i += stride) P.t.lookback[i] = 0ull;
-  for (size_t i = tid; i < (size_t)P.steps; i += stride) P.t.tickets[i] = 0;
+  for (size_t i = tid; i < (size_t)P.steps; i += stride) T.cnt[i] = 0;
   if (blk == 0) {
+    uint4* r = reinterpret_cast<uint4*>(T.rec);
+    for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
     const int j = threadIdx.x;
-    const int A = P.m.nA, Apad = P.m.Apad;
-    if (j < Apad) {
-      P.t.b_child[j] = -1;
-      P.t.psi[j] = j < A ? P.psi0 : 0.0f;
-      if (j < A) P.t.psi_root[j] = P.psi0_64;
+    if (j < P.m.nA) {
+      rec_psi(T, 0)[j] = P.psi0;
+      T.psi_root[j] = P.psi0_64;
     }
     if (j == 0) {
-      P.t.b_parent[0] = -1;
-      P.t.b_obs[0] = -1;
-      P.t.b_V[0] = 0.0f;
-      P.t.b_N[0] = 0;
-      P.t.leaf_cnt[0] = 0;
-      P.t.leaf_h[0] = 0ull;
-      P.t.b_hslot[0] = 0;
-      P.t.v_root[0] = 0.0;
-      P.t.bel_base[0] = 1;
-      P.t.act_base[0] = 0;
-      P.t.counters[0] = 0ull;
-      P.t.counters[1] = 0ull;
+      RecMeta* mt = rec_meta(T, 0);
+      mt->obs = -1;
+      mt->parent = kEmptyKey;
+      T.v_root[0] = 0.0;
+      T.counters[0] = 0ull;
+      T.counters[1] = 0ull;
+      T.counters[4] = 0ull;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Phase: expand one level (Alg. 2, one recursion step).
+// Phase: the forward search of iteration k over D levels (Alg. 2).
 // ---------------------------------------------------------------------------
+
+// A new belief's record: Psi = psi0 (Eq. 6 starts uniform), N = C = W = 0.
+__device__ __forceinline__ void init_record(const PlanView& P, int id, int parent, int a,
+                                            int obs) {
+  const TreeView& T = P.t;
+  uint4* q = reinterpret_cast<uint4*>(rec_at(T, id));
+  const int ra = T.ra, A = P.m.nA;
+  const uint32_t p0 = __float_as_uint(P.psi0);
+  for (int j = 0; j < ra; j += 4)
+    q[j >> 2] = make_uint4(j < A ? p0 : 0u, j + 1 < A ? p0 : 0u, j + 2 < A ? p0 : 0u,
+                           j + 3 < A ? p0 : 0u);
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  const int meta_q = 6 * ra / 4;                // N, C and W take 5*ra/4 quads
+  for (int i = ra / 4; i < meta_q; ++i) q[i] = z;
+  const unsigned long long par = ((unsigned long long)(uint32_t)parent << 6) | (uint32_t)a;
+  q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);                 // V, N_b, leaf_cnt, obs
+  q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)par, (uint32_t)(par >> 32));   // leaf_h, parent
+}
+
 template <int AM>
-__device__ void dev_expand(const PlanView& P, int k, int d, int blk, Smem& sm) {
-  AggTable& T = sm.agg;
+__device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
+  const TreeView& T = P.t;
   const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
-  bool alive = false;
-  int b = -1, s = 0;
+  const int A = P.m.nA;
+  const size_t n_p = (size_t)P.n_p;
+  const unsigned long long stamp = (unsigned long long)(k - 1) << kStampShift;
+  int s = 0;
   float x = 0.0f, y = 0.0f;
-  if (d == 0) {
-    if (ep_ok) {
-      // Alg. 1: the episode starts at the root with a state drawn from the
-      // belief particles.
-      const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
-      const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
-      if (P.m.kind == kTabular) {
-        s = ((const int*)P.e.belief)[idx];
-        if ((unsigned)s >= (unsigned)P.m.nS) {   // caller's particle out of range
-          atomicOr((unsigned int*)&P.t.counters[1], 1u);
-          s = 0;
-        }
-      } else {
-        const float* bf = (const float*)P.e.belief;
-        x = bf[idx];
-        y = bf[P.e.n_belief + idx];
-      }
-      b = 0;
-      alive = true;
-    }
-  } else {
-    // The state load does not depend on the previous level's tables.
-    if (ep_ok) {
-      if (P.m.kind == kTabular) s = P.e.s_i[ep];
-      else { x = P.e.s_x[ep]; y = P.e.s_y[ep]; }
-    }
-    b = close_level(P, ep, ep_ok, T);
-    alive = b >= 0;
-  }
-  int as = -1, hs = -1;
-  bool claim_a = false, claim_b = false;
-  if (alive) {
-    const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
-    const int A = P.m.nA;
-    int a;
-    if (b == 0) {
-      a = draw_action64(P.t.psi_root, A, P.eta64, w.x);
-    } else {
-      a = draw_action32<AM>(P.t.psi + (size_t)b * P.m.Apad, A, P.eta, w.x);
-    }
-    int obs;
-    float r;
-    bool term = false;
+  int b = 0;                  // current belief id (0: root)
+  bool fresh = false;         // b was inserted during this iteration
+  bool made = false;          // ... by this episode
+  bool alive = false;
+  if (ep_ok) {
+    // Alg. 1: the episode starts at the root with a state drawn from the
+    // belief particles.
+    const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
+    const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
     if (P.m.kind == kTabular) {
-      int sn;
-      tabular_step(P.m, s, a, w, sn, obs, r);
-      P.e.s_i[ep] = sn;
+      s = ((const int*)P.e.belief)[idx];
+      if ((unsigned)s >= (unsigned)P.m.nS) {   // caller's particle out of range
+        atomicOr((unsigned int*)&T.counters[1], 1u);
+        s = 0;
+      }
     } else {
-      float nx, ny;
-      nav_step(P.m, x, y, a, w, nx, ny, obs, r, term);
-      P.e.s_x[ep] = nx;
-      P.e.s_y[ep] = ny;
+      const float* bf = (const float*)P.e.belief;
+      x = bf[idx];
+      y = bf[P.e.n_belief + idx];
     }
-    P.e.r[ep] = r;
-    as = b * P.m.Apad + a;
-    claim_a = P.t.b_child[as] < 0;
-    if (!term) {                              // FilterTerminals
-      hs = hash_slot(P.t, belief_key(b, a, obs));
-      claim_b = P.t.h_val[hs] < 0;
+    alive = true;
+  }
+  unsigned long long g = 0;   // generative-model calls of this episode
+  for (int d = 0; d < D; ++d) {
+    unsigned long long tk = kEmptyKey;
+    float r = 0.0f;
+    if (alive) {
+      const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
+      int a;
+      if (b == 0) a = draw_action64(T.psi_root, A, P.eta64, w.x);
+      else if (fresh) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
+      else a = draw_action32<AM>(rec_psi(T, b), A, P.eta, w.x);
+      int obs;
+      bool term = false;
+      if (P.m.kind == kTabular) {
+        int sn;
+        tabular_step(P.m, s, a, w, sn, obs, r);
+        s = sn;
+      } else {
+        float nx, ny;
+        nav_step(P.m, x, y, a, w, nx, ny, obs, r, term);
+        x = nx;
+        y = ny;
+      }
+      tk = ((unsigned long long)(uint32_t)b << 6) | (uint32_t)a;
+      if (made) tk |= kTraceNew;
+      ++g;
+      if (term) {
+        alive = false;                          // FilterTerminals
+      } else {
+        bool won, fr;
+        const uint32_t h = probe(T, belief_key(b, a, obs), stamp, won, fr);
+        if (h == ~0u) {                         // table full: stop and report
+          atomicOr((unsigned int*)&T.counters[1], 2u);
+          alive = false;
+        } else {
+          const int c = (int)h + 1;
+          if (won) init_record(P, c, b, a, obs);
+          b = c;
+          fresh = fr;
+          made = won;
+        }
+      }
+    }
+    if (ep_ok) {
+      T.tr_key[(size_t)d * n_p + ep] = tk;
+      T.tr_val[(size_t)d * n_p + ep] = r;
     }
   }
   if (ep_ok) {
-    P.e.aslot[ep] = as;
-    P.e.hslot[ep] = hs;
-  }
-  // AppendActions / AppendBeliefs claims: the smallest episode id per new
-  // pair wins.
-  if (__syncthreads_or(claim_a)) claim_min(T, P.t.b_child, claim_a ? as : -1, ep);
-  if (__syncthreads_or(claim_b)) claim_min(T, P.t.h_val, claim_b ? hs : -1, ep);
-  // Particle-step count: one generative-model call per running episode.
-  const unsigned long long ballot = __ballot(alive);
-  if ((threadIdx.x & 63) == 0 && ballot)
-    atomicAdd(&P.t.counters[0], (unsigned long long)__popcll(ballot));
-}
-
-// ---------------------------------------------------------------------------
-// Phase: resolve the claims of level step t (first-visitor numbering).
-// Packed scan word: (count_a << 31) | count_b, both < 2^31.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    unsigned long long n = __shfl_up(v, off, 64);
-    if (lane >= off) v += n;
-  }
-  return v;
-}
-
-constexpr unsigned long long kFlagAgg = 1ull << 62;
-constexpr unsigned long long kFlagIncl = 2ull << 62;
-constexpr unsigned long long kPayload = (1ull << 62) - 1;
-
-__device__ void dev_resolve(const PlanView& P, int t, Smem& sm) {
-  if (threadIdx.x == 0) sm.tile = atomicAdd(&P.t.tickets[t], 1);
-  __syncthreads();
-  const int tile = sm.tile;
-  const int items = P.t.res_items;
-  const int base_ep = (tile * kBlock + threadIdx.x) * items;
-
-  int aslot[kResItemsMax], hslot[kResItemsMax];
-  unsigned flags = 0;   // bit i: action creator, bit 16+i: belief creator
-  unsigned long long mine = 0;
-#pragma unroll
-  for (int i = 0; i < kResItemsMax; ++i) {
-    const int ep = base_ep + i;
-    aslot[i] = -1;
-    hslot[i] = -1;
-    if (i < items && ep < P.n_p) {
-      aslot[i] = P.e.aslot[ep];
-      hslot[i] = P.e.hslot[ep];
-      if (aslot[i] >= 0 && P.t.b_child[aslot[i]] == kClaimBase + ep) {
-        flags |= 1u << i;
-        mine += 1ull << 31;
-      }
-      if (hslot[i] >= 0 && P.t.h_val[hslot[i]] == kClaimBase + ep) {
-        flags |= 1u << (16 + i);
-        mine += 1ull;
-      }
-    }
-  }
-  // Block scan.
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const unsigned long long incl = wave_incl_scan(mine);
-  if (lane == 63) sm.wave[wid] = incl;
-  __syncthreads();
-  unsigned long long wave_off = 0, block_total = 0;
-#pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) {
-    if (i < wid) wave_off += sm.wave[i];
-    block_total += sm.wave[i];
-  }
-  const unsigned long long local_excl = wave_off + incl - mine;
-
-  // Decoupled look-back across tiles, one wavefront probing 64 predecessors
-  // at a time.
-  if (wid == 0) {
-    unsigned long long* st = P.t.lookback + (size_t)t * P.t.res_tiles;
-    if (lane == 0)
-      __hip_atomic_store(&st[tile], (tile == 0 ? kFlagIncl : kFlagAgg) | block_total,
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long excl = 0;
-    int hi = tile - 1;
-    while (hi >= 0) {
-      const int j = hi - lane;
-      unsigned long long v = kFlagIncl;          // before tile 0: inclusive 0
-      if (j >= 0) {
-        v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        while ((v >> 62) == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          v = __hip_atomic_load(&st[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      const unsigned long long incl_mask = __ballot((v >> 62) == 2);
-      unsigned long long part;
-      if (incl_mask) {
-        const int first = __ffsll((long long)incl_mask) - 1;   // nearest inclusive
-        part = lane <= first ? (v & kPayload) : 0ull;
+    unsigned long long tk = kEmptyKey;
+    float h = 0.0f;                             // ValueHeuristic of the leaf state
+    if (alive) {
+      tk = (unsigned long long)(uint32_t)b | (made ? kTraceNew : 0ull);
+      if (P.m.kind == kTabular) {
+        if (P.m.H) h = P.m.H[s];
       } else {
-        part = v & kPayload;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-      excl += part;
-      if (incl_mask) break;
-      hi -= 64;
-    }
-    if (lane == 0) {
-      if (tile > 0)
-        __hip_atomic_store(&st[tile], kFlagIncl | (excl + block_total),
-                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      sm.prefix = excl;
-      if (tile == P.t.res_tiles - 1) {
-        const unsigned long long tot = excl + block_total;
-        P.t.act_base[t + 1] = P.t.act_base[t] + (int)(tot >> 31);
-        P.t.bel_base[t + 1] = P.t.bel_base[t] + (int)(tot & 0x7FFFFFFFull);
+        h = nav_heuristic(P.m.nav, x, y);
       }
     }
+    T.tr_key[(size_t)D * n_p + ep] = tk;
+    T.tr_val[(size_t)D * n_p + ep] = h;
   }
-  __syncthreads();
-  if (!flags) return;
-  const unsigned long long pre = sm.prefix + local_excl;
-  int na = P.t.act_base[t] + (int)(pre >> 31);
-  int nb = P.t.bel_base[t] + (int)(pre & 0x7FFFFFFFull);
-  const int Apad = P.m.Apad, A = P.m.nA;
-#pragma unroll
-  for (int i = 0; i < kResItemsMax; ++i) {
-    if (flags & (1u << i)) {
-      const int as = aslot[i];
-      P.t.b_child[as] = na;
-      P.t.a_parent[na] = as / Apad;
-      P.t.a_act[na] = as % Apad;
-      P.t.a_C[na] = 0ull;
-      P.t.a_N[na] = 0;
-      P.t.a_W[na] = 0ull;
-      ++na;
-    }
-    if (flags & (1u << (16 + i))) {
-      const int hs = hslot[i];
-      const unsigned long long key = P.t.h_key[hs];
-      P.t.h_val[hs] = nb;
-      P.t.b_obs[nb] = (int)(key & 0xFFFFFFull);
-      P.t.b_hslot[nb] = hs;
-      P.t.b_V[nb] = 0.0f;
-      P.t.b_N[nb] = 0;
-      P.t.leaf_cnt[nb] = 0;
-      P.t.leaf_h[nb] = 0ull;
-      float4* row = reinterpret_cast<float4*>(P.t.psi + (size_t)nb * Apad);
-      int4* crow = reinterpret_cast<int4*>(P.t.b_child + (size_t)nb * Apad);
-      for (int j = 0; j < Apad; j += 4) {
-        const float p0 = P.psi0;
-        row[j >> 2] = make_float4(j < A ? p0 : 0.0f, j + 1 < A ? p0 : 0.0f,
-                                  j + 2 < A ? p0 : 0.0f, j + 3 < A ? p0 : 0.0f);
-        crow[j >> 2] = make_int4(-1, -1, -1, -1);
-      }
-      P.e.hslot[base_ep + i] = hs | kWinBit;
-      ++nb;
-    }
-  }
+  g = wave_sum(g);
+  if ((threadIdx.x & 63) == 0 && g) atomicAdd(&T.counters[0], g);
 }
 
 // ---------------------------------------------------------------------------
-// Phase: close the deepest level and accumulate this iteration's leaves.
+// Phase: fold the trace of an iteration with D levels into the tree.  Trace
+// item i is level i / n_p; level-step t0 + d created the beliefs of depth
+// d + 1.  Aggregation keys: (id << 7) | (a << 1) for action nodes, (id << 7) | 1
+// for leaves.
 // ---------------------------------------------------------------------------
-__device__ void dev_finish(const PlanView& P, int blk, Smem& sm) {
-  AggTable& T = sm.agg;
-  const int ep = blk * kBlock + threadIdx.x;
-  const bool ep_ok = ep < P.n_p;
-  const int b = close_level(P, ep, ep_ok, T);
-  unsigned long long hf = 0ull;
-  if (b >= 0) {
-    float h = 0.0f;                           // ValueHeuristic
-    if (P.m.kind == kTabular) {
-      if (P.m.H) h = P.m.H[P.e.s_i[ep]];
-    } else {
-      h = nav_heuristic(P.m.nav, P.e.s_x[ep], P.e.s_y[ep]);
+__device__ void dev_accum(const PlanView& P, int D, int t0, int blk, int nblk, Smem& sm) {
+  const TreeView& T = P.t;
+  AggTable& G = sm.agg;
+  const long long n_p = P.n_p;
+  const long long total = (long long)(D + 1) * n_p;
+  const int lane = threadIdx.x & 63;
+  unsigned long long new_nodes = 0;
+  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
+    const long long i = base + threadIdx.x;
+    unsigned long long tk = kEmptyKey;
+    float v = 0.0f;
+    int lvl = 0;
+    if (i < total) {
+      tk = T.tr_key[i];
+      v = T.tr_val[i];
+      lvl = (int)(i / n_p);
     }
-    hf = to_fix(h, P.fix_scale);
-  }
-  agg_clear(T, 0ull);
-  __syncthreads();
-  if (b >= 0) {
-    const int sl = agg_slot(T, b);
-    atomicAdd(&T.a[sl], 1ull);
-    if (hf) atomicAdd(&T.b[sl], hf);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-    const int key = T.key[i];
-    if (key >= 0) {
-      atomicAdd(&P.t.leaf_cnt[key], (int)T.a[i]);
-      if (T.b[i]) atomicAdd(&P.t.leaf_h[key], T.b[i]);
+    const bool has = tk != kEmptyKey;
+    bool pend = has && (tk & kTraceNew);
+    const unsigned long long body = tk & ~kTraceNew;
+    const bool leaf = lvl == D;
+    const int id = has ? (int)(leaf ? body : body >> 6) : -1;
+    // AppendBeliefs: the inserting episode files the belief under its level
+    // step, one atomic per wavefront and level.
+    while (true) {
+      const unsigned long long m = __ballot(pend);
+      if (!m) break;
+      const int leader = __ffsll((long long)m) - 1;
+      const int L = __shfl(lvl, leader, 64);
+      const bool mine = pend && lvl == L;
+      const unsigned long long grp = __ballot(mine);
+      int at = 0;
+      if (lane == leader) at = atomicAdd(&T.cnt[t0 + L - 1], __popcll(grp));
+      at = __shfl(at, leader, 64);
+      if (mine) {
+        T.list[(size_t)(t0 + L - 1) * n_p + at + __popcll(grp & ((1ull << lane) - 1ull))] = id;
+        pend = false;
+      }
     }
+    agg_clear(G);
+    __syncthreads();
+    if (has) {
+      const unsigned long long key =
+          leaf ? (((unsigned long long)(uint32_t)id << 7) | 1ull) : (body << 1);
+      const int sl = agg_slot(G, key);
+      atomicAdd(&G.a[sl], 1ull);
+      const unsigned long long fx = to_fix(v, P.fix_scale);
+      if (fx) atomicAdd(&G.b[sl], fx);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+      const unsigned long long key = G.key[j];
+      if (key == kEmptyKey) continue;
+      const int nid = (int)(key >> 7);
+      if (key & 1ull) {
+        RecMeta* mt = rec_meta(T, nid);
+        atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
+        if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
+      } else {
+        const int a = (int)((key >> 1) & 63ull);
+        if (atomicAdd(&rec_n(T, nid)[a], (int)G.a[j]) == 0) ++new_nodes;
+        if (G.b[j]) atomicAdd(&rec_c(T, nid)[a], G.b[j]);
+      }
+    }
+    __syncthreads();
   }
+  new_nodes = wave_sum(new_nodes);
+  if (lane == 0 && new_nodes) atomicAdd(&T.counters[4], new_nodes);
 }
 
 // ---------------------------------------------------------------------------
 // Backup (Alg. 3).  Beliefs of depth `dep` were created by level dep-1 of
 // every iteration k' <= k whose depth D_k' >= dep.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
-                                            Ranges& R) {
+__device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, Ranges& R) {
   if (threadIdx.x == 0) {
     int n = 0, off = 0;
     for (int kk = 1; kk <= k; ++kk) {
@@ -498,11 +381,9 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
       const int Dk = P.t.step_base[kk] - s0;
       if (Dk >= dep) {
         const int t = s0 + dep - 1;
-        const int lo = P.t.bel_base[t];
-        const int len = P.t.bel_base[t + 1] - lo;
-        R.lo[n] = lo;
+        R.step[n] = t;
         R.off[n] = off;
-        off += len;
+        off += P.t.cnt[t];
         ++n;
       }
     }
@@ -512,32 +393,31 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k,
   __syncthreads();
 }
 
-__device__ __forceinline__ int range_row(const Ranges& R, int i) {
+// Belief id of the i-th belief of the ranges.
+__device__ __forceinline__ int range_id(const PlanView& P, const Ranges& R, int i) {
   int lo = 0, hi = R.n - 1;          // last r with off[r] <= i
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (R.off[mid] <= i) lo = mid; else hi = mid - 1;
   }
-  return R.lo[lo] + (i - R.off[lo]);
+  return P.t.list[(size_t)R.step[lo] * (size_t)P.n_p + (size_t)(i - R.off[lo])];
 }
 
-// Push V*N_b of belief b (or nothing if b < 0) into its parent action's W
-// accumulator, aggregated per block.  Called by every thread of the block.
-__device__ __forceinline__ void push_values(const PlanView& P, AggTable& T, int b,
-                                            float V, int N) {
-  int par = -1;
+// Push V*N_b of a belief into its parent action's W accumulator (parent =
+// (id << 6) | a, or kEmptyKey for none), aggregated per block.  Called by
+// every thread of the block (it contains barriers).
+__device__ __forceinline__ void push_values(const PlanView& P, AggTable& G,
+                                            unsigned long long parent, float V, int N) {
   unsigned long long f = 0ull;
-  if (b >= 0 && N > 0) {
-    f = to_fix(V * (float)N, P.fix_scale);
-    if (f) par = P.t.b_parent[b];
-  }
-  agg_clear(T, 0ull);
+  if (parent != kEmptyKey && N > 0) f = to_fix(V * (float)N, P.fix_scale);
+  agg_clear(G);
   __syncthreads();
-  if (par >= 0) atomicAdd(&T.a[agg_slot(T, par)], f);
+  if (f) atomicAdd(&G.a[agg_slot(G, parent)], f);
   __syncthreads();
-  for (int i = threadIdx.x; i < kAggSlots; i += kBlock) {
-    const int key = T.key[i];
-    if (key >= 0 && T.a[i]) atomicAdd(&P.t.a_W[key], T.a[i]);
+  for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+    const unsigned long long key = G.key[j];
+    if (key != kEmptyKey && G.a[j])
+      atomicAdd(&rec_w(P.t, (int)(key >> 6))[key & 63ull], G.a[j]);
   }
   __syncthreads();
 }
@@ -551,25 +431,27 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
   const int total = R.off[R.n];
   for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
     const int i = base + threadIdx.x;
-    int b = -1, N = 0;
+    int N = 0;
     float V = 0.0f;
+    unsigned long long parent = kEmptyKey;
     if (i < total) {
-      b = range_row(R, i);
-      const int c = P.t.leaf_cnt[b];
+      RecMeta* mt = rec_meta(P.t, range_id(P, R, i));
+      const int c = mt->leaf_cnt;
       if (c > 0) {
-        const unsigned long long hs = P.t.leaf_h[b];
+        const unsigned long long hs = mt->leaf_h;
         V = from_fix(hs, P.fix_inv) / (float)c;
         N = c;
-        P.t.b_V[b] = V;
-        P.t.b_N[b] = N;
-        P.t.leaf_cnt[b] = 0;
-        if (hs) P.t.leaf_h[b] = 0ull;
+        mt->V = V;
+        mt->Nb = N;
+        mt->leaf_cnt = 0;
+        if (hs) mt->leaf_h = 0ull;
       } else {
-        V = P.t.b_V[b];
-        N = P.t.b_N[b];
+        V = mt->V;
+        N = mt->Nb;
       }
+      parent = mt->parent;
     }
-    push_values(P, sm.agg, b, V, N);
+    push_values(P, sm.agg, parent, V, N);
   }
 }
 
@@ -580,26 +462,30 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
   Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
   const int total = R.off[R.n];
-  const int A = P.m.nA, Apad = P.m.Apad;
+  const int A = P.m.nA;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
   for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
     const int i = base + threadIdx.x;
-    int b = -1, N = 0;
+    int N = 0;
     float V = 0.0f;
+    unsigned long long parent = kEmptyKey;
     if (i < total) {
-      b = range_row(R, i);
-      const int* crow = P.t.b_child + (size_t)b * Apad;
-      float* prow = P.t.psi + (size_t)b * Apad;
-      int child[AM];
+      const int b = range_id(P, R, i);
+      float* prow = rec_psi(P.t, b);
+      const int* nrow = rec_n(P.t, b);
+      unsigned long long* crow = rec_c(P.t, b);
+      unsigned long long* wrow = rec_w(P.t, b);
+      RecMeta* mt = rec_meta(P.t, b);
+      int n[AM];
       bool any = false;
 #pragma unroll
       for (int j = 0; j < AM; j += 4) {
-        int4 c = make_int4(-1, -1, -1, -1);
-        if (j < A) c = *reinterpret_cast<const int4*>(crow + j);
-        child[j] = c.x; child[j + 1] = c.y; child[j + 2] = c.z; child[j + 3] = c.w;
+        int4 c = make_int4(0, 0, 0, 0);
+        if (j < A) c = *reinterpret_cast<const int4*>(nrow + j);
+        n[j] = c.x; n[j + 1] = c.y; n[j + 2] = c.z; n[j + 3] = c.w;
       }
 #pragma unroll
-      for (int j = 0; j < AM; ++j) any = any || (j < A && child[j] >= 0);
+      for (int j = 0; j < AM; ++j) any = any || (j < A && n[j] > 0);
       if (any) {
         float psi[AM];
 #pragma unroll
@@ -622,17 +508,15 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
         int nsum = 0;
 #pragma unroll
         for (int j = 0; j < AM; ++j) {
-          const int an = child[j];
-          if (j < A && an >= 0) {
-            const int n = P.t.a_N[an];
-            const float c = from_fix(P.t.a_C[an], inv);
-            const unsigned long long wf = P.t.a_W[an];
+          if (j < A && n[j] > 0) {
+            const float c = from_fix(crow[j], inv);
+            const unsigned long long wf = wrow[j];
             const float w = from_fix(wf, inv);
-            if (wf) P.t.a_W[an] = 0ull;
-            const float fn = (float)n;
+            if (wf) wrow[j] = 0ull;
+            const float fn = (float)n[j];
             const float q = c / fn + gamma * (w / fn);
             psi[j] = (psi[j] - vc) + q;
-            nsum += n;
+            nsum += n[j];
           }
         }
         // V = L_eta Psi after the update; N_b = sum_a N(b, a).
@@ -651,14 +535,15 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
           if (j < A)
             *reinterpret_cast<float4*>(prow + j) =
                 make_float4(psi[j], psi[j + 1], psi[j + 2], psi[j + 3]);
-        P.t.b_V[b] = V;
-        P.t.b_N[b] = N;
+        mt->V = V;
+        mt->Nb = N;
       } else {
-        V = P.t.b_V[b];
-        N = P.t.b_N[b];
+        V = mt->V;
+        N = mt->Nb;
       }
+      parent = mt->parent;
     }
-    push_values(P, sm.agg, b, V, N);
+    push_values(P, sm.agg, parent, V, N);
   }
 }
 
@@ -667,17 +552,19 @@ __device__ void dev_backup_root(const PlanView& P) {
   if (threadIdx.x != 0) return;
   const int A = P.m.nA;
   double* psi = P.t.psi_root;
+  const int* nrow = rec_n(P.t, 0);
+  const unsigned long long* crow = rec_c(P.t, 0);
+  unsigned long long* wrow = rec_w(P.t, 0);
   const double vc = lse64(psi, A, P.eta64);
   long long nsum = 0;
   bool any = false;
   for (int j = 0; j < A; ++j) {
-    const int an = P.t.b_child[j];
-    if (an < 0) continue;
+    const int n = nrow[j];
+    if (n <= 0) continue;
     any = true;
-    const int n = P.t.a_N[an];
-    const double c = (double)(long long)P.t.a_C[an] * P.fix_inv64;
-    const double w = (double)(long long)P.t.a_W[an] * P.fix_inv64;
-    P.t.a_W[an] = 0ull;
+    const double c = (double)(long long)crow[j] * P.fix_inv64;
+    const double w = (double)(long long)wrow[j] * P.fix_inv64;
+    wrow[j] = 0ull;
     const double q = c / (double)n + P.m.gamma64 * (w / (double)n);
     psi[j] = (psi[j] - vc) + q;
     nsum += n;
@@ -685,28 +572,53 @@ __device__ void dev_backup_root(const PlanView& P) {
   if (!any) return;
   const double v = lse64(psi, A, P.eta64);
   P.t.v_root[0] = v;
-  P.t.b_V[0] = (float)v;
-  P.t.b_N[0] = (int)nsum;
+  RecMeta* mt = rec_meta(P.t, 0);
+  mt->V = (float)v;
+  mt->Nb = (int)nsum;
 }
 
 // Alg. 1: argmax of the root preferences (lowest index on ties) and the
-// result record; also records the belief count for the next plan's set-up.
-__device__ void dev_select(const PlanView& P, int last_step) {
+// result record; also keeps this plan's list lengths for the next set-up.
+__device__ void dev_select(const PlanView& P, Smem& sm) {
+  const TreeView& T = P.t;
+  unsigned long long part = 0;
+  for (int t = threadIdx.x; t < P.steps; t += kBlock) {
+    const int c = T.cnt[t];
+    T.cnt_prev[t] = c;
+    part += (unsigned long long)c;
+  }
+  part = wave_sum(part);
+  if ((threadIdx.x & 63) == 0) sm.wave[threadIdx.x >> 6] = part;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  unsigned long long nb = 1;
+  for (int i = 0; i < kBlock / 64; ++i) nb += sm.wave[i];
   const int A = P.m.nA;
   int best = 0;
   for (int j = 1; j < A; ++j)
-    if (P.t.psi_root[j] > P.t.psi_root[best]) best = j;
+    if (T.psi_root[j] > T.psi_root[best]) best = j;
   double* out = P.out;
   out[0] = (double)best;
-  for (int j = 0; j < A; ++j) out[1 + j] = P.t.psi_root[j];
-  out[A + 1] = P.t.v_root[0];
-  out[A + 2] = (double)P.t.counters[0];
-  out[A + 3] = (double)P.t.bel_base[last_step];
-  out[A + 4] = (double)P.t.act_base[last_step];
-  out[A + 5] = (double)P.t.counters[1];
-  P.t.counters[2] = (unsigned long long)P.t.bel_base[last_step];
-  P.t.counters[3] = 0ull;
+  for (int j = 0; j < A; ++j) out[1 + j] = T.psi_root[j];
+  out[A + 1] = T.v_root[0];
+  out[A + 2] = (double)T.counters[0];
+  out[A + 3] = (double)nb;
+  out[A + 4] = (double)T.counters[4];
+  out[A + 5] = (double)T.counters[1];
+  T.counters[2] = nb;
+  T.counters[3] = 0ull;
+  T.counters[5] = (unsigned long long)P.steps;
+  T.counters[6] = (unsigned long long)P.n_p;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    unsigned long long n = __shfl_up(v, off, 64);
+    if (lane >= off) v += n;
+  }
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -873,17 +785,12 @@ __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
   dev_setup(P, blockIdx.x, gridDim.x);
 }
 template <int AM>
-__global__ __launch_bounds__(kBlock) void k_expand(PlanView P, int k, int d) {
-  __shared__ Smem sm;
-  dev_expand<AM>(P, k, d, blockIdx.x, sm);
+__global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
+  dev_forward<AM>(P, k, D, blockIdx.x);
 }
-__global__ __launch_bounds__(kBlock) void k_resolve(PlanView P, int t) {
+__global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D, int t0) {
   __shared__ Smem sm;
-  dev_resolve(P, t, sm);
-}
-__global__ __launch_bounds__(kBlock) void k_finish(PlanView P) {
-  __shared__ Smem sm;
-  dev_finish(P, blockIdx.x, sm);
+  dev_accum(P, D, t0, blockIdx.x, gridDim.x, sm);
 }
 __global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
   __shared__ Smem sm;
@@ -895,7 +802,10 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
   dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
 __global__ void k_backup_root(PlanView P) { dev_backup_root(P); }
-__global__ void k_select(PlanView P, int last_step) { dev_select(P, last_step); }
+__global__ __launch_bounds__(kBlock) void k_select(PlanView P) {
+  __shared__ Smem sm;
+  dev_select(P, sm);
+}
 
 // ---------------------------------------------------------------------------
 // Batched kernel: block -> (instance, phase) through the item list, sorted by
@@ -919,16 +829,15 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
   const int Apad = P.m.Apad;
   switch (it.kind) {
     case kPhaseSetup: dev_setup(P, blk, it.nblk); break;
-    case kPhaseExpand:
+    case kPhaseForward:
       if (Apad <= 4) {
-        dev_expand<4>(P, it.a0, it.a1, blk, sm);
+        dev_forward<4>(P, it.a0, it.a1, blk);
       } else if constexpr (AMAX >= 8) {
-        if (Apad <= 8) dev_expand<8>(P, it.a0, it.a1, blk, sm);
-        else if constexpr (AMAX >= 16) dev_expand<16>(P, it.a0, it.a1, blk, sm);
+        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk);
+        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk);
       }
       break;
-    case kPhaseResolve: dev_resolve(P, it.a0, sm); break;
-    case kPhaseFinish: dev_finish(P, blk, sm); break;
+    case kPhaseAccum: dev_accum(P, it.a0, it.a1, blk, it.nblk, sm); break;
     case kPhaseLeaf: dev_backup_leaf(P, it.a0, it.a1, blk, it.nblk, sm); break;
     case kPhaseLevel:
       if (Apad <= 4) {
@@ -939,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
       }
       break;
     case kPhaseRoot: dev_backup_root(P); break;
-    case kPhaseSelect: dev_select(P, it.a0); break;
+    case kPhaseSelect: dev_select(P, sm); break;
     case kPhaseEnv: dev_env(P, it.a0); break;
     case kPhasePFWeight: dev_pf_weight(P, it.a0, blk); break;
     case kPhasePFScan: dev_pf_scan(P, sm); break;
@@ -959,26 +868,29 @@ int setup_blocks(const PlanView& P) {
   return (int)std::max(1ll, std::min(g, 1024ll));
 }
 
+int forward_blocks(const PlanView& P) { return blocks_for(P.n_p); }
+
+int accum_blocks(const PlanView& P, int D, int cap) {
+  const long long g = blocks_for((long long)(D + 1) * P.n_p);
+  return (int)std::max(1ll, std::min(g, (long long)cap));
+}
+
 hipError_t launch_setup(const PlanView& P, hipStream_t s) {
   hipLaunchKernelGGL(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
-hipError_t launch_expand(const PlanView& P, int k, int d, hipStream_t s) {
-  const dim3 g(blocks_for(P.n_p)), b(kBlock);
+hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
+  const dim3 g(forward_blocks(P)), b(kBlock);
   const int Ap = P.m.Apad;
-  if (Ap <= 4) hipLaunchKernelGGL(k_expand<4>, g, b, 0, s, P, k, d);
-  else if (Ap <= 8) hipLaunchKernelGGL(k_expand<8>, g, b, 0, s, P, k, d);
-  else if (Ap <= 16) hipLaunchKernelGGL(k_expand<16>, g, b, 0, s, P, k, d);
-  else if (Ap <= 32) hipLaunchKernelGGL(k_expand<32>, g, b, 0, s, P, k, d);
-  else hipLaunchKernelGGL(k_expand<64>, g, b, 0, s, P, k, d);
+  if (Ap <= 4) hipLaunchKernelGGL(k_forward<4>, g, b, 0, s, P, k, D);
+  else if (Ap <= 8) hipLaunchKernelGGL(k_forward<8>, g, b, 0, s, P, k, D);
+  else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, P, k, D);
+  else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
+  else hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
   return hipGetLastError();
 }
-hipError_t launch_resolve(const PlanView& P, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_resolve, dim3(P.t.res_tiles), dim3(kBlock), 0, s, P, t);
-  return hipGetLastError();
-}
-hipError_t launch_finish(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(blocks_for(P.n_p)), dim3(kBlock), 0, s, P);
+hipError_t launch_accum(const PlanView& P, int D, int t0, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D, t0);
   return hipGetLastError();
 }
 hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
@@ -999,8 +911,8 @@ hipError_t launch_backup_root(const PlanView& P, hipStream_t s) {
   hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }
-hipError_t launch_select(const PlanView& P, int last_step, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P, last_step);
+hipError_t launch_select(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {
@@ -1016,6 +928,24 @@ hipError_t launch_pf(const PlanView& P, int t, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pf_resample, g, b, 0, s, P, t);
+  return hipGetLastError();
+}
+__global__ __launch_bounds__(kBlock) void k_gather(TreeView t, const int* ids, int n,
+                                                   unsigned char* out) {
+  const int q = t.rs / 16;
+  const long long total = (long long)n * q;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+       i += (long long)gridDim.x * kBlock) {
+    const long long b = i / q;
+    const int j = (int)(i - b * q);
+    reinterpret_cast<uint4*>(out)[i] = reinterpret_cast<const uint4*>(rec_at(t, ids[b]))[j];
+  }
+}
+hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char* out,
+                         hipStream_t s) {
+  const long long total = (long long)n * (t.rs / 16);
+  const int g = (int)std::max(1ll, std::min((total + kBlock - 1) / kBlock, 4096ll));
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, s, t, ids, n, out);
   return hipGetLastError();
 }
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,

@@ -7,17 +7,22 @@
 namespace vopp {
 
 int setup_blocks(const PlanView& P);
+int forward_blocks(const PlanView& P);
+// Blocks of the accumulate sweep of an iteration with D levels (at most cap).
+int accum_blocks(const PlanView& P, int D, int cap);
 hipError_t launch_setup(const PlanView& P, hipStream_t s);
-hipError_t launch_expand(const PlanView& P, int k, int d, hipStream_t s);
-hipError_t launch_resolve(const PlanView& P, int t, hipStream_t s);
-hipError_t launch_finish(const PlanView& P, hipStream_t s);
+hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s);
+hipError_t launch_accum(const PlanView& P, int D, int t0, int grid, hipStream_t s);
 hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s);
 hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s);
 hipError_t launch_backup_root(const PlanView& P, hipStream_t s);
-hipError_t launch_select(const PlanView& P, int last_step, hipStream_t s);
+hipError_t launch_select(const PlanView& P, hipStream_t s);
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s);
 // SIR update of P.f: weight, scan, resample (three launches).
 hipError_t launch_pf(const PlanView& P, int t, hipStream_t s);
+// Copy the records of beliefs ids[0..n) (device) to out[n * rs] (device).
+hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char* out,
+                         hipStream_t s);
 // One batched launch: n_blocks blocks over n_items phase items (device arrays).
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
                         int n_blocks, int amax, hipStream_t s);

@@ -158,7 +158,7 @@ void start_request(vopp_server* s, Episode& e, double arrival) {
   int* env;
   carve(e, &part, &prop, &w, &env);
   PlanView P = make_view(e.d.pomdp, e.res.ws, part, e.d.n_particles, e.d.budget, e.d.depth,
-                         &prm, kResTargetTiles);
+                         &prm);
   P.out = s->out_dev + (size_t)e.slot * kOutStride;
   P.f.part = part;
   P.f.prop = prop;
@@ -177,7 +177,7 @@ void start_request(vopp_server* s, Episode& e, double arrival) {
     e.phases.push_back({kPhasePFScan, 0, 0, 1});
     e.phases.push_back({kPhasePFResample, t, 0, pb});
   }
-  std::vector<Phase> plan = plan_phases(e.d.pomdp, P, kBackupCap);
+  std::vector<Phase> plan = plan_phases(e.d.pomdp, P, kAccumCap, kBackupCap);
   e.phases.insert(e.phases.end(), plan.begin(), plan.end());
   e.next = 0;
   e.waiting = false;
@@ -240,7 +240,8 @@ vopp_status harvest_one(vopp_server* s, bool wait) {
     v.episode = id;
     v.step = e.step;
     v.action = (int32_t)o[0];
-    v.status = o[A + 5] != 0.0 ? VOPP_E_INVALID : VOPP_OK;
+    const int flags = (int)o[A + 5];
+    v.status = (flags & 2) ? VOPP_E_INTERNAL : (flags & 1) ? VOPP_E_INVALID : VOPP_OK;
     v.v_root = o[A + 1];
     v.particle_steps = (int64_t)o[A + 2];
     v.arrival_s = e.arrival;

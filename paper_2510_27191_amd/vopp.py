@@ -29,7 +29,7 @@ EXPORTS = (
     "vopp_last_error", "vopp_version", "vopp_pomdp_tabular", "vopp_pomdp_nav2d",
     "vopp_pomdp_num_actions", "vopp_pomdp_free", "vopp_plan_footprint",
     "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
-    "vopp_tree_dump", "vopp_profile_enable", "vopp_profile_reset",
+    "vopp_tree_dump", "vopp_level_counts", "vopp_profile_enable", "vopp_profile_reset",
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
     "vopp_batch_num_launches", "vopp_batch_free", "vopp_plan_batch",
@@ -39,8 +39,8 @@ EXPORTS = (
 )
 MAX_ACTIONS = 64
 
-KERNEL_KINDS = ("expand", "resolve", "finish", "backup_leaf", "backup_level",
-                "backup_root", "setup", "select")
+KERNEL_KINDS = ("forward", "accumulate", "backup_leaf", "backup_level", "backup_root",
+                "setup", "select")
 
 
 class VoppError(RuntimeError):
@@ -91,7 +91,7 @@ class vopp_result(C.Structure):
 
 
 class vopp_tuning(C.Structure):
-    _fields_ = [("res_target_tiles", C.c_int32), ("backup_cap", C.c_int32)]
+    _fields_ = [("accum_cap", C.c_int32), ("backup_cap", C.c_int32)]
 
 
 class vopp_server_config(C.Structure):
@@ -148,6 +148,8 @@ def lib():
     L.vopp_plan.restype = st
     L.vopp_tree_dump.argtypes = [vp] * 11
     L.vopp_tree_dump.restype = st
+    L.vopp_level_counts.argtypes = [vp, vp, i32, C.POINTER(i32)]
+    L.vopp_level_counts.restype = st
     L.vopp_profile_enable.argtypes = [vp, i32]
     L.vopp_profile_enable.restype = st
     L.vopp_profile_reset.argtypes = [vp]
@@ -330,6 +332,15 @@ def tree_dump(ws, nA, n_beliefs, n_actions):
     return out
 
 
+def level_counts(ws):
+    """Beliefs created by each level step of the last plan in ws."""
+    n = C.c_int32(0)
+    _check(lib().vopp_level_counts(ws.handle, None, 0, C.byref(n)))
+    out = np.zeros(n.value, np.int32)
+    _check(lib().vopp_level_counts(ws.handle, _p(out), n.value, C.byref(n)))
+    return out
+
+
 def profile_enable(ws, kinds=None):
     """Bracket launches of the given kernel kinds (None: all; []: stop)."""
     if kinds is None:
@@ -414,7 +425,7 @@ class Batch:
         tu = vopp_tuning()
         _check(lib().vopp_batch_autotune(self.handle, C.c_void_p(stream.cuda_stream),
                                          int(reps), C.byref(tu)))
-        return (int(tu.res_target_tiles), int(tu.backup_cap))
+        return (int(tu.accum_cap), int(tu.backup_cap))
 
     def close(self):
         if self.handle:

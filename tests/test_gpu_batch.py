@@ -135,7 +135,7 @@ def test_autotune_keeps_results(V):
     ref = plain(V, items)
     batch = V.Batch(items)
     chosen = batch.autotune(reps=1)
-    assert chosen[0] in (64, 256, 1024) and chosen[1] in (256, 1024, 4096)
+    assert chosen[0] in (256, 1024, 4096) and chosen[1] in (256, 1024, 4096)
     res, _ = batch.run()
     for a, b in zip(res, ref):
         same(a, b)
