@@ -33,27 +33,27 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes of each kernel kind over one plan: every field the kernel
-# must touch in HBM-resident tree or trace arrays, counted once (model tables
-# are cache resident and not counted).  ra = |A| rounded up to a multiple of
-# 4; a belief record holds 24*ra + 32 used bytes.  The kernel table of
-# the design doc derives each term.
-#   forward, per particle-step: preference row 4|A| + table probe 8 + trace
-#     word and value 12; per new belief: key insert 8 + record 24*ra + 32;
-#     per episode and iteration: leaf trace 12.
-#   accumulate, per trace item: 12 read; per particle-step: N 8 + C 16
-#     (atomic read + write); per leaf (bounded by n_p per iteration): 24;
-#     per new belief: list entry 4.
+# must touch in HBM-resident tree, table or trace arrays, counted once (model
+# tables are cache resident and not counted).  ra = |A| rounded up to a
+# multiple of 4; a belief record holds 24*ra + 32 used bytes.  The kernel
+# table of the design doc derives each term.
+#   forward, per particle-step: preference row 4|A| + table slot 16 + N 8 and
+#     C 16 (atomic read + write) + trace word and value 12; per new belief:
+#     key insert 8 + record index 4 + list entry 4 + record 24*ra + 32; per
+#     episode and iteration: leaf count 8 and sum 16, leaf trace 12.
+#   accumulate, per trace item: 8 (the value only where the word is set).
+#     The visits it folds are counted under forward.
 #   backup_level, per belief of the swept depth: record 24*ra + 32 read, row
-#     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16,
-#     list entry 4.
+#     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16.
 #   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
-#     written, push 16, list entry 4.
+#     written, push 16.
 def plan_bytes(nA, n_p, K, depth, counts, particle_steps):
     ra = (nA + 3) // 4 * 4
     rec = 24 * ra + 32
     D = [min(k, depth) for k in range(1, K + 1)]
     t0 = np.concatenate([[0], np.cumsum(D)[:-1]]).astype(int)
     new_b = int(np.sum(counts))
+    items = sum((d + 1) * n_p for d in D)
 
     def beliefs_at(k, dep):       # beliefs of depth dep after iteration k (1-based)
         return sum(int(counts[t0[kk] + dep - 1]) for kk in range(k) if D[kk] >= dep)
@@ -62,11 +62,11 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps):
                 for dep in range(2, D[k - 1] + 1))
     leaf = sum(beliefs_at(k, D[k - 1]) for k in range(1, K + 1))
     return {
-        "forward": particle_steps * (4 * nA + 8 + 12) + new_b * (8 + rec) + K * n_p * 12,
-        "accumulate": sum((d + 1) * n_p * 12 for d in D) + particle_steps * 24
-                      + K * n_p * 24 + new_b * 4,
-        "backup_level": level * (rec + 4 * ra + 8 + 8 * nA + 16 + 4),
-        "backup_leaf": leaf * (32 + 24 + 16 + 4),
+        "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec)
+                   + K * n_p * (24 + 12),
+        "accumulate": items * 8,
+        "backup_level": level * (rec + 4 * ra + 8 + 8 * nA + 16),
+        "backup_leaf": leaf * (32 + 24 + 16),
     }
 
 

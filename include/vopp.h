@@ -134,9 +134,9 @@ typedef struct {
 /* A workspace holds one plan's tree and per-episode trace in HBM, sized for
  * the worst case (beliefs <= 1 + n_p * sum_k D_k <= 2^28), so no plan can
  * overflow it.  Each belief owns a record of 24*ra + 32 bytes rounded up to a
- * multiple of 128 (ra = |A| rounded up to a multiple of 4), addressed by its
- * slot in an open-addressing table of 2^ceil(log2(2*(1 + n_p*sum_k D_k)))
- * slots (load <= 1/2). */
+ * multiple of 128 (ra = |A| rounded up to a multiple of 4), stored by level
+ * step, and a 16-byte slot of an open-addressing table of
+ * 2^ceil(log2(2*(1 + n_p*sum_k D_k))) slots (load <= 1/2). */
 typedef struct vopp_workspace vopp_workspace;
 
 /* Bytes of device memory a workspace for (pomdp, params, budget, depth) needs. */
@@ -360,7 +360,7 @@ void vopp_server_free(vopp_server* s);
 /* Kernel kinds of a plan, in the order of vopp_profile_read's arrays. */
 enum {
   VOPP_KERNEL_FORWARD = 0,      /* all levels of one iteration's search      */
-  VOPP_KERNEL_ACCUMULATE = 1,   /* trace -> action nodes, leaves, lists      */
+  VOPP_KERNEL_ACCUMULATE = 1,   /* shallow and shared visits from the trace  */
   VOPP_KERNEL_BACKUP_LEAF = 2,  /* leaf values (Alg. 3, leaves)              */
   VOPP_KERNEL_BACKUP_LEVEL = 3, /* one depth of the backup (Alg. 3 loop)     */
   VOPP_KERNEL_BACKUP_ROOT = 4,  /* root backup in double precision           */

@@ -270,8 +270,8 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) 
 size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
   auto add = [&](size_t n) { b += align_up(n, 256); };
-  add((z.hcap + 1) * (size_t)z.rs);                  // belief records
-  add(z.hcap * 8);                                   // table keys
+  add((size_t)z.cap_b * z.rs);                       // belief records
+  add(z.hcap * sizeof(HSlot));                       // table
   add(kMaxA * 8); add(8);                            // root row, V(root)
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add((size_t)z.steps * 4); add((size_t)z.steps * 4);
@@ -301,10 +301,10 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   }
   Carver c(w->arena);
   TreeView& t = w->tree;
-  t.rec = c.take<unsigned char>((z.hcap + 1) * (size_t)z.rs);
+  t.rec = c.take<unsigned char>((size_t)z.cap_b * z.rs);
   t.rs = z.rs;
   t.ra = z.Apad;
-  t.h_key = c.take<unsigned long long>(z.hcap);
+  t.h_slot = c.take<HSlot>(z.hcap);
   t.h_mask = (uint32_t)(z.hcap - 1);
   t.psi_root = c.take<double>(kMaxA);
   t.v_root = c.take<double>(1);
@@ -485,7 +485,7 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   for (int k = 1; k <= K; ++k) {
     VOPP_TIMED(VOPP_KERNEL_FORWARD, launch_forward(P, k, D[k], s));
     VOPP_TIMED(VOPP_KERNEL_ACCUMULATE,
-               launch_accum(P, D[k], t, accum_blocks(P, D[k], kAccumCap), s));
+               launch_accum(P, D[k], accum_blocks(P, D[k], kAccumCap), s));
     if (e != hipSuccess) return hip_fail(e, "forward-search launch");
     t += D[k];
     VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
@@ -493,7 +493,7 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     for (int dep = D[k]; dep >= 2; --dep)
       VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
                  launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap), s));
-    VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, s));
+    VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, k, s));
     if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
   VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, s));
@@ -643,9 +643,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
       const int D = w->last_schedule == VOPP_SCHEDULE_FIXED ? w->last_depth
                                                            : std::min(k, w->last_depth);
       for (int d = 0; d < D; ++d, ++t) {
-        const size_t at = ids.size();
-        ids.resize(at + cnt[t]);
-        cp(ids.data() + at, w->tree.list + (size_t)t * n_p, (size_t)cnt[t] * 4);
+        for (int j = 0; j < cnt[t]; ++j) ids.push_back(1 + t * n_p + j);
         depth.resize(ids.size(), d + 1);
       }
     }
@@ -655,7 +653,8 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   if ((long long)nb != w->n_prev_beliefs)
     return fail(VOPP_E_INTERNAL, "tree dump: %zu listed beliefs, %d counted", nb,
                 w->n_prev_beliefs);
-  // Gather the records on the device, then copy them.
+  // Gather the records on the device (one contiguous run per level step),
+  // then copy them.
   std::vector<unsigned char> rec(nb * (size_t)rs);
   int* ids_dev = nullptr;
   unsigned char* rec_dev = nullptr;

@@ -19,22 +19,39 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 
 // Belief keys of the open-addressing table (AppendBeliefs):
 //   bits  0..19  observation key      bits 20..25  action
-//   bits 26..55  parent belief id     bits 56..63  iteration that inserted it
-// A belief's id is its table slot + 1 (the root is id 0), so every episode
-// that reaches a belief knows its id as soon as its probe ends, without
-// waiting for a numbering pass.  The iteration stamp tells whether the
-// belief's record was written by an earlier kernel (then its preference row
-// may be read) or is being created by this one (then the row is psi0).
+//   bits 26..55  parent's slot id     bits 56..63  iteration that inserted it
+// A belief's slot id is its table slot + 1 (the root is 0): every episode that
+// reaches a belief knows it as soon as its probe ends, without waiting for a
+// numbering pass, so one launch can run every level.  The iteration stamp
+// tells whether the belief was inserted by an earlier kernel (then its record
+// exists and may be read) or by this one (then its preference row is psi0).
+// Records are stored densely by creation (level step, position); the
+// inserting episode takes the next position of its level step and stores the
+// record index in the slot for later kernels.
 constexpr int kObsBits = 20;
 constexpr int kMaxObs = 1 << kObsBits;
 constexpr int kStampShift = 56;
 constexpr unsigned long long kStampMask = 0xFFull << kStampShift;
-constexpr long long kMaxBeliefs = 1ll << 28;   // ids stay below 2^29 + 1
+constexpr unsigned long long kSidMask = (1ull << 30) - 1;
+constexpr long long kMaxBeliefs = 1ll << 28;   // slot ids stay below 2^29 + 1
 
-// Trace words written by the forward kernel, one per (level, episode):
-//   level d < D: (belief id << 6) | action;  leaf (d = D): belief id;
-//   kTraceNew: this episode inserted that belief;  kEmptyKey: no step.
-constexpr unsigned long long kTraceNew = 1ull << 61;
+struct HSlot {
+  unsigned long long key;
+  int id;                    // record index (valid in later kernels)
+  int pad;
+};
+
+// Trace words written by the forward kernel, one per (level, episode), for
+// the visits it does not count itself (the two shallowest levels, which many
+// episodes share, and beliefs another episode inserted in this iteration):
+//   level d < D: (id << 6) | action;  leaf (d = D): id;
+//   kTraceRec: id is a record index, else a slot id;  kEmptyKey: nothing.
+constexpr unsigned long long kTraceRec = 1ull << 62;
+constexpr int kDirectLevel = 2;             // levels >= this count in place
+
+// Parent link of a record: (record << 6) | action, or kLinkSlot | (slot id
+// << 6) | action while the parent's record is not known yet; ~0 for the root.
+constexpr unsigned long long kLinkSlot = 1ull << 62;
 
 enum : uint32_t { kTagRoot = 1, kTagStep = 2, kTagEnv = 4, kTagPF = 5, kTagResample = 6 };
 enum : int { kTabular = 0, kNav = 1 };
@@ -76,24 +93,26 @@ struct RecMeta {
 };
 
 // The tree store in HBM.  Each belief owns one record of rs bytes (a multiple
-// of the 128-byte cache line), addressed by its id; with ra = |A| rounded up
-// to a multiple of 4 the record holds
+// of the 128-byte cache line); with ra = |A| rounded up to a multiple of 4 it
+// holds
 //   Psi[ra] f32 | N[ra] i32 | C[ra] i64 | W[ra] i64 | RecMeta
 // where N, C (cumulative reward) and W (sum of V*N_b over the child beliefs)
 // are the action nodes (b, a) of tensor A, stored with their parent belief.
-// C, W and the leaf sums are 64-bit two's-complement fixed point.  The root
-// (id 0) keeps its preference row in double precision in psi_root.
+// C, W and the leaf sums are 64-bit two's-complement fixed point.  Record 0 is
+// the root (its preference row is kept in double precision in psi_root);
+// the beliefs created by level step t occupy records 1 + t*n_p + [0, cnt[t]),
+// so one depth of the tree is a few contiguous runs of records.
 struct TreeView {
-  unsigned char* rec;            // [(h_mask + 2) * rs]
+  unsigned char* rec;            // [(1 + steps * n_p) * rs]
   int rs, ra;
-  unsigned long long* h_key;     // [h_mask + 1] open-addressing table
+  HSlot* h_slot;                 // [h_mask + 1] open-addressing table
   uint32_t h_mask;
   double* psi_root;              // [nA]
   double* v_root;                // [1]
-  int* list;                     // [steps * n_p]: ids created by each level step
+  int* list;                     // [steps * n_p]: slot ids created by each level step
   int* cnt;                      // [steps] lengths of this plan's lists
   int* cnt_prev;                 // [steps] lengths of the previous plan's lists
-  unsigned long long* counters;  // [0] particle steps [1] input errors
+  unsigned long long* counters;  // [0] particle steps [1] error flags
                                  // [2] beliefs of the last plan [3] table dirty
                                  // [4] action nodes [5] last plan's level steps
                                  // [6] last plan's list stride

@@ -5,14 +5,14 @@
 //   forward     one thread per episode runs every level of the vectorized
 //               forward search (Alg. 2) with its state in registers: draw the
 //               action from the softmax of the belief's preferences (Eq. 6),
-//               call G, and find or insert the child belief (belief, action,
-//               observation) in the open-addressing table.  A belief's id is
-//               its table slot, so no episode ever waits for another, and one
-//               launch covers all D_k levels.  Each step goes to a trace.
-//   accumulate  folds the trace into the tree: visit counts and reward sums of
-//               the action nodes (AppendActions), this iteration's leaf visits
-//               and heuristic sums, and the new beliefs into per-level-step
-//               lists (AppendBeliefs) that the backup sweeps.
+//               call G, count the visit and reward into the action node
+//               (AppendActions), and find or insert the child belief
+//               (belief, action, observation) in the open-addressing table
+//               (AppendBeliefs).  A belief is named by its table slot, so no
+//               episode ever waits for another and one launch covers all D_k
+//               levels; the inserting episode also takes the belief's record.
+//               Visits it cannot count in place go to a trace.
+//   accumulate  folds the trace into the records (LDS-aggregated atomics).
 //   backup      Alg. 3, one phase per depth over every belief of that depth:
 //               leaves take their mean heuristic, internal beliefs update their
 //               preference row with Q = C/N + gamma W and V = L_eta Psi, and
@@ -20,8 +20,9 @@
 //               accumulator.  The root runs in double precision.
 //
 // All cross-episode sums (rewards, heuristics, V*N_b) are 64-bit fixed-point
-// integer atomics, so the results do not depend on thread order; the tree's
-// ids depend on the order of insertions, its content does not.
+// integer atomics, so the results do not depend on thread order; which slot
+// and record a belief gets depends on the order of insertions, the tree and
+// every value in it do not.
 //
 // Every phase is a __device__ function of (plan view, block index within the
 // phase, block count of the phase).  The single-plan path launches one kernel
@@ -38,32 +39,40 @@ namespace vopp {
 // ---------------------------------------------------------------------------
 // Open-addressing table (linear probing, load <= 1/2).  Finds or inserts key;
 // the inserting thread writes key | stamp.  Returns the slot, or ~0u if the
-// table has no free slot left (an internal error, reported by the plan).
+// table has no free slot left (an internal error, reported by the plan).  A
+// slot is read with one plain 16-byte load: keys and record indices written
+// by earlier kernels are visible to it; a key being inserted by this kernel
+// may read as empty, and then the compare-and-swap returns it.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t probe(const TreeView& t, unsigned long long key,
                                           unsigned long long stamp, bool& won,
-                                          bool& fresh) {
+                                          bool& fresh, int& id) {
   uint32_t h = (uint32_t)mix64(key) & t.h_mask;
   for (uint32_t n = 0; n <= t.h_mask; ++n) {
-    unsigned long long cur = __hip_atomic_load(&t.h_key[h], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+    const uint4 v = *reinterpret_cast<const uint4*>(&t.h_slot[h]);
+    unsigned long long cur = ((unsigned long long)v.y << 32) | v.x;
+    bool reread = false;
     if (cur == kEmptyKey) {
-      cur = atomicCAS(&t.h_key[h], kEmptyKey, key | stamp);
+      cur = atomicCAS(&t.h_slot[h].key, kEmptyKey, key | stamp);
       if (cur == kEmptyKey) {
         won = true;
         fresh = true;
+        id = -1;
         return h;
       }
+      reread = true;
     }
     if ((cur & ~kStampMask) == key) {
       won = false;
       fresh = (cur & kStampMask) == stamp;
+      id = fresh ? -1 : (reread ? t.h_slot[h].id : (int)v.z);
       return h;
     }
     h = (h + 1) & t.h_mask;
   }
   won = false;
   fresh = false;
+  id = -1;
   return ~0u;
 }
 
@@ -141,15 +150,15 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
   const size_t tid = (size_t)blk * kBlock + threadIdx.x;
   const size_t stride = (size_t)nblk * kBlock;
   if (full) {
-    uint4* hk = reinterpret_cast<uint4*>(T.h_key);
+    uint4* hs = reinterpret_cast<uint4*>(T.h_slot);
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (size_t i = tid; i < hcap / 2; i += stride) hk[i] = ones;
+    for (size_t i = tid; i < hcap; i += stride) hs[i] = ones;
   } else {
     const int prev_steps = (int)T.counters[5];
     const size_t lstride = (size_t)T.counters[6];
     for (int t = 0; t < prev_steps; ++t) {
       const size_t n = (size_t)T.cnt_prev[t];
-      for (size_t i = tid; i < n; i += stride) T.h_key[T.list[t * lstride + i] - 1] = kEmptyKey;
+      for (size_t i = tid; i < n; i += stride) T.h_slot[T.list[t * lstride + i] - 1].key = kEmptyKey;
     }
   }
   for (size_t i = tid; i < (size_t)P.steps; i += stride) T.cnt[i] = 0;
@@ -178,9 +187,10 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
 // Phase: the forward search of iteration k over D levels (Alg. 2).
 // ---------------------------------------------------------------------------
 
-// A new belief's record: Psi = psi0 (Eq. 6 starts uniform), N = C = W = 0.
-__device__ __forceinline__ void init_record(const PlanView& P, int id, int parent, int a,
-                                            int obs) {
+// A new belief's record: Psi = psi0 (Eq. 6 starts uniform), N = C = W = 0,
+// its observation key and its parent link.
+__device__ __forceinline__ void init_record(const PlanView& P, int id, int obs,
+                                            unsigned long long link) {
   const TreeView& T = P.t;
   uint4* q = reinterpret_cast<uint4*>(rec_at(T, id));
   const int ra = T.ra, A = P.m.nA;
@@ -191,14 +201,14 @@ __device__ __forceinline__ void init_record(const PlanView& P, int id, int paren
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   const int meta_q = 6 * ra / 4;                // N, C and W take 5*ra/4 quads
   for (int i = ra / 4; i < meta_q; ++i) q[i] = z;
-  const unsigned long long par = ((unsigned long long)(uint32_t)parent << 6) | (uint32_t)a;
-  q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);                 // V, N_b, leaf_cnt, obs
-  q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)par, (uint32_t)(par >> 32));   // leaf_h, parent
+  q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);            // V, N_b, leaf_cnt, obs
+  q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));  // leaf_h, parent
 }
 
 template <int AM>
 __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
   const TreeView& T = P.t;
+  const int t0 = T.step_base[k - 1];          // level step of level 0
   const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
   const int A = P.m.nA;
@@ -206,9 +216,9 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
   const unsigned long long stamp = (unsigned long long)(k - 1) << kStampShift;
   int s = 0;
   float x = 0.0f, y = 0.0f;
-  int b = 0;                  // current belief id (0: root)
-  bool fresh = false;         // b was inserted during this iteration
-  bool made = false;          // ... by this episode
+  int sid = 0;                // current belief's slot id (0: root)
+  int rid = 0;                // its record, -1 if another episode inserted it
+                              // during this iteration (its row is then psi0)
   bool alive = false;
   if (ep_ok) {
     // Alg. 1: the episode starts at the root with a state drawn from the
@@ -229,16 +239,20 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
     alive = true;
   }
   unsigned long long g = 0;   // generative-model calls of this episode
+  const int lane = threadIdx.x & 63;
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey;
     float r = 0.0f;
+    bool won = false;
+    int obs = 0;
+    uint32_t h = 0;
+    unsigned long long link = kEmptyKey;
     if (alive) {
       const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
       int a;
-      if (b == 0) a = draw_action64(T.psi_root, A, P.eta64, w.x);
-      else if (fresh) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
-      else a = draw_action32<AM>(rec_psi(T, b), A, P.eta, w.x);
-      int obs;
+      if (sid == 0) a = draw_action64(T.psi_root, A, P.eta64, w.x);
+      else if (rid < 0) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
+      else a = draw_action32<AM>(rec_psi(T, rid), A, P.eta, w.x);
       bool term = false;
       if (P.m.kind == kTabular) {
         int sn;
@@ -250,23 +264,30 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
         x = nx;
         y = ny;
       }
-      tk = ((unsigned long long)(uint32_t)b << 6) | (uint32_t)a;
-      if (made) tk |= kTraceNew;
       ++g;
+      // AppendActions: visit count and reward sum of (b, a).
+      if (d >= kDirectLevel && rid >= 0) {
+        atomicAdd(&rec_n(T, rid)[a], 1);
+        const unsigned long long fx = to_fix(r, P.fix_scale);
+        if (fx) atomicAdd(&rec_c(T, rid)[a], fx);
+      } else {
+        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a | kTraceRec)
+                      : (((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
+      }
+      link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a)
+                      : (kLinkSlot | ((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
       if (term) {
         alive = false;                          // FilterTerminals
       } else {
-        bool won, fr;
-        const uint32_t h = probe(T, belief_key(b, a, obs), stamp, won, fr);
+        bool fr;
+        int id;
+        h = probe(T, belief_key(sid, a, obs), stamp, won, fr, id);
         if (h == ~0u) {                         // table full: stop and report
           atomicOr((unsigned int*)&T.counters[1], 2u);
           alive = false;
         } else {
-          const int c = (int)h + 1;
-          if (won) init_record(P, c, b, a, obs);
-          b = c;
-          fresh = fr;
-          made = won;
+          sid = (int)h + 1;
+          rid = id;                             // -1 while fresh
         }
       }
     }
@@ -274,38 +295,64 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
       T.tr_key[(size_t)d * n_p + ep] = tk;
       T.tr_val[(size_t)d * n_p + ep] = r;
     }
+    // AppendBeliefs: each inserted belief takes the next record of this level
+    // step, one atomic per wavefront.
+    const unsigned long long m = __ballot(won);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      const int t = t0 + d;
+      int at = 0;
+      if (lane == leader) at = atomicAdd(&T.cnt[t], __popcll(m));
+      at = __shfl(at, leader, 64);
+      if (won) {
+        const int j = at + __popcll(m & ((1ull << lane) - 1ull));
+        rid = 1 + t * P.n_p + j;
+        T.list[(size_t)t * n_p + j] = sid;
+        T.h_slot[h].id = rid;
+        init_record(P, rid, obs, link);
+      }
+    }
   }
   if (ep_ok) {
     unsigned long long tk = kEmptyKey;
-    float h = 0.0f;                             // ValueHeuristic of the leaf state
+    float hv = 0.0f;                            // ValueHeuristic of the leaf state
     if (alive) {
-      tk = (unsigned long long)(uint32_t)b | (made ? kTraceNew : 0ull);
       if (P.m.kind == kTabular) {
-        if (P.m.H) h = P.m.H[s];
+        if (P.m.H) hv = P.m.H[s];
       } else {
-        h = nav_heuristic(P.m.nav, x, y);
+        hv = nav_heuristic(P.m.nav, x, y);
+      }
+      if (D >= kDirectLevel && rid >= 0) {
+        RecMeta* mt = rec_meta(T, rid);
+        atomicAdd(&mt->leaf_cnt, 1);
+        const unsigned long long fx = to_fix(hv, P.fix_scale);
+        if (fx) atomicAdd(&mt->leaf_h, fx);
+      } else {
+        tk = rid >= 0 ? ((unsigned long long)(uint32_t)rid | kTraceRec)
+                      : (unsigned long long)(uint32_t)sid;
       }
     }
     T.tr_key[(size_t)D * n_p + ep] = tk;
-    T.tr_val[(size_t)D * n_p + ep] = h;
+    T.tr_val[(size_t)D * n_p + ep] = hv;
   }
   g = wave_sum(g);
   if ((threadIdx.x & 63) == 0 && g) atomicAdd(&T.counters[0], g);
 }
 
 // ---------------------------------------------------------------------------
-// Phase: fold the trace of an iteration with D levels into the tree.  Trace
-// item i is level i / n_p; level-step t0 + d created the beliefs of depth
-// d + 1.  Aggregation keys: (id << 7) | (a << 1) for action nodes, (id << 7) | 1
+// Phase: fold the trace of an iteration with D levels into the records.
+// Aggregation keys: (record << 7) | (a << 1) for action nodes, (record << 7) | 1
 // for leaves.
 // ---------------------------------------------------------------------------
-__device__ void dev_accum(const PlanView& P, int D, int t0, int blk, int nblk, Smem& sm) {
+__device__ __forceinline__ int record_of(const TreeView& T, int sid) {
+  return sid == 0 ? 0 : T.h_slot[sid - 1].id;
+}
+
+__device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm) {
   const TreeView& T = P.t;
   AggTable& G = sm.agg;
   const long long n_p = P.n_p;
   const long long total = (long long)(D + 1) * n_p;
-  const int lane = threadIdx.x & 63;
-  unsigned long long new_nodes = 0;
   for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
     const long long i = base + threadIdx.x;
     unsigned long long tk = kEmptyKey;
@@ -313,60 +360,45 @@ __device__ void dev_accum(const PlanView& P, int D, int t0, int blk, int nblk, S
     int lvl = 0;
     if (i < total) {
       tk = T.tr_key[i];
-      v = T.tr_val[i];
       lvl = (int)(i / n_p);
     }
     const bool has = tk != kEmptyKey;
-    bool pend = has && (tk & kTraceNew);
-    const unsigned long long body = tk & ~kTraceNew;
     const bool leaf = lvl == D;
-    const int id = has ? (int)(leaf ? body : body >> 6) : -1;
-    // AppendBeliefs: the inserting episode files the belief under its level
-    // step, one atomic per wavefront and level.
-    while (true) {
-      const unsigned long long m = __ballot(pend);
-      if (!m) break;
-      const int leader = __ffsll((long long)m) - 1;
-      const int L = __shfl(lvl, leader, 64);
-      const bool mine = pend && lvl == L;
-      const unsigned long long grp = __ballot(mine);
-      int at = 0;
-      if (lane == leader) at = atomicAdd(&T.cnt[t0 + L - 1], __popcll(grp));
-      at = __shfl(at, leader, 64);
-      if (mine) {
-        T.list[(size_t)(t0 + L - 1) * n_p + at + __popcll(grp & ((1ull << lane) - 1ull))] = id;
-        pend = false;
-      }
-    }
-    agg_clear(G);
-    __syncthreads();
+    unsigned long long key = kEmptyKey;
     if (has) {
-      const unsigned long long key =
-          leaf ? (((unsigned long long)(uint32_t)id << 7) | 1ull) : (body << 1);
-      const int sl = agg_slot(G, key);
-      atomicAdd(&G.a[sl], 1ull);
-      const unsigned long long fx = to_fix(v, P.fix_scale);
-      if (fx) atomicAdd(&G.b[sl], fx);
+      v = T.tr_val[i];
+      const unsigned long long body = tk & ~kTraceRec;
+      const int id = (int)(leaf ? body : body >> 6);
+      const int rid = (tk & kTraceRec) ? id : record_of(T, id);
+      key = ((unsigned long long)(uint32_t)rid << 7) | (leaf ? 1ull : ((body & 63ull) << 1));
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
-      const unsigned long long key = G.key[j];
-      if (key == kEmptyKey) continue;
-      const int nid = (int)(key >> 7);
-      if (key & 1ull) {
-        RecMeta* mt = rec_meta(T, nid);
-        atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
-        if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
-      } else {
-        const int a = (int)((key >> 1) & 63ull);
-        if (atomicAdd(&rec_n(T, nid)[a], (int)G.a[j]) == 0) ++new_nodes;
-        if (G.b[j]) atomicAdd(&rec_c(T, nid)[a], G.b[j]);
+    if (__syncthreads_or(has)) {
+      agg_clear(G);
+      __syncthreads();
+      if (has) {
+        const int sl = agg_slot(G, key);
+        atomicAdd(&G.a[sl], 1ull);
+        const unsigned long long fx = to_fix(v, P.fix_scale);
+        if (fx) atomicAdd(&G.b[sl], fx);
       }
+      __syncthreads();
+      for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+        const unsigned long long k2 = G.key[j];
+        if (k2 == kEmptyKey) continue;
+        const int rid = (int)(k2 >> 7);
+        if (k2 & 1ull) {
+          RecMeta* mt = rec_meta(T, rid);
+          atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
+          if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
+        } else {
+          const int a = (int)((k2 >> 1) & 63ull);
+          atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
+          if (G.b[j]) atomicAdd(&rec_c(T, rid)[a], G.b[j]);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  new_nodes = wave_sum(new_nodes);
-  if (lane == 0 && new_nodes) atomicAdd(&T.counters[4], new_nodes);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,18 +425,29 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, R
   __syncthreads();
 }
 
-// Belief id of the i-th belief of the ranges.
+// The parent link of a record, resolved to (record << 6) | a (written back).
+__device__ __forceinline__ unsigned long long parent_link(const TreeView& T, RecMeta* mt) {
+  unsigned long long par = mt->parent;
+  if (par != kEmptyKey && (par & kLinkSlot)) {
+    const int psid = (int)((par & ~kLinkSlot) >> 6);
+    par = ((unsigned long long)(uint32_t)record_of(T, psid) << 6) | (par & 63ull);
+    mt->parent = par;
+  }
+  return par;
+}
+
+// Record of the i-th belief of the ranges.
 __device__ __forceinline__ int range_id(const PlanView& P, const Ranges& R, int i) {
   int lo = 0, hi = R.n - 1;          // last r with off[r] <= i
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (R.off[mid] <= i) lo = mid; else hi = mid - 1;
   }
-  return P.t.list[(size_t)R.step[lo] * (size_t)P.n_p + (size_t)(i - R.off[lo])];
+  return 1 + R.step[lo] * P.n_p + (i - R.off[lo]);
 }
 
 // Push V*N_b of a belief into its parent action's W accumulator (parent =
-// (id << 6) | a, or kEmptyKey for none), aggregated per block.  Called by
+// (record << 6) | a, or kEmptyKey for none), aggregated per block.  Called by
 // every thread of the block (it contains barriers).
 __device__ __forceinline__ void push_values(const PlanView& P, AggTable& G,
                                             unsigned long long parent, float V, int N) {
@@ -449,7 +492,7 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
         V = mt->V;
         N = mt->Nb;
       }
-      parent = mt->parent;
+      parent = parent_link(P.t, mt);
     }
     push_values(P, sm.agg, parent, V, N);
   }
@@ -464,6 +507,7 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
   const int total = R.off[R.n];
   const int A = P.m.nA;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
+  unsigned long long nodes = 0;               // action nodes (last iteration)
   for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
     const int i = base + threadIdx.x;
     int N = 0;
@@ -541,14 +585,20 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
         V = mt->V;
         N = mt->Nb;
       }
-      parent = mt->parent;
+      parent = parent_link(P.t, mt);
+      if (k == P.K) {                           // tree statistics, once
+#pragma unroll
+        for (int j = 0; j < AM; ++j) nodes += (j < A && n[j] > 0) ? 1ull : 0ull;
+      }
     }
     push_values(P, sm.agg, parent, V, N);
   }
+  nodes = wave_sum(nodes);
+  if ((threadIdx.x & 63) == 0 && nodes) atomicAdd(&P.t.counters[4], nodes);
 }
 
 // The root row in double precision, updated in place (one thread).
-__device__ void dev_backup_root(const PlanView& P) {
+__device__ void dev_backup_root(const PlanView& P, int k) {
   if (threadIdx.x != 0) return;
   const int A = P.m.nA;
   double* psi = P.t.psi_root;
@@ -558,10 +608,12 @@ __device__ void dev_backup_root(const PlanView& P) {
   const double vc = lse64(psi, A, P.eta64);
   long long nsum = 0;
   bool any = false;
+  int nodes = 0;
   for (int j = 0; j < A; ++j) {
     const int n = nrow[j];
     if (n <= 0) continue;
     any = true;
+    ++nodes;
     const double c = (double)(long long)crow[j] * P.fix_inv64;
     const double w = (double)(long long)wrow[j] * P.fix_inv64;
     wrow[j] = 0ull;
@@ -569,6 +621,7 @@ __device__ void dev_backup_root(const PlanView& P) {
     psi[j] = (psi[j] - vc) + q;
     nsum += n;
   }
+  if (k == P.K) atomicAdd(&P.t.counters[4], (unsigned long long)nodes);
   if (!any) return;
   const double v = lse64(psi, A, P.eta64);
   P.t.v_root[0] = v;
@@ -788,9 +841,9 @@ template <int AM>
 __global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
   dev_forward<AM>(P, k, D, blockIdx.x);
 }
-__global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D, int t0) {
+__global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D) {
   __shared__ Smem sm;
-  dev_accum(P, D, t0, blockIdx.x, gridDim.x, sm);
+  dev_accum(P, D, blockIdx.x, gridDim.x, sm);
 }
 __global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
   __shared__ Smem sm;
@@ -801,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
   __shared__ Smem sm;
   dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
-__global__ void k_backup_root(PlanView P) { dev_backup_root(P); }
+__global__ void k_backup_root(PlanView P, int k) { dev_backup_root(P, k); }
 __global__ __launch_bounds__(kBlock) void k_select(PlanView P) {
   __shared__ Smem sm;
   dev_select(P, sm);
@@ -837,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
         else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk);
       }
       break;
-    case kPhaseAccum: dev_accum(P, it.a0, it.a1, blk, it.nblk, sm); break;
+    case kPhaseAccum: dev_accum(P, it.a0, blk, it.nblk, sm); break;
     case kPhaseLeaf: dev_backup_leaf(P, it.a0, it.a1, blk, it.nblk, sm); break;
     case kPhaseLevel:
       if (Apad <= 4) {
@@ -847,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
         else if constexpr (AMAX >= 16) dev_backup_level<16>(P, it.a0, it.a1, blk, it.nblk, sm);
       }
       break;
-    case kPhaseRoot: dev_backup_root(P); break;
+    case kPhaseRoot: dev_backup_root(P, it.a0); break;
     case kPhaseSelect: dev_select(P, sm); break;
     case kPhaseEnv: dev_env(P, it.a0); break;
     case kPhasePFWeight: dev_pf_weight(P, it.a0, blk); break;
@@ -863,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
 static inline int blocks_for(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 int setup_blocks(const PlanView& P) {
-  const long long work = ((long long)P.t.h_mask + 1) / 2;   // 16-byte stores
+  const long long work = (long long)P.t.h_mask + 1;         // 16-byte stores
   long long g = (work + kBlock * 8 - 1) / (kBlock * 8);
   return (int)std::max(1ll, std::min(g, 1024ll));
 }
@@ -889,8 +942,8 @@ hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   else hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
   return hipGetLastError();
 }
-hipError_t launch_accum(const PlanView& P, int D, int t0, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D, t0);
+hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D);
   return hipGetLastError();
 }
 hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
@@ -907,8 +960,8 @@ hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipS
   else hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
   return hipGetLastError();
 }
-hipError_t launch_backup_root(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P);
+hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
   return hipGetLastError();
 }
 hipError_t launch_select(const PlanView& P, hipStream_t s) {

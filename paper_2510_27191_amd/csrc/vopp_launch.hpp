@@ -8,14 +8,14 @@ namespace vopp {
 
 int setup_blocks(const PlanView& P);
 int forward_blocks(const PlanView& P);
-// Blocks of the accumulate sweep of an iteration with D levels (at most cap).
+// Blocks of a sweep over the trace of an iteration with D levels (at most cap).
 int accum_blocks(const PlanView& P, int D, int cap);
 hipError_t launch_setup(const PlanView& P, hipStream_t s);
 hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s);
-hipError_t launch_accum(const PlanView& P, int D, int t0, int grid, hipStream_t s);
+hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s);
 hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s);
 hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s);
-hipError_t launch_backup_root(const PlanView& P, hipStream_t s);
+hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s);
 hipError_t launch_select(const PlanView& P, hipStream_t s);
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s);
 // SIR update of P.f: weight, scan, resample (three launches).
