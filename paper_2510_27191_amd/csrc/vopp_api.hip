@@ -274,8 +274,7 @@ size_t bytes_for(const WsSizes& z) {
   add(z.hcap * sizeof(HSlot));                       // table
   add(kMaxA * 8); add(8);                            // root row, V(root)
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
-  add((size_t)z.steps * 4); add((size_t)z.steps * 4);
-  add(64); add((z.K + 1) * 4);
+  add(64); add(3 * kStripes * 8); add((z.K + 1) * 4);
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
   add(256 * 8);
@@ -309,9 +308,8 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.psi_root = c.take<double>(kMaxA);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
-  t.cnt = c.take<int>(z.steps);
-  t.cnt_prev = c.take<int>(z.steps);
   t.counters = c.take<unsigned long long>(8);
+  t.stats = c.take<unsigned long long>(3 * kStripes);
   int* step_base = c.take<int>(z.K + 1);
   t.step_base = step_base;
   w->step_base_dev = step_base;
@@ -439,12 +437,11 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
 // Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
                 int cap) {
-  int iters = 0;
+  (void)p;
+  // One thread per record position of the level steps that hold depth dep.
+  long long iters = 0;
   for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
-  double bound = (double)n_p * iters;
-  const double tree = std::pow(p->branch, (double)dep);
-  if (tree < bound) bound = tree;
-  long long g = (long long)std::ceil(bound / kBlock);
+  const long long g = (n_p * iters + kBlock - 1) / kBlock;
   return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 
@@ -634,8 +631,8 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   };
   // Beliefs with their depth: the root, then each level step's list (level d
   // creates depth d + 1).
-  std::vector<int> cnt(steps);
-  cp(cnt.data(), w->tree.cnt, cnt.size() * 4);
+  std::vector<int> list((size_t)steps * n_p);
+  cp(list.data(), w->tree.list, list.size() * 4);
   std::vector<int> ids{0}, depth{0};
   {
     int t = 0;
@@ -643,7 +640,8 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
       const int D = w->last_schedule == VOPP_SCHEDULE_FIXED ? w->last_depth
                                                            : std::min(k, w->last_depth);
       for (int d = 0; d < D; ++d, ++t) {
-        for (int j = 0; j < cnt[t]; ++j) ids.push_back(1 + t * n_p + j);
+        for (int j = 0; j < n_p; ++j)
+          if (list[(size_t)t * n_p + j]) ids.push_back(1 + t * n_p + j);
         depth.resize(ids.size(), d + 1);
       }
     }
@@ -653,8 +651,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   if ((long long)nb != w->n_prev_beliefs)
     return fail(VOPP_E_INTERNAL, "tree dump: %zu listed beliefs, %d counted", nb,
                 w->n_prev_beliefs);
-  // Gather the records on the device (one contiguous run per level step),
-  // then copy them.
+  // Gather the records on the device, then copy them.
   std::vector<unsigned char> rec(nb * (size_t)rs);
   int* ids_dev = nullptr;
   unsigned char* rec_dev = nullptr;
@@ -746,9 +743,17 @@ extern "C" vopp_status vopp_level_counts(const vopp_workspace* w, int32_t* count
   *n_steps = w->last_steps;
   const int n = std::min(cap, w->last_steps);
   if (counts && n > 0) {
+    const size_t n_p = (size_t)w->last_n_p;
+    std::vector<int> list((size_t)n * n_p);
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(counts, w->tree.cnt, (size_t)n * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(list.data(), w->tree.list, list.size() * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "level counts");
+    for (int t = 0; t < n; ++t) {
+      int c = 0;
+      for (size_t j = 0; j < n_p; ++j) c += list[t * n_p + j] != 0;
+      counts[t] = c;
+    }
   }
   return VOPP_OK;
 }

@@ -25,9 +25,10 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 // numbering pass, so one launch can run every level.  The iteration stamp
 // tells whether the belief was inserted by an earlier kernel (then its record
 // exists and may be read) or by this one (then its preference row is psi0).
-// Records are stored densely by creation (level step, position); the
-// inserting episode takes the next position of its level step and stores the
-// record index in the slot for later kernels.
+// Records are stored by creation: the belief that episode ep inserts at level
+// step t owns record 1 + t*n_p + ep (an episode inserts at most one belief per
+// level step), so no episode allocates anything; the inserting episode stores
+// the record index in the slot for later kernels.
 constexpr int kObsBits = 20;
 constexpr int kMaxObs = 1 << kObsBits;
 constexpr int kStampShift = 56;
@@ -99,9 +100,10 @@ struct RecMeta {
 // where N, C (cumulative reward) and W (sum of V*N_b over the child beliefs)
 // are the action nodes (b, a) of tensor A, stored with their parent belief.
 // C, W and the leaf sums are 64-bit two's-complement fixed point.  Record 0 is
-// the root (its preference row is kept in double precision in psi_root);
-// the beliefs created by level step t occupy records 1 + t*n_p + [0, cnt[t]),
-// so one depth of the tree is a few contiguous runs of records.
+// the root (its preference row is kept in double precision in psi_root); the
+// beliefs created by level step t occupy records 1 + t*n_p + [0, n_p), where
+// list[t*n_p + ep] says which positions are used, so one depth of the tree is
+// a few contiguous runs of records.
 struct TreeView {
   unsigned char* rec;            // [(1 + steps * n_p) * rs]
   int rs, ra;
@@ -109,13 +111,14 @@ struct TreeView {
   uint32_t h_mask;
   double* psi_root;              // [nA]
   double* v_root;                // [1]
-  int* list;                     // [steps * n_p]: slot ids created by each level step
-  int* cnt;                      // [steps] lengths of this plan's lists
-  int* cnt_prev;                 // [steps] lengths of the previous plan's lists
-  unsigned long long* counters;  // [0] particle steps [1] error flags
-                                 // [2] beliefs of the last plan [3] table dirty
-                                 // [4] action nodes [5] last plan's level steps
-                                 // [6] last plan's list stride
+  int* list;                     // [steps * n_p]: slot id of the belief that
+                                 // episode ep inserted at level step t, or 0
+  unsigned long long* counters;  // [1] error flags [2] beliefs of the last plan
+                                 // [3] table dirty [5] last plan's level steps
+                                 // [6] last plan's n_p
+  unsigned long long* stats;     // [3][kStripes] particle steps, action nodes
+                                 // and beliefs, striped over blocks so that
+                                 // no address takes many atomics
   const int* step_base;          // [K+1] first level step of each iteration
   unsigned long long* tr_key;    // [(depth + 1) * n_p] trace words
   float* tr_val;                 // reward (levels) or heuristic (leaf)
@@ -151,6 +154,7 @@ struct EpisodeView {
 };
 
 constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
+constexpr int kStripes = 64;                // stripes of each tree statistic
 constexpr int kAccumCap = 4096;             // default block cap of the accumulate sweep
 
 // Particle-filter belief and true-environment state of a served episode.

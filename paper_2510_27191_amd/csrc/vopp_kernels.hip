@@ -99,12 +99,11 @@ struct AggTable {
   unsigned long long b[kAggSlots];
 };
 
-// Level-step lists holding the beliefs of one depth: level dep-1 of every
-// iteration that reached depth dep created one list.
+// Level steps holding the beliefs of one depth: level dep-1 of every
+// iteration that reached that depth created one run of n_p records.
 struct Ranges {
   int n;
   int step[kMaxRanges];
-  int off[kMaxRanges + 1];
 };
 
 struct Smem {
@@ -136,6 +135,20 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
+// Sum over the block; red holds kBlock / 64 words of LDS.  Called by every
+// thread of the block (it contains barriers); thread 0 gets the total.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v,
+                                                        unsigned long long* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // Phase: set-up of a plan.  Clears the belief table (a full fill, or only the
 // slots the previous plan used when that is cheaper), the list lengths and
@@ -154,19 +167,18 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (size_t i = tid; i < hcap; i += stride) hs[i] = ones;
   } else {
-    const int prev_steps = (int)T.counters[5];
-    const size_t lstride = (size_t)T.counters[6];
-    for (int t = 0; t < prev_steps; ++t) {
-      const size_t n = (size_t)T.cnt_prev[t];
-      for (size_t i = tid; i < n; i += stride) T.h_slot[T.list[t * lstride + i] - 1].key = kEmptyKey;
+    const size_t used = (size_t)T.counters[5] * (size_t)T.counters[6];
+    for (size_t i = tid; i < used; i += stride) {
+      const int sid = T.list[i];
+      if (sid) T.h_slot[sid - 1].key = kEmptyKey;
     }
   }
-  for (size_t i = tid; i < (size_t)P.steps; i += stride) T.cnt[i] = 0;
   if (blk == 0) {
     uint4* r = reinterpret_cast<uint4*>(T.rec);
     for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int j = threadIdx.x;
+    if (j < 3 * kStripes) T.stats[j] = 0ull;
     if (j < P.m.nA) {
       rec_psi(T, 0)[j] = P.psi0;
       T.psi_root[j] = P.psi0_64;
@@ -176,9 +188,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       mt->obs = -1;
       mt->parent = kEmptyKey;
       T.v_root[0] = 0.0;
-      T.counters[0] = 0ull;
       T.counters[1] = 0ull;
-      T.counters[4] = 0ull;
     }
   }
 }
@@ -206,7 +216,8 @@ __device__ __forceinline__ void init_record(const PlanView& P, int id, int obs,
 }
 
 template <int AM>
-__device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
+__device__ void dev_forward(const PlanView& P, int k, int D, int blk,
+                            unsigned long long* red) {
   const TreeView& T = P.t;
   const int t0 = T.step_base[k - 1];          // level step of level 0
   const int ep = blk * kBlock + threadIdx.x;
@@ -239,7 +250,6 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
     alive = true;
   }
   unsigned long long g = 0;   // generative-model calls of this episode
-  const int lane = threadIdx.x & 63;
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey;
     float r = 0.0f;
@@ -295,19 +305,12 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
       T.tr_key[(size_t)d * n_p + ep] = tk;
       T.tr_val[(size_t)d * n_p + ep] = r;
     }
-    // AppendBeliefs: each inserted belief takes the next record of this level
-    // step, one atomic per wavefront.
-    const unsigned long long m = __ballot(won);
-    if (m) {
-      const int leader = __ffsll((long long)m) - 1;
+    // AppendBeliefs: the inserted belief owns record 1 + t*n_p + ep.
+    if (ep_ok) {
       const int t = t0 + d;
-      int at = 0;
-      if (lane == leader) at = atomicAdd(&T.cnt[t], __popcll(m));
-      at = __shfl(at, leader, 64);
+      T.list[(size_t)t * n_p + ep] = won ? sid : 0;
       if (won) {
-        const int j = at + __popcll(m & ((1ull << lane) - 1ull));
-        rid = 1 + t * P.n_p + j;
-        T.list[(size_t)t * n_p + j] = sid;
+        rid = 1 + t * P.n_p + ep;
         T.h_slot[h].id = rid;
         init_record(P, rid, obs, link);
       }
@@ -335,8 +338,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk) {
     T.tr_key[(size_t)D * n_p + ep] = tk;
     T.tr_val[(size_t)D * n_p + ep] = hv;
   }
-  g = wave_sum(g);
-  if ((threadIdx.x & 63) == 0 && g) atomicAdd(&T.counters[0], g);
+  g = block_sum(g, red);
+  if (threadIdx.x == 0 && g) atomicAdd(&T.stats[blk % kStripes], g);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,19 +410,12 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, Ranges& R) {
   if (threadIdx.x == 0) {
-    int n = 0, off = 0;
+    int n = 0;
     for (int kk = 1; kk <= k; ++kk) {
       const int s0 = P.t.step_base[kk - 1];
       const int Dk = P.t.step_base[kk] - s0;
-      if (Dk >= dep) {
-        const int t = s0 + dep - 1;
-        R.step[n] = t;
-        R.off[n] = off;
-        off += P.t.cnt[t];
-        ++n;
-      }
+      if (Dk >= dep) R.step[n++] = s0 + dep - 1;
     }
-    R.off[n] = off;
     R.n = n;
   }
   __syncthreads();
@@ -436,14 +432,12 @@ __device__ __forceinline__ unsigned long long parent_link(const TreeView& T, Rec
   return par;
 }
 
-// Record of the i-th belief of the ranges.
-__device__ __forceinline__ int range_id(const PlanView& P, const Ranges& R, int i) {
-  int lo = 0, hi = R.n - 1;          // last r with off[r] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (R.off[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  return 1 + R.step[lo] * P.n_p + (i - R.off[lo]);
+// Record of position i of the ranges, or -1 if no belief was inserted there.
+__device__ __forceinline__ int range_id(const PlanView& P, const Ranges& R, long long i) {
+  const long long n_p = P.n_p;
+  const long long t = R.step[i / n_p];
+  const long long pos = t * n_p + i % n_p;
+  return P.t.list[pos] ? (int)(1 + pos) : -1;
 }
 
 // Push V*N_b of a belief into its parent action's W accumulator (parent =
@@ -453,6 +447,7 @@ __device__ __forceinline__ void push_values(const PlanView& P, AggTable& G,
                                             unsigned long long parent, float V, int N) {
   unsigned long long f = 0ull;
   if (parent != kEmptyKey && N > 0) f = to_fix(V * (float)N, P.fix_scale);
+  if (!__syncthreads_or(f != 0ull)) return;   // uniform: nothing to push
   agg_clear(G);
   __syncthreads();
   if (f) atomicAdd(&G.a[agg_slot(G, parent)], f);
@@ -471,14 +466,16 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
                                 Smem& sm) {
   Ranges& R = sm.ranges;
   load_ranges(P, dep, k, R);
-  const int total = R.off[R.n];
-  for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
-    const int i = base + threadIdx.x;
+  const long long total = (long long)R.n * P.n_p;
+  unsigned long long beliefs = 0;             // tree statistics (last iteration)
+  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
+    const long long i = base + threadIdx.x;
     int N = 0;
     float V = 0.0f;
     unsigned long long parent = kEmptyKey;
-    if (i < total) {
-      RecMeta* mt = rec_meta(P.t, range_id(P, R, i));
+    const int b = i < total ? range_id(P, R, i) : -1;
+    if (b > 0) {
+      RecMeta* mt = rec_meta(P.t, b);
       const int c = mt->leaf_cnt;
       if (c > 0) {
         const unsigned long long hs = mt->leaf_h;
@@ -493,8 +490,13 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
         N = mt->Nb;
       }
       parent = parent_link(P.t, mt);
+      ++beliefs;
     }
     push_values(P, sm.agg, parent, V, N);
+  }
+  if (k == P.K) {
+    beliefs = block_sum(beliefs, sm.wave);
+    if (threadIdx.x == 0 && beliefs) atomicAdd(&P.t.stats[2 * kStripes + blk % kStripes], beliefs);
   }
 }
 
@@ -504,17 +506,17 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
                                  Smem& sm) {
   Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
-  const int total = R.off[R.n];
+  const long long total = (long long)R.n * P.n_p;
   const int A = P.m.nA;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
-  unsigned long long nodes = 0;               // action nodes (last iteration)
-  for (int base = blk * kBlock; base < total; base += nblk * kBlock) {
-    const int i = base + threadIdx.x;
+  unsigned long long nodes = 0, beliefs = 0;  // tree statistics (last iteration)
+  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
+    const long long i = base + threadIdx.x;
     int N = 0;
     float V = 0.0f;
     unsigned long long parent = kEmptyKey;
-    if (i < total) {
-      const int b = range_id(P, R, i);
+    const int b = i < total ? range_id(P, R, i) : -1;
+    if (b > 0) {
       float* prow = rec_psi(P.t, b);
       const int* nrow = rec_n(P.t, b);
       unsigned long long* crow = rec_c(P.t, b);
@@ -586,15 +588,18 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
         N = mt->Nb;
       }
       parent = parent_link(P.t, mt);
-      if (k == P.K) {                           // tree statistics, once
 #pragma unroll
-        for (int j = 0; j < AM; ++j) nodes += (j < A && n[j] > 0) ? 1ull : 0ull;
-      }
+      for (int j = 0; j < AM; ++j) nodes += (j < A && n[j] > 0) ? 1ull : 0ull;
+      ++beliefs;
     }
     push_values(P, sm.agg, parent, V, N);
   }
-  nodes = wave_sum(nodes);
-  if ((threadIdx.x & 63) == 0 && nodes) atomicAdd(&P.t.counters[4], nodes);
+  if (k == P.K) {
+    nodes = block_sum(nodes, sm.wave);
+    if (threadIdx.x == 0 && nodes) atomicAdd(&P.t.stats[kStripes + blk % kStripes], nodes);
+    beliefs = block_sum(beliefs, sm.wave);
+    if (threadIdx.x == 0 && beliefs) atomicAdd(&P.t.stats[2 * kStripes + blk % kStripes], beliefs);
+  }
 }
 
 // The root row in double precision, updated in place (one thread).
@@ -621,7 +626,7 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
     psi[j] = (psi[j] - vc) + q;
     nsum += n;
   }
-  if (k == P.K) atomicAdd(&P.t.counters[4], (unsigned long long)nodes);
+  if (k == P.K) atomicAdd(&P.t.stats[kStripes], (unsigned long long)nodes);
   if (!any) return;
   const double v = lse64(psi, A, P.eta64);
   P.t.v_root[0] = v;
@@ -632,20 +637,16 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
 
 // Alg. 1: argmax of the root preferences (lowest index on ties) and the
 // result record; also keeps this plan's list lengths for the next set-up.
-__device__ void dev_select(const PlanView& P, Smem& sm) {
+// Run by the block's first wavefront (64 lanes, one per stripe).
+__device__ void dev_select(const PlanView& P) {
+  static_assert(kStripes == 64, "one lane per stripe");
+  if (threadIdx.x >= 64) return;
   const TreeView& T = P.t;
-  unsigned long long part = 0;
-  for (int t = threadIdx.x; t < P.steps; t += kBlock) {
-    const int c = T.cnt[t];
-    T.cnt_prev[t] = c;
-    part += (unsigned long long)c;
-  }
-  part = wave_sum(part);
-  if ((threadIdx.x & 63) == 0) sm.wave[threadIdx.x >> 6] = part;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  unsigned long long nb = 1;
-  for (int i = 0; i < kBlock / 64; ++i) nb += sm.wave[i];
+  const int lane = threadIdx.x;
+  const unsigned long long steps = wave_sum(T.stats[lane]);
+  const unsigned long long nodes = wave_sum(T.stats[kStripes + lane]);
+  const unsigned long long nb = 1 + wave_sum(T.stats[2 * kStripes + lane]);
+  if (lane != 0) return;
   const int A = P.m.nA;
   int best = 0;
   for (int j = 1; j < A; ++j)
@@ -654,9 +655,9 @@ __device__ void dev_select(const PlanView& P, Smem& sm) {
   out[0] = (double)best;
   for (int j = 0; j < A; ++j) out[1 + j] = T.psi_root[j];
   out[A + 1] = T.v_root[0];
-  out[A + 2] = (double)T.counters[0];
+  out[A + 2] = (double)steps;
   out[A + 3] = (double)nb;
-  out[A + 4] = (double)T.counters[4];
+  out[A + 4] = (double)nodes;
   out[A + 5] = (double)T.counters[1];
   T.counters[2] = nb;
   T.counters[3] = 0ull;
@@ -839,7 +840,8 @@ __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
 }
 template <int AM>
 __global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
-  dev_forward<AM>(P, k, D, blockIdx.x);
+  __shared__ unsigned long long red[kBlock / 64];
+  dev_forward<AM>(P, k, D, blockIdx.x, red);
 }
 __global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D) {
   __shared__ Smem sm;
@@ -855,10 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, in
   dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
 __global__ void k_backup_root(PlanView P, int k) { dev_backup_root(P, k); }
-__global__ __launch_bounds__(kBlock) void k_select(PlanView P) {
-  __shared__ Smem sm;
-  dev_select(P, sm);
-}
+__global__ void k_select(PlanView P) { dev_select(P); }
 
 // ---------------------------------------------------------------------------
 // Batched kernel: block -> (instance, phase) through the item list, sorted by
@@ -884,10 +883,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
     case kPhaseSetup: dev_setup(P, blk, it.nblk); break;
     case kPhaseForward:
       if (Apad <= 4) {
-        dev_forward<4>(P, it.a0, it.a1, blk);
+        dev_forward<4>(P, it.a0, it.a1, blk, sm.wave);
       } else if constexpr (AMAX >= 8) {
-        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk);
-        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk);
+        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk, sm.wave);
+        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk, sm.wave);
       }
       break;
     case kPhaseAccum: dev_accum(P, it.a0, blk, it.nblk, sm); break;
@@ -901,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
       }
       break;
     case kPhaseRoot: dev_backup_root(P, it.a0); break;
-    case kPhaseSelect: dev_select(P, sm); break;
+    case kPhaseSelect: dev_select(P); break;
     case kPhaseEnv: dev_env(P, it.a0); break;
     case kPhasePFWeight: dev_pf_weight(P, it.a0, blk); break;
     case kPhasePFScan: dev_pf_scan(P, sm); break;
@@ -965,7 +964,7 @@ hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_select(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {
