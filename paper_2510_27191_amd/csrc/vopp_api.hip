@@ -262,7 +262,7 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) 
   z.rs = rec_bytes(z.Apad);
   z.cap_b = 1 + (long long)n_p * z.steps;
   uint64_t h = 1024;
-  while (h < 2 * (uint64_t)z.cap_b) h <<= 1;
+  while (h < 2 * (uint64_t)z.cap_b) h <<= 1;      // load <= 1/2
   z.hcap = h;
   return z;
 }
@@ -272,7 +272,7 @@ size_t bytes_for(const WsSizes& z) {
   auto add = [&](size_t n) { b += align_up(n, 256); };
   add((size_t)z.cap_b * z.rs);                       // belief records
   add(z.hcap * sizeof(HSlot));                       // table
-  add(kMaxA * 8); add(8);                            // root row, V(root)
+  add(kMaxA * 8); add(kMaxA * 8); add(8);            // root row and its CDF, V(root)
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(3 * kStripes * 8); add((z.K + 1) * 4);
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
@@ -306,6 +306,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.h_slot = c.take<HSlot>(z.hcap);
   t.h_mask = (uint32_t)(z.hcap - 1);
   t.psi_root = c.take<double>(kMaxA);
+  t.root_cdf = c.take<double>(kMaxA);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
   t.counters = c.take<unsigned long long>(8);

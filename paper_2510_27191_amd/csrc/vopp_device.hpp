@@ -34,7 +34,7 @@ constexpr int kMaxObs = 1 << kObsBits;
 constexpr int kStampShift = 56;
 constexpr unsigned long long kStampMask = 0xFFull << kStampShift;
 constexpr unsigned long long kSidMask = (1ull << 30) - 1;
-constexpr long long kMaxBeliefs = 1ll << 28;   // slot ids stay below 2^29 + 1
+constexpr long long kMaxBeliefs = 1ll << 28;   // twice as many slots: ids <= 2^29
 
 struct HSlot {
   unsigned long long key;
@@ -110,6 +110,7 @@ struct TreeView {
   HSlot* h_slot;                 // [h_mask + 1] open-addressing table
   uint32_t h_mask;
   double* psi_root;              // [nA]
+  double* root_cdf;              // [nA] running sums of the root's softmax weights
   double* v_root;                // [1]
   int* list;                     // [steps * n_p]: slot id of the belief that
                                  // episode ep inserted at level step t, or 0
@@ -243,17 +244,28 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // Count of thresholds <= u among n monotone thresholds = first j with u < thr_j.
-// Rows are read as 16-byte vectors when 16-byte aligned.
+// Rows are read as 16-byte vectors when 16-byte aligned, four vectors in
+// flight at a time, so a row costs one memory round trip rather than one per
+// vector.
 __device__ __forceinline__ int count_le(const uint32_t* __restrict__ thr, int n,
                                         uint32_t u) {
   int c = 0;
   int j = 0;
   if ((((uintptr_t)thr) & 15) == 0) {
+    for (; j + 16 <= n; j += 16) {
+      const uint4* q = reinterpret_cast<const uint4*>(thr + j);
+      const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+      c += (q0.x <= u) + (q0.y <= u) + (q0.z <= u) + (q0.w <= u);
+      c += (q1.x <= u) + (q1.y <= u) + (q1.z <= u) + (q1.w <= u);
+      c += (q2.x <= u) + (q2.y <= u) + (q2.z <= u) + (q2.w <= u);
+      c += (q3.x <= u) + (q3.y <= u) + (q3.z <= u) + (q3.w <= u);
+    }
     for (; j + 4 <= n; j += 4) {
       const uint4 q = *reinterpret_cast<const uint4*>(thr + j);
       c += (q.x <= u) + (q.y <= u) + (q.z <= u) + (q.w <= u);
     }
   }
+#pragma unroll 8
   for (; j < n; ++j) c += (thr[j] <= u) ? 1 : 0;
   return c;
 }
@@ -306,29 +318,85 @@ __device__ __forceinline__ float nav_obs_sd(const NavParams& p, float nx) {
   return p.sigma_obs0 + p.sigma_obs_slope * fabsf(nx - p.obs_center_x);
 }
 
-// Navigation G.  Built without contraction: each operation rounds once.
-__device__ __forceinline__ void nav_step(const ModelView& m, float x, float y,
-                                         int a, const U4& w, float& nx,
-                                         float& ny, int& key, float& r,
-                                         bool& term) {
+// Obstacle centres of the navigation model held in registers (uniform across
+// the wavefront) when there are at most kDiskRegs of them; more are read from
+// memory.  Reading them once per kernel keeps the obstacle test free of
+// memory waits.
+constexpr int kDiskRegs = 8;
+struct DiskCache {
+  float c[2 * kDiskRegs];
+};
+__device__ __forceinline__ DiskCache load_disks(const ModelView& m) {
+  DiskCache d;
+  const int n = m.nav.n_disks;
+#pragma unroll
+  for (int i = 0; i < 2 * kDiskRegs; ++i) d.c[i] = i < 2 * n ? m.disks[i] : 0.0f;
+  return d;
+}
+__device__ __forceinline__ bool nav_hit(const ModelView& m, const DiskCache& dc, float nx,
+                                        float ny) {
   const NavParams& p = m.nav;
-  nav_move(m, x, y, a, w.y, nx, ny);
+  bool hit = false;
+  if (p.n_disks <= kDiskRegs) {
+#pragma unroll
+    for (int i = 0; i < kDiskRegs; ++i) {
+      const float ex = nx - dc.c[2 * i], ey = ny - dc.c[2 * i + 1];
+      hit = hit || (i < p.n_disks && (ex * ex + ey * ey) <= p.disk_r2);
+    }
+  } else {
+    for (int i = 0; i < p.n_disks; ++i) {
+      const float ex = nx - m.disks[2 * i], ey = ny - m.disks[2 * i + 1];
+      hit = hit || ((ex * ex + ey * ey) <= p.disk_r2);
+    }
+  }
+  return hit;
+}
+
+// The four standard-normal quantiles one navigation step uses: motion noise
+// from word y, observation noise from word z.
+struct NavNoise {
+  float mx, my, ox, oy;
+};
+__device__ __forceinline__ NavNoise nav_noise(const ModelView& m, const U4& w) {
+  return NavNoise{m.gauss[w.y >> 20], m.gauss[(w.y >> 8) & 4095u], m.gauss[w.z >> 20],
+                  m.gauss[(w.z >> 8) & 4095u]};
+}
+
+// Navigation G with its noise already read.  Built without contraction: each
+// operation rounds once.
+__device__ __forceinline__ void nav_step_z(const ModelView& m, const DiskCache& dc, float x,
+                                           float y, int a, const NavNoise& z, float& nx,
+                                           float& ny, int& key, float& r, bool& term) {
+  const NavParams& p = m.nav;
+  float dx = 0.0f, dy = 0.0f;
+  if (a == 0) dy = p.step;
+  else if (a == 1) dx = p.step;
+  else if (a == 2) dy = -p.step;
+  else dx = -p.step;
+  const float mx = x + dx;
+  const float my = y + dy;
+  nx = fminf(fmaxf(mx + p.sigma_move * z.mx, p.lo), p.hi);
+  ny = fminf(fmaxf(my + p.sigma_move * z.my, p.lo), p.hi);
   const float sd = nav_obs_sd(p, nx);
-  const float ox = nx + sd * m.gauss[w.z >> 20];
-  const float oy = ny + sd * m.gauss[(w.z >> 8) & 4095u];
+  const float ox = nx + sd * z.ox;
+  const float oy = ny + sd * z.oy;
   key = nav_axis(p, ox) * p.key_n + nav_axis(p, oy);
   const float gx = nx - p.goal_x, gy = ny - p.goal_y;
   const bool goal = (gx * gx + gy * gy) <= p.goal_r2;
-  bool hit = false;
-  for (int i = 0; i < p.n_disks; ++i) {
-    const float ex = nx - m.disks[2 * i], ey = ny - m.disks[2 * i + 1];
-    hit = hit || ((ex * ex + ey * ey) <= p.disk_r2);
-  }
+  const bool hit = nav_hit(m, dc, nx, ny);
   float rr = p.r_step;
   if (goal) rr = rr + p.r_goal;
   if (hit) rr = rr + p.r_hit;
   r = rr;
   term = goal;
+}
+
+// Navigation G (Sec. III-B generative model of the navigation workload).
+__device__ __forceinline__ void nav_step(const ModelView& m, float x, float y,
+                                         int a, const U4& w, float& nx,
+                                         float& ny, int& key, float& r,
+                                         bool& term) {
+  nav_step_z(m, load_disks(m), x, y, a, nav_noise(m, w), nx, ny, key, r, term);
 }
 
 __device__ __forceinline__ float nav_heuristic(const NavParams& p, float x, float y) {
@@ -362,6 +430,17 @@ __device__ __forceinline__ int draw_row32(float (&v)[AM], int A, float eta, uint
     }
   }
   return a;
+}
+
+// A preference row (padded to a multiple of 4) read into registers.
+template <int AM>
+__device__ __forceinline__ void load_row(const float* __restrict__ row, int A, float (&v)[AM]) {
+#pragma unroll
+  for (int j = 0; j < AM; j += 4) {
+    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j < A) q = *reinterpret_cast<const float4*>(row + j);
+    v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
+  }
 }
 
 // The same draw from a preference row in memory (padded to a multiple of 4).
@@ -401,6 +480,30 @@ __device__ __forceinline__ int draw_action64(const double* __restrict__ row, int
     run = run + exp(eta * (row[j] - m));
     if (t < run) return j;
   }
+  return A - 1;
+}
+
+// The running sums P_j of the weights exp(eta (psi_j - max)) of the root row,
+// accumulated in the same order as draw_action64 does, so that a draw from
+// them (draw_cdf64) is the same draw.  The root row changes once per
+// iteration, so every episode's root draw reads these instead of evaluating
+// 2|A| double exponentials.
+__device__ __forceinline__ void root_cdf(const double* __restrict__ row, int A, double eta,
+                                         double* __restrict__ cdf) {
+  double m = row[0];
+  for (int j = 1; j < A; ++j) m = fmax(m, row[j]);
+  double run = 0.0;
+  for (int j = 0; j < A; ++j) {
+    run = run + exp(eta * (row[j] - m));
+    cdf[j] = run;
+  }
+}
+
+__device__ __forceinline__ int draw_cdf64(const double* __restrict__ cdf, int A, uint32_t x0) {
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double t = u * cdf[A - 1];
+  for (int j = 0; j < A; ++j)
+    if (t < cdf[j]) return j;
   return A - 1;
 }
 

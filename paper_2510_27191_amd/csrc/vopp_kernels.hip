@@ -37,38 +37,73 @@
 namespace vopp {
 
 // ---------------------------------------------------------------------------
-// Open-addressing table (linear probing, load <= 1/2).  Finds or inserts key;
+// Open-addressing table of 16-byte slots, load <= 1/2.  Finds or inserts key;
 // the inserting thread writes key | stamp.  Returns the slot, or ~0u if the
-// table has no free slot left (an internal error, reported by the plan).  A
-// slot is read with one plain 16-byte load: keys and record indices written
-// by earlier kernels are visible to it; a key being inserted by this kernel
-// may read as empty, and then the compare-and-swap returns it.
+// table has no free slot left (an internal error, reported by the plan).
+//
+// A key hashes to a bucket, one 128-byte line of 8 slots, which the probe
+// reads with one round of loads and scans in registers; a full bucket
+// continues into the next line.  Within a line the key visits the slots in a
+// rotated order that is a function of the key, so every thread that looks
+// for one key meets the same first empty slot (linear probing over a fixed
+// per-key sequence: one compare-and-swap there decides the insert), while
+// different keys spread their inserts over the line.  A wavefront waits for
+// its slowest lane, so reading whole lines and deciding in registers keeps
+// most wavefronts at one read and at most one compare-and-swap per lane (a
+// compare-and-swap is about twice as slow as a read).  Keys and record indices written by earlier kernels are
+// visible to the plain loads; a key being inserted by this kernel may read
+// as empty, and then the compare-and-swap returns it.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t probe(const TreeView& t, unsigned long long key,
                                           unsigned long long stamp, bool& won,
                                           bool& fresh, int& id) {
-  uint32_t h = (uint32_t)mix64(key) & t.h_mask;
-  for (uint32_t n = 0; n <= t.h_mask; ++n) {
-    const uint4 v = *reinterpret_cast<const uint4*>(&t.h_slot[h]);
-    unsigned long long cur = ((unsigned long long)v.y << 32) | v.x;
-    bool reread = false;
-    if (cur == kEmptyKey) {
-      cur = atomicCAS(&t.h_slot[h].key, kEmptyKey, key | stamp);
-      if (cur == kEmptyKey) {
+  const unsigned long long hk = mix64(key);
+  uint32_t base = (uint32_t)hk & t.h_mask & ~7u;
+  const uint32_t rot = (uint32_t)(hk >> 40) & 7u;
+  const uint32_t lines = (t.h_mask >> 3) + 1;
+  for (uint32_t n = 0; n <= 2 * lines; ++n) {
+    const uint4* ln = reinterpret_cast<const uint4*>(&t.h_slot[base]);
+    uint4 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = ln[j];
+    // The first slot in the key's order that holds the key or is empty.
+    uint32_t best = 8;
+    int at = -1;
+    bool empty = false;
+    int rid = -1;
+    unsigned long long seen = kEmptyKey;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned long long cur = ((unsigned long long)v[j].y << 32) | v[j].x;
+      const uint32_t pos = ((uint32_t)j - rot) & 7u;
+      if ((cur == kEmptyKey || (cur & ~kStampMask) == key) && pos < best) {
+        best = pos;
+        at = j;
+        empty = cur == kEmptyKey;
+        seen = cur;
+        rid = (int)v[j].z;
+      }
+    }
+    if (at < 0) {                               // the bucket is full: next line
+      base = (base + 8u) & t.h_mask;
+      continue;
+    }
+    const uint32_t slot = base + (uint32_t)at;
+    if (empty) {
+      seen = atomicCAS(&t.h_slot[slot].key, kEmptyKey, key | stamp);
+      if (seen == kEmptyKey) {
         won = true;
         fresh = true;
         id = -1;
-        return h;
+        return slot;
       }
-      reread = true;
+      if ((seen & ~kStampMask) != key) continue;  // another key took it: re-read
+      rid = -1;                                 // inserted by this kernel: fresh
     }
-    if ((cur & ~kStampMask) == key) {
-      won = false;
-      fresh = (cur & kStampMask) == stamp;
-      id = fresh ? -1 : (reread ? t.h_slot[h].id : (int)v.z);
-      return h;
-    }
-    h = (h + 1) & t.h_mask;
+    won = false;
+    fresh = (seen & kStampMask) == stamp;
+    id = fresh ? -1 : rid;
+    return slot;
   }
   won = false;
   fresh = false;
@@ -183,7 +218,9 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       rec_psi(T, 0)[j] = P.psi0;
       T.psi_root[j] = P.psi0_64;
     }
+    __syncthreads();
     if (j == 0) {
+      root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
       RecMeta* mt = rec_meta(T, 0);
       mt->obs = -1;
       mt->parent = kEmptyKey;
@@ -223,20 +260,22 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
   const int A = P.m.nA;
+  const bool nav = P.m.kind != kTabular;
   const size_t n_p = (size_t)P.n_p;
   const unsigned long long stamp = (unsigned long long)(k - 1) << kStampShift;
   int s = 0;
   float x = 0.0f, y = 0.0f;
   int sid = 0;                // current belief's slot id (0: root)
   int rid = 0;                // its record, -1 if another episode inserted it
-                              // during this iteration (its row is then psi0)
+                              // during this iteration
+  bool fresh = false;         // inserted during this iteration (Psi = psi0)
   bool alive = false;
   if (ep_ok) {
     // Alg. 1: the episode starts at the root with a state drawn from the
     // belief particles.
     const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
     const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
-    if (P.m.kind == kTabular) {
+    if (!nav) {
       s = ((const int*)P.e.belief)[idx];
       if ((unsigned)s >= (unsigned)P.m.nS) {   // caller's particle out of range
         atomicOr((unsigned int*)&T.counters[1], 1u);
@@ -249,68 +288,86 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     alive = true;
   }
+  // Inputs of the next level, read ahead of the previous level's writes: a
+  // wait for a load also waits for every memory operation issued before it.
+  U4 w = draw(P, (uint32_t)ep, kTagStep, 0u, (uint32_t)k);
+  float row[AM];
+#pragma unroll
+  for (int j = 0; j < AM; ++j) row[j] = 0.0f;
+  NavNoise z{0.0f, 0.0f, 0.0f, 0.0f};
+  if (alive && nav) z = nav_noise(P.m, w);
+  DiskCache dc;
+#pragma unroll
+  for (int i = 0; i < 2 * kDiskRegs; ++i) dc.c[i] = 0.0f;
+  if (nav) dc = load_disks(P.m);
   unsigned long long g = 0;   // generative-model calls of this episode
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey;
     float r = 0.0f;
-    bool won = false;
-    int obs = 0;
+    bool won = false, direct = false;
+    int obs = 0, a = 0;
     uint32_t h = 0;
     unsigned long long link = kEmptyKey;
+    const int rid_b = rid;
     if (alive) {
-      const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
-      int a;
-      if (sid == 0) a = draw_action64(T.psi_root, A, P.eta64, w.x);
-      else if (rid < 0) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
-      else a = draw_action32<AM>(rec_psi(T, rid), A, P.eta, w.x);
+      if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
+      else if (fresh) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
+      else a = draw_row32<AM>(row, A, P.eta, w.x);
       bool term = false;
-      if (P.m.kind == kTabular) {
+      if (!nav) {
         int sn;
         tabular_step(P.m, s, a, w, sn, obs, r);
         s = sn;
       } else {
         float nx, ny;
-        nav_step(P.m, x, y, a, w, nx, ny, obs, r, term);
+        nav_step_z(P.m, dc, x, y, a, z, nx, ny, obs, r, term);
         x = nx;
         y = ny;
       }
       ++g;
-      // AppendActions: visit count and reward sum of (b, a).
-      if (d >= kDirectLevel && rid >= 0) {
-        atomicAdd(&rec_n(T, rid)[a], 1);
-        const unsigned long long fx = to_fix(r, P.fix_scale);
-        if (fx) atomicAdd(&rec_c(T, rid)[a], fx);
-      } else {
+      // AppendActions: visit count and reward sum of (b, a), counted below
+      // when b's record is known, else left to the accumulate pass.
+      direct = d >= kDirectLevel && rid >= 0;
+      if (!direct)
         tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a | kTraceRec)
                       : (((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
-      }
       link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a)
                       : (kLinkSlot | ((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
       if (term) {
         alive = false;                          // FilterTerminals
       } else {
+        // AppendBeliefs: find or insert (b, a, o).
+        const unsigned long long key = belief_key(sid, a, obs);
         bool fr;
         int id;
-        h = probe(T, belief_key(sid, a, obs), stamp, won, fr, id);
+        h = probe(T, key, stamp, won, fr, id);
         if (h == ~0u) {                         // table full: stop and report
           atomicOr((unsigned int*)&T.counters[1], 2u);
           alive = false;
         } else {
           sid = (int)h + 1;
-          rid = id;                             // -1 while fresh
+          fresh = fr;
+          rid = won ? 1 + (t0 + d) * P.n_p + ep : id;   // the inserter's own record
         }
       }
     }
-    if (ep_ok) {
-      T.tr_key[(size_t)d * n_p + ep] = tk;
-      T.tr_val[(size_t)d * n_p + ep] = r;
+    if (alive && d + 1 < D) {
+      w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
+      if (!fresh) load_row<AM>(rec_psi(T, rid), A, row);
+      if (nav) z = nav_noise(P.m, w);
     }
-    // AppendBeliefs: the inserted belief owns record 1 + t*n_p + ep.
+    // Writes of level d.
+    if (direct) {
+      atomicAdd(&rec_n(T, rid_b)[a], 1);
+      const unsigned long long fx = to_fix(r, P.fix_scale);
+      if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
+    }
     if (ep_ok) {
       const int t = t0 + d;
+      T.tr_key[(size_t)d * n_p + ep] = tk;
+      T.tr_val[(size_t)d * n_p + ep] = r;
       T.list[(size_t)t * n_p + ep] = won ? sid : 0;
       if (won) {
-        rid = 1 + t * P.n_p + ep;
         T.h_slot[h].id = rid;
         init_record(P, rid, obs, link);
       }
@@ -320,7 +377,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     unsigned long long tk = kEmptyKey;
     float hv = 0.0f;                            // ValueHeuristic of the leaf state
     if (alive) {
-      if (P.m.kind == kTabular) {
+      if (!nav) {
         if (P.m.H) hv = P.m.H[s];
       } else {
         hv = nav_heuristic(P.m.nav, x, y);
@@ -628,6 +685,7 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
   }
   if (k == P.K) atomicAdd(&P.t.stats[kStripes], (unsigned long long)nodes);
   if (!any) return;
+  root_cdf(psi, A, P.eta64, P.t.root_cdf);
   const double v = lse64(psi, A, P.eta64);
   P.t.v_root[0] = v;
   RecMeta* mt = rec_meta(P.t, 0);
