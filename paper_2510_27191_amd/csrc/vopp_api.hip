@@ -273,6 +273,7 @@ size_t bytes_for(const WsSizes& z) {
   add((size_t)z.cap_b * z.rs);                       // belief records
   add(z.hcap * sizeof(HSlot));                       // table
   add(kMaxA * 8); add(kMaxA * 8); add(8);            // root row and its CDF, V(root)
+  add((size_t)3 * kMaxA * kStripes * 8);             // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(3 * kStripes * 8); add((z.K + 1) * 4);
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
@@ -307,6 +308,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.h_mask = (uint32_t)(z.hcap - 1);
   t.psi_root = c.take<double>(kMaxA);
   t.root_cdf = c.take<double>(kMaxA);
+  t.root_acc = c.take<unsigned long long>((size_t)3 * kMaxA * kStripes);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
   t.counters = c.take<unsigned long long>(8);
@@ -439,10 +441,11 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
                 int cap) {
   (void)p;
-  // One thread per record position of the level steps that hold depth dep.
+  // One chunk of kBlock record positions per block, over the level steps
+  // that hold depth dep.
   long long iters = 0;
   for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
-  const long long g = (n_p * iters + kBlock - 1) / kBlock;
+  const long long g = ((long long)n_p + kBlock - 1) / kBlock * iters;
   return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 

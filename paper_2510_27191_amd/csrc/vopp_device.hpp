@@ -111,6 +111,9 @@ struct TreeView {
   uint32_t h_mask;
   double* psi_root;              // [nA]
   double* root_cdf;              // [nA] running sums of the root's softmax weights
+  unsigned long long* root_acc;  // [3][kMaxA][kStripes]: N, C and W of the root's
+                                 // action nodes, striped over blocks (every
+                                 // episode passes through one of them)
   double* v_root;                // [1]
   int* list;                     // [steps * n_p]: slot id of the belief that
                                  // episode ep inserted at level step t, or 0

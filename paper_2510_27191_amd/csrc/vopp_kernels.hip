@@ -208,6 +208,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       if (sid) T.h_slot[sid - 1].key = kEmptyKey;
     }
   }
+  for (size_t i = tid; i < (size_t)3 * kMaxA * kStripes; i += stride) T.root_acc[i] = 0ull;
   if (blk == 0) {
     uint4* r = reinterpret_cast<uint4*>(T.rec);
     for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -408,20 +409,23 @@ __device__ __forceinline__ int record_of(const TreeView& T, int sid) {
   return sid == 0 ? 0 : T.h_slot[sid - 1].id;
 }
 
+// Stripe q (0: N, 1: C, 2: W) of root action a for the calling block.
+__device__ __forceinline__ unsigned long long* root_stripe(const TreeView& T, int q, int a) {
+  return T.root_acc + ((size_t)q * kMaxA + a) * kStripes + blockIdx.x % kStripes;
+}
+
 __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm) {
   const TreeView& T = P.t;
   AggTable& G = sm.agg;
-  const long long n_p = P.n_p;
-  const long long total = (long long)(D + 1) * n_p;
-  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
-    const long long i = base + threadIdx.x;
+  const size_t n_p = (size_t)P.n_p;
+  const int per = (P.n_p + kBlock - 1) / kBlock;   // chunks of kBlock items per level
+  for (int c = blk; c < (D + 1) * per; c += nblk) {
+    const int lvl = c / per;
+    const int ep = (c - lvl * per) * kBlock + threadIdx.x;
+    const size_t i = (size_t)lvl * n_p + (size_t)ep;
     unsigned long long tk = kEmptyKey;
     float v = 0.0f;
-    int lvl = 0;
-    if (i < total) {
-      tk = T.tr_key[i];
-      lvl = (int)(i / n_p);
-    }
+    if (ep < P.n_p) tk = T.tr_key[i];
     const bool has = tk != kEmptyKey;
     const bool leaf = lvl == D;
     unsigned long long key = kEmptyKey;
@@ -450,6 +454,10 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
           RecMeta* mt = rec_meta(T, rid);
           atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
           if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
+        } else if (rid == 0) {
+          const int a = (int)((k2 >> 1) & 63ull);
+          atomicAdd(root_stripe(T, 0, a), G.a[j]);
+          if (G.b[j]) atomicAdd(root_stripe(T, 1, a), G.b[j]);
         } else {
           const int a = (int)((k2 >> 1) & 63ull);
           atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
@@ -489,11 +497,9 @@ __device__ __forceinline__ unsigned long long parent_link(const TreeView& T, Rec
   return par;
 }
 
-// Record of position i of the ranges, or -1 if no belief was inserted there.
-__device__ __forceinline__ int range_id(const PlanView& P, const Ranges& R, long long i) {
-  const long long n_p = P.n_p;
-  const long long t = R.step[i / n_p];
-  const long long pos = t * n_p + i % n_p;
+// Record of position ep of level step t, or -1 if no belief was inserted there.
+__device__ __forceinline__ int record_at(const PlanView& P, int t, int ep) {
+  const size_t pos = (size_t)t * (size_t)P.n_p + (size_t)ep;
   return P.t.list[pos] ? (int)(1 + pos) : -1;
 }
 
@@ -511,8 +517,11 @@ __device__ __forceinline__ void push_values(const PlanView& P, AggTable& G,
   __syncthreads();
   for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
     const unsigned long long key = G.key[j];
-    if (key != kEmptyKey && G.a[j])
-      atomicAdd(&rec_w(P.t, (int)(key >> 6))[key & 63ull], G.a[j]);
+    if (key != kEmptyKey && G.a[j]) {
+      const int pr = (int)(key >> 6), a = (int)(key & 63ull);
+      if (pr == 0) atomicAdd(root_stripe(P.t, 2, a), G.a[j]);
+      else atomicAdd(&rec_w(P.t, pr)[a], G.a[j]);
+    }
   }
   __syncthreads();
 }
@@ -523,14 +532,17 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
                                 Smem& sm) {
   Ranges& R = sm.ranges;
   load_ranges(P, dep, k, R);
-  const long long total = (long long)R.n * P.n_p;
   unsigned long long beliefs = 0;             // tree statistics (last iteration)
-  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
-    const long long i = base + threadIdx.x;
+  // Chunks of kBlock positions: chunk c is block c % per of range c / per
+  // (a division per chunk, on the scalar unit).
+  const int per = (P.n_p + kBlock - 1) / kBlock;
+  for (int c = blk; c < R.n * per; c += nblk) {
+    const int r = c / per;
+    const int ep = (c - r * per) * kBlock + threadIdx.x;
     int N = 0;
     float V = 0.0f;
     unsigned long long parent = kEmptyKey;
-    const int b = i < total ? range_id(P, R, i) : -1;
+    const int b = ep < P.n_p ? record_at(P, R.step[r], ep) : -1;
     if (b > 0) {
       RecMeta* mt = rec_meta(P.t, b);
       const int c = mt->leaf_cnt;
@@ -563,16 +575,17 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
                                  Smem& sm) {
   Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
-  const long long total = (long long)R.n * P.n_p;
   const int A = P.m.nA;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
   unsigned long long nodes = 0, beliefs = 0;  // tree statistics (last iteration)
-  for (long long base = (long long)blk * kBlock; base < total; base += (long long)nblk * kBlock) {
-    const long long i = base + threadIdx.x;
+  const int per = (P.n_p + kBlock - 1) / kBlock;
+  for (int c = blk; c < R.n * per; c += nblk) {
+    const int r = c / per;
+    const int ep = (c - r * per) * kBlock + threadIdx.x;
     int N = 0;
     float V = 0.0f;
     unsigned long long parent = kEmptyKey;
-    const int b = i < total ? range_id(P, R, i) : -1;
+    const int b = ep < P.n_p ? record_at(P, R.step[r], ep) : -1;
     if (b > 0) {
       float* prow = rec_psi(P.t, b);
       const int* nrow = rec_n(P.t, b);
@@ -660,9 +673,29 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
 }
 
 // The root row in double precision, updated in place (one thread).
+// Run by the block's first wavefront: lane s sums stripe s of the root's
+// action nodes into record 0, then lane 0 updates the row.
 __device__ void dev_backup_root(const PlanView& P, int k) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x >= 64) return;
   const int A = P.m.nA;
+  {
+    const int lane = threadIdx.x;
+    unsigned long long* acc = P.t.root_acc;
+#pragma unroll 4
+    for (int j = 0; j < A; ++j) {
+      unsigned long long* w = &acc[((size_t)2 * kMaxA + j) * kStripes + lane];
+      const unsigned long long n = wave_sum(acc[((size_t)0 * kMaxA + j) * kStripes + lane]);
+      const unsigned long long c = wave_sum(acc[((size_t)1 * kMaxA + j) * kStripes + lane]);
+      const unsigned long long wv = wave_sum(*w);
+      *w = 0ull;
+      if (lane == 0) {
+        rec_n(P.t, 0)[j] = (int)n;
+        rec_c(P.t, 0)[j] = c;
+        rec_w(P.t, 0)[j] = wv;
+      }
+    }
+    if (lane != 0) return;
+  }
   double* psi = P.t.psi_root;
   const int* nrow = rec_n(P.t, 0);
   const unsigned long long* crow = rec_c(P.t, 0);
@@ -981,7 +1014,7 @@ int setup_blocks(const PlanView& P) {
 int forward_blocks(const PlanView& P) { return blocks_for(P.n_p); }
 
 int accum_blocks(const PlanView& P, int D, int cap) {
-  const long long g = blocks_for((long long)(D + 1) * P.n_p);
+  const long long g = (long long)blocks_for(P.n_p) * (D + 1);
   return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 
