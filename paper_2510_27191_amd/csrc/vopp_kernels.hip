@@ -673,53 +673,76 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
 }
 
 // The root row in double precision, updated in place (one thread).
-// Run by the block's first wavefront: lane s sums stripe s of the root's
-// action nodes into record 0, then lane 0 updates the row.
+// Run by the block's first wavefront.  Lane s sums stripe s of the root's
+// action nodes; lane j then owns action j: it evaluates that action's
+// exponentials, and lane 0 adds them up in action order (the order of the
+// serial definition, so every sum rounds exactly as it would there).
+__device__ __forceinline__ double wave_max64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Sum of x over lanes 0..A-1 in lane order, broadcast to the wave.
+__device__ __forceinline__ double ordered_sum(double x, int A) {
+  double s = 0.0;
+  for (int j = 0; j < A; ++j) s = s + __shfl(x, j, 64);
+  return s;
+}
+
 __device__ void dev_backup_root(const PlanView& P, int k) {
   if (threadIdx.x >= 64) return;
   const int A = P.m.nA;
-  {
-    const int lane = threadIdx.x;
-    unsigned long long* acc = P.t.root_acc;
+  const int lane = threadIdx.x;
+  const bool act = lane < A;
+  unsigned long long* acc = P.t.root_acc;
+  long long n_me = 0, c_me = 0, w_me = 0;     // sums of action `lane`
 #pragma unroll 4
-    for (int j = 0; j < A; ++j) {
-      unsigned long long* w = &acc[((size_t)2 * kMaxA + j) * kStripes + lane];
-      const unsigned long long n = wave_sum(acc[((size_t)0 * kMaxA + j) * kStripes + lane]);
-      const unsigned long long c = wave_sum(acc[((size_t)1 * kMaxA + j) * kStripes + lane]);
-      const unsigned long long wv = wave_sum(*w);
-      *w = 0ull;
-      if (lane == 0) {
-        rec_n(P.t, 0)[j] = (int)n;
-        rec_c(P.t, 0)[j] = c;
-        rec_w(P.t, 0)[j] = wv;
-      }
+  for (int j = 0; j < A; ++j) {
+    unsigned long long* w = &acc[((size_t)2 * kMaxA + j) * kStripes + lane];
+    const unsigned long long n = wave_sum(acc[((size_t)0 * kMaxA + j) * kStripes + lane]);
+    const unsigned long long c = wave_sum(acc[((size_t)1 * kMaxA + j) * kStripes + lane]);
+    const unsigned long long wv = wave_sum(*w);
+    *w = 0ull;
+    if (lane == j) {
+      n_me = (long long)n;
+      c_me = (long long)c;
+      w_me = (long long)wv;
     }
-    if (lane != 0) return;
   }
   double* psi = P.t.psi_root;
-  const int* nrow = rec_n(P.t, 0);
-  const unsigned long long* crow = rec_c(P.t, 0);
-  unsigned long long* wrow = rec_w(P.t, 0);
-  const double vc = lse64(psi, A, P.eta64);
-  long long nsum = 0;
-  bool any = false;
-  int nodes = 0;
-  for (int j = 0; j < A; ++j) {
-    const int n = nrow[j];
-    if (n <= 0) continue;
-    any = true;
-    ++nodes;
-    const double c = (double)(long long)crow[j] * P.fix_inv64;
-    const double w = (double)(long long)wrow[j] * P.fix_inv64;
-    wrow[j] = 0ull;
-    const double q = c / (double)n + P.m.gamma64 * (w / (double)n);
-    psi[j] = (psi[j] - vc) + q;
-    nsum += n;
+  const double eta = P.eta64;
+  const double p_me = act ? psi[lane] : -INFINITY;
+  if (act) {                                  // record 0 keeps the totals
+    rec_n(P.t, 0)[lane] = (int)n_me;
+    rec_c(P.t, 0)[lane] = (unsigned long long)c_me;
   }
-  if (k == P.K) atomicAdd(&P.t.stats[kStripes], (unsigned long long)nodes);
-  if (!any) return;
-  root_cdf(psi, A, P.eta64, P.t.root_cdf);
-  const double v = lse64(psi, A, P.eta64);
+  const int nodes = __popcll(__ballot(act && n_me > 0));
+  if (k == P.K && lane == 0) atomicAdd(&P.t.stats[kStripes], (unsigned long long)nodes);
+  if (nodes == 0) return;
+  // V_curr = L_eta Psi before the update (Eq. 3).
+  const double m = wave_max64(p_me);
+  const double vc = m + log(ordered_sum(act ? exp(eta * (p_me - m)) : 0.0, A)) / eta;
+  // Psi <- Psi - V_curr + Q for the actions with an action node (Eq. 5).
+  double p_new = p_me;
+  if (act && n_me > 0) {
+    const double c = (double)c_me * P.fix_inv64;
+    const double w = (double)w_me * P.fix_inv64;
+    const double q = c / (double)n_me + P.m.gamma64 * (w / (double)n_me);
+    p_new = (p_me - vc) + q;
+    psi[lane] = p_new;
+  }
+  // V = L_eta Psi after the update, and the running sums of the root draw.
+  const double m2 = wave_max64(act ? p_new : -INFINITY);
+  const double e2 = act ? exp(eta * (p_new - m2)) : 0.0;
+  double run = 0.0;
+  for (int j = 0; j < A; ++j) {
+    run = run + __shfl(e2, j, 64);
+    if (lane == 0) P.t.root_cdf[j] = run;
+  }
+  const long long nsum = (long long)wave_sum((unsigned long long)n_me);
+  if (lane != 0) return;
+  const double v = m2 + log(run) / eta;
   P.t.v_root[0] = v;
   RecMeta* mt = rec_meta(P.t, 0);
   mt->V = (float)v;
