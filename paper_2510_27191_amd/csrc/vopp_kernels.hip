@@ -504,12 +504,24 @@ __device__ __forceinline__ int record_at(const PlanView& P, int t, int ep) {
 }
 
 // Push V*N_b of a belief into its parent action's W accumulator (parent =
-// (record << 6) | a, or kEmptyKey for none), aggregated per block.  Called by
-// every thread of the block (it contains barriers).
-__device__ __forceinline__ void push_values(const PlanView& P, AggTable& G,
+// (record << 6) | a, or kEmptyKey for none).  Beliefs of depth >= 3 mostly
+// have distinct parents, so they add directly; shallower ones share a few
+// parents and are combined per block first (then every thread of the block
+// must call, as it contains barriers; `shared` is uniform).
+constexpr int kPushDirectDepth = 3;
+
+__device__ __forceinline__ void push_values(const PlanView& P, AggTable& G, bool shared,
                                             unsigned long long parent, float V, int N) {
   unsigned long long f = 0ull;
   if (parent != kEmptyKey && N > 0) f = to_fix(V * (float)N, P.fix_scale);
+  if (!shared) {
+    if (f) {
+      const int pr = (int)(parent >> 6), a = (int)(parent & 63ull);
+      if (pr == 0) atomicAdd(root_stripe(P.t, 2, a), f);
+      else atomicAdd(&rec_w(P.t, pr)[a], f);
+    }
+    return;
+  }
   if (!__syncthreads_or(f != 0ull)) return;   // uniform: nothing to push
   agg_clear(G);
   __syncthreads();
@@ -561,7 +573,7 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
       parent = parent_link(P.t, mt);
       ++beliefs;
     }
-    push_values(P, sm.agg, parent, V, N);
+    push_values(P, sm.agg, dep < kPushDirectDepth, parent, V, N);
   }
   if (k == P.K) {
     beliefs = block_sum(beliefs, sm.wave);
@@ -662,7 +674,7 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
       for (int j = 0; j < AM; ++j) nodes += (j < A && n[j] > 0) ? 1ull : 0ull;
       ++beliefs;
     }
-    push_values(P, sm.agg, parent, V, N);
+    push_values(P, sm.agg, dep - 1 < kPushDirectDepth, parent, V, N);
   }
   if (k == P.K) {
     nodes = block_sum(nodes, sm.wave);
