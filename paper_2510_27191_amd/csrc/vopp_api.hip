@@ -145,7 +145,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   p->h_max = hmax;
   p->gamma = d->gamma;
   p->branch = (double)d->nA * d->nO;
-  hipGetDevice(&p->device);
+  (void)hipGetDevice(&p->device);
   size_t bytes = 0;
   bytes += align_up((rows + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) * 2;
   bytes += align_up(thrZ.size() * 4, 256) + align_up(rows * 4, 256) +
@@ -166,7 +166,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   if (e == hipSuccess) e = hipMemcpy(tZ, thrZ.data(), thrZ.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(R, d->reward, rows * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && H) e = hipMemcpy(H, d->heur, (size_t)d->nS * 4, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
+  if (e != hipSuccess) { (void)hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
   ModelView& m = p->view;
   std::memset(&m, 0, sizeof(m));
   m.kind = kTabular;
@@ -200,7 +200,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
                        std::fabs(rs + rg + rh)});
   p->h_max = d->heuristic ? 2.0 * (double)(d->hi - d->lo) + 1.0 : 0.0;
   p->branch = 4.0 * (double)d->key_n * d->key_n;
-  hipGetDevice(&p->device);
+  (void)hipGetDevice(&p->device);
   size_t bytes = align_up(4096 * 4, 256) + align_up((size_t)2 * d->n_disks * 4 + 4, 256) + 512;
   hipError_t e = hipMalloc(&p->arena, bytes);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
@@ -211,7 +211,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   e = hipMemcpy(g, d->gauss, 4096 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && d->n_disks)
     e = hipMemcpy(disks, d->disks, 2 * (size_t)d->n_disks * 4, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
+  if (e != hipSuccess) { (void)hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
   ModelView& m = p->view;
   std::memset(&m, 0, sizeof(m));
   m.kind = kNav;
@@ -236,8 +236,8 @@ extern "C" int32_t vopp_pomdp_num_actions(const vopp_pomdp* p) { return p ? p->n
 extern "C" void vopp_pomdp_free(vopp_pomdp* p) {
   if (!p) return;
   if (p->own_ws) vopp_workspace_free(p->own_ws);
-  if (p->filt) hipFree(p->filt);
-  if (p->arena) hipFree(p->arena);
+  if (p->filt) (void)hipFree(p->filt);
+  if (p->arena) (void)hipFree(p->arena);
   delete p;
 }
 
@@ -292,7 +292,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   vopp_workspace* w = new vopp_workspace();
   w->z = z;
   w->bytes = bytes_for(z);
-  hipGetDevice(&w->device);
+  (void)hipGetDevice(&w->device);
   hipError_t e = hipMalloc(&w->arena, w->bytes);
   if (e != hipSuccess) {
     delete w;
@@ -385,12 +385,12 @@ extern "C" vopp_status vopp_workspace_create(const vopp_pomdp* p, const vopp_par
 
 extern "C" void vopp_workspace_free(vopp_workspace* w) {
   if (!w) return;
-  if (w->arena) hipFree(w->arena);
-  if (w->out_host) hipHostFree(w->out_host);
-  if (w->step_host) hipHostFree(w->step_host);
-  if (w->ev0) hipEventDestroy(w->ev0);
-  if (w->ev1) hipEventDestroy(w->ev1);
-  for (hipEvent_t ev : w->prof_events) hipEventDestroy(ev);
+  if (w->arena) (void)hipFree(w->arena);
+  if (w->out_host) (void)hipHostFree(w->out_host);
+  if (w->step_host) (void)hipHostFree(w->step_host);
+  if (w->ev0) (void)hipEventDestroy(w->ev0);
+  if (w->ev1) (void)hipEventDestroy(w->ev1);
+  for (hipEvent_t ev : w->prof_events) (void)hipEventDestroy(ev);
   delete w;
 }
 
@@ -563,7 +563,7 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
   if (!action) return fail(VOPP_E_INVALID, "null action pointer");
   int dev = -1;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   if (dev != p->device) return fail(VOPP_E_INVALID, "model lives on device %d, current is %d", p->device, dev);
   if (ws) {
     if (!fits(ws->z, sizes_for(p, prm->n_particles, budget, depth, prm->schedule)))
@@ -614,7 +614,7 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
     stats->n_beliefs = (int64_t)o[A + 3];
     stats->n_actions = (int64_t)o[A + 4];
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
+    (void)hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
     stats->device_ms = ms;
   }
   return VOPP_OK;
@@ -664,8 +664,8 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   if (e == hipSuccess) e = hipMemcpy(ids_dev, ids.data(), nb * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_gather(w->tree, ids_dev, (int)nb, rec_dev, nullptr);
   cp(rec.data(), rec_dev, nb * (size_t)rs);
-  if (ids_dev) hipFree(ids_dev);
-  if (rec_dev) hipFree(rec_dev);
+  if (ids_dev) (void)hipFree(ids_dev);
+  if (rec_dev) (void)hipFree(rec_dev);
   if (e != hipSuccess) return hip_fail(e, "tree dump");
   auto meta = [&](size_t i) {
     return reinterpret_cast<const RecMeta*>(rec.data() + i * rs + 24 * ra);
@@ -798,7 +798,7 @@ vopp_status filter_scratch(vopp_pomdp* p, int n, double** out, int** env,
                            unsigned long long** w, void** prop) {
   const size_t need = 4096 + (size_t)n * 8 + (size_t)n * 8 + 512;
   if (p->filt_bytes < need) {
-    if (p->filt) hipFree(p->filt);
+    if (p->filt) (void)hipFree(p->filt);
     p->filt = nullptr;
     p->filt_bytes = 0;
     hipError_t e = hipMalloc(&p->filt, need);

@@ -72,8 +72,8 @@ std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int accum
 namespace {
 
 void release_graph(vopp_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -118,7 +118,7 @@ vopp_status build_schedule(vopp_batch* b) {
     b->launch_blocks.push_back(blocks);
   }
   hipError_t e = hipSuccess;
-  if (b->items_dev) hipFree(b->items_dev);
+  if (b->items_dev) (void)hipFree(b->items_dev);
   b->items_dev = nullptr;
   e = hipMalloc(&b->items_dev, b->items.size() * sizeof(BatchItem));
   if (e == hipSuccess)
@@ -186,14 +186,14 @@ extern "C" void vopp_batch_free(vopp_batch* b) {
   if (!b) return;
   release_graph(b);
   for (vopp_workspace* w : b->ws) vopp_workspace_free(w);
-  if (b->views_dev) hipFree(b->views_dev);
-  if (b->items_dev) hipFree(b->items_dev);
-  if (b->out_dev) hipFree(b->out_dev);
-  if (b->out_host) hipHostFree(b->out_host);
-  if (b->ev0) hipEventDestroy(b->ev0);
-  if (b->ev1) hipEventDestroy(b->ev1);
-  if (b->ev_in) hipEventDestroy(b->ev_in);
-  if (b->stream) hipStreamDestroy(b->stream);
+  if (b->views_dev) (void)hipFree(b->views_dev);
+  if (b->items_dev) (void)hipFree(b->items_dev);
+  if (b->out_dev) (void)hipFree(b->out_dev);
+  if (b->out_host) (void)hipHostFree(b->out_host);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 
@@ -204,7 +204,7 @@ extern "C" vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
   *out = nullptr;
   if (!reqs || n < 1) return fail(VOPP_E_INVALID, "empty batch");
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   int amax = 4;
   for (int i = 0; i < n; ++i) {
     const vopp_request& r = reqs[i];
@@ -311,12 +311,12 @@ extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_g
   if (e != hipSuccess) {
     // The tables of every instance are in an unknown state now.
     const unsigned long long one = 1ull;
-    for (vopp_workspace* w : b->ws) hipMemcpy(&w->tree.counters[3], &one, 8, hipMemcpyHostToDevice);
+    for (vopp_workspace* w : b->ws) (void)hipMemcpy(&w->tree.counters[3], &one, 8, hipMemcpyHostToDevice);
     return hip_fail(e, "batch execution");
   }
   if (device_ms) {
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, b->ev0, b->ev1);
+    (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
     *device_ms = ms;
   }
   parse_results(b, results);

@@ -709,7 +709,6 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
   const bool act = lane < A;
   unsigned long long* acc = P.t.root_acc;
   long long n_me = 0, c_me = 0, w_me = 0;     // sums of action `lane`
-#pragma unroll 4
   for (int j = 0; j < A; ++j) {
     unsigned long long* w = &acc[((size_t)2 * kMaxA + j) * kStripes + lane];
     const unsigned long long n = wave_sum(acc[((size_t)0 * kMaxA + j) * kStripes + lane]);

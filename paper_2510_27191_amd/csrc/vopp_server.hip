@@ -101,7 +101,7 @@ size_t filter_bytes(const Episode& e) {
 
 void free_resources(Resources& r) {
   if (r.ws) vopp_workspace_free(r.ws);
-  if (r.fbuf) hipFree(r.fbuf);
+  if (r.fbuf) (void)hipFree(r.fbuf);
   r = Resources{};
 }
 
@@ -254,7 +254,7 @@ vopp_status harvest_one(vopp_server* s, bool wait) {
       unsigned long long* w;
       int* env;
       carve(e, &part, &prop, &w, &env);
-      hipMemcpyAsync(e.final_env, env, 8 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
+      (void)hipMemcpyAsync(e.final_env, env, 8 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
       s->slot_ep[e.slot] = -1;
       s->used -= e.footprint;
       e.slot = -1;
@@ -280,7 +280,7 @@ extern "C" vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_se
     return fail(VOPP_E_INVALID, "max_inflight must be in [1, %d]", kMaxInflight);
   vopp_server* s = new vopp_server();
   s->cfg = *cfg;
-  hipGetDevice(&s->device);
+  (void)hipGetDevice(&s->device);
   s->slot_ep.assign(cfg->max_active, -1);
   s->t0 = std::chrono::steady_clock::now();
   const size_t na = (size_t)cfg->max_active;
@@ -308,23 +308,23 @@ extern "C" vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_se
 
 extern "C" void vopp_server_free(vopp_server* s) {
   if (!s) return;
-  if (s->stream) hipStreamSynchronize(s->stream);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (Episode& e : s->eps) {
     if (!e.finished && e.admitted) free_resources(e.res);
-    if (e.final_env) hipHostFree(e.final_env);
-    if (e.init) hipHostFree(e.init);
+    if (e.final_env) (void)hipHostFree(e.final_env);
+    if (e.init) (void)hipHostFree(e.init);
   }
   for (Resources& r : s->pool) free_resources(r);
   for (int k = 0; k <= kMaxInflight; ++k) {
-    if (s->items_dev[k]) hipFree(s->items_dev[k]);
-    if (s->items_host[k]) hipHostFree(s->items_host[k]);
-    if (s->out_host[k]) hipHostFree(s->out_host[k]);
-    if (s->ev[k]) hipEventDestroy(s->ev[k]);
+    if (s->items_dev[k]) (void)hipFree(s->items_dev[k]);
+    if (s->items_host[k]) (void)hipHostFree(s->items_host[k]);
+    if (s->out_host[k]) (void)hipHostFree(s->out_host[k]);
+    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
   }
-  if (s->views_dev) hipFree(s->views_dev);
-  if (s->views_host) hipHostFree(s->views_host);
-  if (s->out_dev) hipFree(s->out_dev);
-  if (s->stream) hipStreamDestroy(s->stream);
+  if (s->views_dev) (void)hipFree(s->views_dev);
+  if (s->views_host) (void)hipHostFree(s->views_host);
+  if (s->out_dev) (void)hipFree(s->out_dev);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
 
@@ -358,7 +358,7 @@ extern "C" vopp_status vopp_server_submit(vopp_server* s, const vopp_episode_des
   hipError_t err = hipHostMalloc((void**)&e.final_env, 8 * sizeof(int), hipHostMallocDefault);
   if (err == hipSuccess) err = hipHostMalloc((void**)&e.init, bytes, hipHostMallocDefault);
   if (err != hipSuccess) {
-    if (e.final_env) hipHostFree(e.final_env);
+    if (e.final_env) (void)hipHostFree(e.final_env);
     return hip_fail(err, "hipHostMalloc");
   }
   std::memcpy(e.init, d->init_particles, bytes);
