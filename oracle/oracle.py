@@ -57,7 +57,8 @@ class OrcParams(C.Structure):
                 ("depth", C.c_int32), ("schedule", C.c_int32),
                 ("eta", C.c_double), ("seed", C.c_uint64),
                 ("step", C.c_uint32), ("tau", C.c_double),
-                ("trace", C.c_int32), ("mutate", C.c_int32)]
+                ("trace", C.c_int32), ("mutate", C.c_int32),
+                ("pi0", C.c_void_p)]
 
 
 def load():
@@ -167,12 +168,19 @@ class OracleResult:
 
 
 def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
-         schedule=0, step=0, tau=2.0 ** -16, trace=False, mutate=0):
-    """Run one serial planning step and return the full tree."""
+         schedule=0, step=0, tau=2.0 ** -16, trace=False, mutate=0, pi0=None):
+    """Run one serial planning step and return the full tree.  pi0: reference
+    policy weights over the actions (positive; normalised), or None: uniform."""
     lib = load()
     keep = _Keep()
+    pi = None
+    if pi0 is not None:
+        pi = np.ascontiguousarray(pi0, np.float64)
+        assert pi.shape == (inst["nA"],) and np.all(pi > 0)
+        keep.arrs.append(pi)
     prm = OrcParams(n_particles, budget, depth, schedule, eta, seed, step,
-                    tau, 1 if trace else 0, mutate)
+                    tau, 1 if trace else 0, mutate,
+                    None if pi is None else pi.ctypes.data)
     if inst["kind"] == "tabular":
         m = tabular_struct(inst, keep)
         bel = _c32(belief, np.int32)

@@ -31,7 +31,9 @@
  *   - Levels d = 0 .. D-1 are expanded; leaves sit at depth D.
  *   - The budget is K iterations; D_k = min(k, depth) (deepening schedule of
  *     Alg. 1) or D_k = depth (fixed schedule).
- *   - Uniform reference policy: Psi0(b,a) = -ln|A| / eta, so L_eta Psi0 = 0.
+ *   - Reference policy pi0 (Eq. 4, first term): Psi0(b,a) = ln(pi0(a)) / eta
+ *     with pi0 normalised by its sum, the same at every belief; uniform by
+ *     default, Psi0 = -ln|A| / eta.  Either way L_eta Psi0 = 0.
  *   - Only actions that own an action node are updated in the backup; all
  *     of them use the same V_curr.  Every node of the backed-up depth in the
  *     whole tree takes part; an action node without child beliefs has W = 0.
@@ -184,6 +186,7 @@ typedef struct {
   double tau;      // margins below tau are counted as near ties
   int32_t trace;   // keep a per-draw trace
   int32_t mutate;  // 0: none.  >0 plants a known mistake (pin sensitivity)
+  const double* pi0;  // [A] reference policy weights (> 0), or NULL: uniform
 } orc_params;
 
 }  // extern "C"
@@ -355,17 +358,25 @@ struct Tree {
   std::unordered_map<uint64_t, int32_t> obs_child;  // (action node, obs)
   std::vector<std::vector<int32_t>> beliefs_at, actions_at;
 
-  void init(int nA, double eta) {
+  std::vector<double> psi0;          // initial preference row (Eq. 4, first term)
+
+  void init(int nA, double eta, const double* pi0) {
     A = nA;
+    psi0.assign(A, -std::log((double)A) / eta);
+    if (pi0) {
+      double sum = 0.0;
+      for (int a = 0; a < A; ++a) sum += pi0[a];
+      for (int a = 0; a < A; ++a) psi0[a] = std::log(pi0[a] / sum) / eta;
+    }
     new_belief(-1, -1, 0, eta);
   }
   int32_t new_belief(int32_t parent, int32_t obs, int32_t depth, double eta) {
+    (void)eta;
     int32_t id = (int32_t)b_parent.size();
     b_parent.push_back(parent);
     b_obs.push_back(obs);
     b_depth.push_back(depth);
-    double psi0 = -std::log((double)A) / eta;
-    for (int a = 0; a < A; ++a) { psi.push_back(psi0); b_child.push_back(-1); }
+    for (int a = 0; a < A; ++a) { psi.push_back(psi0[a]); b_child.push_back(-1); }
     b_V.push_back(0.0);
     b_N.push_back(0);
     if ((int)beliefs_at.size() <= depth) beliefs_at.resize(depth + 1);
@@ -479,7 +490,7 @@ Result* plan(const Model& model, int A, const State* belief, int M,
   Tree& T = res->tree;
   const double eta = prm->eta;
   const double gamma = model.gamma;
-  T.init(A, eta);
+  T.init(A, eta, prm->pi0);
   const int K = prm->budget;
   const int n_p = prm->n_particles;
   const int mut = prm->mutate;

@@ -295,10 +295,16 @@ def k1_values(rep, eta):
 # Exact reference-based Bellman recursion (Eq. 3-4) on Bayes beliefs.
 # ---------------------------------------------------------------------------
 
-def ref_bellman(inst, b0, depth, eta):
+def ref_bellman(inst, b0, depth, eta, pi0=None):
+    """The reference-based Bellman recursion of Eq. (3)-(4) on exact Bayes
+    beliefs: V(b) = L_eta[(1/eta) log pi0 + R(b, .) + gamma E_o V(tau(b, ., o))]."""
     mdl = Tabular(inst)
     A = mdl.nA
-    logpi0 = -math.log(A)
+    if pi0 is None:
+        logpi0 = -math.log(A)
+    else:
+        pi = np.asarray(pi0, np.float64)
+        logpi0 = np.log(pi / pi.sum())
 
     def V(b, d):
         if d == depth:
