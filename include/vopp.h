@@ -103,6 +103,19 @@ vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* desc, vopp_pomdp** out);
 vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* desc, vopp_pomdp** out);
 /* Number of actions |A| of a model (0 for NULL). */
 int32_t vopp_pomdp_num_actions(const vopp_pomdp* pomdp);
+/* Reference policy pi0 of the KL-regularised objective (Sec. 3, Eq. 4): every
+ * belief's preference row starts at ln pi0(a) / eta instead of the uniform
+ * -ln|A| / eta, so the first softmax draws at a new belief follow pi0 and the
+ * values are the pi0-weighted soft maxima.
+ *   pi0  host array of |A| weights, each finite and > 0; they are normalised
+ *        by their sum (a plain double sum in index order).  NULL restores the
+ *        uniform policy.
+ * Copied synchronously to the model's device memory; the model must live on
+ * the current device.  Plans already enqueued may see either policy: do not
+ * call it while a plan with this model is in flight.
+ * Returns VOPP_E_INVALID (null model, bad entry, wrong device) with the model
+ * unchanged, or VOPP_E_DEVICE. */
+vopp_status vopp_pomdp_set_reference_policy(vopp_pomdp* pomdp, const double* pi0);
 void vopp_pomdp_free(vopp_pomdp* pomdp);
 
 /* ------------------------------------------------------------------------ */

@@ -70,6 +70,21 @@ static bool valid_row(const float* p, int n) {
   return std::fabs(s - 1.0) <= 1e-5;
 }
 
+// ln pi0(a) of a reference policy (Eq. 4), normalised by its sequential double
+// sum, written to the model's device row of kMaxA entries (zero past nA).  A
+// null pi0 gives the uniform row -ln nA.
+static hipError_t upload_log_prior(double* dst, int nA, const double* pi0) {
+  double row[kMaxA] = {};
+  if (pi0) {
+    double sum = 0.0;
+    for (int a = 0; a < nA; ++a) sum += pi0[a];
+    for (int a = 0; a < nA; ++a) row[a] = std::log(pi0[a] / sum);
+  } else {
+    for (int a = 0; a < nA; ++a) row[a] = -std::log((double)nA);
+  }
+  return hipMemcpy(dst, row, sizeof(row), hipMemcpyHostToDevice);
+}
+
 // Carves aligned sub-buffers out of one device allocation.
 struct Carver {
   char* base;
@@ -149,7 +164,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   size_t bytes = 0;
   bytes += align_up((rows + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) * 2;
   bytes += align_up(thrZ.size() * 4, 256) + align_up(rows * 4, 256) +
-           align_up((size_t)d->nS * 4, 256) + 1024;
+           align_up((size_t)d->nS * 4, 256) + align_up(kMaxA * 8, 256) + 1024;
   hipError_t e = hipMalloc(&p->arena, bytes);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
   p->bytes = bytes;
@@ -160,12 +175,14 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   uint32_t* tZ = c.take<uint32_t>(thrZ.size());
   float* R = c.take<float>(rows);
   float* H = d->heur ? c.take<float>(d->nS) : nullptr;
+  double* logpi0 = c.take<double>(kMaxA);
   e = hipMemcpy(rowptr, d->rowptr, (rows + 1) * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(col, d->col, (size_t)nnz * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(tT, thrT.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(tZ, thrZ.data(), thrZ.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(R, d->reward, rows * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && H) e = hipMemcpy(H, d->heur, (size_t)d->nS * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload_log_prior(logpi0, d->nA, nullptr);
   if (e != hipSuccess) { (void)hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
   ModelView& m = p->view;
   std::memset(&m, 0, sizeof(m));
@@ -173,6 +190,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   m.nS = d->nS; m.nA = d->nA; m.nO = d->nO;
   m.Apad = (d->nA + 3) / 4 * 4;
   m.rowptr = rowptr; m.col = col; m.thrT = tT; m.thrZ = tZ; m.R = R; m.H = H;
+  m.logpi0 = logpi0;
   m.gamma = (float)d->gamma;
   m.gamma64 = d->gamma;
   *out = p;
@@ -201,16 +219,19 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   p->h_max = d->heuristic ? 2.0 * (double)(d->hi - d->lo) + 1.0 : 0.0;
   p->branch = 4.0 * (double)d->key_n * d->key_n;
   (void)hipGetDevice(&p->device);
-  size_t bytes = align_up(4096 * 4, 256) + align_up((size_t)2 * d->n_disks * 4 + 4, 256) + 512;
+  size_t bytes = align_up(4096 * 4, 256) + align_up((size_t)2 * d->n_disks * 4 + 4, 256) +
+                 align_up(kMaxA * 8, 256) + 512;
   hipError_t e = hipMalloc(&p->arena, bytes);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
   p->bytes = bytes;
   Carver c(p->arena);
   float* g = c.take<float>(4096);
   float* disks = c.take<float>(2 * (size_t)d->n_disks + 1);
+  double* logpi0 = c.take<double>(kMaxA);
   e = hipMemcpy(g, d->gauss, 4096 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && d->n_disks)
     e = hipMemcpy(disks, d->disks, 2 * (size_t)d->n_disks * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload_log_prior(logpi0, 4, nullptr);
   if (e != hipSuccess) { (void)hipFree(p->arena); delete p; return hip_fail(e, "hipMemcpy(model)"); }
   ModelView& m = p->view;
   std::memset(&m, 0, sizeof(m));
@@ -225,6 +246,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   np.disk_r2 = d->disk_r2; np.r_step = d->r_step; np.r_goal = d->r_goal;
   np.r_hit = d->r_hit; np.heuristic = d->heuristic; np.n_disks = d->n_disks;
   m.gauss = g; m.disks = disks;
+  m.logpi0 = logpi0;
   m.gamma = (float)d->gamma;
   m.gamma64 = d->gamma;
   *out = p;
@@ -232,6 +254,22 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
 }
 
 extern "C" int32_t vopp_pomdp_num_actions(const vopp_pomdp* p) { return p ? p->nA : 0; }
+
+extern "C" vopp_status vopp_pomdp_set_reference_policy(vopp_pomdp* p, const double* pi0) {
+  clear_error();
+  if (!p) return fail(VOPP_E_INVALID, "null model");
+  if (pi0)
+    for (int a = 0; a < p->nA; ++a)
+      if (!(std::isfinite(pi0[a]) && pi0[a] > 0.0))
+        return fail(VOPP_E_INVALID, "reference policy entry %d is not a positive finite number", a);
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != p->device)
+    return fail(VOPP_E_INVALID, "model lives on device %d, current is %d", p->device, dev);
+  const hipError_t e = upload_log_prior(const_cast<double*>(p->view.logpi0), p->nA, pi0);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(reference policy)");
+  return VOPP_OK;
+}
 
 extern "C" void vopp_pomdp_free(vopp_pomdp* p) {
   if (!p) return;
@@ -273,6 +311,7 @@ size_t bytes_for(const WsSizes& z) {
   add((size_t)z.cap_b * z.rs);                       // belief records
   add(z.hcap * sizeof(HSlot));                       // table
   add(kMaxA * 8); add(kMaxA * 8); add(8);            // root row and its CDF, V(root)
+  add(kMaxA * 4);                                    // initial preference row
   add((size_t)3 * kMaxA * kStripes * 8);             // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(3 * kStripes * 8); add((z.K + 1) * 4);
@@ -307,6 +346,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.h_slot = c.take<HSlot>(z.hcap);
   t.h_mask = (uint32_t)(z.hcap - 1);
   t.psi_root = c.take<double>(kMaxA);
+  t.psi0 = c.take<float>(kMaxA);
   t.root_cdf = c.take<double>(kMaxA);
   t.root_acc = c.take<unsigned long long>((size_t)3 * kMaxA * kStripes);
   t.v_root = c.take<double>(1);
@@ -427,8 +467,6 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
   P.fix_scale = std::ldexp(1.0f, S);
   P.fix_inv = std::ldexp(1.0f, -S);
   P.fix_inv64 = std::ldexp(1.0, -S);
-  P.psi0_64 = -std::log((double)p->nA) / prm->eta;
-  P.psi0 = (float)P.psi0_64;
   P.K = K;
   P.depth = depth;
   P.schedule = prm->schedule;

@@ -79,6 +79,8 @@ struct ModelView {
   NavParams nav;
   const float* disks;                      // [2*n_disks]
   const float* gauss;                      // [4096]
+  const double* logpi0;                    // [kMaxA] ln pi0(a) of the reference
+                                           // policy, normalised; -ln|A| if uniform
   float gamma;
   double gamma64;
 };
@@ -110,6 +112,8 @@ struct TreeView {
   HSlot* h_slot;                 // [h_mask + 1] open-addressing table
   uint32_t h_mask;
   double* psi_root;              // [nA]
+  float* psi0;                   // [kMaxA] initial preference row ln pi0 / eta,
+                                 // zero past |A|
   double* root_cdf;              // [nA] running sums of the root's softmax weights
   unsigned long long* root_acc;  // [3][kMaxA][kStripes]: N, C and W of the root's
                                  // action nodes, striped over blocks (every
@@ -184,8 +188,6 @@ struct PlanView {
   float fix_scale;         // 2^S: fixed-point scale of the deterministic sums
   float fix_inv;           // 2^-S
   double fix_inv64;
-  float psi0;              // -ln|A| / eta
-  double psi0_64;
   int K, depth, schedule;
   int steps;               // level steps of the plan (sum of D_k)
   double* out;             // kOutStride doubles: the plan's result
@@ -457,15 +459,6 @@ __device__ __forceinline__ int draw_action32(const float* __restrict__ row, int 
     if (j < A) q = *reinterpret_cast<const float4*>(row + j);
     v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
   }
-  return draw_row32<AM>(v, A, eta, x0);
-}
-
-// The draw from a row that still holds its initial value psi0 everywhere.
-template <int AM>
-__device__ __forceinline__ int draw_initial32(float psi0, int A, float eta, uint32_t x0) {
-  float v[AM];
-#pragma unroll
-  for (int j = 0; j < AM; ++j) v[j] = psi0;
   return draw_row32<AM>(v, A, eta, x0);
 }
 

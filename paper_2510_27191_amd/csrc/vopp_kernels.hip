@@ -215,9 +215,15 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
     __syncthreads();
     const int j = threadIdx.x;
     if (j < 3 * kStripes) T.stats[j] = 0ull;
-    if (j < P.m.nA) {
-      rec_psi(T, 0)[j] = P.psi0;
-      T.psi_root[j] = P.psi0_64;
+    if (j < kMaxA) {
+      // Initial preferences ln pi0 / eta: the root keeps them in double
+      // precision, every other belief starts from their f32 rounding.
+      const double v = j < P.m.nA ? P.m.logpi0[j] / P.eta64 : 0.0;
+      T.psi0[j] = (float)v;
+      if (j < P.m.nA) {
+        rec_psi(T, 0)[j] = (float)v;
+        T.psi_root[j] = v;
+      }
     }
     __syncthreads();
     if (j == 0) {
@@ -235,17 +241,16 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
 // Phase: the forward search of iteration k over D levels (Alg. 2).
 // ---------------------------------------------------------------------------
 
-// A new belief's record: Psi = psi0 (Eq. 6 starts uniform), N = C = W = 0,
-// its observation key and its parent link.
+// A new belief's record: Psi = ln pi0 / eta (the first term of Eq. 4; uniform
+// unless a reference policy is set), N = C = W = 0, its observation key and its
+// parent link.
 __device__ __forceinline__ void init_record(const PlanView& P, int id, int obs,
                                             unsigned long long link) {
   const TreeView& T = P.t;
   uint4* q = reinterpret_cast<uint4*>(rec_at(T, id));
-  const int ra = T.ra, A = P.m.nA;
-  const uint32_t p0 = __float_as_uint(P.psi0);
-  for (int j = 0; j < ra; j += 4)
-    q[j >> 2] = make_uint4(j < A ? p0 : 0u, j + 1 < A ? p0 : 0u, j + 2 < A ? p0 : 0u,
-                           j + 3 < A ? p0 : 0u);
+  const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
+  const int ra = T.ra;
+  for (int j = 0; j < ra; j += 4) q[j >> 2] = p0[j >> 2];
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   const int meta_q = 6 * ra / 4;                // N, C and W take 5*ra/4 quads
   for (int i = ra / 4; i < meta_q; ++i) q[i] = z;
@@ -269,7 +274,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   int sid = 0;                // current belief's slot id (0: root)
   int rid = 0;                // its record, -1 if another episode inserted it
                               // during this iteration
-  bool fresh = false;         // inserted during this iteration (Psi = psi0)
+  bool fresh = false;         // inserted during this iteration (Psi initial)
   bool alive = false;
   if (ep_ok) {
     // Alg. 1: the episode starts at the root with a state drawn from the
@@ -312,7 +317,6 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     const int rid_b = rid;
     if (alive) {
       if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
-      else if (fresh) a = draw_initial32<AM>(P.psi0, A, P.eta, w.x);
       else a = draw_row32<AM>(row, A, P.eta, w.x);
       bool term = false;
       if (!nav) {
@@ -354,7 +358,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     if (alive && d + 1 < D) {
       w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
-      if (!fresh) load_row<AM>(rec_psi(T, rid), A, row);
+      load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
       if (nav) z = nav_noise(P.m, w);
     }
     // Writes of level d.

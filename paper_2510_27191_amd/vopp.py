@@ -27,7 +27,8 @@ SCHEDULE_FIXED = 1
 
 EXPORTS = (
     "vopp_last_error", "vopp_version", "vopp_pomdp_tabular", "vopp_pomdp_nav2d",
-    "vopp_pomdp_num_actions", "vopp_pomdp_free", "vopp_plan_footprint",
+    "vopp_pomdp_num_actions", "vopp_pomdp_set_reference_policy", "vopp_pomdp_free",
+    "vopp_plan_footprint",
     "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
     "vopp_tree_dump", "vopp_level_counts", "vopp_profile_enable", "vopp_profile_reset",
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
@@ -134,6 +135,8 @@ def lib():
     L.vopp_pomdp_nav2d.restype = st
     L.vopp_pomdp_num_actions.argtypes = [vp]
     L.vopp_pomdp_num_actions.restype = i32
+    L.vopp_pomdp_set_reference_policy.argtypes = [vp, C.POINTER(C.c_double)]
+    L.vopp_pomdp_set_reference_policy.restype = st
     L.vopp_pomdp_free.argtypes = [vp]
     L.vopp_pomdp_free.restype = None
     L.vopp_plan_footprint.argtypes = [vp, C.POINTER(vopp_params), i32, i32]
@@ -238,6 +241,18 @@ class Pomdp:
                             disks.size // 2, _p(disks), _p(gauss), inst["gamma"])
         _check(L.vopp_pomdp_nav2d(C.byref(d), C.byref(h)))
         return cls(h.value, "nav", 4)
+
+    def set_reference_policy(self, pi0):
+        """vopp_pomdp_set_reference_policy: pi0 of |A| positive weights, or None
+        for the uniform policy."""
+        if pi0 is None:
+            _check(lib().vopp_pomdp_set_reference_policy(self.handle, None))
+            return
+        a = _arr(pi0, np.float64).reshape(-1)
+        if a.size != self.nA:
+            raise ValueError(f"reference policy has {a.size} entries, the model {self.nA} actions")
+        _check(lib().vopp_pomdp_set_reference_policy(
+            self.handle, a.ctypes.data_as(C.POINTER(C.c_double))))
 
     def close(self):
         if self.handle:
