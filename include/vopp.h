@@ -103,7 +103,7 @@ vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* desc, vopp_pomdp** out);
 vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* desc, vopp_pomdp** out);
 /* Number of actions |A| of a model (0 for NULL). */
 int32_t vopp_pomdp_num_actions(const vopp_pomdp* pomdp);
-/* Reference policy pi0 of the KL-regularised objective (Sec. 3, Eq. 4): every
+/* Reference policy pi0 of the KL-regularised objective (Sec. III-A, Eq. 4): every
  * belief's preference row starts at ln pi0(a) / eta instead of the uniform
  * -ln|A| / eta, so the first softmax draws at a new belief follow pi0 and the
  * values are the pi0-weighted soft maxima.
@@ -180,6 +180,31 @@ vopp_status vopp_plan(const vopp_pomdp* pomdp, const void* belief_particles,
                       const vopp_params* params, vopp_workspace* ws,
                       void* stream, int32_t* action, double* values,
                       double* v_root, vopp_stats* stats);
+
+/* Anytime planning step: Alg. 1 with its wall-clock budget.  Iterations run
+ * while the planning time is not used up: after each iteration the device
+ * compares its wall clock with the start of the plan's first kernel, and the
+ * next iteration runs only if less than time_ms has passed, so the plan ends
+ * at most one iteration after the budget.  At least one and at most
+ * max_budget iterations run.
+ *   max_budget: the cap K (sizes the workspace like vopp_plan's budget).
+ *   time_ms: the planning time, > 0 milliseconds of device time.
+ *   iterations (host, out, may be NULL): the number K' of iterations run.
+ * Other arguments and outputs as for vopp_plan.  The tree and result are
+ * those of vopp_plan with budget K' (same draws, the same schedule D_k),
+ * except that the fixed-point resolution of the sums is chosen for
+ * max_budget, so values agree to that resolution.  The host enqueues
+ * iterations at most two ahead of the device and stops once the device
+ * reports the budget spent; kernels of iterations already enqueued then
+ * return at once.  The workspace allocates a small pinned host word on its
+ * first anytime plan.  The vopp_tree_dump and vopp_level_counts of the
+ * workspace then describe the K'-iteration tree. */
+vopp_status vopp_plan_anytime(const vopp_pomdp* pomdp, const void* belief_particles,
+                              int32_t n_belief, int32_t max_budget, int32_t depth,
+                              double time_ms, const vopp_params* params,
+                              vopp_workspace* ws, void* stream, int32_t* action,
+                              double* values, double* v_root, vopp_stats* stats,
+                              int32_t* iterations);
 
 /* Copy the tree of the last plan run in `ws` to host arrays (any may be
  * NULL).  Sizes come from vopp_stats.  Belief arrays [n_beliefs]: parent

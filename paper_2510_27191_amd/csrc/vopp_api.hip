@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -314,7 +315,7 @@ size_t bytes_for(const WsSizes& z) {
   add(kMaxA * 4);                                    // initial preference row
   add((size_t)3 * kMaxA * kStripes * 8);             // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
-  add(64); add(3 * kStripes * 8); add((z.K + 1) * 4);
+  add(64); add(5 * kStripes * 8); add(32); add((z.K + 1) * 4);
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
   add(256 * 8);
@@ -352,7 +353,8 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
   t.counters = c.take<unsigned long long>(8);
-  t.stats = c.take<unsigned long long>(3 * kStripes);
+  t.stats = c.take<unsigned long long>(5 * kStripes);
+  t.gate = c.take<unsigned long long>(4);
   int* step_base = c.take<int>(z.K + 1);
   t.step_base = step_base;
   w->step_base_dev = step_base;
@@ -428,6 +430,7 @@ extern "C" void vopp_workspace_free(vopp_workspace* w) {
   if (w->arena) (void)hipFree(w->arena);
   if (w->out_host) (void)hipHostFree(w->out_host);
   if (w->step_host) (void)hipHostFree(w->step_host);
+  if (w->gate_host) (void)hipHostFree(w->gate_host);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
   if (w->ev1) (void)hipEventDestroy(w->ev1);
   for (hipEvent_t ev : w->prof_events) (void)hipEventDestroy(ev);
@@ -488,6 +491,31 @@ int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep
 }
 
 // Enqueue one planning step on stream s.  Returns the level-step count.
+// Anytime plans: iterations enqueued ahead of the last finished one.  Two
+// keep the device busy while the host enqueues the next.
+constexpr int kTimedAhead = 2;
+
+// Before iteration k of an anytime plan is enqueued: wait until fewer than
+// kTimedAhead iterations are in flight.  *go is false once the device has
+// stopped the plan (budget spent or K reached).
+static vopp_status timed_gate(const vopp_workspace* w, hipStream_t s, int k, bool* go) {
+  for (;;) {
+    const unsigned long long g = __atomic_load_n(w->gate_host, __ATOMIC_ACQUIRE);
+    if (g >> 32) { *go = false; return VOPP_OK; }
+    if (k - 1 - (int)(g & 0xffffffffull) < kTimedAhead) { *go = true; return VOPP_OK; }
+    // The stream may have drained (the word is then final): read it once more.
+    const hipError_t q = hipStreamQuery(s);
+    if (q == hipSuccess) {
+      const unsigned long long g2 = __atomic_load_n(w->gate_host, __ATOMIC_ACQUIRE);
+      if (g2 >> 32) { *go = false; return VOPP_OK; }
+      if (k - 1 - (int)(g2 & 0xffffffffull) < kTimedAhead) { *go = true; return VOPP_OK; }
+      return fail(VOPP_E_INTERNAL, "anytime plan: iteration %d not reported by the device", k - 1);
+    }
+    if (q != hipErrorNotReady) return hip_fail(q, "anytime plan");
+    std::this_thread::yield();
+  }
+}
+
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
                          hipStream_t s, int* n_steps_out) {
   const int K = P.K;
@@ -522,6 +550,12 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   w->hash_dirty = true;   // until the plan has finished
   int t = 0;
   for (int k = 1; k <= K; ++k) {
+    if (P.timed && k > 1) {
+      bool go = true;
+      const vopp_status gs = timed_gate(w, s, k, &go);
+      if (gs != VOPP_OK) return gs;
+      if (!go) break;
+    }
     VOPP_TIMED(VOPP_KERNEL_FORWARD, launch_forward(P, k, D[k], s));
     VOPP_TIMED(VOPP_KERNEL_ACCUMULATE,
                launch_accum(P, D[k], accum_blocks(P, D[k], kAccumCap), s));
@@ -591,11 +625,14 @@ vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_param
 
 }  // namespace vopp
 
-extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_t n_belief,
-                                 int32_t budget, int32_t depth, const vopp_params* prm,
-                                 vopp_workspace* ws, void* stream, int32_t* action,
-                                 double* values, double* v_root, vopp_stats* stats) {
-  clear_error();
+namespace vopp {
+// vopp_plan (time_ms = 0) and vopp_plan_anytime (time_ms > 0; budget is then
+// the iteration cap).
+static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t n_belief,
+                               int32_t budget, int32_t depth, const vopp_params* prm,
+                               vopp_workspace* ws, void* stream, double time_ms,
+                               int32_t* action, double* values, double* v_root,
+                               vopp_stats* stats, int32_t* iterations) {
   vopp_status st = check_params(p, prm, budget, depth);
   if (st != VOPP_OK) return st;
   if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
@@ -615,7 +652,23 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   if (ws->z.Apad < p->view.Apad) return fail(VOPP_E_INVALID, "workspace built for fewer actions");
   hipStream_t s = (hipStream_t)stream;
   PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm);
-  hipError_t e = hipEventRecord(ws->ev0, s);
+  hipError_t e = hipSuccess;
+  if (time_ms > 0.0) {
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device);
+    if (e != hipSuccess) return hip_fail(e, "wall-clock rate");
+    if (khz <= 0) return fail(VOPP_E_DEVICE, "the device reports no wall-clock rate");
+    if (!ws->gate_host) {
+      e = hipHostMalloc((void**)&ws->gate_host, 64, hipHostMallocMapped | hipHostMallocCoherent);
+      if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&ws->gate_dev, ws->gate_host, 0);
+      if (e != hipSuccess) return hip_fail(e, "anytime gate");
+    }
+    __atomic_store_n(ws->gate_host, 0ull, __ATOMIC_RELEASE);
+    P.timed = 1;
+    P.budget_ticks = (unsigned long long)std::max(1.0, std::floor(time_ms * (double)khz));
+    P.gate_host = ws->gate_dev;
+  }
+  e = hipEventRecord(ws->ev0, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   int steps = 0;
   st = enqueue_plan(p, ws, P, s, &steps);
@@ -633,6 +686,14 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   const int flags = (int)o[A + 5];
   if (flags & 1) return fail(VOPP_E_INVALID, "a belief particle holds a state outside [0, nS)");
   if (flags & 2) return fail(VOPP_E_INTERNAL, "belief table overflow");
+  int k_run = budget;
+  if (P.timed) {
+    k_run = (int)(__atomic_load_n(ws->gate_host, __ATOMIC_ACQUIRE) & 0xffffffffull);
+    if (k_run < 1 || k_run > budget)
+      return fail(VOPP_E_INTERNAL, "anytime plan reported %d iterations", k_run);
+    steps = sum_depths(k_run, depth, prm->schedule);
+  }
+  if (iterations) *iterations = k_run;
   *action = (int32_t)o[0];
   if (values) for (int j = 0; j < A; ++j) values[j] = o[1 + j];
   if (v_root) *v_root = o[A + 1];
@@ -643,7 +704,7 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   ws->last_apad = p->view.Apad;
   ws->last_steps = steps;
   ws->last_n_p = prm->n_particles;
-  ws->last_K = budget;
+  ws->last_K = k_run;
   ws->last_depth = depth;
   ws->last_schedule = prm->schedule;
   ws->last_fix_inv64 = P.fix_inv64;
@@ -656,6 +717,30 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
     stats->device_ms = ms;
   }
   return VOPP_OK;
+}
+
+}  // namespace vopp
+
+extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_t n_belief,
+                                 int32_t budget, int32_t depth, const vopp_params* prm,
+                                 vopp_workspace* ws, void* stream, int32_t* action,
+                                 double* values, double* v_root, vopp_stats* stats) {
+  clear_error();
+  return plan_common(p, belief, n_belief, budget, depth, prm, ws, stream, 0.0, action, values,
+                     v_root, stats, nullptr);
+}
+
+extern "C" vopp_status vopp_plan_anytime(const vopp_pomdp* p, const void* belief,
+                                         int32_t n_belief, int32_t max_budget, int32_t depth,
+                                         double time_ms, const vopp_params* prm,
+                                         vopp_workspace* ws, void* stream, int32_t* action,
+                                         double* values, double* v_root, vopp_stats* stats,
+                                         int32_t* iterations) {
+  clear_error();
+  if (!(time_ms > 0.0) || !std::isfinite(time_ms))
+    return fail(VOPP_E_INVALID, "time budget must be a positive number of milliseconds");
+  return plan_common(p, belief, n_belief, max_budget, depth, prm, ws, stream, time_ms, action,
+                     values, v_root, stats, iterations);
 }
 
 extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int32_t* b_obs,

@@ -124,9 +124,11 @@ struct TreeView {
   unsigned long long* counters;  // [1] error flags [2] beliefs of the last plan
                                  // [3] table dirty [5] last plan's level steps
                                  // [6] last plan's n_p
-  unsigned long long* stats;     // [3][kStripes] particle steps, action nodes
-                                 // and beliefs, striped over blocks so that
-                                 // no address takes many atomics
+  unsigned long long* stats;     // [5][kStripes] particle steps, then two banks
+                                 // of (action nodes, beliefs), striped over
+                                 // blocks so that no address takes many atomics
+  unsigned long long* gate;      // [4] plans with a time budget: [0] start on
+                                 // the wall clock, [1] stop flag, [2] iterations run
   const int* step_base;          // [K+1] first level step of each iteration
   unsigned long long* tr_key;    // [(depth + 1) * n_p] trace words
   float* tr_val;                 // reward (levels) or heuristic (leaf)
@@ -191,8 +193,31 @@ struct PlanView {
   int K, depth, schedule;
   int steps;               // level steps of the plan (sum of D_k)
   double* out;             // kOutStride doubles: the plan's result
+  // Time budget (anytime plan): 0 = run all K iterations.  Otherwise the
+  // iterations after the first run only while fewer than budget_ticks
+  // wall-clock ticks have passed since set-up; K is then the cap.
+  unsigned long long budget_ticks;
+  unsigned long long* gate_host;  // pinned host word: iterations run | stop << 32
+  int timed;
   FilterView f;            // served episodes only
 };
+
+// Tree statistics are counted by the backups of one iteration (the backup
+// sweeps the whole tree): the last one, K.  Under a time budget the last
+// iteration is not known in advance, so every iteration counts, into bank
+// k & 1, and the root backup clears the other bank for the next iteration.
+__device__ __forceinline__ bool counts_tree(const PlanView& P, int k) {
+  return P.timed || k == P.K;
+}
+// Nodes stripes; the beliefs stripes follow at + kStripes.
+__device__ __forceinline__ unsigned long long* stat_bank(const PlanView& P, int k) {
+  return P.t.stats + (size_t)(1 + 2 * (P.timed ? (k & 1) : 0)) * kStripes;
+}
+// The time budget ran out at the end of an earlier iteration: the phases of
+// later iterations return at once (uniform over the grid).
+__device__ __forceinline__ bool budget_spent(const PlanView& P) {
+  return P.timed && *reinterpret_cast<const volatile unsigned long long*>(&P.t.gate[1]) != 0ull;
+}
 
 // Result record written by the select phase (doubles): [0] action,
 // [1..A] root preferences, [A+1] V(root), [A+2] particle steps, [A+3] beliefs,

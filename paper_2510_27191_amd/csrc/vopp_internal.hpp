@@ -42,6 +42,10 @@ struct vopp_workspace {
   int* step_host = nullptr;       // pinned
   double* out_dev = nullptr;
   double* out_host = nullptr;     // pinned
+  // Anytime plans: pinned coherent host word written by the device at the end
+  // of each iteration (iterations run | stop << 32), and its device address.
+  unsigned long long* gate_host = nullptr;
+  unsigned long long* gate_dev = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool hash_dirty = true;
   int n_prev_beliefs = 0, n_prev_actions = 0;

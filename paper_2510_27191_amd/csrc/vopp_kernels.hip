@@ -214,7 +214,12 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
     for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int j = threadIdx.x;
-    if (j < 3 * kStripes) T.stats[j] = 0ull;
+    for (int i = j; i < 5 * kStripes; i += kBlock) T.stats[i] = 0ull;
+    if (j == 0) {
+      T.gate[0] = (unsigned long long)wall_clock64();   // start of the plan
+      T.gate[1] = 0ull;
+      T.gate[2] = 0ull;
+    }
     if (j < kMaxA) {
       // Initial preferences ln pi0 / eta: the root keeps them in double
       // precision, every other belief starts from their f32 rounding.
@@ -579,9 +584,9 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
     }
     push_values(P, sm.agg, dep < kPushDirectDepth, parent, V, N);
   }
-  if (k == P.K) {
+  if (counts_tree(P, k)) {
     beliefs = block_sum(beliefs, sm.wave);
-    if (threadIdx.x == 0 && beliefs) atomicAdd(&P.t.stats[2 * kStripes + blk % kStripes], beliefs);
+    if (threadIdx.x == 0 && beliefs) atomicAdd(&stat_bank(P, k)[kStripes + blk % kStripes], beliefs);
   }
 }
 
@@ -680,11 +685,12 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
     }
     push_values(P, sm.agg, dep - 1 < kPushDirectDepth, parent, V, N);
   }
-  if (k == P.K) {
+  if (counts_tree(P, k)) {
+    unsigned long long* bank = stat_bank(P, k);
     nodes = block_sum(nodes, sm.wave);
-    if (threadIdx.x == 0 && nodes) atomicAdd(&P.t.stats[kStripes + blk % kStripes], nodes);
+    if (threadIdx.x == 0 && nodes) atomicAdd(&bank[blk % kStripes], nodes);
     beliefs = block_sum(beliefs, sm.wave);
-    if (threadIdx.x == 0 && beliefs) atomicAdd(&P.t.stats[2 * kStripes + blk % kStripes], beliefs);
+    if (threadIdx.x == 0 && beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
   }
 }
 
@@ -710,6 +716,24 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
   if (threadIdx.x >= 64) return;
   const int A = P.m.nA;
   const int lane = threadIdx.x;
+  if (P.timed) {
+    // Anytime plan (Alg. 1 loops while the budget lasts): this iteration's
+    // backups are done; the next one runs only if time is left and K is not
+    // reached.  The decision goes to the later phases (gate) and to the host,
+    // which stops enqueueing.
+    unsigned long long* next = stat_bank(P, k + 1);
+    next[lane] = 0ull;
+    next[kStripes + lane] = 0ull;
+    if (lane == 0) {
+      const unsigned long long now = (unsigned long long)wall_clock64();
+      const unsigned long long stop =
+          (k >= P.K || now - P.t.gate[0] >= P.budget_ticks) ? 1ull : 0ull;
+      P.t.gate[1] = stop;
+      P.t.gate[2] = (unsigned long long)k;
+      __hip_atomic_store(P.gate_host, (unsigned long long)k | (stop << 32), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
   const bool act = lane < A;
   unsigned long long* acc = P.t.root_acc;
   long long n_me = 0, c_me = 0, w_me = 0;     // sums of action `lane`
@@ -733,7 +757,7 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
     rec_c(P.t, 0)[lane] = (unsigned long long)c_me;
   }
   const int nodes = __popcll(__ballot(act && n_me > 0));
-  if (k == P.K && lane == 0) atomicAdd(&P.t.stats[kStripes], (unsigned long long)nodes);
+  if (counts_tree(P, k) && lane == 0) atomicAdd(&stat_bank(P, k)[0], (unsigned long long)nodes);
   if (nodes == 0) return;
   // V_curr = L_eta Psi before the update (Eq. 3).
   const double m = wave_max64(p_me);
@@ -772,9 +796,11 @@ __device__ void dev_select(const PlanView& P) {
   if (threadIdx.x >= 64) return;
   const TreeView& T = P.t;
   const int lane = threadIdx.x;
+  const int k_last = P.timed ? (int)T.gate[2] : P.K;   // iterations that ran
+  const unsigned long long* bank = stat_bank(P, k_last);
   const unsigned long long steps = wave_sum(T.stats[lane]);
-  const unsigned long long nodes = wave_sum(T.stats[kStripes + lane]);
-  const unsigned long long nb = 1 + wave_sum(T.stats[2 * kStripes + lane]);
+  const unsigned long long nodes = wave_sum(bank[lane]);
+  const unsigned long long nb = 1 + wave_sum(bank[kStripes + lane]);
   if (lane != 0) return;
   const int A = P.m.nA;
   int best = 0;
@@ -790,7 +816,7 @@ __device__ void dev_select(const PlanView& P) {
   out[A + 5] = (double)T.counters[1];
   T.counters[2] = nb;
   T.counters[3] = 0ull;
-  T.counters[5] = (unsigned long long)P.steps;
+  T.counters[5] = (unsigned long long)(P.timed ? T.step_base[k_last] : P.steps);
   T.counters[6] = (unsigned long long)P.n_p;
 }
 
@@ -967,25 +993,34 @@ __global__ __launch_bounds__(kBlock) void k_pf_resample(PlanView P, int t) {
 __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
   dev_setup(P, blockIdx.x, gridDim.x);
 }
+// The phases of one iteration return at once when a time budget ran out
+// at the end of an earlier iteration.
 template <int AM>
 __global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
+  if (budget_spent(P)) return;
   dev_forward<AM>(P, k, D, blockIdx.x, red);
 }
 __global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D) {
   __shared__ Smem sm;
+  if (budget_spent(P)) return;
   dev_accum(P, D, blockIdx.x, gridDim.x, sm);
 }
 __global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
   __shared__ Smem sm;
+  if (budget_spent(P)) return;
   dev_backup_leaf(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
 template <int AM>
 __global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, int k) {
   __shared__ Smem sm;
+  if (budget_spent(P)) return;
   dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
-__global__ void k_backup_root(PlanView P, int k) { dev_backup_root(P, k); }
+__global__ void k_backup_root(PlanView P, int k) {
+  if (budget_spent(P)) return;
+  dev_backup_root(P, k);
+}
 __global__ void k_select(PlanView P) { dev_select(P); }
 
 // ---------------------------------------------------------------------------

@@ -29,7 +29,7 @@ EXPORTS = (
     "vopp_last_error", "vopp_version", "vopp_pomdp_tabular", "vopp_pomdp_nav2d",
     "vopp_pomdp_num_actions", "vopp_pomdp_set_reference_policy", "vopp_pomdp_free",
     "vopp_plan_footprint",
-    "vopp_workspace_create", "vopp_workspace_free", "vopp_plan",
+    "vopp_workspace_create", "vopp_workspace_free", "vopp_plan", "vopp_plan_anytime",
     "vopp_tree_dump", "vopp_level_counts", "vopp_profile_enable", "vopp_profile_reset",
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
@@ -149,6 +149,10 @@ def lib():
     L.vopp_plan.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vopp_params), vp, vp,
                             C.POINTER(i32), vp, vp, C.POINTER(vopp_stats)]
     L.vopp_plan.restype = st
+    L.vopp_plan_anytime.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.POINTER(vopp_params),
+                                    vp, vp, C.POINTER(i32), vp, vp, C.POINTER(vopp_stats),
+                                    C.POINTER(i32)]
+    L.vopp_plan_anytime.restype = st
     L.vopp_tree_dump.argtypes = [vp] * 11
     L.vopp_tree_dump.restype = st
     L.vopp_level_counts.argtypes = [vp, vp, i32, C.POINTER(i32)]
@@ -332,6 +336,28 @@ def plan(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None):
                            _p(vroot), C.byref(st)))
     return PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                       int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
+
+
+def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, ws=None,
+                 stream=None):
+    """vopp_plan_anytime: returns (PlanResult, iterations run)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    act = C.c_int32(-1)
+    iters = C.c_int32(0)
+    vals = np.zeros(pomdp.nA, np.float64)
+    vroot = np.zeros(1, np.float64)
+    st = vopp_stats()
+    _check(lib().vopp_plan_anytime(pomdp.handle, C.c_void_p(belief_dev.data_ptr()),
+                                   int(n_belief), int(max_budget), int(depth),
+                                   float(time_ms), C.byref(prm),
+                                   ws.handle if ws is not None else None,
+                                   C.c_void_p(stream.cuda_stream), C.byref(act), _p(vals),
+                                   _p(vroot), C.byref(st), C.byref(iters)))
+    res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
+                     int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
+    return res, int(iters.value)
 
 
 def tree_dump(ws, nA, n_beliefs, n_actions):

@@ -1,5 +1,5 @@
 """Parity of the HIP planner with the oracle under a non-uniform reference
-policy pi0 (Sec. 3, Eq. 4: every preference row starts at ln pi0 / eta).
+policy pi0 (Sec. III-A, Eq. 4: every preference row starts at ln pi0 / eta).
 
 Same bar as the uniform parity tests: bit-exact structure on plans whose
 oracle run has no near-tie draw, values within 1e-4 relative.  With pi0 the
