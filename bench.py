@@ -183,6 +183,32 @@ def bench_batch(V, I, reps=3, autotune=True):
     return out
 
 
+def bench_anytime(V, pom, belt, n_bel, n_p, depth, eta, budgets_ms=(10.0, 30.0, 100.0),
+                  k_max=64, reps=3):
+    """Anytime planning (Alg. 1's wall-clock budget) on the same workload:
+    iterations reached, particle steps and the overshoot past the budget."""
+    prm = V.params(n_p, eta=eta, seed=1)
+    ws = V.Workspace(pom, prm, k_max, depth)
+    V.plan_anytime(pom, belt, n_bel, k_max, depth, budgets_ms[0], prm, ws=ws)   # warm-up
+    rows = []
+    for b in budgets_ms:
+        ks, steps, dev = [], [], []
+        for i in range(reps):
+            r, k = V.plan_anytime(pom, belt, n_bel, k_max, depth, b,
+                                  V.params(n_p, eta=eta, seed=2000 + i), ws=ws)
+            ks.append(k)
+            steps.append(r.particle_steps)
+            dev.append(r.device_ms)
+        rows.append({"budget_ms": b, "iterations": ks, "particle_steps": steps,
+                     "device_ms": [round(x, 3) for x in dev],
+                     "max_overshoot_ms": round(max(d - b for d in dev), 3),
+                     "particle_steps_per_s": sum(steps) / (sum(dev) * 1e-3)})
+    ws.close()
+    return {"k_max": k_max, "rows": rows,
+            "note": "iteration k+1 starts only if the device wall clock shows less "
+                    "than the budget since set-up; device_ms includes set-up and select"}
+
+
 def serve_trace(seed, qps, seconds, steps_per_episode):
     """Poisson episode starts at rate qps / steps (each episode then issues
     its requests back to back, so the offered load is about qps requests/s)."""
@@ -321,6 +347,8 @@ def main():
                     help="skip the 256-instance batched vs plain comparison")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served (continuous batching) vs plain comparison")
+    ap.add_argument("--no-anytime", action="store_true",
+                    help="skip the wall-clock-budget (anytime) planning report")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to "
@@ -451,6 +479,8 @@ def main():
                         note=f"dominant kernel {dom} has no byte model")
         out["roofline"] = roof
     ws.close()
+    if not args.no_anytime:
+        out["anytime"] = bench_anytime(V, pom, belt, n_bel, n_p, depth, eta)
     pom.close()
     if not args.no_batch:
         out["batched_vs_plain"] = bench_batch(V, I)
