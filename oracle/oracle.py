@@ -58,7 +58,7 @@ class OrcParams(C.Structure):
                 ("eta", C.c_double), ("seed", C.c_uint64),
                 ("step", C.c_uint32), ("tau", C.c_double),
                 ("trace", C.c_int32), ("mutate", C.c_int32),
-                ("pi0", C.c_void_p)]
+                ("pi0", C.c_void_p), ("start", C.c_void_p)]
 
 
 def load():
@@ -79,6 +79,8 @@ def load():
     lib.orc_result_tree.argtypes = [vp] * 11
     lib.orc_result_trace.argtypes = [vp] * 4
     lib.orc_result_free.argtypes = [vp]
+    lib.orc_reroot.restype = vp
+    lib.orc_reroot.argtypes = [vp, C.c_int32, C.c_int32]
     lib.orc_philox.argtypes = [C.c_uint32] * 6 + [vp]
     lib.orc_thresholds.argtypes = [vp, C.c_int32, vp]
     lib.orc_pick.argtypes = [vp, C.c_int32, C.c_uint32]
@@ -165,12 +167,58 @@ class OracleResult:
     a_C: np.ndarray
     a_N: np.ndarray
     trace: dict | None = None
+    handle: "Handle | None" = None
+
+
+class Handle:
+    """Owns an oracle result (a finished plan or a re-rooted tree)."""
+
+    def __init__(self, h):
+        self.h = h
+
+    def __del__(self):
+        if self.h:
+            load().orc_result_free(self.h)
+            self.h = None
+
+
+def _tree_arrays(h, A):
+    lib = load()
+    info = np.zeros(8, np.int64)
+    mm = np.zeros(1, np.float64)
+    vr = np.zeros(1, np.float64)
+    lib.orc_result_info(h, _ptr(info), _ptr(mm), _ptr(vr))
+    nb, na = int(info[0]), int(info[1])
+    out = dict(b_parent=np.zeros(nb, np.int32), b_obs=np.zeros(nb, np.int32),
+               b_depth=np.zeros(nb, np.int32),
+               psi=np.zeros((nb, A), np.float64),
+               b_V=np.zeros(nb, np.float64), b_N=np.zeros(nb, np.int64),
+               a_parent=np.zeros(na, np.int32), a_act=np.zeros(na, np.int32),
+               a_C=np.zeros(na, np.float64), a_N=np.zeros(na, np.int64))
+    lib.orc_result_tree(h, *[_ptr(out[k]) for k in (
+        "b_parent", "b_obs", "b_depth", "psi", "b_V", "b_N", "a_parent",
+        "a_act", "a_C", "a_N")])
+    return info, mm, vr, out
+
+
+def reroot(result, a, o, A):
+    """Tree re-rooting between real steps: the subtree of ``result``'s tree
+    (kept with ``plan(..., keep=True)``) under action a and observation o.
+    Returns (Handle, tree arrays); the arrays are empty when the tree has no
+    belief for (a, o), and a plan started from the handle then starts fresh."""
+    h = load().orc_reroot(result.handle.h, int(a), int(o))
+    hd = Handle(h)
+    _, _, _, out = _tree_arrays(h, A)
+    return hd, out
 
 
 def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
-         schedule=0, step=0, tau=2.0 ** -16, trace=False, mutate=0, pi0=None):
+         schedule=0, step=0, tau=2.0 ** -16, trace=False, mutate=0, pi0=None,
+         start=None, keep=False):
     """Run one serial planning step and return the full tree.  pi0: reference
-    policy weights over the actions (positive; normalised), or None: uniform."""
+    policy weights over the actions (positive; normalised), or None: uniform.
+    start: a Handle from ``reroot`` to plan from its tree.  keep: keep the
+    result's handle (``.handle``) for re-rooting."""
     lib = load()
     keep = _Keep()
     pi = None
@@ -180,7 +228,8 @@ def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
         keep.arrs.append(pi)
     prm = OrcParams(n_particles, budget, depth, schedule, eta, seed, step,
                     tau, 1 if trace else 0, mutate,
-                    None if pi is None else pi.ctypes.data)
+                    None if pi is None else pi.ctypes.data,
+                    None if start is None else start.h)
     if inst["kind"] == "tabular":
         m = tabular_struct(inst, keep)
         bel = _c32(belief, np.int32)
@@ -191,22 +240,9 @@ def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
         by = _c32(belief[1], np.float32)
         h = lib.orc_plan_nav(C.byref(m), _ptr(bx), _ptr(by), bx.size,
                              C.byref(prm))
+    hd = Handle(h)
     try:
-        info = np.zeros(8, np.int64)
-        mm = np.zeros(1, np.float64)
-        vr = np.zeros(1, np.float64)
-        lib.orc_result_info(h, _ptr(info), _ptr(mm), _ptr(vr))
-        nb, na = int(info[0]), int(info[1])
-        A = inst["nA"]
-        out = dict(b_parent=np.zeros(nb, np.int32), b_obs=np.zeros(nb, np.int32),
-                   b_depth=np.zeros(nb, np.int32),
-                   psi=np.zeros((nb, A), np.float64),
-                   b_V=np.zeros(nb, np.float64), b_N=np.zeros(nb, np.int64),
-                   a_parent=np.zeros(na, np.int32), a_act=np.zeros(na, np.int32),
-                   a_C=np.zeros(na, np.float64), a_N=np.zeros(na, np.int64))
-        lib.orc_result_tree(h, *[_ptr(out[k]) for k in (
-            "b_parent", "b_obs", "b_depth", "psi", "b_V", "b_N", "a_parent",
-            "a_act", "a_C", "a_N")])
+        info, mm, vr, out = _tree_arrays(h, inst["nA"])
         tr = None
         if trace:
             n = int(info[6])
@@ -221,9 +257,10 @@ def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
                             psi_root=out["psi"][0].copy(),
                             particle_steps=int(info[3]), n_draws=int(info[4]),
                             near_ties=int(info[5]), min_margin=float(mm[0]),
-                            trace=tr, **out)
+                            trace=tr, handle=hd if keep else None, **out)
     finally:
-        lib.orc_result_free(h)
+        if not keep:
+            del hd
 
 
 # Building blocks for the pins -------------------------------------------------

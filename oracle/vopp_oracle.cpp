@@ -187,6 +187,7 @@ typedef struct {
   int32_t trace;   // keep a per-draw trace
   int32_t mutate;  // 0: none.  >0 plants a known mistake (pin sensitivity)
   const double* pi0;  // [A] reference policy weights (> 0), or NULL: uniform
+  const void* start;  // a re-rooted tree (orc_reroot) to plan from, or NULL
 } orc_params;
 
 }  // extern "C"
@@ -360,7 +361,7 @@ struct Tree {
 
   std::vector<double> psi0;          // initial preference row (Eq. 4, first term)
 
-  void init(int nA, double eta, const double* pi0) {
+  void set_psi0(int nA, double eta, const double* pi0) {
     A = nA;
     psi0.assign(A, -std::log((double)A) / eta);
     if (pi0) {
@@ -368,6 +369,9 @@ struct Tree {
       for (int a = 0; a < A; ++a) sum += pi0[a];
       for (int a = 0; a < A; ++a) psi0[a] = std::log(pi0[a] / sum) / eta;
     }
+  }
+  void init(int nA, double eta, const double* pi0) {
+    set_psi0(nA, eta, pi0);
     new_belief(-1, -1, 0, eta);
   }
   int32_t new_belief(int32_t parent, int32_t obs, int32_t depth, double eta) {
@@ -407,6 +411,71 @@ struct Tree {
     return id;
   }
 };
+
+// Tree re-rooting between real steps (Alg. 1 outer loop): after action a is
+// executed and observation o perceived, the belief reached by (a, o) from the
+// root becomes the new root and its descendants are kept with every
+// statistic (preference rows, C, N, V, N_b), one level shallower; everything
+// else is dropped.  Rows keep their relative order (parents precede their
+// children).  If the tree has no such belief, the result is empty and the
+// next plan starts from a fresh root as Alg. 1 does.
+Tree reroot(const Tree& T, int a, int o) {
+  Tree R;
+  R.A = T.A;
+  R.psi0 = T.psi0;
+  const int A = T.A;
+  int32_t an = T.b_child[(size_t)0 * A + a];
+  if (an < 0) return R;
+  auto it = T.obs_child.find(((uint64_t)(uint32_t)an << 32) | (uint32_t)o);
+  if (it == T.obs_child.end()) return R;
+  const int32_t nb = (int32_t)T.b_parent.size();
+  std::vector<int32_t> bmap(nb, -1), amap(T.a_parent.size(), -1);
+  bmap[it->second] = 0;
+  // Rows are in creation order, so a belief's parent action node and that
+  // node's parent belief precede it.
+  for (int32_t b = 0; b < nb; ++b) {
+    if (b != it->second) {
+      const int32_t pa = T.b_parent[b];
+      if (pa < 0 || amap[pa] < 0) continue;
+    }
+    const int32_t id = (int32_t)R.b_parent.size();
+    bmap[b] = id;
+    const bool root = b == it->second;
+    R.b_parent.push_back(root ? -1 : amap[T.b_parent[b]]);
+    R.b_obs.push_back(root ? -1 : T.b_obs[b]);
+    R.b_depth.push_back(T.b_depth[b] - 1);
+    for (int j = 0; j < A; ++j) {
+      R.psi.push_back(T.psi[(size_t)b * A + j]);
+      R.b_child.push_back(-1);
+    }
+    R.b_V.push_back(T.b_V[b]);
+    R.b_N.push_back(T.b_N[b]);
+    const int d = T.b_depth[b] - 1;
+    if ((int)R.beliefs_at.size() <= d) R.beliefs_at.resize(d + 1);
+    R.beliefs_at[d].push_back(id);
+    if (!root) {
+      const uint64_t key = ((uint64_t)(uint32_t)R.b_parent[id] << 32) | (uint32_t)T.b_obs[b];
+      R.obs_child.emplace(key, id);
+    }
+    // The action nodes of b follow b in this construction; in the source
+    // they were created after b as well.
+    for (int j = 0; j < A; ++j) {
+      const int32_t src = T.b_child[(size_t)b * A + j];
+      if (src < 0) continue;
+      const int32_t na = (int32_t)R.a_parent.size();
+      amap[src] = na;
+      R.a_parent.push_back(id);
+      R.a_act.push_back(j);
+      R.a_depth.push_back(d);
+      R.a_C.push_back(T.a_C[src]);
+      R.a_N.push_back(T.a_N[src]);
+      if ((int)R.actions_at.size() <= d) R.actions_at.resize(d + 1);
+      R.actions_at[d].push_back(na);
+      R.b_child[(size_t)id * A + j] = na;
+    }
+  }
+  return R;
+}
 
 // L_eta x = (1/eta) log sum_j exp(eta x_j), evaluated with the max shift.
 double lse(const double* x, int n, double eta) {
@@ -490,7 +559,13 @@ Result* plan(const Model& model, int A, const State* belief, int M,
   Tree& T = res->tree;
   const double eta = prm->eta;
   const double gamma = model.gamma;
-  T.init(A, eta, prm->pi0);
+  const Tree* start = prm->start ? &((const Result*)prm->start)->tree : nullptr;
+  if (start && !start->b_parent.empty()) {
+    T = *start;                                // plan from the kept subtree
+    T.set_psi0(A, eta, prm->pi0);
+  } else {
+    T.init(A, eta, prm->pi0);
+  }
   const int K = prm->budget;
   const int n_p = prm->n_particles;
   const int mut = prm->mutate;
@@ -664,6 +739,15 @@ void orc_result_trace(const void* h, int32_t* ints, float* r, double* margin) {
 }
 
 void orc_result_free(void* h) { delete (Result*)h; }
+
+// The tree of a finished plan re-rooted at (a, o); a result handle holding
+// only the tree (empty when the plan's tree has no such belief).
+void* orc_reroot(const void* h, int32_t a, int32_t o) {
+  Result* r = new Result();
+  r->tree = reroot(((const Result*)h)->tree, a, o);
+  if (!r->tree.b_parent.empty()) r->v_root = r->tree.b_V[0];
+  return r;
+}
 
 // Building blocks exposed for the pins.
 void orc_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
