@@ -209,6 +209,53 @@ def bench_anytime(V, pom, belt, n_bel, n_p, depth, eta, budgets_ms=(10.0, 30.0, 
                     "than the budget since set-up; device_ms includes set-up and select"}
 
 
+def bench_reroot(V, inst, pom, belt, n_bel, n_p, K, depth, eta, steps=6):
+    """Closed-loop real steps (plan, act in a simulated environment, update the
+    belief), once starting every plan from a fresh root (Alg. 1) and once
+    keeping the subtree under the executed action and perceived observation
+    (vopp_reroot).  Reports the re-rooting time, the kept beliefs and the plan
+    times of both."""
+    import torch
+    out = {}
+    for mode in ("fresh", "kept"):
+        prm = V.params(n_p, eta=eta, seed=1)
+        wss = [V.Workspace(pom, prm, K, depth), V.Workspace(pom, prm, K, depth)]
+        parts = belt.clone()
+        if inst["kind"] == "tabular":
+            state = parts[:1].clone()
+        else:
+            state = torch.stack([parts[0], parts[n_bel]]).contiguous()
+        plan_ms, reroot_ms, kept, tree = [], [], [], []
+        for t in range(steps):
+            ws = wss[t % 2]
+            p_t = V.params(n_p, eta=eta, seed=3000 + t, step=t)
+            r = V.plan(pom, parts, n_bel, K, depth, p_t, ws=ws)
+            plan_ms.append(r.device_ms)
+            tree.append(r.n_beliefs)
+            obs, _, term = V.env_step(pom, state, r.action, 77, t)
+            if term:
+                break
+            V.belief_update(pom, parts, n_bel, r.action, obs, 78, t)
+            if mode == "kept" and t + 1 < steps:
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                kept.append(V.reroot(pom, ws, r.action, obs,
+                                     V.params(n_p, eta=eta, seed=3001 + t, step=t + 1),
+                                     K, depth, wss[(t + 1) % 2]))
+                reroot_ms.append((time.perf_counter() - a) * 1e3)
+        for w in wss:
+            w.close()
+        row = {"plans": len(plan_ms), "plan_device_ms": [round(x, 3) for x in plan_ms],
+               "tree_beliefs": tree}
+        if mode == "kept":
+            row.update(reroot_ms=[round(x, 3) for x in reroot_ms], kept_beliefs=kept)
+        out[mode] = row
+    out["note"] = ("kept: each plan starts from the subtree under the executed action "
+                   "and perceived observation; reroot_ms is the host-timed vopp_reroot "
+                   "call (scratch allocation and synchronisation included)")
+    return out
+
+
 def serve_trace(seed, qps, seconds, steps_per_episode):
     """Poisson episode starts at rate qps / steps (each episode then issues
     its requests back to back, so the offered load is about qps requests/s)."""
@@ -349,6 +396,8 @@ def main():
                     help="skip the served (continuous batching) vs plain comparison")
     ap.add_argument("--no-anytime", action="store_true",
                     help="skip the wall-clock-budget (anytime) planning report")
+    ap.add_argument("--no-reroot", action="store_true",
+                    help="skip the closed-loop tree re-rooting report")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to "
@@ -481,6 +530,8 @@ def main():
     ws.close()
     if not args.no_anytime:
         out["anytime"] = bench_anytime(V, pom, belt, n_bel, n_p, depth, eta)
+    if not args.no_reroot:
+        out["reroot"] = bench_reroot(V, inst, pom, belt, n_bel, n_p, K, depth, eta)
     pom.close()
     if not args.no_batch:
         out["batched_vs_plain"] = bench_batch(V, I)

@@ -206,6 +206,36 @@ vopp_status vopp_plan_anytime(const vopp_pomdp* pomdp, const void* belief_partic
                               double* values, double* v_root, vopp_stats* stats,
                               int32_t* iterations);
 
+/* Tree re-rooting between real steps (the outer loop of Alg. 1).  After the
+ * plan in `src` chose an action, the environment executed `action` and
+ * returned observation `obs`: the belief reached from the root by (action,
+ * obs) becomes the root of the next plan, and its descendants are kept with
+ * their statistics (preference rows, C, N, V, N_b), one level shallower.  The
+ * paper's Alg. 1 starts every real step from a fresh tree; this keeps the
+ * relevant subtree instead.
+ *   src: a workspace whose last plan (vopp_plan or vopp_plan_anytime) holds
+ *     the tree; it is only read.
+ *   next, next_budget, next_depth: the parameters of the next plan, which
+ *     runs in dst.  That plan must use next->n_particles and at most
+ *     next_budget (<= 255) iterations.
+ *   dst: receives the kept subtree; the next vopp_plan or vopp_plan_anytime
+ *     on dst starts from it (its root preferences, visit counts and rewards
+ *     included) instead of a fresh root.  dst is re-allocated (same handle)
+ *     when it is too small for the subtree plus the next plan.  Its previous
+ *     tree is discarded.
+ *   kept (host, out, may be NULL): beliefs kept, the new root included; 0
+ *     when the tree has no belief for (action, obs) -- dst then holds nothing
+ *     and the next plan on it starts from a fresh root.
+ * Kept beliefs are packed by depth into level steps ahead of the next plan's
+ * own, and the next plan's sweeps visit them as every belief of their depth
+ * (the backup of Alg. 3 covers the whole tree).  The call allocates and frees
+ * temporary device memory (5 bytes per source belief slot) and synchronizes
+ * the stream. */
+vopp_status vopp_reroot(const vopp_pomdp* pomdp, vopp_workspace* src, int32_t action,
+                        int32_t obs, const vopp_params* next, int32_t next_budget,
+                        int32_t next_depth, vopp_workspace* dst, void* stream,
+                        int64_t* kept);
+
 /* Copy the tree of the last plan run in `ws` to host arrays (any may be
  * NULL).  Sizes come from vopp_stats.  Belief arrays [n_beliefs]: parent
  * action row (-1 for the root), observation key (-1 for the root), depth,

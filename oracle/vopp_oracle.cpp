@@ -560,7 +560,10 @@ Result* plan(const Model& model, int A, const State* belief, int M,
   const double eta = prm->eta;
   const double gamma = model.gamma;
   const Tree* start = prm->start ? &((const Result*)prm->start)->tree : nullptr;
-  if (start && !start->b_parent.empty()) {
+  // A kept root's preference row was a non-root row before (single precision
+  // in the GPU's records), so its draws are screened like non-root draws.
+  const bool kept_root = start && !start->b_parent.empty();
+  if (kept_root) {
     T = *start;                                // plan from the kept subtree
     T.set_psi0(A, eta, prm->pi0);
   } else {
@@ -592,7 +595,7 @@ Result* plan(const Model& model, int A, const State* belief, int M,
                               P.b == 0, &margin);
         res->n_draws++;
         // The root row is double precision on both sides.
-        if (margin < (P.b == 0 ? 1e-12 : prm->tau)) res->near_ties++;
+        if (margin < (P.b == 0 && !kept_root ? 1e-12 : prm->tau)) res->near_ties++;
         res->min_margin = std::min(res->min_margin, margin);
         Outcome o = model.step(P.st, a, x);
         res->particle_steps++;

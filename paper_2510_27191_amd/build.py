@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvopp.so")
-SOURCES = ["vopp_kernels.hip", "vopp_api.hip", "vopp_batch.hip", "vopp_server.hip"]
+SOURCES = ["vopp_kernels.hip", "vopp_api.hip", "vopp_batch.hip", "vopp_server.hip",
+           "vopp_reroot.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

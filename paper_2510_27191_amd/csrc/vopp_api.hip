@@ -291,10 +291,11 @@ int sum_depths(int K, int depth, int schedule) {
   return (int)s;
 }
 
-WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule) {
+WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,
+                  int extra_steps) {
   WsSizes z;
   z.n_p = n_p;
-  z.steps = sum_depths(K, depth, schedule);
+  z.steps = sum_depths(K, depth, schedule) + extra_steps;
   z.K = K;
   z.depth = depth;
   z.Apad = p->view.Apad;
@@ -316,6 +317,7 @@ size_t bytes_for(const WsSizes& z) {
   add((size_t)3 * kMaxA * kStripes * 8);             // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(5 * kStripes * 8); add(32); add((z.K + 1) * 4);
+  add(2 * (kMaxDepth + 1) * 4);                      // kept-subtree steps by depth
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
   add(256 * 8);
@@ -355,6 +357,8 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.counters = c.take<unsigned long long>(8);
   t.stats = c.take<unsigned long long>(5 * kStripes);
   t.gate = c.take<unsigned long long>(4);
+  w->carry_rng_dev = c.take<int>(2 * (kMaxDepth + 1));
+  t.carry_rng = w->carry_rng_dev;
   int* step_base = c.take<int>(z.K + 1);
   t.step_base = step_base;
   w->step_base_dev = step_base;
@@ -445,9 +449,9 @@ namespace vopp {
 // Fixed-point scale 2^S for the cross-episode sums: every partial sum is
 // bounded by n_p * K * vmax with vmax >= |V| = R_max/(1-gamma) + H_max, and S
 // keeps that bound below 2^61.
-static int fixed_shift(const vopp_pomdp* p, int n_p, int K) {
+int fixed_shift(const vopp_pomdp* p, double visits) {
   const double vmax = p->r_max / (1.0 - p->gamma) + p->h_max + 1.0;
-  const double lg = std::log2((double)n_p * (double)K * vmax);
+  const double lg = std::log2(visits * vmax);
   int S = (int)std::floor(61.0 - lg);
   return std::min(std::max(S, 4), 40);
 }
@@ -466,25 +470,29 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
   P.seed_lo = (uint32_t)prm->seed;
   P.seed_hi = (uint32_t)(prm->seed >> 32);
   P.step = prm->step;
-  const int S = fixed_shift(p, prm->n_particles, K);
+  // A kept subtree's sums were scaled when it was kept, for a bound on the
+  // iterations that covers this plan.
+  const bool carry = w->carry.pending;
+  const int S = carry ? w->carry.shift : fixed_shift(p, (double)prm->n_particles * (double)K);
   P.fix_scale = std::ldexp(1.0f, S);
   P.fix_inv = std::ldexp(1.0f, -S);
   P.fix_inv64 = std::ldexp(1.0, -S);
   P.K = K;
   P.depth = depth;
   P.schedule = prm->schedule;
-  P.steps = sum_depths(K, depth, prm->schedule);
+  P.steps = sum_depths(K, depth, prm->schedule) + (carry ? w->carry.n_steps : 0);
+  P.carry = carry ? 1 : 0;
   P.out = w->out_dev;
   return P;
 }
 
 // Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
-                int cap) {
+                int cap, int extra) {
   (void)p;
   // One chunk of kBlock record positions per block, over the level steps
   // that hold depth dep.
-  long long iters = 0;
+  long long iters = extra;
   for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
   const long long g = ((long long)n_p + kBlock - 1) / kBlock * iters;
   return (int)std::max(1ll, std::min(g, (long long)cap));
@@ -520,8 +528,9 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
                          hipStream_t s, int* n_steps_out) {
   const int K = P.K;
   std::vector<int> D(K + 1, 0);
-  int steps = 0;
-  w->step_host[0] = 0;
+  const int c0 = P.carry ? w->carry.n_steps : 0;   // a kept subtree's steps first
+  int steps = c0;
+  w->step_host[0] = c0;
   for (int k = 1; k <= K; ++k) {
     D[k] = P.schedule == VOPP_SCHEDULE_FIXED ? P.depth : std::min(k, P.depth);
     steps += D[k];
@@ -548,7 +557,7 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   VOPP_TIMED(VOPP_KERNEL_SETUP, launch_setup(P, s));
   if (e != hipSuccess) return hip_fail(e, "plan set-up launch");
   w->hash_dirty = true;   // until the plan has finished
-  int t = 0;
+  int t = c0;
   for (int k = 1; k <= K; ++k) {
     if (P.timed && k > 1) {
       bool go = true;
@@ -562,10 +571,14 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     if (e != hipSuccess) return hip_fail(e, "forward-search launch");
     t += D[k];
     VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
-               launch_backup_leaf(P, D[k], k, backup_grid(p, P.n_p, D, D[k], k, kBackupCap), s));
+               launch_backup_leaf(P, D[k], k,
+                                  backup_grid(p, P.n_p, D, D[k], k, kBackupCap,
+                                              P.carry ? w->carry.count[D[k]] : 0), s));
     for (int dep = D[k]; dep >= 2; --dep)
       VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
-                 launch_backup_level(P, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap), s));
+                 launch_backup_level(P, dep, k,
+                                     backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap,
+                                                 P.carry ? w->carry.count[dep - 1] : 0), s));
     VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, k, s));
     if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
@@ -640,7 +653,18 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
   int dev = -1;
   (void)hipGetDevice(&dev);
   if (dev != p->device) return fail(VOPP_E_INVALID, "model lives on device %d, current is %d", p->device, dev);
-  if (ws) {
+  if (ws && ws->carry.pending) {
+    // The plan starts from the subtree kept by vopp_reroot.
+    if (prm->n_particles != ws->carry.n_p)
+      return fail(VOPP_E_INVALID, "a plan from a kept subtree must use n_particles = %d",
+                  ws->carry.n_p);
+    if (budget > ws->carry.budget)
+      return fail(VOPP_E_INVALID, "the kept subtree was prepared for at most %d iterations",
+                  ws->carry.budget);
+    if (!fits(ws->z, sizes_for(p, prm->n_particles, budget, depth, prm->schedule,
+                               ws->carry.n_steps)))
+      return fail(VOPP_E_INVALID, "workspace too small for this plan and its kept subtree");
+  } else if (ws) {
     if (!fits(ws->z, sizes_for(p, prm->n_particles, budget, depth, prm->schedule)))
       return fail(VOPP_E_INVALID, "workspace too small for this plan");
   } else {
@@ -687,18 +711,40 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
   if (flags & 1) return fail(VOPP_E_INVALID, "a belief particle holds a state outside [0, nS)");
   if (flags & 2) return fail(VOPP_E_INTERNAL, "belief table overflow");
   int k_run = budget;
+  const int c0 = P.carry ? ws->carry.n_steps : 0;
   if (P.timed) {
     k_run = (int)(__atomic_load_n(ws->gate_host, __ATOMIC_ACQUIRE) & 0xffffffffull);
     if (k_run < 1 || k_run > budget)
       return fail(VOPP_E_INTERNAL, "anytime plan reported %d iterations", k_run);
-    steps = sum_depths(k_run, depth, prm->schedule);
+    steps = c0 + sum_depths(k_run, depth, prm->schedule);
   }
   if (iterations) *iterations = k_run;
+  // The backups count the beliefs of depth <= D_K and the action nodes of
+  // beliefs shallower than D_K.  A kept subtree may reach deeper; no episode
+  // of this plan went there, so those parts are as kept.
+  long long nb = (long long)o[A + 3], na = (long long)o[A + 4];
+  const int D_last = prm->schedule == VOPP_SCHEDULE_FIXED ? depth : std::min(k_run, depth);
+  if (P.carry)
+    for (int d = 1; d <= kMaxDepth; ++d) {
+      if (d > D_last) nb += ws->carry.beliefs[d];
+      if (d >= D_last) na += ws->carry.nodes[d];
+    }
+  // Level-step depths of this tree.
+  ws->step_depth.clear();
+  if (P.carry)
+    for (int d = 1; d <= kMaxDepth; ++d)
+      for (int i = 0; i < ws->carry.count[d]; ++i) ws->step_depth.push_back(d);
+  for (int k = 1; k <= k_run; ++k) {
+    const int D = prm->schedule == VOPP_SCHEDULE_FIXED ? depth : std::min(k, depth);
+    for (int d = 0; d < D; ++d) ws->step_depth.push_back(d + 1);
+  }
+  ws->carried = P.carry != 0;
+  ws->carry.pending = false;
   *action = (int32_t)o[0];
   if (values) for (int j = 0; j < A; ++j) values[j] = o[1 + j];
   if (v_root) *v_root = o[A + 1];
-  ws->n_prev_beliefs = (int)o[A + 3];
-  ws->n_prev_actions = (int)o[A + 4];
+  ws->n_prev_beliefs = (int)nb;
+  ws->n_prev_actions = (int)na;
   ws->hash_dirty = false;
   ws->last_A = A;
   ws->last_apad = p->view.Apad;
@@ -710,8 +756,8 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
   ws->last_fix_inv64 = P.fix_inv64;
   if (stats) {
     stats->particle_steps = (int64_t)o[A + 2];
-    stats->n_beliefs = (int64_t)o[A + 3];
-    stats->n_actions = (int64_t)o[A + 4];
+    stats->n_beliefs = (int64_t)nb;
+    stats->n_actions = (int64_t)na;
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
     stats->device_ms = ms;
@@ -761,17 +807,13 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   std::vector<int> list((size_t)steps * n_p);
   cp(list.data(), w->tree.list, list.size() * 4);
   std::vector<int> ids{0}, depth{0};
-  {
-    int t = 0;
-    for (int k = 1; k <= w->last_K; ++k) {
-      const int D = w->last_schedule == VOPP_SCHEDULE_FIXED ? w->last_depth
-                                                           : std::min(k, w->last_depth);
-      for (int d = 0; d < D; ++d, ++t) {
-        for (int j = 0; j < n_p; ++j)
-          if (list[(size_t)t * n_p + j]) ids.push_back(1 + t * n_p + j);
-        depth.resize(ids.size(), d + 1);
-      }
-    }
+  if ((int)w->step_depth.size() != steps)
+    return fail(VOPP_E_INTERNAL, "tree dump: %zu level-step depths for %d steps",
+                w->step_depth.size(), steps);
+  for (int t = 0; t < steps; ++t) {
+    for (int j = 0; j < n_p; ++j)
+      if (list[(size_t)t * n_p + j]) ids.push_back(1 + t * n_p + j);
+    depth.resize(ids.size(), w->step_depth[t]);
   }
   if (e != hipSuccess) return hip_fail(e, "tree dump");
   const size_t nb = ids.size();

@@ -14,7 +14,10 @@ namespace vopp {
 constexpr int kBlock = 256;                 // threads per block (4 wavefronts)
 constexpr int kMaxA = 64;
 constexpr int kMaxBudget = 256;             // iterations per plan
-constexpr int kMaxRanges = kMaxBudget;
+constexpr int kMaxDepth = 64;               // maximum leaf depth of a plan
+// Level steps a sweep of one depth may visit: the plan's own (one per
+// iteration) and up to as many again holding a kept subtree.
+constexpr int kMaxRanges = 2 * kMaxBudget;
 constexpr unsigned long long kEmptyKey = ~0ull;
 
 // Belief keys of the open-addressing table (AppendBeliefs):
@@ -25,6 +28,8 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 // numbering pass, so one launch can run every level.  The iteration stamp
 // tells whether the belief was inserted by an earlier kernel (then its record
 // exists and may be read) or by this one (then its preference row is psi0).
+// Beliefs of a kept subtree carry the stamp 0xFF, which no iteration of a plan
+// from a kept tree uses (such plans have at most 255 iterations).
 // Records are stored by creation: the belief that episode ep inserts at level
 // step t owns record 1 + t*n_p + ep (an episode inserts at most one belief per
 // level step), so no episode allocates anything; the inserting episode stores
@@ -35,6 +40,8 @@ constexpr int kStampShift = 56;
 constexpr unsigned long long kStampMask = 0xFFull << kStampShift;
 constexpr unsigned long long kSidMask = (1ull << 30) - 1;
 constexpr long long kMaxBeliefs = 1ll << 28;   // twice as many slots: ids <= 2^29
+constexpr unsigned long long kCarryStamp = 0xFFull << kStampShift;
+constexpr int kMaxCarryBudget = kMaxBudget - 1;
 
 struct HSlot {
   unsigned long long key;
@@ -129,6 +136,8 @@ struct TreeView {
                                  // blocks so that no address takes many atomics
   unsigned long long* gate;      // [4] plans with a time budget: [0] start on
                                  // the wall clock, [1] stop flag, [2] iterations run
+  const int* carry_rng;          // [kMaxDepth + 1][2] level steps of a kept
+                                 // subtree by depth: first step, step count
   const int* step_base;          // [K+1] first level step of each iteration
   unsigned long long* tr_key;    // [(depth + 1) * n_p] trace words
   float* tr_val;                 // reward (levels) or heuristic (leaf)
@@ -199,6 +208,9 @@ struct PlanView {
   unsigned long long budget_ticks;
   unsigned long long* gate_host;  // pinned host word: iterations run | stop << 32
   int timed;
+  // The plan starts from a kept subtree (tree re-rooting): its beliefs sit in
+  // the level steps before the plan's own, listed by depth in t.carry_rng.
+  int carry;
   FilterView f;            // served episodes only
 };
 

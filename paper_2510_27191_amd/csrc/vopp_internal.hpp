@@ -42,6 +42,23 @@ struct vopp_workspace {
   int* step_host = nullptr;       // pinned
   double* out_dev = nullptr;
   double* out_host = nullptr;     // pinned
+  // Depth of the beliefs each level step of the last plan's tree holds (the
+  // steps of a kept subtree first, then the plan's own).
+  std::vector<int> step_depth;
+  // A kept subtree written by vopp_reroot: its layout by depth, and whether
+  // the next plan starts from it.  `carried` says the last plan's tree holds
+  // these steps.
+  struct Carry {
+    bool pending = false;
+    int n_p = 0, n_steps = 0;
+    int first[vopp::kMaxDepth + 1] = {0}, count[vopp::kMaxDepth + 1] = {0};
+    long long beliefs[vopp::kMaxDepth + 1] = {0}, nodes[vopp::kMaxDepth + 1] = {0};
+    long long root_visits = 0;
+    int shift = 0;               // fixed-point shift the kept sums were scaled to
+    int budget = 0;              // iterations that shift allows
+  } carry;
+  bool carried = false;
+  int* carry_rng_dev = nullptr;   // [kMaxDepth + 1][2] device copy of first, count
   // Anytime plans: pinned coherent host word written by the device at the end
   // of each iteration (iterations run | stop << 32), and its device address.
   unsigned long long* gate_host = nullptr;
@@ -84,9 +101,15 @@ vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_param
                       int K, int depth);
 PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
                    int n_belief, int K, int depth, const vopp_params* prm);
+// Blocks of a backup sweep over the beliefs of depth dep after iteration k;
+// extra: level steps of a kept subtree holding that depth.
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
-                int cap);
-WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule);
+                int cap, int extra = 0);
+// Sizes of a plan; extra_steps: level steps of a kept subtree in front.
+WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,
+                  int extra_steps = 0);
+// Fixed-point shift S of the sums for visits root visits in one plan.
+int fixed_shift(const vopp_pomdp* p, double visits);
 bool fits(const WsSizes& have, const WsSizes& need);
 size_t bytes_for(const WsSizes& z);
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,

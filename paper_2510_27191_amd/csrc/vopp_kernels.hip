@@ -197,7 +197,9 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
   const bool full = T.counters[3] != 0ull || n_prev * 10ull >= (unsigned long long)hcap;
   const size_t tid = (size_t)blk * kBlock + threadIdx.x;
   const size_t stride = (size_t)nblk * kBlock;
-  if (full) {
+  if (P.carry) {
+    // The table and the kept records were written by the re-rooting.
+  } else if (full) {
     uint4* hs = reinterpret_cast<uint4*>(T.h_slot);
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (size_t i = tid; i < hcap; i += stride) hs[i] = ones;
@@ -208,10 +210,14 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       if (sid) T.h_slot[sid - 1].key = kEmptyKey;
     }
   }
-  for (size_t i = tid; i < (size_t)3 * kMaxA * kStripes; i += stride) T.root_acc[i] = 0ull;
+  // Root action-node sums; with a kept root, stripe 0 of N and C starts from
+  // its record (written below by block 0).
+  for (size_t i = tid; i < (size_t)3 * kMaxA * kStripes; i += stride)
+    if (!(P.carry && i % kStripes == 0 && i < (size_t)2 * kMaxA * kStripes)) T.root_acc[i] = 0ull;
   if (blk == 0) {
     uint4* r = reinterpret_cast<uint4*>(T.rec);
-    for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (!P.carry)
+      for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int j = threadIdx.x;
     for (int i = j; i < 5 * kStripes; i += kBlock) T.stats[i] = 0ull;
@@ -226,8 +232,17 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       const double v = j < P.m.nA ? P.m.logpi0[j] / P.eta64 : 0.0;
       T.psi0[j] = (float)v;
       if (j < P.m.nA) {
-        rec_psi(T, 0)[j] = (float)v;
-        T.psi_root[j] = v;
+        if (P.carry) {                          // the kept root's own row and sums
+          T.psi_root[j] = (double)rec_psi(T, 0)[j];
+          T.root_acc[((size_t)0 * kMaxA + j) * kStripes] = (unsigned long long)(long long)rec_n(T, 0)[j];
+          T.root_acc[((size_t)1 * kMaxA + j) * kStripes] = rec_c(T, 0)[j];
+        } else {
+          rec_psi(T, 0)[j] = (float)v;
+          T.psi_root[j] = v;
+        }
+      } else if (P.carry && j < kMaxA) {
+        T.root_acc[((size_t)0 * kMaxA + j) * kStripes] = 0ull;
+        T.root_acc[((size_t)1 * kMaxA + j) * kStripes] = 0ull;
       }
     }
     __syncthreads();
@@ -236,7 +251,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       RecMeta* mt = rec_meta(T, 0);
       mt->obs = -1;
       mt->parent = kEmptyKey;
-      T.v_root[0] = 0.0;
+      T.v_root[0] = P.carry ? (double)mt->V : 0.0;
       T.counters[1] = 0ull;
     }
   }
@@ -485,6 +500,10 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
 __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, Ranges& R) {
   if (threadIdx.x == 0) {
     int n = 0;
+    if (P.carry) {                              // a kept subtree's steps first
+      const int f = P.t.carry_rng[2 * dep], c = P.t.carry_rng[2 * dep + 1];
+      for (int i = 0; i < c; ++i) R.step[n++] = f + i;
+    }
     for (int kk = 1; kk <= k; ++kk) {
       const int s0 = P.t.step_base[kk - 1];
       const int Dk = P.t.step_base[kk] - s0;
@@ -1164,6 +1183,183 @@ hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char
   hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, s, t, ids, n, out);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------
+// Tree re-rooting between real steps (the outer loop of Alg. 1): the belief
+// reached from the root by the executed action and the perceived observation
+// becomes the root of the next plan; its descendants keep their records
+// (statistics) and move one level up.  The passes run depth by depth, so a
+// belief's parent is always done before it.
+// ---------------------------------------------------------------------------
+
+// Slot of `key` (any stamp) in a table no kernel is inserting into, or ~0u.
+// An insert takes the first empty-or-matching slot of the key's line in the
+// key's rotated order and moves to the next line only when the line is full,
+// and slots are never emptied during a plan, so the first such slot decides.
+__device__ uint32_t find_slot(const TreeView& t, unsigned long long key) {
+  const unsigned long long hk = mix64(key);
+  uint32_t base = (uint32_t)hk & t.h_mask & ~7u;
+  const uint32_t rot = (uint32_t)(hk >> 40) & 7u;
+  const uint32_t lines = (t.h_mask >> 3) + 1;
+  for (uint32_t n = 0; n < lines; ++n) {
+    uint32_t best = 8;
+    int at = -1;
+    bool empty = false;
+    for (int j = 0; j < 8; ++j) {
+      const unsigned long long cur = t.h_slot[base + j].key;
+      const uint32_t pos = ((uint32_t)j - rot) & 7u;
+      if ((cur == kEmptyKey || (cur & ~kStampMask) == key) && pos < best) {
+        best = pos;
+        at = j;
+        empty = cur == kEmptyKey;
+      }
+    }
+    if (at >= 0) return empty ? ~0u : base + (uint32_t)at;
+    base = (base + 8u) & t.h_mask;
+  }
+  return ~0u;
+}
+
+__global__ void k_reroot_find(TreeView t, int a, int obs, int* out) {
+  if (threadIdx.x != 0) return;
+  const uint32_t h = find_slot(t, belief_key(0, a, obs));
+  out[0] = h == ~0u ? -1 : t.h_slot[h].id;
+}
+
+// Source record of position i of the launch's level steps, or -1.
+__device__ __forceinline__ int reroot_record(const RerootView& V, long long i) {
+  const int s = V.steps[i / V.src_n_p];
+  const size_t pos = (size_t)s * (size_t)V.src_n_p + (size_t)(i % V.src_n_p);
+  return V.src.list[pos] ? (int)(1 + pos) : -1;
+}
+
+// The parent link (record << 6 | action) of a source record, resolved.
+__device__ __forceinline__ unsigned long long reroot_parent(const TreeView& T, int r) {
+  unsigned long long par = rec_meta(T, r)->parent;
+  if (par != kEmptyKey && (par & kLinkSlot)) {
+    const int psid = (int)((par & ~kLinkSlot) >> 6);
+    par = ((unsigned long long)(uint32_t)record_of(T, psid) << 6) | (par & 63ull);
+  }
+  return par;
+}
+
+// Mark pass: kept[r] for the beliefs of one source depth, with counts of the
+// kept beliefs and of their action nodes (and, at depth 1, the root's visits).
+__global__ __launch_bounds__(kBlock) void k_reroot_mark(RerootView V) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long nb = 0, nn = 0, nv = 0;
+  if (i < (long long)V.n_steps * V.src_n_p) {
+    const int r = reroot_record(V, i);
+    if (r > 0) {
+      bool keep;
+      if (V.src_depth == 1) {
+        keep = r == V.root_rec;
+      } else {
+        const unsigned long long par = reroot_parent(V.src, r);
+        keep = par != kEmptyKey && V.kept[par >> 6] != 0;
+      }
+      if (keep) {
+        V.kept[r] = 1;
+        nb = 1;
+        const int* n = rec_n(V.src, r);
+        for (int j = 0; j < V.A; ++j) {
+          nn += n[j] > 0 ? 1ull : 0ull;
+          nv += (unsigned long long)(n[j] > 0 ? n[j] : 0);
+        }
+      }
+    }
+  }
+  nb = wave_sum(nb);
+  nn = wave_sum(nn);
+  nv = wave_sum(nv);
+  if ((threadIdx.x & 63) == 0 && nb) {
+    atomicAdd(&V.cnt[V.src_depth], nb);
+    atomicAdd(&V.cnt[kRerootCnt + V.src_depth], nn);
+    if (V.src_depth == 1) atomicAdd(&V.cnt[2 * kRerootCnt + 1], nv);
+  }
+}
+
+// Copy pass: each kept belief of one source depth gets the next position of
+// its new depth's level steps (the root: record 0), its record is copied with
+// the fixed-point sums rescaled, and it is inserted in the destination table
+// under its new parent's slot id.
+__global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= (long long)V.n_steps * V.src_n_p) return;
+  const int r = reroot_record(V, i);
+  if (r <= 0 || !V.kept[r]) return;
+  const int d_new = V.src_depth - 1;
+  int nr = 0;
+  if (d_new > 0) {
+    const unsigned long long q = atomicAdd(&V.cnt[3 * kRerootCnt + d_new], 1ull);
+    const long long t = (long long)V.first_step + (long long)(q / (unsigned long long)V.dst_n_p);
+    nr = (int)(1 + t * V.dst_n_p + (long long)(q % (unsigned long long)V.dst_n_p));
+  }
+  V.new_id[r] = nr;
+  const uint4* a = reinterpret_cast<const uint4*>(rec_at(V.src, r));
+  uint4* b = reinterpret_cast<uint4*>(rec_at(V.dst, nr));
+  for (int j = 0; j < V.src.rs / 16; ++j) b[j] = a[j];
+  unsigned long long* c = rec_c(V.dst, nr);
+  unsigned long long* w = rec_w(V.dst, nr);
+  for (int j = 0; j < V.dst.ra; ++j) {
+    if (V.rescale != 1.0 && c[j])
+      c[j] = (unsigned long long)llrint((double)(long long)c[j] * V.rescale);
+    w[j] = 0ull;
+  }
+  RecMeta* mt = rec_meta(V.dst, nr);
+  mt->leaf_cnt = 0;
+  mt->leaf_h = 0ull;
+  if (d_new == 0) {
+    mt->obs = -1;
+    mt->parent = kEmptyKey;
+    return;
+  }
+  const unsigned long long par = reroot_parent(V.src, r);
+  const int a_par = (int)(par & 63ull);
+  const int np = V.new_id[(int)(par >> 6)];
+  const int psid = np == 0 ? 0 : V.dst.list[np - 1];
+  const unsigned long long key = belief_key(psid, a_par, mt->obs);
+  bool won = false, fresh = false;
+  int id = -1;
+  const uint32_t h = probe(V.dst, key, kCarryStamp, won, fresh, id);
+  if (h == ~0u || !won) {
+    atomicOr((unsigned int*)&V.cnt[4 * kRerootCnt], 1u);
+    return;
+  }
+  V.dst.list[nr - 1] = (int)h + 1;
+  V.dst.h_slot[h].id = nr;
+  mt->parent = ((unsigned long long)(uint32_t)np << 6) | (unsigned long long)a_par;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill16(uint4* p, size_t n, uint4 v) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * kBlock)
+    p[i] = v;
+}
+
+hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reroot_find, dim3(1), dim3(64), 0, s, t, a, obs, out);
+  return hipGetLastError();
+}
+static int reroot_blocks(const RerootView& V) {
+  return (int)std::max(1ll, ((long long)V.n_steps * V.src_n_p + kBlock - 1) / kBlock);
+}
+hipError_t launch_reroot_mark(const RerootView& V, hipStream_t s) {
+  if (V.n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reroot_mark, dim3(reroot_blocks(V)), dim3(kBlock), 0, s, V);
+  return hipGetLastError();
+}
+hipError_t launch_reroot_copy(const RerootView& V, hipStream_t s) {
+  if (V.n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reroot_copy, dim3(reroot_blocks(V)), dim3(kBlock), 0, s, V);
+  return hipGetLastError();
+}
+hipError_t launch_fill16(void* p, size_t n, uint4 v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_fill16, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<uint4*>(p), n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
                         int n_blocks, int amax, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;

@@ -23,6 +23,34 @@ hipError_t launch_pf(const PlanView& P, int t, hipStream_t s);
 // Copy the records of beliefs ids[0..n) (device) to out[n * rs] (device).
 hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char* out,
                          hipStream_t s);
+// Tree re-rooting between real steps.  One launch of the mark or copy pass
+// covers the source beliefs of one depth (src_depth), in the source's level
+// steps steps[0 .. n_steps).
+struct RerootView {
+  TreeView src, dst;
+  int src_n_p, dst_n_p;
+  int A;
+  const int* steps;
+  int n_steps;
+  int src_depth;
+  int root_rec;               // source record of the new root (depth 1)
+  int first_step;             // copy: first destination step of depth src_depth-1
+  double rescale;             // copy: 2^(S_dst - S_src) for the fixed-point sums
+  unsigned char* kept;        // [source records] 1: in the kept subtree
+  int* new_id;                // [source records] destination record
+  // [4][kMaxDepth + 1]: kept beliefs, their action nodes, the root's visits
+  // (depth 1) and the copy's fill counters; [4 * (kMaxDepth + 1)] error flags.
+  unsigned long long* cnt;
+};
+constexpr int kRerootCnt = kMaxDepth + 1;
+// Record of the root's child belief for (a, obs) in a finished plan's table,
+// or -1 (one thread; out is a device int).
+hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int* out, hipStream_t s);
+hipError_t launch_reroot_mark(const RerootView& V, hipStream_t s);
+hipError_t launch_reroot_copy(const RerootView& V, hipStream_t s);
+// Fill n 16-byte words at p with v.
+hipError_t launch_fill16(void* p, size_t n, uint4 v, hipStream_t s);
+
 // One batched launch: n_blocks blocks over n_items phase items (device arrays).
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
                         int n_blocks, int amax, hipStream_t s);

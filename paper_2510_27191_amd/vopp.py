@@ -30,6 +30,7 @@ EXPORTS = (
     "vopp_pomdp_num_actions", "vopp_pomdp_set_reference_policy", "vopp_pomdp_free",
     "vopp_plan_footprint",
     "vopp_workspace_create", "vopp_workspace_free", "vopp_plan", "vopp_plan_anytime",
+    "vopp_reroot",
     "vopp_tree_dump", "vopp_level_counts", "vopp_profile_enable", "vopp_profile_reset",
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
@@ -153,6 +154,9 @@ def lib():
                                     vp, vp, C.POINTER(i32), vp, vp, C.POINTER(vopp_stats),
                                     C.POINTER(i32)]
     L.vopp_plan_anytime.restype = st
+    L.vopp_reroot.argtypes = [vp, vp, i32, i32, C.POINTER(vopp_params), i32, i32, vp, vp,
+                              C.POINTER(C.c_int64)]
+    L.vopp_reroot.restype = st
     L.vopp_tree_dump.argtypes = [vp] * 11
     L.vopp_tree_dump.restype = st
     L.vopp_level_counts.argtypes = [vp, vp, i32, C.POINTER(i32)]
@@ -358,6 +362,19 @@ def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, w
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
     return res, int(iters.value)
+
+
+def reroot(pomdp, src, action, obs, next_prm, next_budget, next_depth, dst, stream=None):
+    """vopp_reroot: keep the subtree of src's tree under (action, obs) in dst
+    for the next plan; returns the number of kept beliefs (0: none)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    kept = C.c_int64(0)
+    _check(lib().vopp_reroot(pomdp.handle, src.handle, int(action), int(obs),
+                             C.byref(next_prm), int(next_budget), int(next_depth),
+                             dst.handle, C.c_void_p(stream.cuda_stream), C.byref(kept)))
+    return int(kept.value)
 
 
 def tree_dump(ws, nA, n_beliefs, n_actions):

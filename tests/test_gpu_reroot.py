@@ -1,0 +1,225 @@
+"""Tree re-rooting between real steps through the C ABI, against the oracle.
+
+A chain is: plan in workspace A, keep the subtree under (action, observation)
+in workspace B, plan from it in B (and optionally keep again into A and plan
+a third time).  Each plan of a chain is held to the uniform parity bar
+(bit-exact structure in canonical order, values within 1e-4) on seeds whose
+oracle runs have no near-tie draw; a kept root's draws are screened like
+non-root draws, because the GPU keeps non-root rows in single precision.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2510_27191_amd import instances as I
+from tests.test_gpu_parity import TAU, assert_parity
+from tests.test_oracle_reroot import branches
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_27191_amd import vopp
+    vopp.lib()
+    return vopp
+
+
+def clean_chain(orc, inst, bel, plans, A, tries=30):
+    """Seeds (one per plan) whose oracle chain has no near tie, with the
+    oracle results and the (action, observation) kept after each plan."""
+    for s1 in range(1, tries):
+        seeds, outs, keys, start = [], [], [], None
+        ok = True
+        for i, (n_p, K, depth) in enumerate(plans):
+            for sd in range(s1 * 100 + i * 10, s1 * 100 + i * 10 + 10):
+                o = orc.plan(inst, bel, n_p, K, depth, seed=sd, tau=TAU, start=start,
+                             keep=True)
+                if o.near_ties == 0:
+                    break
+            else:
+                ok = False
+                break
+            seeds.append(sd)
+            outs.append(o)
+            if i + 1 < len(plans):
+                a, ob = branches(o, A, 1)[0]
+                keys.append((a, ob))
+                start, _ = orc.reroot(o, a, ob, A)
+        if ok:
+            return seeds, outs, keys
+    pytest.fail("no seed chain without near ties")
+
+
+def run_chain(V, inst, bel, plans, seeds, keys, A):
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    nb = b.numel() if inst["kind"] == "tabular" else b.numel() // 2
+    n_p, K, depth = plans[0]
+    wss = [V.Workspace(pom, V.params(n_p, seed=seeds[0]), K, depth),
+           V.Workspace(pom, V.params(plans[1][0], seed=seeds[1]), plans[1][1], plans[1][2])]
+    out, kept = [], []
+    try:
+        for i, (n_p, K, depth) in enumerate(plans):
+            ws = wss[i % 2]
+            res = V.plan(pom, b, nb, K, depth, V.params(n_p, seed=seeds[i]), ws=ws)
+            out.append((res, V.tree_dump(ws, A, res.n_beliefs, res.n_actions)))
+            if i + 1 < len(plans):
+                nn, nK, nd = plans[i + 1]
+                kept.append(V.reroot(pom, ws, keys[i][0], keys[i][1],
+                                     V.params(nn, seed=seeds[i + 1]), nK, nd, wss[(i + 1) % 2]))
+    finally:
+        for w in wss:
+            w.close()
+        pom.close()
+    return out, kept
+
+
+@pytest.mark.parametrize("plans", [
+    [(1024, 4, 4), (1024, 3, 4)],
+    [(1024, 4, 4), (1024, 4, 3)],
+    [(1024, 3, 5), (1024, 2, 5), (1024, 3, 5)],
+])
+def test_tabular_chain(V, orc, plans):
+    inst, bel, _ = I.workload("tabular16", seed=0)
+    seeds, outs, keys = clean_chain(orc, inst, bel, plans, 3)
+    res, kept = run_chain(V, inst, bel, plans, seeds, keys, 3)
+    for (r, t), o in zip(res, outs):
+        assert_parity(r, t, o, 3)
+    for i, k in enumerate(kept):
+        _, tr = orc.reroot(outs[i], keys[i][0], keys[i][1], 3)
+        assert k == len(tr["b_parent"])
+
+
+def test_nav_chain(V, orc):
+    inst = I.nav2d(4, 6, heuristic=1)
+    bel = I.nav_belief(5, 500, 6.6, 8.6)          # near the goal: terminals
+    plans = [(1500, 4, 4), (1500, 3, 4)]
+    seeds, outs, keys = clean_chain(orc, inst, bel, plans, 4)
+    res, _ = run_chain(V, inst, bel, plans, seeds, keys, 4)
+    for (r, t), o in zip(res, outs):
+        assert_parity(r, t, o, 4)
+
+
+def test_sparse_chain_fixed_schedule(V, orc):
+    inst = I.tabular_sparse(3, 256, 5, 6, 4)
+    bel = I.tabular_belief(inst)
+    plans = [(2000, 3, 3), (1000, 3, 3)]     # a different n_p for the second plan
+    for s1 in range(1, 30):
+        o1 = orc.plan(inst, bel, 2000, 3, 3, seed=s1, schedule=1, tau=TAU, keep=True)
+        if o1.near_ties:
+            continue
+        a, ob = branches(o1, 5, 1)[0]
+        h, _ = orc.reroot(o1, a, ob, 5)
+        o2 = orc.plan(inst, bel, 1000, 3, 3, seed=s1 + 500, schedule=1, tau=TAU, start=h)
+        if o2.near_ties == 0:
+            break
+    else:
+        pytest.fail("no clean seeds")
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    p1 = V.params(2000, seed=s1, schedule=1)
+    p2 = V.params(1000, seed=s1 + 500, schedule=1)
+    A_ws, B_ws = V.Workspace(pom, p1, 3, 3), V.Workspace(pom, p2, 3, 3)
+    try:
+        r1 = V.plan(pom, b, b.numel(), 3, 3, p1, ws=A_ws)
+        assert_parity(r1, V.tree_dump(A_ws, 5, r1.n_beliefs, r1.n_actions), o1, 5)
+        V.reroot(pom, A_ws, a, ob, p2, 3, 3, B_ws)
+        r2 = V.plan(pom, b, b.numel(), 3, 3, p2, ws=B_ws)
+        assert_parity(r2, V.tree_dump(B_ws, 5, r2.n_beliefs, r2.n_actions), o2, 5)
+    finally:
+        A_ws.close()
+        B_ws.close()
+        pom.close()
+
+
+def test_missing_branch_gives_a_fresh_plan(V):
+    inst, bel, _ = I.workload("tabular16", seed=0)
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    p1, p2 = V.params(1024, seed=3), V.params(1024, seed=9)
+    A_ws, B_ws, C_ws = (V.Workspace(pom, p1, 4, 4) for _ in range(3))
+    try:
+        V.plan(pom, b, b.numel(), 4, 4, p1, ws=A_ws)
+        assert V.reroot(pom, A_ws, 0, inst["nO"] + 3, p2, 4, 4, B_ws) == 0
+        r = V.plan(pom, b, b.numel(), 4, 4, p2, ws=B_ws)
+        f = V.plan(pom, b, b.numel(), 4, 4, p2, ws=C_ws)
+        assert np.array_equal(r.values, f.values) and r.n_beliefs == f.n_beliefs
+        tr, tf = (V.tree_dump(w, 3, f.n_beliefs, f.n_actions) for w in (B_ws, C_ws))
+        for k in tf:
+            assert np.array_equal(tr[k], tf[k]), k
+    finally:
+        for w in (A_ws, B_ws, C_ws):
+            w.close()
+        pom.close()
+
+
+def top_branch(tree, a):
+    """The most visited observation below root action a in a dumped tree."""
+    best, obs = -1, None
+    for b in range(1, len(tree["b_parent"])):
+        an = tree["b_parent"][b]
+        if tree["b_depth"][b] == 1 and tree["a_act"][an] == a and tree["b_N"][b] > best:
+            best, obs = tree["b_N"][b], int(tree["b_obs"][b])
+    return obs
+
+
+def test_anytime_plan_from_kept_tree(V):
+    # Two destinations receive the same kept subtree; a plain plan in one and
+    # an anytime plan with ample time in the other give the same tree.
+    inst, bel, _ = I.workload("tabular16", seed=0)
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    p1, p2 = V.params(1024, seed=2), V.params(1024, seed=11)
+    A_ws = V.Workspace(pom, p1, 4, 4)
+    B_ws, C_ws = V.Workspace(pom, p2, 5, 4), V.Workspace(pom, p2, 5, 4)
+    try:
+        r1 = V.plan(pom, b, b.numel(), 4, 4, p1, ws=A_ws)
+        o = top_branch(V.tree_dump(A_ws, 3, r1.n_beliefs, r1.n_actions), r1.action)
+        k1 = V.reroot(pom, A_ws, r1.action, o, p2, 5, 4, B_ws)
+        k2 = V.reroot(pom, A_ws, r1.action, o, p2, 5, 4, C_ws)
+        assert k1 == k2 > 1
+        r = V.plan(pom, b, b.numel(), 5, 4, p2, ws=B_ws)
+        q, k = V.plan_anytime(pom, b, b.numel(), 5, 4, 1e6, p2, ws=C_ws)
+        assert k == 5
+        assert np.array_equal(r.values, q.values)
+        tr = V.tree_dump(B_ws, 3, r.n_beliefs, r.n_actions)
+        tq = V.tree_dump(C_ws, 3, q.n_beliefs, q.n_actions)
+        for key in tr:
+            assert np.array_equal(tr[key], tq[key]), key
+    finally:
+        for w in (A_ws, B_ws, C_ws):
+            w.close()
+        pom.close()
+
+
+def test_reroot_argument_errors(V):
+    inst, bel, _ = I.workload("tabular16", seed=0)
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    p1 = V.params(1024, seed=2)
+    A_ws, B_ws = V.Workspace(pom, p1, 4, 4), V.Workspace(pom, p1, 4, 4)
+    try:
+        with pytest.raises(V.VoppError):            # no plan yet
+            V.reroot(pom, A_ws, 0, 0, p1, 4, 4, B_ws)
+        r1 = V.plan(pom, b, b.numel(), 4, 4, p1, ws=A_ws)
+        with pytest.raises(V.VoppError):
+            V.reroot(pom, A_ws, 0, 0, p1, 4, 4, A_ws)
+        with pytest.raises(V.VoppError):
+            V.reroot(pom, A_ws, 3, 0, p1, 4, 4, B_ws)
+        with pytest.raises(V.VoppError):
+            V.reroot(pom, A_ws, 0, 0, p1, 256, 4, B_ws)
+        o = top_branch(V.tree_dump(A_ws, 3, r1.n_beliefs, r1.n_actions), r1.action)
+        assert V.reroot(pom, A_ws, r1.action, o, p1, 3, 4, B_ws) > 0
+        with pytest.raises(V.VoppError):            # other n_particles
+            V.plan(pom, b, b.numel(), 3, 4, V.params(512, seed=2), ws=B_ws)
+        with pytest.raises(V.VoppError):            # more iterations than prepared
+            V.plan(pom, b, b.numel(), 4, 4, p1, ws=B_ws)
+        V.plan(pom, b, b.numel(), 3, 4, p1, ws=B_ws)
+    finally:
+        A_ws.close()
+        B_ws.close()
+        pom.close()
