@@ -62,7 +62,12 @@ typedef struct vopp_pomdp vopp_pomdp;
  *     summing to 1 within 1e-5.
  *   zprob [nS*nA*nO]: observation rows Z(s', a, .) indexed [s'][a][o].
  *   reward [nS*nA]: R(s, a).   heur [nS] or NULL: leaf value heuristic.
- * Limits: 1 <= nA <= 64, 1 <= nO <= 2^20, 1 <= nS < 2^31, 0 < gamma < 1.
+ * Limits: 1 <= nA <= 4096, 1 <= nS < 2^31, 0 < gamma < 1, and 1 <= nO <=
+ * 2^(26 - b) with b = max(6, ceil(log2 nA)) (belief keys hold the action and
+ * observation in 26 bits): nO <= 2^20 up to 64 actions, 2^16 for 625, 2^14
+ * for 3025.  Models with more than 64 actions keep preference rows in memory
+ * (one wavefront per belief in the backup sweeps); batched and served plans
+ * take at most 16 actions.
  * Sampling uses integer thresholds rint(cum/total * 2^31) per row. */
 typedef struct {
   int32_t nS, nA, nO;

@@ -71,11 +71,14 @@ static bool valid_row(const float* p, int n) {
   return std::fabs(s - 1.0) <= 1e-5;
 }
 
+// Entries of a model's ln pi0 row (at least kMaxA, at least |A| rounded up to 4).
+static int prior_len(int nA) { return std::max(kMaxA, (nA + 3) / 4 * 4); }
+
 // ln pi0(a) of a reference policy (Eq. 4), normalised by its sequential double
-// sum, written to the model's device row of kMaxA entries (zero past nA).  A
-// null pi0 gives the uniform row -ln nA.
+// sum, written to the model's device row of prior_len(nA) entries (zero past
+// nA).  A null pi0 gives the uniform row -ln nA.
 static hipError_t upload_log_prior(double* dst, int nA, const double* pi0) {
-  double row[kMaxA] = {};
+  std::vector<double> row(prior_len(nA), 0.0);
   if (pi0) {
     double sum = 0.0;
     for (int a = 0; a < nA; ++a) sum += pi0[a];
@@ -83,7 +86,7 @@ static hipError_t upload_log_prior(double* dst, int nA, const double* pi0) {
   } else {
     for (int a = 0; a < nA; ++a) row[a] = -std::log((double)nA);
   }
-  return hipMemcpy(dst, row, sizeof(row), hipMemcpyHostToDevice);
+  return hipMemcpy(dst, row.data(), row.size() * sizeof(double), hipMemcpyHostToDevice);
 }
 
 // Carves aligned sub-buffers out of one device allocation.
@@ -112,7 +115,10 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   clear_error();
   if (!d || !out) return fail(VOPP_E_INVALID, "null argument");
   *out = nullptr;
-  if (d->nS < 1 || d->nA < 1 || d->nA > kMaxA || d->nO < 1 || d->nO > kMaxObs)
+  int act_bits = 6;                               // action field of belief keys
+  while (d->nA > 0 && (1 << act_bits) < d->nA) ++act_bits;
+  const int obs_bits = kKeyLowBits - act_bits;
+  if (d->nS < 1 || d->nA < 1 || d->nA > kMaxAWide || d->nO < 1 || d->nO > (1 << obs_bits))
     return fail(VOPP_E_INVALID, "sizes out of range (nS=%d nA=%d nO=%d)", d->nS, d->nA, d->nO);
   if (!(d->gamma > 0.0 && d->gamma < 1.0)) return fail(VOPP_E_INVALID, "gamma must be in (0,1)");
   if (!d->rowptr || !d->col || !d->tprob || !d->zprob || !d->reward)
@@ -165,7 +171,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   size_t bytes = 0;
   bytes += align_up((rows + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) * 2;
   bytes += align_up(thrZ.size() * 4, 256) + align_up(rows * 4, 256) +
-           align_up((size_t)d->nS * 4, 256) + align_up(kMaxA * 8, 256) + 1024;
+           align_up((size_t)d->nS * 4, 256) + align_up((size_t)prior_len(d->nA) * 8, 256) + 1024;
   hipError_t e = hipMalloc(&p->arena, bytes);
   if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(model)"); }
   p->bytes = bytes;
@@ -176,7 +182,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   uint32_t* tZ = c.take<uint32_t>(thrZ.size());
   float* R = c.take<float>(rows);
   float* H = d->heur ? c.take<float>(d->nS) : nullptr;
-  double* logpi0 = c.take<double>(kMaxA);
+  double* logpi0 = c.take<double>(prior_len(d->nA));
   e = hipMemcpy(rowptr, d->rowptr, (rows + 1) * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(col, d->col, (size_t)nnz * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(tT, thrT.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
@@ -192,6 +198,7 @@ extern "C" vopp_status vopp_pomdp_tabular(const vopp_tabular_desc* d, vopp_pomdp
   m.Apad = (d->nA + 3) / 4 * 4;
   m.rowptr = rowptr; m.col = col; m.thrT = tT; m.thrZ = tZ; m.R = R; m.H = H;
   m.logpi0 = logpi0;
+  m.obs_bits = obs_bits;
   m.gamma = (float)d->gamma;
   m.gamma64 = d->gamma;
   *out = p;
@@ -228,7 +235,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   Carver c(p->arena);
   float* g = c.take<float>(4096);
   float* disks = c.take<float>(2 * (size_t)d->n_disks + 1);
-  double* logpi0 = c.take<double>(kMaxA);
+  double* logpi0 = c.take<double>(prior_len(4));
   e = hipMemcpy(g, d->gauss, 4096 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && d->n_disks)
     e = hipMemcpy(disks, d->disks, 2 * (size_t)d->n_disks * 4, hipMemcpyHostToDevice);
@@ -248,6 +255,7 @@ extern "C" vopp_status vopp_pomdp_nav2d(const vopp_nav2d_desc* d, vopp_pomdp** o
   np.r_hit = d->r_hit; np.heuristic = d->heuristic; np.n_disks = d->n_disks;
   m.gauss = g; m.disks = disks;
   m.logpi0 = logpi0;
+  m.obs_bits = kObsBits;
   m.gamma = (float)d->gamma;
   m.gamma64 = d->gamma;
   *out = p;
@@ -307,20 +315,25 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,
   return z;
 }
 
+// Doubles of a workspace's result record: action, |A| root preferences, V,
+// counts and flags.
+size_t out_len(const WsSizes& z) { return (size_t)std::max(kOutStride, z.Apad + 8); }
+
 size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
   auto add = [&](size_t n) { b += align_up(n, 256); };
   add((size_t)z.cap_b * z.rs);                       // belief records
   add(z.hcap * sizeof(HSlot));                       // table
-  add(kMaxA * 8); add(kMaxA * 8); add(8);            // root row and its CDF, V(root)
-  add(kMaxA * 4);                                    // initial preference row
-  add((size_t)3 * kMaxA * kStripes * 8);             // striped root action nodes
+  const size_t ar = (size_t)std::max(kMaxA, z.Apad);
+  add(ar * 8); add(ar * 8); add(8);                  // root row and its CDF, V(root)
+  add(ar * 4);                                       // initial preference row
+  add((size_t)3 * z.Apad * kStripes * 8);            // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(5 * kStripes * 8); add(32); add((z.K + 1) * 4);
   add(2 * (kMaxDepth + 1) * 4);                      // kept-subtree steps by depth
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
-  add(256 * 8);
+  add(out_len(z) * 8);                               // result record
   return b + 4096;
 }
 
@@ -348,10 +361,11 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.ra = z.Apad;
   t.h_slot = c.take<HSlot>(z.hcap);
   t.h_mask = (uint32_t)(z.hcap - 1);
-  t.psi_root = c.take<double>(kMaxA);
-  t.psi0 = c.take<float>(kMaxA);
-  t.root_cdf = c.take<double>(kMaxA);
-  t.root_acc = c.take<unsigned long long>((size_t)3 * kMaxA * kStripes);
+  const size_t ar = (size_t)std::max(kMaxA, z.Apad);
+  t.psi_root = c.take<double>(ar);
+  t.psi0 = c.take<float>(ar);
+  t.root_cdf = c.take<double>(ar);
+  t.root_acc = c.take<unsigned long long>((size_t)3 * z.Apad * kStripes);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
   t.counters = c.take<unsigned long long>(8);
@@ -364,8 +378,8 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   w->step_base_dev = step_base;
   t.tr_key = c.take<unsigned long long>((size_t)(z.depth + 1) * z.n_p);
   t.tr_val = c.take<float>((size_t)(z.depth + 1) * z.n_p);
-  w->out_dev = c.take<double>(256);
-  e = hipHostMalloc((void**)&w->out_host, 256 * sizeof(double), hipHostMallocDefault);
+  w->out_dev = c.take<double>(out_len(z));
+  e = hipHostMalloc((void**)&w->out_host, out_len(z) * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 8) * sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) {
@@ -698,7 +712,7 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
   st = enqueue_plan(p, ws, P, s, &steps);
   if (st != VOPP_OK) return st;
   const int A = p->nA;
-  e = hipMemcpyAsync(ws->out_host, ws->out_dev, kOutStride * sizeof(double),
+  e = hipMemcpyAsync(ws->out_host, ws->out_dev, out_len(ws->z) * sizeof(double),
                      hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(ws->ev1, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -857,7 +871,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
       if (depth[i] == d) grp.push_back(i);
     auto key = [&](size_t i) {
       const unsigned long long par = meta(i)->parent;
-      return std::make_tuple(pos_of[(int)(par >> 6)], (int)(par & 63ull), meta(i)->obs);
+      return std::make_tuple(pos_of[(int)(par >> kActBits)], (int)(par & kActMask), meta(i)->obs);
     };
     std::sort(grp.begin(), grp.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
     for (size_t j = 0; j < grp.size(); ++j) {
@@ -890,8 +904,8 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
     const RecMeta* m = meta(i);
     int par = -1;
     if (q > 0) {
-      const int pq = pos_of[(int)(m->parent >> 6)];
-      par = act_of[(size_t)pq * A + (int)(m->parent & 63ull)];
+      const int pq = pos_of[(int)(m->parent >> kActBits)];
+      par = act_of[(size_t)pq * A + (int)(m->parent & kActMask)];
     }
     if (b_parent) b_parent[q] = par;
     if (b_obs) b_obs[q] = q > 0 ? m->obs : -1;

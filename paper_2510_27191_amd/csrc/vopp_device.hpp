@@ -12,7 +12,10 @@
 namespace vopp {
 
 constexpr int kBlock = 256;                 // threads per block (4 wavefronts)
-constexpr int kMaxA = 64;
+constexpr int kMaxA = 64;                   // actions held in registers
+// Action field of parent links, trace words and aggregation keys.
+constexpr int kActBits = 12;
+constexpr unsigned long long kActMask = (1ull << kActBits) - 1;
 constexpr int kMaxBudget = 256;             // iterations per plan
 constexpr int kMaxDepth = 64;               // maximum leaf depth of a plan
 // Level steps a sweep of one depth may visit: the plan's own (one per
@@ -34,8 +37,10 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 // step t owns record 1 + t*n_p + ep (an episode inserts at most one belief per
 // level step), so no episode allocates anything; the inserting episode stores
 // the record index in the slot for later kernels.
-constexpr int kObsBits = 20;
+constexpr int kObsBits = 20;                // observation field for |A| <= 64
 constexpr int kMaxObs = 1 << kObsBits;
+constexpr int kKeyLowBits = 26;             // action and observation fields together
+constexpr int kMaxAWide = 1 << 12;          // largest action set (rows in memory)
 constexpr int kStampShift = 56;
 constexpr unsigned long long kStampMask = 0xFFull << kStampShift;
 constexpr unsigned long long kSidMask = (1ull << 30) - 1;
@@ -52,13 +57,14 @@ struct HSlot {
 // Trace words written by the forward kernel, one per (level, episode), for
 // the visits it does not count itself (the two shallowest levels, which many
 // episodes share, and beliefs another episode inserted in this iteration):
-//   level d < D: (id << 6) | action;  leaf (d = D): id;
+//   level d < D: (id << kActBits) | action;  leaf (d = D): id;
 //   kTraceRec: id is a record index, else a slot id;  kEmptyKey: nothing.
 constexpr unsigned long long kTraceRec = 1ull << 62;
 constexpr int kDirectLevel = 2;             // levels >= this count in place
 
-// Parent link of a record: (record << 6) | action, or kLinkSlot | (slot id
-// << 6) | action while the parent's record is not known yet; ~0 for the root.
+// Parent link of a record: (record << kActBits) | action, or kLinkSlot |
+// (slot id << kActBits) | action while the parent's record is not known yet;
+// ~0 for the root.
 constexpr unsigned long long kLinkSlot = 1ull << 62;
 
 enum : uint32_t { kTagRoot = 1, kTagStep = 2, kTagEnv = 4, kTagPF = 5, kTagResample = 6 };
@@ -86,7 +92,9 @@ struct ModelView {
   NavParams nav;
   const float* disks;                      // [2*n_disks]
   const float* gauss;                      // [4096]
-  const double* logpi0;                    // [kMaxA] ln pi0(a) of the reference
+  int obs_bits;                            // observation field of belief keys; the
+                                           // action field has 26 - obs_bits bits
+  const double* logpi0;                    // [max(kMaxA, Apad)] ln pi0(a) of the reference
                                            // policy, normalised; -ln|A| if uniform
   float gamma;
   double gamma64;
@@ -99,7 +107,7 @@ struct RecMeta {
   int leaf_cnt;              // this iteration's leaf visits (0 between iterations)
   int obs;                   // observation key (-1 for the root)
   unsigned long long leaf_h; // this iteration's heuristic sum (fixed point)
-  unsigned long long parent; // (parent id << 6) | action; ~0 for the root
+  unsigned long long parent; // (parent id << kActBits) | action; ~0 for the root
 };
 
 // The tree store in HBM.  Each belief owns one record of rs bytes (a multiple
@@ -119,10 +127,10 @@ struct TreeView {
   HSlot* h_slot;                 // [h_mask + 1] open-addressing table
   uint32_t h_mask;
   double* psi_root;              // [nA]
-  float* psi0;                   // [kMaxA] initial preference row ln pi0 / eta,
+  float* psi0;                   // [ra] initial preference row ln pi0 / eta,
                                  // zero past |A|
   double* root_cdf;              // [nA] running sums of the root's softmax weights
-  unsigned long long* root_acc;  // [3][kMaxA][kStripes]: N, C and W of the root's
+  unsigned long long* root_acc;  // [3][ra][kStripes]: N, C and W of the root's
                                  // action nodes, striped over blocks (every
                                  // episode passes through one of them)
   double* v_root;                // [1]
@@ -201,7 +209,7 @@ struct PlanView {
   double fix_inv64;
   int K, depth, schedule;
   int steps;               // level steps of the plan (sum of D_k)
-  double* out;             // kOutStride doubles: the plan's result
+  double* out;             // max(kOutStride, ra + 8) doubles: the plan's result
   // Time budget (anytime plan): 0 = run all K iterations.  Otherwise the
   // iterations after the first run only while fewer than budget_ticks
   // wall-clock ticks have passed since set-up; K is then the cap.
@@ -499,6 +507,31 @@ __device__ __forceinline__ int draw_action32(const float* __restrict__ row, int 
   return draw_row32<AM>(v, A, eta, x0);
 }
 
+// The same draw from a long row in memory (|A| > kMaxA): three passes over
+// the row, the weights recomputed in the last one by the same operations in
+// the same order, so the decision equals the register version's.
+__device__ __forceinline__ int draw_mem32(const float* __restrict__ row, int A, float eta,
+                                          uint32_t x0) {
+  float m = row[0];
+  for (int j = 0; j < A; j += 4) {
+    const float4 q = *reinterpret_cast<const float4*>(row + j);
+    m = fmaxf(m, q.x);
+    if (j + 1 < A) m = fmaxf(m, q.y);
+    if (j + 2 < A) m = fmaxf(m, q.z);
+    if (j + 3 < A) m = fmaxf(m, q.w);
+  }
+  float total = 0.0f;
+  for (int j = 0; j < A; ++j) total = total + expf(eta * (row[j] - m));
+  const float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
+  const float t = u * total;
+  float run = 0.0f;
+  for (int j = 0; j < A; ++j) {
+    run = run + expf(eta * (row[j] - m));
+    if (t < run) return j;
+  }
+  return A - 1;
+}
+
 // The same draw in double precision (root row).
 __device__ __forceinline__ int draw_action64(const double* __restrict__ row, int A,
                                              double eta, uint32_t x0) {
@@ -530,6 +563,20 @@ __device__ __forceinline__ void root_cdf(const double* __restrict__ row, int A, 
     run = run + exp(eta * (row[j] - m));
     cdf[j] = run;
   }
+}
+
+// draw_cdf64 by bisection: the first j with t < P_j in a non-decreasing row.
+__device__ __forceinline__ int draw_cdf64_bisect(const double* __restrict__ cdf, int A,
+                                                 uint32_t x0) {
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double t = u * cdf[A - 1];
+  int lo = 0, hi = A - 1;                     // the answer lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (t < cdf[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ int draw_cdf64(const double* __restrict__ cdf, int A, uint32_t x0) {

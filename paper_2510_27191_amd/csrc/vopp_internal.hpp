@@ -112,6 +112,7 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,
 int fixed_shift(const vopp_pomdp* p, double visits);
 bool fits(const WsSizes& have, const WsSizes& need);
 size_t bytes_for(const WsSizes& z);
+size_t out_len(const WsSizes& z);
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
                          hipStream_t s, int* n_steps_out);
 // Event brackets around one launch when profiling is on.

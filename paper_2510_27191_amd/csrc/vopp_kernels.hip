@@ -111,9 +111,11 @@ __device__ __forceinline__ uint32_t probe(const TreeView& t, unsigned long long 
   return ~0u;
 }
 
-__device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs) {
-  return ((unsigned long long)(uint32_t)b << 26) | ((unsigned long long)(uint32_t)a << 20) |
-         (uint32_t)obs;
+// Key of belief (parent slot id b, action a, observation obs); the
+// observation takes the low ob bits, the action the next 26 - ob.
+__device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs, int ob) {
+  return ((unsigned long long)(uint32_t)b << kKeyLowBits) |
+         ((unsigned long long)(uint32_t)a << ob) | (uint32_t)obs;
 }
 
 // ---------------------------------------------------------------------------
@@ -212,8 +214,8 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
   }
   // Root action-node sums; with a kept root, stripe 0 of N and C starts from
   // its record (written below by block 0).
-  for (size_t i = tid; i < (size_t)3 * kMaxA * kStripes; i += stride)
-    if (!(P.carry && i % kStripes == 0 && i < (size_t)2 * kMaxA * kStripes)) T.root_acc[i] = 0ull;
+  for (size_t i = tid; i < (size_t)3 * T.ra * kStripes; i += stride)
+    if (!(P.carry && i % kStripes == 0 && i < (size_t)2 * T.ra * kStripes)) T.root_acc[i] = 0ull;
   if (blk == 0) {
     uint4* r = reinterpret_cast<uint4*>(T.rec);
     if (!P.carry)
@@ -226,23 +228,23 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       T.gate[1] = 0ull;
       T.gate[2] = 0ull;
     }
-    if (j < kMaxA) {
+    for (int a = j; a < T.ra; a += kBlock) {
       // Initial preferences ln pi0 / eta: the root keeps them in double
       // precision, every other belief starts from their f32 rounding.
-      const double v = j < P.m.nA ? P.m.logpi0[j] / P.eta64 : 0.0;
-      T.psi0[j] = (float)v;
-      if (j < P.m.nA) {
+      const double v = a < P.m.nA ? P.m.logpi0[a] / P.eta64 : 0.0;
+      T.psi0[a] = (float)v;
+      if (a < P.m.nA) {
         if (P.carry) {                          // the kept root's own row and sums
-          T.psi_root[j] = (double)rec_psi(T, 0)[j];
-          T.root_acc[((size_t)0 * kMaxA + j) * kStripes] = (unsigned long long)(long long)rec_n(T, 0)[j];
-          T.root_acc[((size_t)1 * kMaxA + j) * kStripes] = rec_c(T, 0)[j];
+          T.psi_root[a] = (double)rec_psi(T, 0)[a];
+          T.root_acc[((size_t)0 * T.ra + a) * kStripes] = (unsigned long long)(long long)rec_n(T, 0)[a];
+          T.root_acc[((size_t)1 * T.ra + a) * kStripes] = rec_c(T, 0)[a];
         } else {
-          rec_psi(T, 0)[j] = (float)v;
-          T.psi_root[j] = v;
+          rec_psi(T, 0)[a] = (float)v;
+          T.psi_root[a] = v;
         }
-      } else if (P.carry && j < kMaxA) {
-        T.root_acc[((size_t)0 * kMaxA + j) * kStripes] = 0ull;
-        T.root_acc[((size_t)1 * kMaxA + j) * kStripes] = 0ull;
+      } else if (P.carry) {
+        T.root_acc[((size_t)0 * T.ra + a) * kStripes] = 0ull;
+        T.root_acc[((size_t)1 * T.ra + a) * kStripes] = 0ull;
       }
     }
     __syncthreads();
@@ -317,9 +319,14 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   // Inputs of the next level, read ahead of the previous level's writes: a
   // wait for a load also waits for every memory operation issued before it.
   U4 w = draw(P, (uint32_t)ep, kTagStep, 0u, (uint32_t)k);
-  float row[AM];
+  // Rows of up to kMaxA actions live in registers; longer rows are drawn
+  // from memory (rowp).
+  constexpr bool kWide = AM > kMaxA;
+  constexpr int RA = kWide ? 4 : AM;
+  float row[RA];
 #pragma unroll
-  for (int j = 0; j < AM; ++j) row[j] = 0.0f;
+  for (int j = 0; j < RA; ++j) row[j] = 0.0f;
+  const float* rowp = T.psi0;
   NavNoise z{0.0f, 0.0f, 0.0f, 0.0f};
   if (alive && nav) z = nav_noise(P.m, w);
   DiskCache dc;
@@ -336,8 +343,13 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     unsigned long long link = kEmptyKey;
     const int rid_b = rid;
     if (alive) {
-      if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
-      else a = draw_row32<AM>(row, A, P.eta, w.x);
+      if constexpr (kWide) {
+        if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
+        else a = draw_mem32(rowp, A, P.eta, w.x);
+      } else {
+        if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
+        else a = draw_row32<AM>(row, A, P.eta, w.x);
+      }
       bool term = false;
       if (!nav) {
         int sn;
@@ -354,15 +366,15 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
       // when b's record is known, else left to the accumulate pass.
       direct = d >= kDirectLevel && rid >= 0;
       if (!direct)
-        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a | kTraceRec)
-                      : (((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
-      link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << 6) | (uint32_t)a)
-                      : (kLinkSlot | ((unsigned long long)(uint32_t)sid << 6) | (uint32_t)a);
+        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
+                      : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
+                      : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
       if (term) {
         alive = false;                          // FilterTerminals
       } else {
         // AppendBeliefs: find or insert (b, a, o).
-        const unsigned long long key = belief_key(sid, a, obs);
+        const unsigned long long key = belief_key(sid, a, obs, P.m.obs_bits);
         bool fr;
         int id;
         h = probe(T, key, stamp, won, fr, id);
@@ -378,7 +390,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     if (alive && d + 1 < D) {
       w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
-      load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
+      if constexpr (kWide) rowp = fresh ? T.psi0 : rec_psi(T, rid);
+      else load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
       if (nav) z = nav_noise(P.m, w);
     }
     // Writes of level d.
@@ -426,7 +439,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
 
 // ---------------------------------------------------------------------------
 // Phase: fold the trace of an iteration with D levels into the records.
-// Aggregation keys: (record << 7) | (a << 1) for action nodes, (record << 7) | 1
+// Aggregation keys: (record << (kActBits + 1)) | (a << 1) for action nodes,
+// (record << (kActBits + 1)) | 1
 // for leaves.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int record_of(const TreeView& T, int sid) {
@@ -435,7 +449,7 @@ __device__ __forceinline__ int record_of(const TreeView& T, int sid) {
 
 // Stripe q (0: N, 1: C, 2: W) of root action a for the calling block.
 __device__ __forceinline__ unsigned long long* root_stripe(const TreeView& T, int q, int a) {
-  return T.root_acc + ((size_t)q * kMaxA + a) * kStripes + blockIdx.x % kStripes;
+  return T.root_acc + ((size_t)q * T.ra + a) * kStripes + blockIdx.x % kStripes;
 }
 
 __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm) {
@@ -456,9 +470,10 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
     if (has) {
       v = T.tr_val[i];
       const unsigned long long body = tk & ~kTraceRec;
-      const int id = (int)(leaf ? body : body >> 6);
+      const int id = (int)(leaf ? body : body >> kActBits);
       const int rid = (tk & kTraceRec) ? id : record_of(T, id);
-      key = ((unsigned long long)(uint32_t)rid << 7) | (leaf ? 1ull : ((body & 63ull) << 1));
+      key = ((unsigned long long)(uint32_t)rid << (kActBits + 1)) |
+            (leaf ? 1ull : ((body & kActMask) << 1));
     }
     if (__syncthreads_or(has)) {
       agg_clear(G);
@@ -473,17 +488,17 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
       for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
         const unsigned long long k2 = G.key[j];
         if (k2 == kEmptyKey) continue;
-        const int rid = (int)(k2 >> 7);
+        const int rid = (int)(k2 >> (kActBits + 1));
         if (k2 & 1ull) {
           RecMeta* mt = rec_meta(T, rid);
           atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
           if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
         } else if (rid == 0) {
-          const int a = (int)((k2 >> 1) & 63ull);
+          const int a = (int)((k2 >> 1) & kActMask);
           atomicAdd(root_stripe(T, 0, a), G.a[j]);
           if (G.b[j]) atomicAdd(root_stripe(T, 1, a), G.b[j]);
         } else {
-          const int a = (int)((k2 >> 1) & 63ull);
+          const int a = (int)((k2 >> 1) & kActMask);
           atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
           if (G.b[j]) atomicAdd(&rec_c(T, rid)[a], G.b[j]);
         }
@@ -514,12 +529,12 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, R
   __syncthreads();
 }
 
-// The parent link of a record, resolved to (record << 6) | a (written back).
+// The parent link of a record, resolved to (record << kActBits) | a (written back).
 __device__ __forceinline__ unsigned long long parent_link(const TreeView& T, RecMeta* mt) {
   unsigned long long par = mt->parent;
   if (par != kEmptyKey && (par & kLinkSlot)) {
-    const int psid = (int)((par & ~kLinkSlot) >> 6);
-    par = ((unsigned long long)(uint32_t)record_of(T, psid) << 6) | (par & 63ull);
+    const int psid = (int)((par & ~kLinkSlot) >> kActBits);
+    par = ((unsigned long long)(uint32_t)record_of(T, psid) << kActBits) | (par & kActMask);
     mt->parent = par;
   }
   return par;
@@ -532,7 +547,7 @@ __device__ __forceinline__ int record_at(const PlanView& P, int t, int ep) {
 }
 
 // Push V*N_b of a belief into its parent action's W accumulator (parent =
-// (record << 6) | a, or kEmptyKey for none).  Beliefs of depth >= 3 mostly
+// (record << kActBits) | a, or kEmptyKey for none).  Beliefs of depth >= 3 mostly
 // have distinct parents, so they add directly; shallower ones share a few
 // parents and are combined per block first (then every thread of the block
 // must call, as it contains barriers; `shared` is uniform).
@@ -544,7 +559,7 @@ __device__ __forceinline__ void push_values(const PlanView& P, AggTable& G, bool
   if (parent != kEmptyKey && N > 0) f = to_fix(V * (float)N, P.fix_scale);
   if (!shared) {
     if (f) {
-      const int pr = (int)(parent >> 6), a = (int)(parent & 63ull);
+      const int pr = (int)(parent >> kActBits), a = (int)(parent & kActMask);
       if (pr == 0) atomicAdd(root_stripe(P.t, 2, a), f);
       else atomicAdd(&rec_w(P.t, pr)[a], f);
     }
@@ -558,7 +573,7 @@ __device__ __forceinline__ void push_values(const PlanView& P, AggTable& G, bool
   for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
     const unsigned long long key = G.key[j];
     if (key != kEmptyKey && G.a[j]) {
-      const int pr = (int)(key >> 6), a = (int)(key & 63ull);
+      const int pr = (int)(key >> kActBits), a = (int)(key & kActMask);
       if (pr == 0) atomicAdd(root_stripe(P.t, 2, a), G.a[j]);
       else atomicAdd(&rec_w(P.t, pr)[a], G.a[j]);
     }
@@ -713,16 +728,245 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
   }
 }
 
-// The root row in double precision, updated in place (one thread).
-// Run by the block's first wavefront.  Lane s sums stripe s of the root's
-// action nodes; lane j then owns action j: it evaluates that action's
-// exponentials, and lane 0 adds them up in action order (the order of the
-// serial definition, so every sum rounds exactly as it would there).
+// Anytime plan (Alg. 1 loops while the budget lasts), run by the first
+// wavefront of the root backup: this iteration's backups are done; the next
+// one runs only if time is left and K is not reached.  The decision goes to
+// the later phases (gate) and to the host, which stops enqueueing.
+__device__ __forceinline__ void root_gate(const PlanView& P, int k, int lane) {
+  if (!P.timed) return;
+  unsigned long long* next = stat_bank(P, k + 1);
+  next[lane] = 0ull;
+  next[kStripes + lane] = 0ull;
+  if (lane == 0) {
+    const unsigned long long now = (unsigned long long)wall_clock64();
+    const unsigned long long stop =
+        (k >= P.K || now - P.t.gate[0] >= P.budget_ticks) ? 1ull : 0ull;
+    P.t.gate[1] = stop;
+    P.t.gate[2] = (unsigned long long)k;
+    __hip_atomic_store(P.gate_host, (unsigned long long)k | (stop << 32), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps for long action rows (|A| > kMaxA): one wavefront per belief, lane j
+// owning actions j, j + 64, ...; the row stays in memory.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_max64(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
+
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Level sweep of the internal beliefs of depth dep-1 >= 1 (Alg. 3, Eq. 3, 5).
+__device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk, int nblk,
+                                      Smem& sm) {
+  Ranges& R = sm.ranges;
+  load_ranges(P, dep - 1, k, R);
+  const TreeView& T = P.t;
+  const int A = P.m.nA;
+  const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
+  const int lane = threadIdx.x & 63;
+  const int waves = kBlock / 64;
+  unsigned long long nodes = 0, beliefs = 0;  // tree statistics (lane 0 counts)
+  const long long total = (long long)R.n * P.n_p;
+  for (long long i = (long long)blk * waves + (threadIdx.x >> 6); i < total;
+       i += (long long)nblk * waves) {
+    const int r = (int)(i / P.n_p);
+    const int b = record_at(P, R.step[r], (int)(i - (long long)r * P.n_p));
+    if (b <= 0) continue;                       // uniform over the wavefront
+    float* prow = rec_psi(T, b);
+    const int* nrow = rec_n(T, b);
+    unsigned long long* crow = rec_c(T, b);
+    unsigned long long* wrow = rec_w(T, b);
+    RecMeta* mt = rec_meta(T, b);
+    bool vis = false;
+    float m = -INFINITY;
+    for (int j = lane; j < A; j += 64) {
+      vis = vis || nrow[j] > 0;
+      m = fmaxf(m, prow[j]);
+    }
+    float V;
+    int N;
+    if (__any(vis)) {
+      // V_curr = L_eta Psi (Eq. 3) before the update.
+      m = wave_maxf(m);
+      float se = 0.0f;
+      for (int j = lane; j < A; j += 64) se = se + expf(eta * (prow[j] - m));
+      const float vc = m + logf(wave_sumf(se)) / eta;
+      // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5).
+      int nsum = 0, nn = 0;
+      float m2 = -INFINITY;
+      for (int j = lane; j < A; j += 64) {
+        float p = prow[j];
+        const int n = nrow[j];
+        if (n > 0) {
+          const float c = from_fix(crow[j], inv);
+          const unsigned long long wf = wrow[j];
+          const float w = from_fix(wf, inv);
+          if (wf) wrow[j] = 0ull;
+          const float fn = (float)n;
+          p = (p - vc) + (c / fn + gamma * (w / fn));
+          prow[j] = p;
+          nsum += n;
+          ++nn;
+        }
+        m2 = fmaxf(m2, p);
+      }
+      m2 = wave_maxf(m2);
+      float se2 = 0.0f;
+      for (int j = lane; j < A; j += 64) se2 = se2 + expf(eta * (prow[j] - m2));
+      V = m2 + logf(wave_sumf(se2)) / eta;
+      N = (int)wave_sum((unsigned long long)nsum);
+      nodes += wave_sum((unsigned long long)nn);
+      if (lane == 0) {
+        mt->V = V;
+        mt->Nb = N;
+      }
+    } else {
+      V = mt->V;
+      N = mt->Nb;
+    }
+    if (lane == 0) {
+      ++beliefs;
+      const unsigned long long parent = parent_link(T, mt);
+      if (parent != kEmptyKey && N > 0) {
+        const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
+        if (f) {
+          const int pr = (int)(parent >> kActBits), a = (int)(parent & kActMask);
+          if (pr == 0) atomicAdd(root_stripe(T, 2, a), f);
+          else atomicAdd(&rec_w(T, pr)[a], f);
+        }
+      }
+    }
+  }
+  if (counts_tree(P, k) && lane == 0) {
+    unsigned long long* bank = stat_bank(P, k);
+    if (nodes) atomicAdd(&bank[blk % kStripes], nodes);
+    if (beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
+  }
+}
+
+// The root row (|A| > kMaxA) in double precision, by one block: the striped
+// action-node sums are folded into the root record, then every sum over the
+// actions is taken in action order (the serial definition's order) from LDS.
+__device__ void dev_backup_root_wide(const PlanView& P, int k, double* buf) {
+  const TreeView& T = P.t;
+  const int A = P.m.nA;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double eta = P.eta64;
+  __shared__ double red[kBlock / 64];
+  __shared__ double bc;
+  __shared__ unsigned long long cnt[2];
+  if (wv == 0) root_gate(P, k, lane);
+  if (threadIdx.x == 0) { cnt[0] = 0ull; cnt[1] = 0ull; }
+  // Fold the stripes: N and C into the root record, W into its W column.
+  for (int j = wv; j < A; j += kBlock / 64) {
+    unsigned long long* w = &T.root_acc[((size_t)2 * T.ra + j) * kStripes + lane];
+    const unsigned long long n = wave_sum(T.root_acc[((size_t)0 * T.ra + j) * kStripes + lane]);
+    const unsigned long long c = wave_sum(T.root_acc[((size_t)1 * T.ra + j) * kStripes + lane]);
+    const unsigned long long wv2 = wave_sum(*w);
+    *w = 0ull;
+    if (lane == 0) {
+      rec_n(T, 0)[j] = (int)n;
+      rec_c(T, 0)[j] = c;
+      rec_w(T, 0)[j] = wv2;
+    }
+  }
+  __syncthreads();
+  // Block maximum of a double over the threads' values.
+  auto block_max = [&](double v) {
+    v = wave_max64(v);
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
+    __syncthreads();
+    return r;
+  };
+  // Sum of exp(eta (x_j - m)) over the actions in action order; with cdf set,
+  // the running sums are stored as the root's draw table.
+  auto ordered = [&](const double* x, double m, double* cdf) {
+    double run = 0.0;
+    for (int base = 0; base < A; base += kBlock) {
+      const int j = base + (int)threadIdx.x;
+      if (j < A) buf[threadIdx.x] = exp(eta * (x[j] - m));
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int n = min(kBlock, A - base);
+        for (int i = 0; i < n; ++i) {
+          run = run + buf[i];
+          if (cdf) cdf[base + i] = run;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bc = run;
+    __syncthreads();
+    return bc;
+  };
+  double* psi = T.psi_root;
+  double mloc = -INFINITY;
+  unsigned long long nodes = 0, nsum = 0;
+  for (int j = threadIdx.x; j < A; j += kBlock) {
+    mloc = fmax(mloc, psi[j]);
+    const int n = rec_n(T, 0)[j];
+    nodes += n > 0 ? 1ull : 0ull;
+    nsum += (unsigned long long)(n > 0 ? n : 0);
+  }
+  nodes = wave_sum(nodes);
+  nsum = wave_sum(nsum);
+  if (lane == 0) {
+    atomicAdd(&cnt[0], nodes);
+    atomicAdd(&cnt[1], nsum);
+  }
+  const double m = block_max(mloc);
+  if (cnt[0] == 0ull) return;                   // uniform: no action node yet
+  // V_curr = L_eta Psi before the update (Eq. 3).
+  const double vc = m + log(ordered(psi, m, nullptr)) / eta;
+  // Psi <- Psi - V_curr + Q for the actions with an action node (Eq. 5).
+  double m2 = -INFINITY;
+  for (int j = threadIdx.x; j < A; j += kBlock) {
+    const int n = rec_n(T, 0)[j];
+    double p = psi[j];
+    if (n > 0) {
+      const double c = (double)(long long)rec_c(T, 0)[j] * P.fix_inv64;
+      const double w = (double)(long long)rec_w(T, 0)[j] * P.fix_inv64;
+      p = (p - vc) + (c / (double)n + P.m.gamma64 * (w / (double)n));
+      psi[j] = p;
+    }
+    m2 = fmax(m2, p);
+  }
+  __syncthreads();
+  const double mm = block_max(m2);
+  // V = L_eta Psi after the update, and the running sums of the root draw.
+  const double run = ordered(psi, mm, T.root_cdf);
+  if (threadIdx.x == 0) {
+    const double v = mm + log(run) / eta;
+    T.v_root[0] = v;
+    RecMeta* mt = rec_meta(T, 0);
+    mt->V = (float)v;
+    mt->Nb = (int)cnt[1];
+    if (counts_tree(P, k)) atomicAdd(&stat_bank(P, k)[0], cnt[0]);
+  }
+}
+
+// The root row in double precision, updated in place (one thread).
+// Run by the block's first wavefront.  Lane s sums stripe s of the root's
+// action nodes; lane j then owns action j: it evaluates that action's
+// exponentials, and lane 0 adds them up in action order (the order of the
+// serial definition, so every sum rounds exactly as it would there).
 
 // Sum of x over lanes 0..A-1 in lane order, broadcast to the wave.
 __device__ __forceinline__ double ordered_sum(double x, int A) {
@@ -735,31 +979,14 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
   if (threadIdx.x >= 64) return;
   const int A = P.m.nA;
   const int lane = threadIdx.x;
-  if (P.timed) {
-    // Anytime plan (Alg. 1 loops while the budget lasts): this iteration's
-    // backups are done; the next one runs only if time is left and K is not
-    // reached.  The decision goes to the later phases (gate) and to the host,
-    // which stops enqueueing.
-    unsigned long long* next = stat_bank(P, k + 1);
-    next[lane] = 0ull;
-    next[kStripes + lane] = 0ull;
-    if (lane == 0) {
-      const unsigned long long now = (unsigned long long)wall_clock64();
-      const unsigned long long stop =
-          (k >= P.K || now - P.t.gate[0] >= P.budget_ticks) ? 1ull : 0ull;
-      P.t.gate[1] = stop;
-      P.t.gate[2] = (unsigned long long)k;
-      __hip_atomic_store(P.gate_host, (unsigned long long)k | (stop << 32), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-  }
+  root_gate(P, k, lane);
   const bool act = lane < A;
   unsigned long long* acc = P.t.root_acc;
   long long n_me = 0, c_me = 0, w_me = 0;     // sums of action `lane`
   for (int j = 0; j < A; ++j) {
-    unsigned long long* w = &acc[((size_t)2 * kMaxA + j) * kStripes + lane];
-    const unsigned long long n = wave_sum(acc[((size_t)0 * kMaxA + j) * kStripes + lane]);
-    const unsigned long long c = wave_sum(acc[((size_t)1 * kMaxA + j) * kStripes + lane]);
+    unsigned long long* w = &acc[((size_t)2 * P.t.ra + j) * kStripes + lane];
+    const unsigned long long n = wave_sum(acc[((size_t)0 * P.t.ra + j) * kStripes + lane]);
+    const unsigned long long c = wave_sum(acc[((size_t)1 * P.t.ra + j) * kStripes + lane]);
     const unsigned long long wv = wave_sum(*w);
     *w = 0ull;
     if (lane == j) {
@@ -1040,6 +1267,16 @@ __global__ void k_backup_root(PlanView P, int k) {
   if (budget_spent(P)) return;
   dev_backup_root(P, k);
 }
+__global__ __launch_bounds__(kBlock) void k_backup_level_wide(PlanView P, int dep, int k) {
+  __shared__ Smem sm;
+  if (budget_spent(P)) return;
+  dev_backup_level_wide(P, dep, k, blockIdx.x, gridDim.x, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_backup_root_wide(PlanView P, int k) {
+  __shared__ double buf[kBlock];
+  if (budget_spent(P)) return;
+  dev_backup_root_wide(P, k, buf);
+}
 __global__ void k_select(PlanView P) { dev_select(P); }
 
 // ---------------------------------------------------------------------------
@@ -1121,7 +1358,8 @@ hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   else if (Ap <= 8) hipLaunchKernelGGL(k_forward<8>, g, b, 0, s, P, k, D);
   else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, P, k, D);
   else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
-  else hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
+  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
+  else hipLaunchKernelGGL(k_forward<kMaxAWide>, g, b, 0, s, P, k, D);
   return hipGetLastError();
 }
 hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
@@ -1139,11 +1377,13 @@ hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipS
   else if (Ap <= 8) hipLaunchKernelGGL(k_backup_level<8>, g, b, 0, s, P, dep, k);
   else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, P, dep, k);
   else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, P, dep, k);
-  else hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
+  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
+  else hipLaunchKernelGGL(k_backup_level_wide, g, b, 0, s, P, dep, k);
   return hipGetLastError();
 }
 hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
+  if (P.m.Apad > kMaxA) hipLaunchKernelGGL(k_backup_root_wide, dim3(1), dim3(kBlock), 0, s, P, k);
+  else hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
   return hipGetLastError();
 }
 hipError_t launch_select(const PlanView& P, hipStream_t s) {
@@ -1219,9 +1459,9 @@ __device__ uint32_t find_slot(const TreeView& t, unsigned long long key) {
   return ~0u;
 }
 
-__global__ void k_reroot_find(TreeView t, int a, int obs, int* out) {
+__global__ void k_reroot_find(TreeView t, int a, int obs, int ob, int* out) {
   if (threadIdx.x != 0) return;
-  const uint32_t h = find_slot(t, belief_key(0, a, obs));
+  const uint32_t h = find_slot(t, belief_key(0, a, obs, ob));
   out[0] = h == ~0u ? -1 : t.h_slot[h].id;
 }
 
@@ -1232,12 +1472,12 @@ __device__ __forceinline__ int reroot_record(const RerootView& V, long long i) {
   return V.src.list[pos] ? (int)(1 + pos) : -1;
 }
 
-// The parent link (record << 6 | action) of a source record, resolved.
+// The parent link (record << kActBits | action) of a source record, resolved.
 __device__ __forceinline__ unsigned long long reroot_parent(const TreeView& T, int r) {
   unsigned long long par = rec_meta(T, r)->parent;
   if (par != kEmptyKey && (par & kLinkSlot)) {
-    const int psid = (int)((par & ~kLinkSlot) >> 6);
-    par = ((unsigned long long)(uint32_t)record_of(T, psid) << 6) | (par & 63ull);
+    const int psid = (int)((par & ~kLinkSlot) >> kActBits);
+    par = ((unsigned long long)(uint32_t)record_of(T, psid) << kActBits) | (par & kActMask);
   }
   return par;
 }
@@ -1255,7 +1495,7 @@ __global__ __launch_bounds__(kBlock) void k_reroot_mark(RerootView V) {
         keep = r == V.root_rec;
       } else {
         const unsigned long long par = reroot_parent(V.src, r);
-        keep = par != kEmptyKey && V.kept[par >> 6] != 0;
+        keep = par != kEmptyKey && V.kept[par >> kActBits] != 0;
       }
       if (keep) {
         V.kept[r] = 1;
@@ -1314,10 +1554,10 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
     return;
   }
   const unsigned long long par = reroot_parent(V.src, r);
-  const int a_par = (int)(par & 63ull);
-  const int np = V.new_id[(int)(par >> 6)];
+  const int a_par = (int)(par & kActMask);
+  const int np = V.new_id[(int)(par >> kActBits)];
   const int psid = np == 0 ? 0 : V.dst.list[np - 1];
-  const unsigned long long key = belief_key(psid, a_par, mt->obs);
+  const unsigned long long key = belief_key(psid, a_par, mt->obs, V.obs_bits);
   bool won = false, fresh = false;
   int id = -1;
   const uint32_t h = probe(V.dst, key, kCarryStamp, won, fresh, id);
@@ -1327,7 +1567,7 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
   }
   V.dst.list[nr - 1] = (int)h + 1;
   V.dst.h_slot[h].id = nr;
-  mt->parent = ((unsigned long long)(uint32_t)np << 6) | (unsigned long long)a_par;
+  mt->parent = ((unsigned long long)(uint32_t)np << kActBits) | (unsigned long long)a_par;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill16(uint4* p, size_t n, uint4 v) {
@@ -1336,8 +1576,9 @@ __global__ __launch_bounds__(kBlock) void k_fill16(uint4* p, size_t n, uint4 v) 
     p[i] = v;
 }
 
-hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reroot_find, dim3(1), dim3(64), 0, s, t, a, obs, out);
+hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int ob, int* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_reroot_find, dim3(1), dim3(64), 0, s, t, a, obs, ob, out);
   return hipGetLastError();
 }
 static int reroot_blocks(const RerootView& V) {

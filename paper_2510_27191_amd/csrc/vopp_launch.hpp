@@ -30,6 +30,7 @@ struct RerootView {
   TreeView src, dst;
   int src_n_p, dst_n_p;
   int A;
+  int obs_bits;               // observation field of the belief keys
   const int* steps;
   int n_steps;
   int src_depth;
@@ -45,7 +46,8 @@ struct RerootView {
 constexpr int kRerootCnt = kMaxDepth + 1;
 // Record of the root's child belief for (a, obs) in a finished plan's table,
 // or -1 (one thread; out is a device int).
-hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int* out, hipStream_t s);
+hipError_t launch_reroot_find(const TreeView& t, int a, int obs, int ob, int* out,
+                              hipStream_t s);
 hipError_t launch_reroot_mark(const RerootView& V, hipStream_t s);
 hipError_t launch_reroot_copy(const RerootView& V, hipStream_t s);
 // Fill n 16-byte words at p with v.

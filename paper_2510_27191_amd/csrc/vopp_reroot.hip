@@ -62,7 +62,7 @@ extern "C" vopp_status vopp_reroot(const vopp_pomdp* p, vopp_workspace* src, int
   hipStream_t s = (hipStream_t)stream;
   if (kept_out) *kept_out = 0;
   dst->carry.pending = false;
-  if (obs >= kMaxObs) return VOPP_OK;            // no belief can have that key
+  if (obs >= (1 << p->view.obs_bits)) return VOPP_OK;   // no belief can have that key
 
   // Source level steps grouped by depth.
   const int n_src_steps = src->last_steps;
@@ -97,7 +97,8 @@ extern "C" vopp_status vopp_reroot(const vopp_pomdp* p, vopp_workspace* src, int
   if (e == hipSuccess && !steps_host.empty())
     e = hipMemcpyAsync(steps_dev, steps_host.data(), steps_host.size() * 4,
                        hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_reroot_find(src->tree, action, obs, found_dev, s);
+  if (e == hipSuccess)
+    e = launch_reroot_find(src->tree, action, obs, p->view.obs_bits, found_dev, s);
   int root_rec = -1;
   if (e == hipSuccess) e = hipMemcpyAsync(&root_rec, found_dev, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -110,6 +111,7 @@ extern "C" vopp_status vopp_reroot(const vopp_pomdp* p, vopp_workspace* src, int
   V.src = src->tree;
   V.src_n_p = src->last_n_p;
   V.A = p->nA;
+  V.obs_bits = p->view.obs_bits;
   V.root_rec = root_rec;
   V.kept = kept;
   V.new_id = new_id;

@@ -101,6 +101,38 @@ def tabular_sparse(seed: int, nS: int = 4096, nA: int = 8, nO: int = 32,
                 heur=heur, gamma=float(gamma))
 
 
+def mars_like(seed: int, nS: int = 2048, nA: int = 625, nO: int = 9, n_succ: int = 4,
+              gamma: float = 0.983, alpha: float = 0.5, reward_scale: float = 1.0) -> dict:
+    """Synthetic tabular POMDP shaped like Multi-Agent RockSample: |A| = (5+m)^2
+    joint actions (625 for m = 20, 3025 for m = 50), |O| = 9 with a NULL
+    observation 0, gamma = 0.983.
+
+    Each (s, a) has ``n_succ`` successors with Dirichlet(alpha) weights.  One
+    action in five of each block of 25 senses: its observation row is
+    Dirichlet(alpha) over the 9 observations; every other action observes NULL.
+    Rewards are -0.1 per step, and +-10 (either sign) for 2% of the (s, a)
+    pairs, like sampling a good or a bad rock; ``reward_scale`` multiplies both.
+    """
+    rng = np.random.default_rng(seed)
+    k = min(n_succ, nS)
+    rows = nS * nA
+    col = _distinct_rows(rng, rows, nS, k)
+    tp = rng.dirichlet(alpha * np.ones(k), size=rows).astype(np.float32)
+    Z = np.zeros((nS, nA, nO), np.float32)
+    Z[:, :, 0] = 1.0
+    sense = np.nonzero(np.arange(nA) % 25 >= 20)[0]
+    Z[:, sense, :] = rng.dirichlet(alpha * np.ones(nO), size=(nS, sense.size)).astype(np.float32)
+    R = np.full((nS, nA), -0.1, np.float32)
+    hit = rng.random((nS, nA)) < 0.02
+    R[hit] = np.where(rng.random(int(hit.sum())) < 0.5, 10.0, -10.0).astype(np.float32)
+    R = (R * np.float32(reward_scale)).astype(np.float32)
+    rowptr = (np.arange(rows + 1, dtype=np.int64) * k).astype(np.int32)
+    return dict(kind="tabular", nS=nS, nA=nA, nO=nO, rowptr=rowptr,
+                col=col.reshape(-1).copy(), tprob=tp.reshape(-1).copy(),
+                zprob=Z.reshape(-1).copy(), reward=R.reshape(-1).copy(),
+                heur=None, gamma=float(gamma))
+
+
 def _distinct_rows(rng, rows: int, n: int, k: int) -> np.ndarray:
     """rows x k distinct integers from [0, n) per row, sorted; uniform over
     k-subsets (rows with a repeated value are drawn again)."""
@@ -183,6 +215,14 @@ def workload(name: str, seed: int = 0):
         inst = nav2d(seed, 8)
         return inst, nav_belief(seed + 1000, 65536), dict(
             n_particles=65536, budget=10, depth=10, eta=1.0)
+    if name == "mars625":            # |S|=2048 |A|=625 |O|=9, n_p=2^14, depth 4
+        inst = mars_like(seed, 2048, 625)
+        return inst, tabular_belief(inst), dict(n_particles=16384, budget=4,
+                                                depth=4, eta=1.0)
+    if name == "mars3025":           # |S|=512 |A|=3025 |O|=9, n_p=2^14, depth 4
+        inst = mars_like(seed, 512, 3025)
+        return inst, tabular_belief(inst), dict(n_particles=16384, budget=4,
+                                                depth=4, eta=1.0)
     if name == "sparse4096":         # |S|=4096 |A|=8 |O|=32, n_p=2^18, depth 8
         inst = tabular_sparse(seed, 4096, 8, 32, 8)
         return inst, tabular_belief(inst), dict(n_particles=262144, budget=8,

@@ -188,7 +188,7 @@ def gpu_invariants(res, tree, n_p, K, depth, schedule):
     np.add.at(kid, tree["b_parent"][1:], tree["b_N"][1:])
     assert np.all(kid <= tree["a_N"])
     assert np.all(tree["b_depth"][1:] == tree["b_depth"][tree["a_parent"][tree["b_parent"][1:]]] + 1)
-    key_a = tree["a_parent"].astype(np.int64) * 64 + tree["a_act"]
+    key_a = tree["a_parent"].astype(np.int64) * 4096 + tree["a_act"]
     assert np.unique(key_a).size == na
     key_b = tree["b_parent"][1:].astype(np.int64) * (1 << 24) + tree["b_obs"][1:]
     assert np.unique(key_b).size == nb - 1
