@@ -47,7 +47,11 @@ HBM_PEAK_GBS = 8000.0
 #     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16.
 #   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
 #     written, push 16.
-def plan_bytes(nA, n_p, K, depth, counts, particle_steps):
+# With more than 64 actions the level sweep reads only what it uses: per
+# belief the N and preference rows 8*ra, the row written 4*ra, the tail 32
+# read and V, N_b 8 written, the push 16, and per action node C and W read
+# 16 and W cleared 8 (nodes_per_belief on average).
+def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
     ra = (nA + 3) // 4 * 4
     rec = 24 * ra + 32
     D = [min(k, depth) for k in range(1, K + 1)]
@@ -65,7 +69,8 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps):
         "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec)
                    + K * n_p * (24 + 12),
         "accumulate": items * 8,
-        "backup_level": level * (rec + 4 * ra + 8 + 8 * nA + 16),
+        "backup_level": (level * (rec + 4 * ra + 8 + 8 * nA + 16) if nA <= 64 else
+                         level * (12 * ra + 32 + 8 + 16 + 24 * nodes_per_belief)),
         "backup_leaf": leaf * (32 + 24 + 16),
     }
 
@@ -386,7 +391,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nav2d",
-                    choices=["nav2d", "sparse4096", "tabular16"])
+                    choices=["nav2d", "sparse4096", "tabular16", "mars625", "mars3025"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-event-profile", action="store_true",
                     help="skip the per-kernel event brackets in the timed region")
@@ -496,6 +501,10 @@ def main():
             "sparse4096": "sparse tabular POMDP |S|=4096 |A|=8 |O|=32, 8 successors, "
                           "n_p=262144, depth 8, budget 8 iterations",
             "tabular16": "tabular POMDP |S|=16 |A|=3 |O|=4, n_p=1024, depth 4, budget 4",
+            "mars625": "MARS-shaped tabular POMDP |S|=2048 |A|=625 |O|=9, 4 successors, "
+                       "n_p=16384, depth 4, budget 4 iterations",
+            "mars3025": "MARS-shaped tabular POMDP |S|=512 |A|=3025 |O|=9, 4 successors, "
+                        "n_p=16384, depth 4, budget 4 iterations",
         }[args.workload], "n_particles": n_p, "budget": K, "depth": depth,
             "eta": eta, "gamma": inst["gamma"], "schedule": "deepening",
             "parallelism": "single GPU"},
@@ -508,7 +517,8 @@ def main():
         out["kernel_share_warmup"] = warm_share
         roof = {"kernel": dom, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "traffic": None}
-        model = plan_bytes(pom.nA, n_p, K, depth, V.level_counts(ws), r.particle_steps)
+        model = plan_bytes(pom.nA, n_p, K, depth, V.level_counts(ws), r.particle_steps,
+                           r.n_actions / max(r.n_beliefs, 1))
         if dom in model:
             ms, launches = kinds[dom]
             per_plan_ms = ms / args.steps

@@ -53,7 +53,11 @@
  *     running sums, t = u * P_last with u = (x0 >> 8) * 2^-24, action = first
  *     j with t < P_j (clamped to |A|-1).  Because floating point decides an
  *     integer here, the decision is taken in the precision the GPU kernel
- *     uses: single precision at non-root beliefs, double at the root.  The
+ *     uses: single precision at non-root beliefs, double at the root.  At a
+ *     non-root belief with more than 64 actions the single-precision weights
+ *     are scaled by 2^24 and truncated to integers W_j, and the action is the
+ *     first j whose integer running sum exceeds ((x0 >> 8) * sum W) >> 24;
+ *     the sums are then exact in any order of addition.  The
  *     oracle also measures, in double precision, how far t lies from the
  *     nearest CDF boundary (the margin) and counts draws closer than tau.
  *   - Tabular G: thresholds thr_j = rint(cum_j / total * 2^31) from the
@@ -503,6 +507,9 @@ struct Result {
   std::vector<TraceRow> trace;
 };
 
+// Rows longer than this draw with integer weights (see the header).
+constexpr int kLongRow = 64;
+
 // Action draw of Eq. (6) in the GPU's decision precision, plus the margin of
 // the exact (double) draw to its nearest CDF boundary.
 int sample_action(const double* psi, int A, double eta, uint32_t x0, bool root,
@@ -542,6 +549,23 @@ int sample_action(const double* psi, int A, double eta, uint32_t x0, bool root,
   std::vector<float> f(A), P(A);
   float m = (float)psi[0];
   for (int j = 0; j < A; ++j) { f[j] = (float)psi[j]; m = std::max(m, f[j]); }
+  if (A > kLongRow) {
+    // Long rows: single-precision weights scaled to 24-bit integers, so the
+    // running sums are exact and do not depend on the order of addition.
+    std::vector<uint64_t> W(A);
+    uint64_t tot = 0;
+    for (int j = 0; j < A; ++j) {
+      W[j] = (uint64_t)(uint32_t)(expf(ef * (f[j] - m)) * 16777216.0f);
+      tot += W[j];
+    }
+    const uint64_t ti = ((uint64_t)(x0 >> 8) * tot) >> 24;
+    uint64_t acc = 0;
+    for (int j = 0; j < A; ++j) {
+      acc += W[j];
+      if (ti < acc) return j;
+    }
+    return A - 1;
+  }
   float run = 0.0f;
   for (int j = 0; j < A; ++j) { run += expf(ef * (f[j] - m)); P[j] = run; }
   float t = uf * P[A - 1];

@@ -14,18 +14,29 @@ from tests import refimpl as R
 
 @pytest.mark.parametrize("A", [625, 3025])
 def test_flat_row_draw(orc, A):
-    # Every weight is exp(0) = 1, so the running sums are the integers 1..A
-    # (exact in f32 below 2^24) and the draw is the first j with t < j + 1.
+    # Every weight is exp(0) = 1: at the root the running sums are the
+    # integers 1..A in double precision, elsewhere the integer weights are all
+    # 2^24; either way the draw is floor(u * A) with u = (x0 >> 8) / 2^24.
     rng = np.random.default_rng(A)
     eta = 1.0
     row = np.full(A, -np.log(A) / eta)
     for x0 in rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64):
         x0 = int(x0)
-        u32 = np.float32((x0 >> 8) * (1.0 / 16777216.0))
-        t32 = np.float32(u32 * np.float32(A))
-        want = min(int(np.floor(t32)), A - 1)
+        want = ((x0 >> 8) * A) >> 24
         assert orc.sample_action(row, eta, x0, False)[0] == want
-        assert orc.sample_action(row, eta, x0, True)[0] == ((x0 >> 8) * A) >> 24
+        assert orc.sample_action(row, eta, x0, True)[0] == want
+
+
+def test_long_row_integer_weights(orc):
+    # A hand-made long row: two actions hold all but a sliver of the mass, so
+    # the truncated weights are known exactly and the boundaries sit at
+    # integer multiples that u = (x0 >> 8) / 2^24 can hit exactly.
+    A, eta = 100, 1.0
+    row = np.full(A, -40.0)          # exp(-40) * 2^24 < 1: weight 0
+    row[17] = row[63] = 0.0          # weight 2^24 each; total 2^25, t = 2q
+    for q in (0, 1, 2 ** 22, 2 ** 23 - 1, 2 ** 23, 2 ** 23 + 1, 2 ** 24 - 1):
+        want = 17 if 2 * q < 2 ** 24 else 63
+        assert orc.sample_action(row, eta, q << 8, False)[0] == want
 
 
 @pytest.mark.parametrize("root", [False, True])
