@@ -507,31 +507,6 @@ __device__ __forceinline__ int draw_action32(const float* __restrict__ row, int 
   return draw_row32<AM>(v, A, eta, x0);
 }
 
-// The same draw from a long row in memory (|A| > kMaxA): three passes over
-// the row, the weights recomputed in the last one by the same operations in
-// the same order, so the decision equals the register version's.
-__device__ __forceinline__ int draw_mem32(const float* __restrict__ row, int A, float eta,
-                                          uint32_t x0) {
-  float m = row[0];
-  for (int j = 0; j < A; j += 4) {
-    const float4 q = *reinterpret_cast<const float4*>(row + j);
-    m = fmaxf(m, q.x);
-    if (j + 1 < A) m = fmaxf(m, q.y);
-    if (j + 2 < A) m = fmaxf(m, q.z);
-    if (j + 3 < A) m = fmaxf(m, q.w);
-  }
-  float total = 0.0f;
-  for (int j = 0; j < A; ++j) total = total + expf(eta * (row[j] - m));
-  const float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
-  const float t = u * total;
-  float run = 0.0f;
-  for (int j = 0; j < A; ++j) {
-    run = run + expf(eta * (row[j] - m));
-    if (t < run) return j;
-  }
-  return A - 1;
-}
-
 // The same draw in double precision (root row).
 __device__ __forceinline__ int draw_action64(const double* __restrict__ row, int A,
                                              double eta, uint32_t x0) {

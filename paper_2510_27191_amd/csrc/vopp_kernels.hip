@@ -192,7 +192,18 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v,
 // the root record.  The previous plan's sizes are read on the device, so the
 // phase is identical on every replay of a captured launch sequence.
 // ---------------------------------------------------------------------------
-__device__ void dev_setup(const PlanView& P, int blk, int nblk) {
+// LDS of the set-up of a plan with more than kMaxA actions (the root's draw
+// table is built by the block).
+struct SetupSmem {
+  double buf[kBlock];
+  double red[kBlock / 64];
+  double bc;
+};
+__device__ double block_max64(double v, double* red);
+__device__ double block_ordered_sum(const double* x, int A, double m, double eta, double* cdf,
+                                    double* buf, double* bc);
+
+__device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
   const TreeView& T = P.t;
   const unsigned long long n_prev = T.counters[2];
   const size_t hcap = (size_t)T.h_mask + 1;
@@ -248,8 +259,14 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk) {
       }
     }
     __syncthreads();
+    if (T.ra > kMaxA) {                         // long rows: the block builds the table
+      double mloc = -INFINITY;
+      for (int a = j; a < P.m.nA; a += kBlock) mloc = fmax(mloc, T.psi_root[a]);
+      const double m = block_max64(mloc, ss->red);
+      block_ordered_sum(T.psi_root, P.m.nA, m, P.eta64, T.root_cdf, ss->buf, &ss->bc);
+    }
     if (j == 0) {
-      root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
+      if (T.ra <= kMaxA) root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
       RecMeta* mt = rec_meta(T, 0);
       mt->obs = -1;
       mt->parent = kEmptyKey;
@@ -319,14 +336,9 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   // Inputs of the next level, read ahead of the previous level's writes: a
   // wait for a load also waits for every memory operation issued before it.
   U4 w = draw(P, (uint32_t)ep, kTagStep, 0u, (uint32_t)k);
-  // Rows of up to kMaxA actions live in registers; longer rows are drawn
-  // from memory (rowp).
-  constexpr bool kWide = AM > kMaxA;
-  constexpr int RA = kWide ? 4 : AM;
-  float row[RA];
+  float row[AM];
 #pragma unroll
-  for (int j = 0; j < RA; ++j) row[j] = 0.0f;
-  const float* rowp = T.psi0;
+  for (int j = 0; j < AM; ++j) row[j] = 0.0f;
   NavNoise z{0.0f, 0.0f, 0.0f, 0.0f};
   if (alive && nav) z = nav_noise(P.m, w);
   DiskCache dc;
@@ -343,13 +355,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     unsigned long long link = kEmptyKey;
     const int rid_b = rid;
     if (alive) {
-      if constexpr (kWide) {
-        if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
-        else a = draw_mem32(rowp, A, P.eta, w.x);
-      } else {
-        if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
-        else a = draw_row32<AM>(row, A, P.eta, w.x);
-      }
+      if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
+      else a = draw_row32<AM>(row, A, P.eta, w.x);
       bool term = false;
       if (!nav) {
         int sn;
@@ -390,8 +397,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     if (alive && d + 1 < D) {
       w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
-      if constexpr (kWide) rowp = fresh ? T.psi0 : rec_psi(T, rid);
-      else load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
+      load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
       if (nav) z = nav_noise(P.m, w);
     }
     // Writes of level d.
@@ -449,7 +455,9 @@ __device__ __forceinline__ int record_of(const TreeView& T, int sid) {
 
 // Stripe q (0: N, 1: C, 2: W) of root action a for the calling block.
 __device__ __forceinline__ unsigned long long* root_stripe(const TreeView& T, int q, int a) {
-  return T.root_acc + ((size_t)q * T.ra + a) * kStripes + blockIdx.x % kStripes;
+  // Long rows spread the root's visits over many actions: no striping there.
+  const int stripe = T.ra > kMaxA ? 0 : (int)(blockIdx.x % kStripes);
+  return T.root_acc + ((size_t)q * T.ra + a) * kStripes + stripe;
 }
 
 __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm) {
@@ -770,83 +778,129 @@ __device__ __forceinline__ float wave_sumf(float v) {
 }
 
 // Level sweep of the internal beliefs of depth dep-1 >= 1 (Alg. 3, Eq. 3, 5).
+// Lane l reads the quads 4l, 4l + 256, ... of each row (16-byte loads, the
+// padding past |A| masked off), so a row of 3025 actions takes 12 loads per
+// lane per pass.
+constexpr int kWideChunk = 16;              // positions a wavefront scans at once
+
 __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk, int nblk,
                                       Smem& sm) {
   Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
   const TreeView& T = P.t;
   const int A = P.m.nA;
+  const int nq = T.ra / 4;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
   const int lane = threadIdx.x & 63;
   const int waves = kBlock / 64;
   unsigned long long nodes = 0, beliefs = 0;  // tree statistics (lane 0 counts)
-  const long long total = (long long)R.n * P.n_p;
-  for (long long i = (long long)blk * waves + (threadIdx.x >> 6); i < total;
-       i += (long long)nblk * waves) {
-    const int r = (int)(i / P.n_p);
-    const int b = record_at(P, R.step[r], (int)(i - (long long)r * P.n_p));
-    if (b <= 0) continue;                       // uniform over the wavefront
-    float* prow = rec_psi(T, b);
-    const int* nrow = rec_n(T, b);
-    unsigned long long* crow = rec_c(T, b);
-    unsigned long long* wrow = rec_w(T, b);
-    RecMeta* mt = rec_meta(T, b);
-    bool vis = false;
-    float m = -INFINITY;
-    for (int j = lane; j < A; j += 64) {
-      vis = vis || nrow[j] > 0;
-      m = fmaxf(m, prow[j]);
-    }
-    float V;
-    int N;
-    if (__any(vis)) {
-      // V_curr = L_eta Psi (Eq. 3) before the update.
-      m = wave_maxf(m);
-      float se = 0.0f;
-      for (int j = lane; j < A; j += 64) se = se + expf(eta * (prow[j] - m));
-      const float vc = m + logf(wave_sumf(se)) / eta;
-      // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5).
-      int nsum = 0, nn = 0;
-      float m2 = -INFINITY;
-      for (int j = lane; j < A; j += 64) {
-        float p = prow[j];
-        const int n = nrow[j];
-        if (n > 0) {
-          const float c = from_fix(crow[j], inv);
-          const unsigned long long wf = wrow[j];
-          const float w = from_fix(wf, inv);
-          if (wf) wrow[j] = 0ull;
-          const float fn = (float)n;
-          p = (p - vc) + (c / fn + gamma * (w / fn));
-          prow[j] = p;
-          nsum += n;
-          ++nn;
+  // Each wavefront takes kWideChunk positions of one level step at a time and
+  // visits the beliefs among them one after the other.
+  const int per = (P.n_p + kWideChunk - 1) / kWideChunk;
+  for (long long c = (long long)blk * waves + (threadIdx.x >> 6); c < (long long)R.n * per;
+       c += (long long)nblk * waves) {
+    const int r = (int)(c / per);
+    const int ep = (int)(c - (long long)r * per) * kWideChunk + lane;
+    const int bl = (lane < kWideChunk && ep < P.n_p) ? record_at(P, R.step[r], ep) : -1;
+    unsigned long long todo = __ballot(bl > 0);
+    while (todo) {
+      const int b = __shfl(bl, __ffsll((long long)todo) - 1, 64);
+      todo &= todo - 1;
+      const float4* p4 = reinterpret_cast<const float4*>(rec_psi(T, b));
+      const int4* n4 = reinterpret_cast<const int4*>(rec_n(T, b));
+      const unsigned long long* crow = rec_c(T, b);
+      unsigned long long* wrow = rec_w(T, b);
+      RecMeta* mt = rec_meta(T, b);
+      bool vis = false;
+      float m = -INFINITY;
+#pragma unroll 4
+      for (int q = lane; q < nq; q += 64) {
+        const float4 v = p4[q];
+        const int4 n = n4[q];
+        const int j = 4 * q;
+        m = fmaxf(m, v.x);                      // j < A always
+        if (j + 1 < A) m = fmaxf(m, v.y);
+        if (j + 2 < A) m = fmaxf(m, v.z);
+        if (j + 3 < A) m = fmaxf(m, v.w);
+        vis = vis || n.x > 0 || n.y > 0 || n.z > 0 || n.w > 0;   // padding holds 0
+      }
+      float V;
+      int N;
+      if (__any(vis)) {
+        // V_curr = L_eta Psi (Eq. 3) before the update.
+        m = wave_maxf(m);
+        float se = 0.0f;
+#pragma unroll 4
+        for (int q = lane; q < nq; q += 64) {
+          const float4 v = p4[q];
+          const int j = 4 * q;
+          se = se + expf(eta * (v.x - m));
+          if (j + 1 < A) se = se + expf(eta * (v.y - m));
+          if (j + 2 < A) se = se + expf(eta * (v.z - m));
+          if (j + 3 < A) se = se + expf(eta * (v.w - m));
         }
-        m2 = fmaxf(m2, p);
+        const float vc = m + logf(wave_sumf(se)) / eta;
+        // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5).
+        int nsum = 0, nn = 0;
+        float m2 = -INFINITY;
+        float4* pw4 = reinterpret_cast<float4*>(rec_psi(T, b));
+        for (int q = lane; q < nq; q += 64) {
+          float4 v = p4[q];
+          const int4 n4v = n4[q];
+          float pv[4] = {v.x, v.y, v.z, v.w};
+          const int nv[4] = {n4v.x, n4v.y, n4v.z, n4v.w};
+          bool changed = false;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = 4 * q + i;
+            if (j >= A) break;
+            if (nv[i] > 0) {
+              const float c = from_fix(crow[j], inv);
+              const unsigned long long wf = wrow[j];
+              const float w = from_fix(wf, inv);
+              if (wf) wrow[j] = 0ull;
+              const float fn = (float)nv[i];
+              pv[i] = (pv[i] - vc) + (c / fn + gamma * (w / fn));
+              nsum += nv[i];
+              ++nn;
+              changed = true;
+            }
+            m2 = fmaxf(m2, pv[i]);
+          }
+          if (changed) pw4[q] = make_float4(pv[0], pv[1], pv[2], pv[3]);
+        }
+        m2 = wave_maxf(m2);
+        float se2 = 0.0f;
+#pragma unroll 4
+        for (int q = lane; q < nq; q += 64) {
+          const float4 v = p4[q];
+          const int j = 4 * q;
+          se2 = se2 + expf(eta * (v.x - m2));
+          if (j + 1 < A) se2 = se2 + expf(eta * (v.y - m2));
+          if (j + 2 < A) se2 = se2 + expf(eta * (v.z - m2));
+          if (j + 3 < A) se2 = se2 + expf(eta * (v.w - m2));
+        }
+        V = m2 + logf(wave_sumf(se2)) / eta;
+        N = (int)wave_sum((unsigned long long)nsum);
+        nodes += wave_sum((unsigned long long)nn);
+        if (lane == 0) {
+          mt->V = V;
+          mt->Nb = N;
+        }
+      } else {
+        V = mt->V;
+        N = mt->Nb;
       }
-      m2 = wave_maxf(m2);
-      float se2 = 0.0f;
-      for (int j = lane; j < A; j += 64) se2 = se2 + expf(eta * (prow[j] - m2));
-      V = m2 + logf(wave_sumf(se2)) / eta;
-      N = (int)wave_sum((unsigned long long)nsum);
-      nodes += wave_sum((unsigned long long)nn);
       if (lane == 0) {
-        mt->V = V;
-        mt->Nb = N;
-      }
-    } else {
-      V = mt->V;
-      N = mt->Nb;
-    }
-    if (lane == 0) {
-      ++beliefs;
-      const unsigned long long parent = parent_link(T, mt);
-      if (parent != kEmptyKey && N > 0) {
-        const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
-        if (f) {
-          const int pr = (int)(parent >> kActBits), a = (int)(parent & kActMask);
-          if (pr == 0) atomicAdd(root_stripe(T, 2, a), f);
-          else atomicAdd(&rec_w(T, pr)[a], f);
+        ++beliefs;
+        const unsigned long long parent = parent_link(T, mt);
+        if (parent != kEmptyKey && N > 0) {
+          const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
+          if (f) {
+            const int pr = (int)(parent >> kActBits), a = (int)(parent & kActMask);
+            if (pr == 0) atomicAdd(root_stripe(T, 2, a), f);
+            else atomicAdd(&rec_w(T, pr)[a], f);
+          }
         }
       }
     }
@@ -856,6 +910,44 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
     if (nodes) atomicAdd(&bank[blk % kStripes], nodes);
     if (beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
   }
+}
+
+// Maximum over the block of one double per thread (every thread calls).
+__device__ double block_max64(double v, double* red) {
+  v = wave_max64(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Sum over a = 0 .. A-1 of exp(eta (x_a - m)) taken in action order (the
+// serial definition's rounding), the terms evaluated by the whole block and
+// added by thread 0 from LDS; with cdf set, the running sums are stored.
+// Every thread calls; all get the sum.
+__device__ double block_ordered_sum(const double* x, int A, double m, double eta, double* cdf,
+                                    double* buf, double* bc) {
+  double run = 0.0;
+  for (int base = 0; base < A; base += kBlock) {
+    const int j = base + (int)threadIdx.x;
+    if (j < A) buf[threadIdx.x] = exp(eta * (x[j] - m));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int n = min(kBlock, A - base);
+      for (int i = 0; i < n; ++i) {
+        run = run + buf[i];
+        if (cdf) cdf[base + i] = run;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *bc = run;
+  __syncthreads();
+  const double r = *bc;
+  __syncthreads();
+  return r;
 }
 
 // The root row (|A| > kMaxA) in double precision, by one block: the striped
@@ -871,50 +963,19 @@ __device__ void dev_backup_root_wide(const PlanView& P, int k, double* buf) {
   __shared__ unsigned long long cnt[2];
   if (wv == 0) root_gate(P, k, lane);
   if (threadIdx.x == 0) { cnt[0] = 0ull; cnt[1] = 0ull; }
-  // Fold the stripes: N and C into the root record, W into its W column.
-  for (int j = wv; j < A; j += kBlock / 64) {
-    unsigned long long* w = &T.root_acc[((size_t)2 * T.ra + j) * kStripes + lane];
-    const unsigned long long n = wave_sum(T.root_acc[((size_t)0 * T.ra + j) * kStripes + lane]);
-    const unsigned long long c = wave_sum(T.root_acc[((size_t)1 * T.ra + j) * kStripes + lane]);
-    const unsigned long long wv2 = wave_sum(*w);
-    *w = 0ull;
-    if (lane == 0) {
-      rec_n(T, 0)[j] = (int)n;
-      rec_c(T, 0)[j] = c;
-      rec_w(T, 0)[j] = wv2;
-    }
+  // The root's sums (one stripe for long rows), one action per thread: N and
+  // C into the root record, W into its W column.
+  for (int j = threadIdx.x; j < A; j += kBlock) {
+    unsigned long long* pw = &T.root_acc[((size_t)2 * T.ra + j) * kStripes];
+    rec_n(T, 0)[j] = (int)T.root_acc[((size_t)0 * T.ra + j) * kStripes];
+    rec_c(T, 0)[j] = T.root_acc[((size_t)1 * T.ra + j) * kStripes];
+    rec_w(T, 0)[j] = *pw;
+    *pw = 0ull;
   }
   __syncthreads();
-  // Block maximum of a double over the threads' values.
-  auto block_max = [&](double v) {
-    v = wave_max64(v);
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    double r = red[0];
-    for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
-    __syncthreads();
-    return r;
-  };
-  // Sum of exp(eta (x_j - m)) over the actions in action order; with cdf set,
-  // the running sums are stored as the root's draw table.
+  auto block_max = [&](double v) { return block_max64(v, red); };
   auto ordered = [&](const double* x, double m, double* cdf) {
-    double run = 0.0;
-    for (int base = 0; base < A; base += kBlock) {
-      const int j = base + (int)threadIdx.x;
-      if (j < A) buf[threadIdx.x] = exp(eta * (x[j] - m));
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const int n = min(kBlock, A - base);
-        for (int i = 0; i < n; ++i) {
-          run = run + buf[i];
-          if (cdf) cdf[base + i] = run;
-        }
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) bc = run;
-    __syncthreads();
-    return bc;
+    return block_ordered_sum(x, A, m, eta, cdf, buf, &bc);
   };
   double* psi = T.psi_root;
   double mloc = -INFINITY;
@@ -1047,14 +1108,26 @@ __device__ void dev_select(const PlanView& P) {
   const unsigned long long steps = wave_sum(T.stats[lane]);
   const unsigned long long nodes = wave_sum(bank[lane]);
   const unsigned long long nb = 1 + wave_sum(bank[kStripes + lane]);
-  if (lane != 0) return;
   const int A = P.m.nA;
-  int best = 0;
-  for (int j = 1; j < A; ++j)
-    if (T.psi_root[j] > T.psi_root[best]) best = j;
   double* out = P.out;
+  // Argmax with the lowest index on ties: each lane scans actions lane,
+  // lane + 64, ..., then the wavefront keeps the larger value, or the lower
+  // index of equal values.
+  int best = lane < A ? lane : 0;
+  double bv = T.psi_root[best];
+  for (int j = lane; j < A; j += 64) {
+    const double v = T.psi_root[j];
+    out[1 + j] = v;
+    if (v > bv) { bv = v; best = j; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int ob = __shfl_xor(best, off, 64);
+    if (ov > bv || (ov == bv && ob < best)) { bv = ov; best = ob; }
+  }
+  if (lane != 0) return;
   out[0] = (double)best;
-  for (int j = 0; j < A; ++j) out[1 + j] = T.psi_root[j];
   out[A + 1] = T.v_root[0];
   out[A + 2] = (double)steps;
   out[A + 3] = (double)nb;
@@ -1225,6 +1298,194 @@ __device__ void dev_pf_resample(const PlanView& P, int t, int blk) {
 // ---------------------------------------------------------------------------
 // Single-plan kernels (one launch per phase).
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Forward search for long action rows (|A| > kMaxA, tabular models): one
+// wavefront per episode.  The episode's state is the same in every lane; the
+// lanes share the softmax draw (each owns actions j = lane, lane + 64, ...),
+// the record initialisation, and lane 0 does the episode's table probe and
+// its scalar writes.  The draw scales the single-precision weights by 2^24 to
+// integers, so the running sums are exact whatever the order of addition:
+// an inclusive wave scan per chunk of 64 actions finds the first running sum
+// above t = ((x0 >> 8) * total) >> 24.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long long_row_weight(float v, float m, float eta) {
+  return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
+}
+
+__device__ int draw_long_row(const float* __restrict__ row, int A, float eta, uint32_t x0,
+                             int lane) {
+  // Lane l holds the quads 4l, 4l + 256, ... (the row is padded to a
+  // multiple of 4; padding is masked off).
+  const float4* r4 = reinterpret_cast<const float4*>(row);
+  const int nq = (A + 3) / 4;
+  float m = -INFINITY;
+#pragma unroll 4
+  for (int q = lane; q < nq; q += 64) {
+    const float4 v = r4[q];
+    const int j = 4 * q;
+    m = fmaxf(m, v.x);
+    if (j + 1 < A) m = fmaxf(m, v.y);
+    if (j + 2 < A) m = fmaxf(m, v.z);
+    if (j + 3 < A) m = fmaxf(m, v.w);
+  }
+  m = wave_maxf(m);
+  auto quad = [&](int q, unsigned long long (&w)[4]) {
+    const float4 v = r4[q];
+    const int j = 4 * q;
+    w[0] = long_row_weight(v.x, m, eta);
+    w[1] = j + 1 < A ? long_row_weight(v.y, m, eta) : 0ull;
+    w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0ull;
+    w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0ull;
+  };
+  unsigned long long tot = 0;
+#pragma unroll 4
+  for (int q = lane; q < nq; q += 64) {
+    unsigned long long w[4];
+    quad(q, w);
+    tot += w[0] + w[1] + w[2] + w[3];
+  }
+  tot = wave_sum(tot);
+  const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
+  // Chunks of 256 actions: the lanes' quad sums are scanned across the
+  // wavefront; the first lane whose running sum passes t holds the action.
+  unsigned long long base = 0;
+  for (int c = 0; c < nq; c += 64) {
+    const int q = c + lane;
+    unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
+    if (q < nq) quad(q, w);
+    const unsigned long long incl = wave_incl_scan(w[0] + w[1] + w[2] + w[3]) + base;
+    const unsigned long long hit = __ballot(q < nq && t < incl);
+    if (hit) {
+      const int src = __ffsll((long long)hit) - 1;
+      int pick = 3;                             // within the lane's quad
+      unsigned long long run = incl - (w[0] + w[1] + w[2] + w[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        run += w[i];
+        if (t < run) { pick = i; break; }
+      }
+      return 4 * (c + src) + __shfl(pick, src, 64);
+    }
+    base = __shfl(incl, 63, 64);
+  }
+  return A - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int D) {
+  __shared__ unsigned long long red[kBlock / 64];
+  if (budget_spent(P)) return;
+  const TreeView& T = P.t;
+  const int lane = threadIdx.x & 63;
+  const int ep = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);   // uniform per wave
+  const bool ep_ok = ep < P.n_p;
+  const int t0 = T.step_base[k - 1];
+  const int A = P.m.nA;
+  const size_t n_p = (size_t)P.n_p;
+  const unsigned long long stamp = (unsigned long long)(k - 1) << kStampShift;
+  int s = 0, sid = 0, rid = 0;
+  bool fresh = false, alive = false;
+  if (ep_ok) {
+    const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
+    const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
+    s = ((const int*)P.e.belief)[idx];
+    if ((unsigned)s >= (unsigned)P.m.nS) {
+      if (lane == 0) atomicOr((unsigned int*)&T.counters[1], 1u);
+      s = 0;
+    }
+    alive = true;
+  }
+  unsigned long long g = 0;
+  for (int d = 0; d < D; ++d) {
+    unsigned long long tk = kEmptyKey, link = kEmptyKey;
+    float r = 0.0f;
+    bool won = false, direct = false;
+    int obs = 0, a = 0;
+    uint32_t h = 0;
+    const int rid_b = rid;
+    if (alive) {
+      const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
+      if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
+      else a = draw_long_row(fresh ? T.psi0 : rec_psi(T, rid), A, P.eta, w.x, lane);
+      int sn;
+      tabular_step(P.m, s, a, w, sn, obs, r);
+      s = sn;
+      ++g;
+      direct = d >= kDirectLevel && rid >= 0;
+      if (!direct)
+        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
+                      : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
+                      : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      // AppendBeliefs by lane 0; the outcome goes to the whole wavefront.
+      int fr = 0, id = -1, wn = 0;
+      if (lane == 0) {
+        bool b_won = false, b_fr = false;
+        h = probe(T, belief_key(sid, a, obs, P.m.obs_bits), stamp, b_won, b_fr, id);
+        wn = b_won;
+        fr = b_fr;
+      }
+      h = __shfl(h, 0, 64);
+      wn = __shfl(wn, 0, 64);
+      fr = __shfl(fr, 0, 64);
+      id = __shfl(id, 0, 64);
+      won = wn != 0;
+      if (h == ~0u) {
+        if (lane == 0) atomicOr((unsigned int*)&T.counters[1], 2u);
+        alive = false;
+      } else {
+        sid = (int)h + 1;
+        fresh = fr != 0;
+        rid = won ? 1 + (t0 + d) * P.n_p + ep : id;
+      }
+    }
+    if (ep_ok) {
+      if (lane == 0) {
+        if (direct) {
+          atomicAdd(&rec_n(T, rid_b)[a], 1);
+          const unsigned long long fx = to_fix(r, P.fix_scale);
+          if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
+        }
+        const int t = t0 + d;
+        T.tr_key[(size_t)d * n_p + ep] = tk;
+        T.tr_val[(size_t)d * n_p + ep] = r;
+        T.list[(size_t)t * n_p + ep] = won ? sid : 0;
+        if (won) T.h_slot[h].id = rid;
+      }
+      if (won) {                                // the new record, by the wavefront
+        uint4* q = reinterpret_cast<uint4*>(rec_at(T, rid));
+        const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
+        const int ra = T.ra, nq = ra / 4, meta_q = 6 * ra / 4;
+        for (int i = lane; i < meta_q; i += 64)
+          q[i] = i < nq ? p0[i] : make_uint4(0u, 0u, 0u, 0u);
+        if (lane == 0) {
+          q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);
+          q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));
+        }
+      }
+    }
+  }
+  if (ep_ok && lane == 0) {
+    unsigned long long tk = kEmptyKey;
+    float hv = 0.0f;
+    if (alive) {
+      if (P.m.H) hv = P.m.H[s];
+      if (D >= kDirectLevel && rid >= 0) {
+        RecMeta* mt = rec_meta(T, rid);
+        atomicAdd(&mt->leaf_cnt, 1);
+        const unsigned long long fx = to_fix(hv, P.fix_scale);
+        if (fx) atomicAdd(&mt->leaf_h, fx);
+      } else {
+        tk = rid >= 0 ? ((unsigned long long)(uint32_t)rid | kTraceRec)
+                      : (unsigned long long)(uint32_t)sid;
+      }
+    }
+    T.tr_key[(size_t)D * n_p + ep] = tk;
+    T.tr_val[(size_t)D * n_p + ep] = hv;
+  }
+  g = block_sum(lane == 0 ? g : 0ull, red);
+  if (threadIdx.x == 0 && g) atomicAdd(&T.stats[blockIdx.x % kStripes], g);
+}
+
 __global__ void k_env(PlanView P, int t) { dev_env(P, t); }
 __global__ __launch_bounds__(kBlock) void k_pf_weight(PlanView P, int t) {
   dev_pf_weight(P, t, blockIdx.x);
@@ -1237,7 +1498,8 @@ __global__ __launch_bounds__(kBlock) void k_pf_resample(PlanView P, int t) {
   dev_pf_resample(P, t, blockIdx.x);
 }
 __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
-  dev_setup(P, blockIdx.x, gridDim.x);
+  __shared__ SetupSmem ss;
+  dev_setup(P, blockIdx.x, gridDim.x, &ss);
 }
 // The phases of one iteration return at once when a time budget ran out
 // at the end of an earlier iteration.
@@ -1300,7 +1562,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
   const PlanView& P = views[it.inst];
   const int Apad = P.m.Apad;
   switch (it.kind) {
-    case kPhaseSetup: dev_setup(P, blk, it.nblk); break;
+    case kPhaseSetup: dev_setup(P, blk, it.nblk, nullptr); break;   // |A| <= 16
     case kPhaseForward:
       if (Apad <= 4) {
         dev_forward<4>(P, it.a0, it.a1, blk, sm.wave);
@@ -1359,7 +1621,9 @@ hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, P, k, D);
   else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
   else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
-  else hipLaunchKernelGGL(k_forward<kMaxAWide>, g, b, 0, s, P, k, D);
+  else
+    hipLaunchKernelGGL(k_forward_wide, dim3((P.n_p + kBlock / 64 - 1) / (kBlock / 64)), b, 0, s,
+                       P, k, D);
   return hipGetLastError();
 }
 hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
