@@ -442,7 +442,10 @@ def main():
     ws = V.Workspace(pom, prm, K, depth)
     belt = V.belief_tensor(inst, bel)
     n_bel = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
-    stream = torch.cuda.current_stream()
+    # Plans run on a stream of their own, where the library replays the
+    # launch sequence captured for the plan's shape.
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
 
     # Warm-up plans; the last ones bracket every kernel kind with events to
     # find the kind that dominates device time.
@@ -459,12 +462,11 @@ def main():
         warm_total = sum(v[0] for v in warm.values())
         warm_share = {k: v[0] / warm_total for k, v in warm.items() if v[1]}
 
-    # Timed region: only the dominant kind is bracketed (each bracket costs
-    # device time).
-    if dom is not None:
-        V.profile_enable(ws, [])
-        V.profile_reset(ws)
-        V.profile_enable(ws, [dom])
+    # Timed region: plain plans, each a replay of the launch sequence the
+    # library captured for this shape.
+    V.profile_enable(ws, [])
+    V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=999), ws=ws,
+           stream=stream)                       # captures the sequence
     torch.cuda.synchronize()
     lat = []
     dev_ms = []
@@ -479,8 +481,19 @@ def main():
         steps += r.particle_steps
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = V.profile_read(ws) if dom is not None else None
-    V.profile_enable(ws, [])
+    # The dominant kind's launches, bracketed with HIP events on the plan
+    # stream, over the same plans again: a captured sequence carries no
+    # brackets, so these plans launch kernel by kernel.
+    prof = None
+    if dom is not None:
+        V.profile_reset(ws)
+        V.profile_enable(ws, [dom])
+        for i in range(args.steps):
+            r = V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
+                       ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        prof = V.profile_read(ws)
+        V.profile_enable(ws, [])
 
     out = {
         "metric": "particle-steps/s at fixed budget; p50/p99 plan latency, batched vs plain",
@@ -528,7 +541,9 @@ def main():
                         avg_launch_us=ms * 1e3 / launches,
                         bytes_per_launch=model[dom] * args.steps / launches,
                         bytes_per_plan=model[dom],
-                        byte_model="algorithmic bytes of the last timed plan's tree")
+                        byte_model="algorithmic bytes of the last timed plan's tree",
+                        timing="HIP events around each launch of the kernel on the plan "
+                               "stream, over the timed plans run again launch by launch")
             tr = MEASURED_TRAFFIC.get(dom, {}).get(args.workload)
             if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
                 roof["traffic"] = tr
