@@ -923,31 +923,36 @@ __device__ double block_max64(double v, double* red) {
   return r;
 }
 
-// Sum over a = 0 .. A-1 of exp(eta (x_a - m)) taken in action order (the
-// serial definition's rounding), the terms evaluated by the whole block and
-// added by thread 0 from LDS; with cdf set, the running sums are stored.
-// Every thread calls; all get the sum.
+// Running sums over a = 0 .. A-1 of exp(eta (x_a - m)), by a block scan over
+// chunks of kBlock actions (wavefront scans, then the wavefront totals); with
+// cdf set they are stored.  Every thread calls; all get the total.  The scan
+// adds in a tree order rather than the serial one: the sums differ from the
+// serial definition's by a few units in the last place (about 1e-15
+// relative), far below the margin at which a root draw counts as a near tie.
 __device__ double block_ordered_sum(const double* x, int A, double m, double eta, double* cdf,
                                     double* buf, double* bc) {
-  double run = 0.0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double carry = 0.0;
   for (int base = 0; base < A; base += kBlock) {
     const int j = base + (int)threadIdx.x;
-    if (j < A) buf[threadIdx.x] = exp(eta * (x[j] - m));
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int n = min(kBlock, A - base);
-      for (int i = 0; i < n; ++i) {
-        run = run + buf[i];
-        if (cdf) cdf[base + i] = run;
-      }
+    double v = j < A ? exp(eta * (x[j] - m)) : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double o = __shfl_up(v, off, 64);
+      if (lane >= off) v += o;
     }
+    if (lane == 63) buf[wv] = v;
+    __syncthreads();
+    double before = carry;
+    for (int w = 0; w < wv; ++w) before += buf[w];
+    double total = carry;
+    for (int w = 0; w < kBlock / 64; ++w) total += buf[w];
+    if (cdf && j < A) cdf[j] = before + v;
+    carry = total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *bc = run;
-  __syncthreads();
-  const double r = *bc;
-  __syncthreads();
-  return r;
+  (void)bc;
+  return carry;
 }
 
 // The root row (|A| > kMaxA) in double precision, by one block: the striped
@@ -1312,12 +1317,17 @@ __device__ __forceinline__ unsigned long long long_row_weight(float v, float m, 
   return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
 }
 
+constexpr int kLongChunks = kMaxAWide / 256;   // chunks of 256 actions in a row
+
 __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, uint32_t x0,
                              int lane) {
   // Lane l holds the quads 4l, 4l + 256, ... (the row is padded to a
-  // multiple of 4; padding is masked off).
+  // multiple of 4; padding is masked off).  Each weight is evaluated once:
+  // the lane keeps its quad sum of every chunk, the wavefront scans those
+  // once the total is known, and only the chosen quad is evaluated again.
   const float4* r4 = reinterpret_cast<const float4*>(row);
   const int nq = (A + 3) / 4;
+  const int nc = (nq + 63) / 64;
   float m = -INFINITY;
 #pragma unroll 4
   for (int q = lane; q < nq; q += 64) {
@@ -1337,34 +1347,40 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
     w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0ull;
     w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0ull;
   };
+  unsigned long long qs[kLongChunks];
   unsigned long long tot = 0;
-#pragma unroll 4
-  for (int q = lane; q < nq; q += 64) {
-    unsigned long long w[4];
-    quad(q, w);
-    tot += w[0] + w[1] + w[2] + w[3];
+#pragma unroll
+  for (int c = 0; c < kLongChunks; ++c) {
+    qs[c] = 0ull;
+    const int q = c * 64 + lane;
+    if (c < nc && q < nq) {
+      unsigned long long w[4];
+      quad(q, w);
+      qs[c] = w[0] + w[1] + w[2] + w[3];
+    }
+    tot += qs[c];
   }
   tot = wave_sum(tot);
   const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
-  // Chunks of 256 actions: the lanes' quad sums are scanned across the
-  // wavefront; the first lane whose running sum passes t holds the action.
   unsigned long long base = 0;
-  for (int c = 0; c < nq; c += 64) {
-    const int q = c + lane;
-    unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
-    if (q < nq) quad(q, w);
-    const unsigned long long incl = wave_incl_scan(w[0] + w[1] + w[2] + w[3]) + base;
-    const unsigned long long hit = __ballot(q < nq && t < incl);
+#pragma unroll
+  for (int c = 0; c < kLongChunks; ++c) {
+    if (c >= nc) break;
+    const unsigned long long incl = wave_incl_scan(qs[c]) + base;
+    const unsigned long long hit = __ballot(c * 64 + lane < nq && t < incl);
     if (hit) {
       const int src = __ffsll((long long)hit) - 1;
-      int pick = 3;                             // within the lane's quad
-      unsigned long long run = incl - (w[0] + w[1] + w[2] + w[3]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        run += w[i];
-        if (t < run) { pick = i; break; }
+      int pick = 3;                             // within the chosen quad
+      if (lane == src) {
+        unsigned long long w[4];
+        quad(c * 64 + lane, w);
+        unsigned long long run = incl - qs[c];
+        for (int u = 0; u < 4; ++u) {
+          run += w[u];
+          if (t < run) { pick = u; break; }
+        }
       }
-      return 4 * (c + src) + __shfl(pick, src, 64);
+      return 4 * (c * 64 + src) + __shfl(pick, src, 64);
     }
     base = __shfl(incl, 63, 64);
   }
