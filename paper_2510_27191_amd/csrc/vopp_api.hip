@@ -508,14 +508,16 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
 
 // Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
 int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
-                int cap, int extra) {
+                int cap, int extra, bool wide) {
   (void)p;
-  // One chunk of kBlock record positions per block, over the level steps
-  // that hold depth dep.
+  // One chunk of record positions per block over the level steps that hold
+  // depth dep: kBlock positions (a thread each), or 64 for the sweeps of long
+  // rows (a wavefront per 16 positions), which may use four times the blocks.
   long long iters = extra;
   for (int kk = 1; kk <= k; ++kk) iters += D[kk] >= dep ? 1 : 0;
-  const long long g = ((long long)n_p + kBlock - 1) / kBlock * iters;
-  return (int)std::max(1ll, std::min(g, (long long)cap));
+  const int per = wide ? 64 : kBlock;
+  const long long g = ((long long)n_p + per - 1) / per * iters;
+  return (int)std::max(1ll, std::min(g, (long long)cap * (wide ? 4 : 1)));
 }
 
 // Enqueue one planning step on stream s.  Returns the level-step count.
@@ -620,7 +622,8 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
       VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
                  launch_backup_level(P, Pd, dep, k,
                                      backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap,
-                                                 P.carry ? w->carry.count[dep - 1] : 0), s));
+                                                 P.carry ? w->carry.count[dep - 1] : 0,
+                                                 P.m.Apad > kMaxA), s));
     VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, Pd, k, s));
   }
   VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, Pd, s));
