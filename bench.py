@@ -81,9 +81,9 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it
 # was taken on (hash below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "3a284110f4e13986",
-    "backup_level": {"nav2d": 70.88e6, "sparse4096": 250.87e6},
-    "forward": {"nav2d": 135.63e6, "sparse4096": 729.79e6},
+    "sources_sha256_16": "3906a7b9a838ef42",
+    "backup_level": {"nav2d": 54.41e6, "sparse4096": 224.43e6},
+    "forward": {"nav2d": 135.71e6, "sparse4096": 700.30e6},
 }
 
 
