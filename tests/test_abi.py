@@ -50,7 +50,7 @@ def _tab_desc(inst, **over):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nA=0), dict(nA=65), dict(nO=0), dict(gamma=1.0), dict(gamma=0.0),
+    dict(nA=0), dict(nA=4097), dict(nO=0), dict(gamma=1.0), dict(gamma=0.0),
     dict(col="oob"), dict(tprob="unnormalised"), dict(zprob="negative"),
 ])
 def test_invalid_models_rejected_before_device_work(bad):
