@@ -118,3 +118,43 @@ def test_wide_limits(V):
         V.Pomdp.from_instance(I.mars_like(5, 8, 4097, nO=9))
     with pytest.raises(V.VoppError):             # 2049+ actions leave 14 observation bits
         V.Pomdp.from_instance(I.mars_like(5, 1, 2049, nO=16385, n_succ=1))
+
+
+def test_wide_anytime_and_reroot(V, orc):
+    # The anytime plan and a kept subtree with 625 actions: the anytime plan
+    # with ample time equals the plain plan, and a plan from the kept subtree
+    # matches the oracle's plan from its own kept subtree.
+    from tests.test_oracle_reroot import branches
+    inst = I.mars_like(3, 128, 625, reward_scale=0.05)
+    bel = I.tabular_belief(inst)
+    found = None
+    for sd in range(1, 30):
+        o1 = orc.plan(inst, bel, 1024, 3, 3, seed=sd, tau=TAU_WIDE, keep=True)
+        if o1.near_ties:
+            continue
+        a, ob = branches(o1, 625, 1)[0]
+        h, _ = orc.reroot(o1, a, ob, 625)
+        o2 = orc.plan(inst, bel, 1024, 2, 3, seed=sd + 100, tau=TAU_WIDE, start=h)
+        if o2.near_ties == 0:
+            found = (sd, o1, a, ob, o2)
+            break
+    assert found, "no seed without near ties"
+    sd, o1, a, ob, o2 = found
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    p1, p2 = V.params(1024, seed=sd), V.params(1024, seed=sd + 100)
+    A_ws, B_ws, C_ws = V.Workspace(pom, p1, 3, 3), V.Workspace(pom, p2, 2, 3), \
+        V.Workspace(pom, p1, 3, 3)
+    try:
+        r1 = V.plan(pom, b, b.numel(), 3, 3, p1, ws=A_ws)
+        assert_parity(r1, V.tree_dump(A_ws, 625, r1.n_beliefs, r1.n_actions), o1, 625)
+        q, k = V.plan_anytime(pom, b, b.numel(), 3, 3, 1e6, p1, ws=C_ws)
+        assert k == 3 and np.array_equal(q.values, r1.values)
+        assert V.reroot(pom, A_ws, a, ob, p2, 2, 3, B_ws) == len(
+            orc.reroot(o1, a, ob, 625)[1]["b_parent"])
+        r2 = V.plan(pom, b, b.numel(), 2, 3, p2, ws=B_ws)
+        assert_parity(r2, V.tree_dump(B_ws, 625, r2.n_beliefs, r2.n_actions), o2, 625)
+    finally:
+        for w in (A_ws, B_ws, C_ws):
+            w.close()
+        pom.close()
