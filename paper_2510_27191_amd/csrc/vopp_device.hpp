@@ -2,8 +2,8 @@
 // of the VOPP planning step on CDNA4 (gfx950).
 //
 // Everything here runs in registers: the Philox4x32-10 counter-based
-// generator, the tabular and navigation generative models G (Sec. III-B),
-// the softmax action draw of Eq. (6) and the log-sum-exp value of Eq. (3).
+// generator, the tabular and navigation generative models G (Sec. III-B)
+// and the softmax action draw of Eq. (6).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,7 +38,6 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 // level step), so no episode allocates anything; the inserting episode stores
 // the record index in the slot for later kernels.
 constexpr int kObsBits = 20;                // observation field for |A| <= 64
-constexpr int kMaxObs = 1 << kObsBits;
 constexpr int kKeyLowBits = 26;             // action and observation fields together
 constexpr int kMaxAWide = 1 << 12;          // largest action set (rows in memory)
 constexpr int kStampShift = 56;
@@ -493,42 +492,11 @@ __device__ __forceinline__ void load_row(const float* __restrict__ row, int A, f
   }
 }
 
-// The same draw from a preference row in memory (padded to a multiple of 4).
-template <int AM>
-__device__ __forceinline__ int draw_action32(const float* __restrict__ row, int A,
-                                             float eta, uint32_t x0) {
-  float v[AM];
-#pragma unroll
-  for (int j = 0; j < AM; j += 4) {
-    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (j < A) q = *reinterpret_cast<const float4*>(row + j);
-    v[j] = q.x; v[j + 1] = q.y; v[j + 2] = q.z; v[j + 3] = q.w;
-  }
-  return draw_row32<AM>(v, A, eta, x0);
-}
-
-// The same draw in double precision (root row).
-__device__ __forceinline__ int draw_action64(const double* __restrict__ row, int A,
-                                             double eta, uint32_t x0) {
-  double m = row[0];
-  for (int j = 1; j < A; ++j) m = fmax(m, row[j]);
-  double total = 0.0;
-  for (int j = 0; j < A; ++j) total = total + exp(eta * (row[j] - m));
-  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
-  const double t = u * total;
-  double run = 0.0;
-  for (int j = 0; j < A; ++j) {
-    run = run + exp(eta * (row[j] - m));
-    if (t < run) return j;
-  }
-  return A - 1;
-}
-
-// The running sums P_j of the weights exp(eta (psi_j - max)) of the root row,
-// accumulated in the same order as draw_action64 does, so that a draw from
-// them (draw_cdf64) is the same draw.  The root row changes once per
-// iteration, so every episode's root draw reads these instead of evaluating
-// 2|A| double exponentials.
+// The running sums P_j of the weights exp(eta (psi_j - max)) of the root row
+// (double precision), accumulated in action order; the root draw
+// (draw_cdf64: t = u * P_last, the first j with t < P_j) reads them.  The
+// root row changes once per iteration, so every episode's root draw reads
+// these instead of evaluating 2|A| double exponentials.
 __device__ __forceinline__ void root_cdf(const double* __restrict__ row, int A, double eta,
                                          double* __restrict__ cdf) {
   double m = row[0];
@@ -560,23 +528,6 @@ __device__ __forceinline__ int draw_cdf64(const double* __restrict__ cdf, int A,
   for (int j = 0; j < A; ++j)
     if (t < cdf[j]) return j;
   return A - 1;
-}
-
-// L_eta x = max + (1/eta) ln sum_j exp(eta (x_j - max))   (Eq. 3).
-__device__ __forceinline__ float lse32(const float* x, int A, float eta) {
-  float m = x[0];
-  for (int j = 1; j < A; ++j) m = fmaxf(m, x[j]);
-  float s = 0.0f;
-  for (int j = 0; j < A; ++j) s = s + expf(eta * (x[j] - m));
-  return m + logf(s) / eta;
-}
-
-__device__ __forceinline__ double lse64(const double* x, int A, double eta) {
-  double m = x[0];
-  for (int j = 1; j < A; ++j) m = fmax(m, x[j]);
-  double s = 0.0;
-  for (int j = 0; j < A; ++j) s = s + exp(eta * (x[j] - m));
-  return m + log(s) / eta;
 }
 
 // Fixed-point conversion of a value for the order-independent sums.
