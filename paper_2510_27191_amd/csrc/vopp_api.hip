@@ -331,7 +331,6 @@ size_t bytes_for(const WsSizes& z) {
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
   add(64); add(5 * kStripes * 8); add(32); add((z.K + 1) * 4);
   add(2 * (kMaxDepth + 1) * 4);                      // kept-subtree steps by depth
-  add(sizeof(PlanView));                             // the kernels' view of a plan
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
   add(out_len(z) * 8);                               // result record
@@ -373,7 +372,6 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.stats = c.take<unsigned long long>(5 * kStripes);
   t.gate = c.take<unsigned long long>(4);
   w->carry_rng_dev = c.take<int>(2 * (kMaxDepth + 1));
-  w->view_dev = c.take<PlanView>(1);
   t.carry_rng = w->carry_rng_dev;
   int* step_base = c.take<int>(z.K + 1);
   t.step_base = step_base;
@@ -384,8 +382,6 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   e = hipHostMalloc((void**)&w->out_host, out_len(z) * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 8) * sizeof(int), hipHostMallocDefault);
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&w->view_host, sizeof(PlanView), hipHostMallocDefault);
   if (e == hipSuccess) {
     // step_host[kMaxBudget + 1 ..] holds the 64-bit constant 1 (dirty flag).
     const unsigned long long one = 1ull;
@@ -453,8 +449,6 @@ extern "C" void vopp_workspace_free(vopp_workspace* w) {
   if (w->out_host) (void)hipHostFree(w->out_host);
   if (w->step_host) (void)hipHostFree(w->step_host);
   if (w->gate_host) (void)hipHostFree(w->gate_host);
-  if (w->view_host) (void)hipHostFree(w->view_host);
-  if (w->graph) (void)hipGraphExecDestroy(w->graph);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
   if (w->ev1) (void)hipEventDestroy(w->ev1);
   for (hipEvent_t ev : w->prof_events) (void)hipEventDestroy(ev);
@@ -560,39 +554,9 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   }
   hipError_t e = hipMemcpyAsync(w->step_base_dev, w->step_host, (K + 1) * sizeof(int),
                                 hipMemcpyHostToDevice, s);
-  // The kernels read the plan's view from the workspace.
-  *w->view_host = P;
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(w->view_dev, w->view_host, sizeof(PlanView), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "upload schedule");
-  const PlanView* Pd = w->view_dev;
+  const WsSizes& z = w->z;
   w->prof_used = 0;
-  if (w->hash_dirty) {
-    // A plan did not finish: the table state is unknown, clear it fully.
-    e = hipMemcpyAsync(&w->tree.counters[3], &w->step_host[kMaxBudget + 1],
-                       sizeof(unsigned long long), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "plan set-up");
-  }
-  // A plain plan replays the launch sequence captured for its shape: the
-  // arguments are the workspace's view and the shape, so one graph serves
-  // every plan of that shape.  Anytime plans, plans from a kept subtree and
-  // plans with profiling brackets launch one by one.
-  const long long key[vopp_workspace::kGraphKey] = {P.n_p, K, P.depth, P.schedule, P.m.Apad,
-                                    0, 0};
-  const bool use_graph = !P.timed && !P.carry && !w->prof_on && s != nullptr;
-  if (use_graph && w->graph && std::equal(key, key + vopp_workspace::kGraphKey, w->graph_key)) {
-    e = hipGraphLaunch(w->graph, s);
-    if (e != hipSuccess) return hip_fail(e, "plan graph launch");
-    w->hash_dirty = true;   // until the plan has finished
-    *n_steps_out = steps;
-    return VOPP_OK;
-  }
-  if (use_graph) {
-    if (w->graph) (void)hipGraphExecDestroy(w->graph);
-    w->graph = nullptr;
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "plan capture");
-  }
   // Each launch below is bracketed by prof_begin/prof_end (no-ops unless
   // profiling is enabled on the workspace).
 #define VOPP_TIMED(kind, call)                              \
@@ -601,46 +565,43 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     if (e == hipSuccess) e = (call);                        \
     if (e == hipSuccess) e = prof_end(w, s);                \
   } while (0)
-  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_setup(P, Pd, s));
+  if (w->hash_dirty) {
+    // A plan did not finish: the table state is unknown, clear it fully.
+    e = hipMemcpyAsync(&w->tree.counters[3], &w->step_host[kMaxBudget + 1],
+                       sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+  }
+  VOPP_TIMED(VOPP_KERNEL_SETUP, launch_setup(P, s));
+  if (e != hipSuccess) return hip_fail(e, "plan set-up launch");
+  w->hash_dirty = true;   // until the plan has finished
   int t = c0;
-  for (int k = 1; k <= K && e == hipSuccess; ++k) {
+  for (int k = 1; k <= K; ++k) {
     if (P.timed && k > 1) {
       bool go = true;
       const vopp_status gs = timed_gate(w, s, k, &go);
       if (gs != VOPP_OK) return gs;
       if (!go) break;
     }
-    VOPP_TIMED(VOPP_KERNEL_FORWARD, launch_forward(P, Pd, k, D[k], s));
+    VOPP_TIMED(VOPP_KERNEL_FORWARD, launch_forward(P, k, D[k], s));
     VOPP_TIMED(VOPP_KERNEL_ACCUMULATE,
-               launch_accum(P, Pd, D[k], accum_blocks(P, D[k], kAccumCap), s));
+               launch_accum(P, D[k], accum_blocks(P, D[k], kAccumCap), s));
+    if (e != hipSuccess) return hip_fail(e, "forward-search launch");
     t += D[k];
     VOPP_TIMED(VOPP_KERNEL_BACKUP_LEAF,
-               launch_backup_leaf(P, Pd, D[k], k,
+               launch_backup_leaf(P, D[k], k,
                                   backup_grid(p, P.n_p, D, D[k], k, kBackupCap,
                                               P.carry ? w->carry.count[D[k]] : 0), s));
     for (int dep = D[k]; dep >= 2; --dep)
       VOPP_TIMED(VOPP_KERNEL_BACKUP_LEVEL,
-                 launch_backup_level(P, Pd, dep, k,
+                 launch_backup_level(P, dep, k,
                                      backup_grid(p, P.n_p, D, dep - 1, k, kBackupCap,
                                                  P.carry ? w->carry.count[dep - 1] : 0,
                                                  P.m.Apad > kMaxA), s));
-    VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, Pd, k, s));
+    VOPP_TIMED(VOPP_KERNEL_BACKUP_ROOT, launch_backup_root(P, k, s));
+    if (e != hipSuccess) return hip_fail(e, "backup launch");
   }
-  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, Pd, s));
+  VOPP_TIMED(VOPP_KERNEL_SELECT, launch_select(P, s));
 #undef VOPP_TIMED
-  if (use_graph) {
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(s, &g);
-    if (e == hipSuccess) e = ec;
-    if (e == hipSuccess) e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    if (e == hipSuccess) {
-      std::copy(key, key + vopp_workspace::kGraphKey, w->graph_key);
-      e = hipGraphLaunch(w->graph, s);
-    }
-  }
-  if (e != hipSuccess) return hip_fail(e, "plan launch");
-  w->hash_dirty = true;   // until the plan has finished
+  if (e != hipSuccess) return hip_fail(e, "select launch");
   *n_steps_out = t;
   return VOPP_OK;
 }

@@ -59,13 +59,6 @@ struct vopp_workspace {
   } carry;
   bool carried = false;
   int* carry_rng_dev = nullptr;   // [kMaxDepth + 1][2] device copy of first, count
-  // The plan's view as the planning kernels read it (device) and its pinned
-  // staging copy; the launch sequence captured for the last plan shape.
-  vopp::PlanView* view_dev = nullptr;
-  vopp::PlanView* view_host = nullptr;
-  hipGraphExec_t graph = nullptr;
-  static constexpr int kGraphKey = 7;   // n_p, K, depth, schedule, Apad (2 spare)
-  long long graph_key[kGraphKey] = {0};
   // Anytime plans: pinned coherent host word written by the device at the end
   // of each iteration (iterations run | stop << 32), and its device address.
   unsigned long long* gate_host = nullptr;

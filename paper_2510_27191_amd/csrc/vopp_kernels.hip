@@ -1387,8 +1387,7 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
   return A - 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_forward_wide(const PlanView* __restrict__ Pp, int k, int D) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
   if (budget_spent(P)) return;
   const TreeView& T = P.t;
@@ -1514,57 +1513,49 @@ __global__ __launch_bounds__(kBlock) void k_pf_scan(PlanView P) {
 __global__ __launch_bounds__(kBlock) void k_pf_resample(PlanView P, int t) {
   dev_pf_resample(P, t, blockIdx.x);
 }
-__global__ __launch_bounds__(kBlock) void k_setup(const PlanView* __restrict__ Pp) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
   __shared__ SetupSmem ss;
   dev_setup(P, blockIdx.x, gridDim.x, &ss);
 }
 // The phases of one iteration return at once when a time budget ran out
 // at the end of an earlier iteration.
 template <int AM>
-__global__ __launch_bounds__(kBlock) void k_forward(const PlanView* __restrict__ Pp, int k, int D) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
   if (budget_spent(P)) return;
   dev_forward<AM>(P, k, D, blockIdx.x, red);
 }
-__global__ __launch_bounds__(kBlock) void k_accum(const PlanView* __restrict__ Pp, int D) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D) {
   __shared__ Smem sm;
   if (budget_spent(P)) return;
   dev_accum(P, D, blockIdx.x, gridDim.x, sm);
 }
-__global__ __launch_bounds__(kBlock) void k_backup_leaf(const PlanView* __restrict__ Pp, int dep, int k) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_backup_leaf(PlanView P, int dep, int k) {
   __shared__ Smem sm;
   if (budget_spent(P)) return;
   dev_backup_leaf(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
 template <int AM>
-__global__ __launch_bounds__(kBlock) void k_backup_level(const PlanView* __restrict__ Pp, int dep, int k) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_backup_level(PlanView P, int dep, int k) {
   __shared__ Smem sm;
   if (budget_spent(P)) return;
   dev_backup_level<AM>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
-__global__ void k_backup_root(const PlanView* __restrict__ Pp, int k) {
-  const PlanView& P = *Pp;
+__global__ void k_backup_root(PlanView P, int k) {
   if (budget_spent(P)) return;
   dev_backup_root(P, k);
 }
-__global__ __launch_bounds__(kBlock) void k_backup_level_wide(const PlanView* __restrict__ Pp, int dep, int k) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_backup_level_wide(PlanView P, int dep, int k) {
   __shared__ Smem sm;
   if (budget_spent(P)) return;
   dev_backup_level_wide(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
-__global__ __launch_bounds__(kBlock) void k_backup_root_wide(const PlanView* __restrict__ Pp, int k) {
-  const PlanView& P = *Pp;
+__global__ __launch_bounds__(kBlock) void k_backup_root_wide(PlanView P, int k) {
   __shared__ double buf[kBlock];
   if (budget_spent(P)) return;
   dev_backup_root_wide(P, k, buf);
 }
-__global__ void k_select(const PlanView* __restrict__ Pp) { dev_select(*Pp); }
+__global__ void k_select(PlanView P) { dev_select(P); }
 
 // ---------------------------------------------------------------------------
 // Batched kernel: block -> (instance, phase) through the item list, sorted by
@@ -1634,54 +1625,49 @@ int accum_blocks(const PlanView& P, int D, int cap) {
   return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 
-hipError_t launch_setup(const PlanView& P, const PlanView* Pd, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, Pd);
+hipError_t launch_setup(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
-hipError_t launch_forward(const PlanView& P, const PlanView* Pd, int k, int D, hipStream_t s) {
+hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   const dim3 g(forward_blocks(P)), b(kBlock);
   const int Ap = P.m.Apad;
-  if (Ap <= 4) hipLaunchKernelGGL(k_forward<4>, g, b, 0, s, Pd, k, D);
-  else if (Ap <= 8) hipLaunchKernelGGL(k_forward<8>, g, b, 0, s, Pd, k, D);
-  else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, Pd, k, D);
-  else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, Pd, k, D);
-  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, Pd, k, D);
+  if (Ap <= 4) hipLaunchKernelGGL(k_forward<4>, g, b, 0, s, P, k, D);
+  else if (Ap <= 8) hipLaunchKernelGGL(k_forward<8>, g, b, 0, s, P, k, D);
+  else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, P, k, D);
+  else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
+  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
   else
     hipLaunchKernelGGL(k_forward_wide, dim3((P.n_p + kBlock / 64 - 1) / (kBlock / 64)), b, 0, s,
-                       Pd, k, D);
+                       P, k, D);
   return hipGetLastError();
 }
-hipError_t launch_accum(const PlanView& P, const PlanView* Pd, int D, int grid, hipStream_t s) {
-  (void)P;
-  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, Pd, D);
+hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D);
   return hipGetLastError();
 }
-hipError_t launch_backup_leaf(const PlanView& P, const PlanView* Pd, int dep, int k, int grid,
-                              hipStream_t s) {
-  (void)P;
-  hipLaunchKernelGGL(k_backup_leaf, dim3(grid), dim3(kBlock), 0, s, Pd, dep, k);
+hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_backup_leaf, dim3(grid), dim3(kBlock), 0, s, P, dep, k);
   return hipGetLastError();
 }
-hipError_t launch_backup_level(const PlanView& P, const PlanView* Pd, int dep, int k, int grid,
-                               hipStream_t s) {
+hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
   const dim3 g(grid), b(kBlock);
   const int Ap = P.m.Apad;
-  if (Ap <= 4) hipLaunchKernelGGL(k_backup_level<4>, g, b, 0, s, Pd, dep, k);
-  else if (Ap <= 8) hipLaunchKernelGGL(k_backup_level<8>, g, b, 0, s, Pd, dep, k);
-  else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, Pd, dep, k);
-  else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, Pd, dep, k);
-  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, Pd, dep, k);
-  else hipLaunchKernelGGL(k_backup_level_wide, g, b, 0, s, Pd, dep, k);
+  if (Ap <= 4) hipLaunchKernelGGL(k_backup_level<4>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 8) hipLaunchKernelGGL(k_backup_level<8>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, P, dep, k);
+  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
+  else hipLaunchKernelGGL(k_backup_level_wide, g, b, 0, s, P, dep, k);
   return hipGetLastError();
 }
-hipError_t launch_backup_root(const PlanView& P, const PlanView* Pd, int k, hipStream_t s) {
-  if (P.m.Apad > kMaxA) hipLaunchKernelGGL(k_backup_root_wide, dim3(1), dim3(kBlock), 0, s, Pd, k);
-  else hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, Pd, k);
+hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
+  if (P.m.Apad > kMaxA) hipLaunchKernelGGL(k_backup_root_wide, dim3(1), dim3(kBlock), 0, s, P, k);
+  else hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
   return hipGetLastError();
 }
-hipError_t launch_select(const PlanView& P, const PlanView* Pd, hipStream_t s) {
-  (void)P;
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, Pd);
+hipError_t launch_select(const PlanView& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {

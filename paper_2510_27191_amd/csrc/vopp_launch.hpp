@@ -10,18 +10,13 @@ int setup_blocks(const PlanView& P);
 int forward_blocks(const PlanView& P);
 // Blocks of a sweep over the trace of an iteration with D levels (at most cap).
 int accum_blocks(const PlanView& P, int D, int cap);
-// The planning kernels read the plan's view from device memory (Pd, a copy
-// of P), so that a captured launch sequence stays valid for new parameters;
-// P (host) gives the launch shapes.
-hipError_t launch_setup(const PlanView& P, const PlanView* Pd, hipStream_t s);
-hipError_t launch_forward(const PlanView& P, const PlanView* Pd, int k, int D, hipStream_t s);
-hipError_t launch_accum(const PlanView& P, const PlanView* Pd, int D, int grid, hipStream_t s);
-hipError_t launch_backup_leaf(const PlanView& P, const PlanView* Pd, int dep, int k, int grid,
-                              hipStream_t s);
-hipError_t launch_backup_level(const PlanView& P, const PlanView* Pd, int dep, int k, int grid,
-                               hipStream_t s);
-hipError_t launch_backup_root(const PlanView& P, const PlanView* Pd, int k, hipStream_t s);
-hipError_t launch_select(const PlanView& P, const PlanView* Pd, hipStream_t s);
+hipError_t launch_setup(const PlanView& P, hipStream_t s);
+hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s);
+hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s);
+hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s);
+hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s);
+hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s);
+hipError_t launch_select(const PlanView& P, hipStream_t s);
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s);
 // SIR update of P.f: weight, scan, resample (three launches).
 hipError_t launch_pf(const PlanView& P, int t, hipStream_t s);
