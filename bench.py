@@ -47,7 +47,9 @@ HBM_PEAK_GBS = 8000.0
 #     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16.
 #   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
 #     written, push 16.
-# With more than 64 actions the level sweep reads only what it uses: per
+# With more than 64 actions a new record is written without its W column
+# (16*ra + 32) and W[a] is cleared at the action node's first visit (8), and
+# the level sweep reads only what it uses: per
 # belief the N and preference rows 8*ra, the row written 4*ra, the tail 32
 # read and V, N_b 8 written, the push 16, and per action node C and W read
 # 16 and W cleared 8 (nodes_per_belief on average).
@@ -65,8 +67,11 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
     level = sum(beliefs_at(k, dep - 1) for k in range(1, K + 1)
                 for dep in range(2, D[k - 1] + 1))
     leaf = sum(beliefs_at(k, D[k - 1]) for k in range(1, K + 1))
+    # Long rows write a new record without its W column (16*ra + 32) and
+    # clear W[a] at the first visit of each action node (8).
+    rec_new = rec if nA <= 64 else 16 * ra + 32 + 8 * nodes_per_belief
     return {
-        "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec)
+        "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec_new)
                    + K * n_p * (24 + 12),
         "accumulate": items * 8,
         "backup_level": (level * (rec + 4 * ra + 8 + 8 * nA + 16) if nA <= 64 else
