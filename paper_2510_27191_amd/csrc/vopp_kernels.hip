@@ -507,9 +507,13 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
           if (G.b[j]) atomicAdd(root_stripe(T, 1, a), G.b[j]);
         } else {
           const int a = (int)((k2 >> 1) & kActMask);
-          // Long rows clear W[a] at the first visit of (b, a) (not at creation).
-          if (atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]) == 0 && T.ra > kMaxA)
-            rec_w(T, rid)[a] = 0ull;
+          // Long rows clear W[a] at the first visit of (b, a) (not at
+          // creation); short rows add without waiting for the old count.
+          if (T.ra > kMaxA) {
+            if (atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]) == 0) rec_w(T, rid)[a] = 0ull;
+          } else {
+            atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
+          }
           if (G.b[j]) atomicAdd(&rec_c(T, rid)[a], G.b[j]);
         }
       }
@@ -539,15 +543,19 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, R
   __syncthreads();
 }
 
-// The parent link of a record, resolved to (record << kActBits) | a (written back).
-__device__ __forceinline__ unsigned long long parent_link(const TreeView& T, RecMeta* mt) {
-  unsigned long long par = mt->parent;
+// The parent link of a record, resolved to (record << kActBits) | a (written
+// back); par is the stored link, read by the caller.
+__device__ __forceinline__ unsigned long long resolve_link(const TreeView& T, RecMeta* mt,
+                                                          unsigned long long par) {
   if (par != kEmptyKey && (par & kLinkSlot)) {
     const int psid = (int)((par & ~kLinkSlot) >> kActBits);
     par = ((unsigned long long)(uint32_t)record_of(T, psid) << kActBits) | (par & kActMask);
     mt->parent = par;
   }
   return par;
+}
+__device__ __forceinline__ unsigned long long parent_link(const TreeView& T, RecMeta* mt) {
+  return resolve_link(T, mt, mt->parent);
 }
 
 // Record of position ep of level step t, or -1 if no belief was inserted there.
@@ -609,10 +617,15 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
     unsigned long long parent = kEmptyKey;
     const int b = ep < P.n_p ? record_at(P, R.step[r], ep) : -1;
     if (b > 0) {
+      // Every field is read before the first store: on CDNA a wait for a
+      // load also waits for the stores issued before it.
       RecMeta* mt = rec_meta(P.t, b);
       const int c = mt->leaf_cnt;
+      const unsigned long long hs = mt->leaf_h;
+      const float V0 = mt->V;
+      const int N0 = mt->Nb;
+      const unsigned long long par = mt->parent;
       if (c > 0) {
-        const unsigned long long hs = mt->leaf_h;
         V = from_fix(hs, P.fix_inv) / (float)c;
         N = c;
         mt->V = V;
@@ -620,10 +633,10 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
         mt->leaf_cnt = 0;
         if (hs) mt->leaf_h = 0ull;
       } else {
-        V = mt->V;
-        N = mt->Nb;
+        V = V0;
+        N = N0;
       }
-      parent = parent_link(P.t, mt);
+      parent = resolve_link(P.t, mt, par);
       ++beliefs;
     }
     push_values(P, sm.agg, dep < kPushDirectDepth, parent, V, N);
@@ -657,24 +670,47 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
       unsigned long long* crow = rec_c(P.t, b);
       unsigned long long* wrow = rec_w(P.t, b);
       RecMeta* mt = rec_meta(P.t, b);
+      // The whole record (its link and stored value included) is read in one
+      // batch, before its first store: a wait for a load also waits for the
+      // stores issued before it.  (Reading
+      // Psi, C and W only after the counts show a visited action costs one
+      // more round trip, which measured slower than the extra bytes.)
+      const float V0 = mt->V;
+      const int N0 = mt->Nb;
+      const unsigned long long par = mt->parent;
       int n[AM];
-      bool any = false;
+      float psi[AM];
+      unsigned long long cf[AM], wf[AM];
 #pragma unroll
       for (int j = 0; j < AM; j += 4) {
         int4 c = make_int4(0, 0, 0, 0);
-        if (j < A) c = *reinterpret_cast<const int4*>(nrow + j);
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        ulonglong2 c0 = make_ulonglong2(0ull, 0ull), c1 = c0, w0 = c0, w1 = c0;
+        if (j < A) {
+          c = *reinterpret_cast<const int4*>(nrow + j);
+          q = *reinterpret_cast<const float4*>(prow + j);
+          c0 = reinterpret_cast<const ulonglong2*>(crow + j)[0];
+          c1 = reinterpret_cast<const ulonglong2*>(crow + j)[1];
+          w0 = reinterpret_cast<const ulonglong2*>(wrow + j)[0];
+          w1 = reinterpret_cast<const ulonglong2*>(wrow + j)[1];
+        }
         n[j] = c.x; n[j + 1] = c.y; n[j + 2] = c.z; n[j + 3] = c.w;
+        psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
+        cf[j] = c0.x; cf[j + 1] = c0.y; cf[j + 2] = c1.x; cf[j + 3] = c1.y;
+        wf[j] = w0.x; wf[j + 1] = w0.y; wf[j + 2] = w1.x; wf[j + 3] = w1.y;
       }
+      // Held here: the compiler would otherwise sink these loads into the
+      // branch below, behind the wait for the counts.
+#pragma unroll
+      for (int j = 0; j < AM; ++j) {
+        asm volatile("" : "+v"(psi[j]));
+        asm volatile("" : "+v"(cf[j]));
+        asm volatile("" : "+v"(wf[j]));
+      }
+      bool any = false;
 #pragma unroll
       for (int j = 0; j < AM; ++j) any = any || (j < A && n[j] > 0);
       if (any) {
-        float psi[AM];
-#pragma unroll
-        for (int j = 0; j < AM; j += 4) {
-          float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          if (j < A) q = *reinterpret_cast<const float4*>(prow + j);
-          psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
-        }
         // V_curr = L_eta Psi (Eq. 3) before the update.
         float m = psi[0];
 #pragma unroll
@@ -690,10 +726,8 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
 #pragma unroll
         for (int j = 0; j < AM; ++j) {
           if (j < A && n[j] > 0) {
-            const float c = from_fix(crow[j], inv);
-            const unsigned long long wf = wrow[j];
-            const float w = from_fix(wf, inv);
-            if (wf) wrow[j] = 0ull;
+            const float c = from_fix(cf[j], inv);
+            const float w = from_fix(wf[j], inv);
             const float fn = (float)n[j];
             const float q = c / fn + gamma * (w / fn);
             psi[j] = (psi[j] - vc) + q;
@@ -716,13 +750,17 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
           if (j < A)
             *reinterpret_cast<float4*>(prow + j) =
                 make_float4(psi[j], psi[j + 1], psi[j + 2], psi[j + 3]);
+        // W is rebuilt by the children's pushes of the next sweep.
+#pragma unroll
+        for (int j = 0; j < AM; ++j)
+          if (j < A && n[j] > 0 && wf[j]) wrow[j] = 0ull;
         mt->V = V;
         mt->Nb = N;
       } else {
-        V = mt->V;
-        N = mt->Nb;
+        V = V0;
+        N = N0;
       }
-      parent = parent_link(P.t, mt);
+      parent = resolve_link(P.t, mt, par);
 #pragma unroll
       for (int j = 0; j < AM; ++j) nodes += (j < A && n[j] > 0) ? 1ull : 0ull;
       ++beliefs;
