@@ -817,14 +817,19 @@ __device__ __forceinline__ float wave_sumf(float v) {
   return v;
 }
 
-// Level sweep of the internal beliefs of depth dep-1 >= 1 (Alg. 3, Eq. 3, 5).
-// Lane l reads the quads 4l, 4l + 256, ... of each row (16-byte loads, the
-// padding past |A| masked off), so a row of 3025 actions takes 12 loads per
-// lane per pass.
+// Level sweep of the internal beliefs of depth dep-1 >= 1 (Alg. 3, Eq. 3, 5)
+// over long rows, one wavefront per belief.  Lane l holds the quads l,
+// l + 64, ... of the row (QPL of them; the padding past |A| and quads past the
+// row masked off) in registers for the whole update, so a belief costs one
+// batch of loads for Psi, N and its metadata, one batch of C and W loads per
+// four quads of the lane, and the stores at the end: no load waits behind a
+// store of the same belief.
 constexpr int kWideChunk = 16;              // positions a wavefront scans at once
 
+template <int QPL>
 __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk, int nblk,
                                       Smem& sm) {
+  static_assert(QPL % 4 == 0 && 4 * QPL <= 64, "quads per lane");
   Ranges& R = sm.ranges;
   load_ranges(P, dep - 1, k, R);
   const TreeView& T = P.t;
@@ -844,96 +849,111 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
     const int bl = (lane < kWideChunk && ep < P.n_p) ? record_at(P, R.step[r], ep) : -1;
     unsigned long long todo = __ballot(bl > 0);
     while (todo) {
-      const int b = __shfl(bl, __ffsll((long long)todo) - 1, 64);
+      // b is uniform: addresses are a scalar base plus 32-bit lane offsets.
+      const int b = __builtin_amdgcn_readfirstlane(__shfl(bl, __ffsll((long long)todo) - 1, 64));
       todo &= todo - 1;
       const float4* p4 = reinterpret_cast<const float4*>(rec_psi(T, b));
       const int4* n4 = reinterpret_cast<const int4*>(rec_n(T, b));
-      const unsigned long long* crow = rec_c(T, b);
+      const char* rec = reinterpret_cast<const char*>(rec_at(T, b));
       unsigned long long* wrow = rec_w(T, b);
       RecMeta* mt = rec_meta(T, b);
-      bool vis = false;
-      float m = -INFINITY;
-#pragma unroll 4
-      for (int q = lane; q < nq; q += 64) {
-        const float4 v = p4[q];
-        const int4 n = n4[q];
-        const int j = 4 * q;
-        m = fmaxf(m, v.x);                      // j < A always
-        if (j + 1 < A) m = fmaxf(m, v.y);
-        if (j + 2 < A) m = fmaxf(m, v.z);
-        if (j + 3 < A) m = fmaxf(m, v.w);
-        vis = vis || n.x > 0 || n.y > 0 || n.z > 0 || n.w > 0;   // padding holds 0
+      float pf[4 * QPL];
+      int nf[4 * QPL];
+#pragma unroll
+      for (int i = 0; i < QPL; ++i) {
+        const int q = lane + 64 * i;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int4 n = make_int4(0, 0, 0, 0);
+        if (q < nq) {
+          v = p4[q];
+          n = n4[q];
+        }
+        pf[4 * i] = v.x; pf[4 * i + 1] = v.y; pf[4 * i + 2] = v.z; pf[4 * i + 3] = v.w;
+        nf[4 * i] = n.x; nf[4 * i + 1] = n.y; nf[4 * i + 2] = n.z; nf[4 * i + 3] = n.w;
       }
+      // Read after the row: these uniform values are moved to scalar
+      // registers at once, which waits for them.
+      const float V0 = mt->V;
+      const int N0 = mt->Nb;
+      const unsigned long long par = mt->parent;
+      bool vis = false;                         // padding and absent quads hold 0
+#pragma unroll
+      for (int i = 0; i < 4 * QPL; ++i) vis = vis || nf[i] > 0;
       float V;
       int N;
-      if (__any(vis)) {
+      const bool upd = __any(vis);
+      unsigned long long clear = 0ull;          // W entries to clear (bit per action)
+      uint32_t changed = 0u;                    // quads of Psi to store
+      if (upd) {
         // V_curr = L_eta Psi (Eq. 3) before the update.
+        float m = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4 * QPL; ++i)
+          if (4 * (lane + 64 * (i >> 2)) + (i & 3) < A) m = fmaxf(m, pf[i]);
         m = wave_maxf(m);
         float se = 0.0f;
-#pragma unroll 4
-        for (int q = lane; q < nq; q += 64) {
-          const float4 v = p4[q];
-          const int j = 4 * q;
-          se = se + expf(eta * (v.x - m));
-          if (j + 1 < A) se = se + expf(eta * (v.y - m));
-          if (j + 2 < A) se = se + expf(eta * (v.z - m));
-          if (j + 3 < A) se = se + expf(eta * (v.w - m));
-        }
-        const float vc = m + logf(wave_sumf(se)) / eta;
-        // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5).
-        int nsum = 0, nn = 0;
-        float m2 = -INFINITY;
-        float4* pw4 = reinterpret_cast<float4*>(rec_psi(T, b));
-        for (int q = lane; q < nq; q += 64) {
-          float4 v = p4[q];
-          const int4 n4v = n4[q];
-          float pv[4] = {v.x, v.y, v.z, v.w};
-          const int nv[4] = {n4v.x, n4v.y, n4v.z, n4v.w};
-          bool changed = false;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int j = 4 * q + i;
-            if (j >= A) break;
-            if (nv[i] > 0) {
-              const float c = from_fix(crow[j], inv);
-              const unsigned long long wf = wrow[j];
-              const float w = from_fix(wf, inv);
-              if (wf) wrow[j] = 0ull;
-              const float fn = (float)nv[i];
-              pv[i] = (pv[i] - vc) + (c / fn + gamma * (w / fn));
-              nsum += nv[i];
-              ++nn;
-              changed = true;
-            }
-            m2 = fmaxf(m2, pv[i]);
+        for (int i = 0; i < 4 * QPL; ++i)
+          if (4 * (lane + 64 * (i >> 2)) + (i & 3) < A) se = se + expf(eta * (pf[i] - m));
+        const float vc = m + logf(wave_sumf(se)) / eta;
+        // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5), for visited
+        // actions.  An unvisited action reads the metadata line instead (read
+        // above), so the loads issue without branches.
+        const uint32_t c_off = 8u * (uint32_t)T.ra, w_off = 16u * (uint32_t)T.ra;
+        const uint32_t spare = 24u * (uint32_t)T.ra + (uint32_t)offsetof(RecMeta, parent);
+        int nsum = 0, nn = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < QPL; i0 += 4) {
+          unsigned long long cf[16], wf[16];
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            const int i = 4 * i0 + t;
+            const int j = 4 * (lane + 64 * (i >> 2)) + (i & 3);
+            const bool v = nf[i] > 0;
+            const uint32_t jb = 8u * (uint32_t)j;
+            cf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? c_off + jb : spare));
+            wf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? w_off + jb : spare));
           }
-          if (changed) pw4[q] = make_float4(pv[0], pv[1], pv[2], pv[3]);
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            asm volatile("" : "+v"(cf[t]));
+            asm volatile("" : "+v"(wf[t]));
+          }
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            const int i = 4 * i0 + t;
+            if (nf[i] > 0) {
+              const float cv = from_fix(cf[t], inv);
+              const float w = from_fix(wf[t], inv);
+              const float fn = (float)nf[i];
+              pf[i] = (pf[i] - vc) + (cv / fn + gamma * (w / fn));
+              nsum += nf[i];
+              ++nn;
+              changed |= 1u << (i >> 2);
+              if (wf[t]) clear |= 1ull << i;
+            }
+          }
         }
+        // V = L_eta Psi after the update; N_b = sum_a N(b, a).
+        float m2 = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4 * QPL; ++i)
+          if (4 * (lane + 64 * (i >> 2)) + (i & 3) < A) m2 = fmaxf(m2, pf[i]);
         m2 = wave_maxf(m2);
         float se2 = 0.0f;
-#pragma unroll 4
-        for (int q = lane; q < nq; q += 64) {
-          const float4 v = p4[q];
-          const int j = 4 * q;
-          se2 = se2 + expf(eta * (v.x - m2));
-          if (j + 1 < A) se2 = se2 + expf(eta * (v.y - m2));
-          if (j + 2 < A) se2 = se2 + expf(eta * (v.z - m2));
-          if (j + 3 < A) se2 = se2 + expf(eta * (v.w - m2));
-        }
+#pragma unroll
+        for (int i = 0; i < 4 * QPL; ++i)
+          if (4 * (lane + 64 * (i >> 2)) + (i & 3) < A) se2 = se2 + expf(eta * (pf[i] - m2));
         V = m2 + logf(wave_sumf(se2)) / eta;
         N = (int)wave_sum((unsigned long long)nsum);
         nodes += wave_sum((unsigned long long)nn);
-        if (lane == 0) {
-          mt->V = V;
-          mt->Nb = N;
-        }
       } else {
-        V = mt->V;
-        N = mt->Nb;
+        V = V0;
+        N = N0;
       }
       if (lane == 0) {
         ++beliefs;
-        const unsigned long long parent = parent_link(T, mt);
+        const unsigned long long parent = resolve_link(T, mt, par);
         if (parent != kEmptyKey && N > 0) {
           const unsigned long long f = to_fix(V * (float)N, P.fix_scale);
           if (f) {
@@ -942,6 +962,19 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
             else atomicAdd(&rec_w(T, pr)[a], f);
           }
         }
+      }
+      // The record's stores come last, so that nothing above waits for them.
+      if (upd) {
+        mt->V = V;                              // the same value in every lane
+        mt->Nb = N;
+        float4* pw4 = reinterpret_cast<float4*>(rec_psi(T, b));
+#pragma unroll
+        for (int i = 0; i < QPL; ++i)
+          if ((changed >> i) & 1u)
+            pw4[lane + 64 * i] = make_float4(pf[4 * i], pf[4 * i + 1], pf[4 * i + 2], pf[4 * i + 3]);
+#pragma unroll
+        for (int i = 0; i < 4 * QPL; ++i)
+          if ((clear >> i) & 1ull) wrow[4 * (lane + 64 * (i >> 2)) + (i & 3)] = 0ull;
       }
     }
   }
@@ -952,7 +985,6 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
   }
 }
 
-// Maximum over the block of one double per thread (every thread calls).
 __device__ double block_max64(double v, double* red) {
   v = wave_max64(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -1587,10 +1619,11 @@ __global__ void k_backup_root(PlanView P, int k) {
   if (budget_spent(P)) return;
   dev_backup_root(P, k);
 }
+template <int QPL>
 __global__ __launch_bounds__(kBlock) void k_backup_level_wide(PlanView P, int dep, int k) {
   __shared__ Smem sm;
   if (budget_spent(P)) return;
-  dev_backup_level_wide(P, dep, k, blockIdx.x, gridDim.x, sm);
+  dev_backup_level_wide<QPL>(P, dep, k, blockIdx.x, gridDim.x, sm);
 }
 __global__ __launch_bounds__(kBlock) void k_backup_root_wide(PlanView P, int k) {
   __shared__ double buf[kBlock];
@@ -1700,7 +1733,14 @@ hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipS
   else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, P, dep, k);
   else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, P, dep, k);
   else if (Ap <= kMaxA) hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
-  else hipLaunchKernelGGL(k_backup_level_wide, g, b, 0, s, P, dep, k);
+  else {
+    // Quads of the row per lane: rows of up to 1024, 2048, 3072, 4096 actions.
+    const int qpl = (Ap / 4 + 63) / 64;
+    if (qpl <= 4) hipLaunchKernelGGL(k_backup_level_wide<4>, g, b, 0, s, P, dep, k);
+    else if (qpl <= 8) hipLaunchKernelGGL(k_backup_level_wide<8>, g, b, 0, s, P, dep, k);
+    else if (qpl <= 12) hipLaunchKernelGGL(k_backup_level_wide<12>, g, b, 0, s, P, dep, k);
+    else hipLaunchKernelGGL(k_backup_level_wide<16>, g, b, 0, s, P, dep, k);
+  }
   return hipGetLastError();
 }
 hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
