@@ -67,15 +67,22 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
     level = sum(beliefs_at(k, dep - 1) for k in range(1, K + 1)
                 for dep in range(2, D[k - 1] + 1))
     leaf = sum(beliefs_at(k, D[k - 1]) for k in range(1, K + 1))
-    # Long rows write a new record without its W column (16*ra + 32) and
-    # clear W[a] at the first visit of each action node (8).
-    rec_new = rec if nA <= 64 else 16 * ra + 32 + 8 * nodes_per_belief
+    # Long rows write a new record's Psi, metadata and bitmap (4*ra + 32 +
+    # 16 per 128 actions); the first visit of an action node sets its bit and
+    # clears N, C and W (4 + 20), in the claim pass before the accumulate.
+    wide = nA > 64
+    nbq = (ra + 127) // 128
+    rec_new = rec if not wide else 4 * ra + 32 + 16 * nbq
+    claim = (sum(d * n_p for d in D) * 8 + new_b * nodes_per_belief * 24) if wide else 0
+    # A long-row sweep reads Psi, the bitmap and the metadata, then N, C and W
+    # of the visited actions (20), writes their Psi quads (16) and clears W
+    # (8), and pushes one word.
     return {
         "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec_new)
                    + K * n_p * (24 + 12),
-        "accumulate": items * 8,
-        "backup_level": (level * (rec + 4 * ra + 8 + 8 * nA + 16) if nA <= 64 else
-                         level * (12 * ra + 32 + 8 + 16 + 24 * nodes_per_belief)),
+        "accumulate": items * 8 + claim,
+        "backup_level": (level * (rec + 4 * ra + 8 + 8 * nA + 16) if not wide else
+                         level * (4 * ra + ra // 8 + 32 + 8 + nodes_per_belief * (20 + 16 + 8))),
         "backup_leaf": leaf * (32 + 24 + 16),
     }
 

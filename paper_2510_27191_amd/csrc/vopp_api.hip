@@ -857,6 +857,14 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
     return reinterpret_cast<const long long*>(rec.data() + i * rs + 8 * ra);
   };
   auto prow = [&](size_t i) { return reinterpret_cast<const float*>(rec.data() + i * rs); };
+  // Long rows: a record other than the root's holds (b, a) only where bit a
+  // of its bitmap is set.
+  auto valid = [&](size_t i, int a) {
+    if (ra <= kMaxA || ids[i] == 0) return true;
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(rec.data() + i * rs + 24 * ra +
+                                                             sizeof(RecMeta));
+    return ((bits[a >> 5] >> (a & 31)) & 1u) != 0;
+  };
   // Canonical order: by depth, then (parent's position, action, observation);
   // action nodes by (parent's position, action).  It depends only on the
   // tree, not on the order in which episodes inserted it.
@@ -889,6 +897,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   for (size_t q = 0; q < nb; ++q) {
     const size_t i = order[q];
     for (int a = 0; a < A; ++a) {
+      if (!valid(i, a)) continue;
       const int n = nrow(i)[a];
       if (n <= 0) continue;
       act_of[q * A + a] = (int)na;

@@ -150,8 +150,16 @@ struct TreeView {
   float* tr_val;                 // reward (levels) or heuristic (leaf)
 };
 
+// Long rows (ra > kMaxA) add a bitmap of ra bits after RecMeta, padded to
+// 16-byte quads: in a record other than the root's, N[a], C[a] and W[a] hold
+// values only where bit a is set (set, and the three cleared, by the first
+// visit of (b, a)); elsewhere they are whatever the memory held.  A new record
+// then writes Psi, its metadata and the bitmap, not three quarters of its
+// bytes.  The root's columns are all valid.
+__host__ __device__ inline int rec_bitmap_quads(int ra) { return (ra + 127) / 128; }
 __host__ __device__ inline int rec_bytes(int ra) {
-  const int used = 24 * ra + (int)sizeof(RecMeta);
+  int used = 24 * ra + (int)sizeof(RecMeta);
+  if (ra > kMaxA) used += 16 * rec_bitmap_quads(ra);
   return (used + 127) / 128 * 128;
 }
 __device__ __forceinline__ unsigned char* rec_at(const TreeView& t, int id) {
@@ -171,6 +179,9 @@ __device__ __forceinline__ unsigned long long* rec_w(const TreeView& t, int id) 
 }
 __device__ __forceinline__ RecMeta* rec_meta(const TreeView& t, int id) {
   return reinterpret_cast<RecMeta*>(rec_at(t, id) + 24 * t.ra);
+}
+__device__ __forceinline__ uint32_t* rec_bits(const TreeView& t, int id) {
+  return reinterpret_cast<uint32_t*>(rec_at(t, id) + 24 * t.ra + sizeof(RecMeta));
 }
 
 // The root belief of a plan.

@@ -246,9 +246,12 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
       T.psi0[a] = (float)v;
       if (a < P.m.nA) {
         if (P.carry) {                          // the kept root's own row and sums
+          // (long rows: the kept belief's columns count where its bitmap says)
+          const bool v = T.ra <= kMaxA || ((rec_bits(T, 0)[a >> 5] >> (a & 31)) & 1u);
           T.psi_root[a] = (double)rec_psi(T, 0)[a];
-          T.root_acc[((size_t)0 * T.ra + a) * kStripes] = (unsigned long long)(long long)rec_n(T, 0)[a];
-          T.root_acc[((size_t)1 * T.ra + a) * kStripes] = rec_c(T, 0)[a];
+          T.root_acc[((size_t)0 * T.ra + a) * kStripes] =
+              v ? (unsigned long long)(long long)rec_n(T, 0)[a] : 0ull;
+          T.root_acc[((size_t)1 * T.ra + a) * kStripes] = v ? rec_c(T, 0)[a] : 0ull;
         } else {
           rec_psi(T, 0)[a] = (float)v;
           T.psi_root[a] = v;
@@ -460,6 +463,31 @@ __device__ __forceinline__ unsigned long long* root_stripe(const TreeView& T, in
   return T.root_acc + ((size_t)q * T.ra + a) * kStripes + stripe;
 }
 
+// Long rows: the first visit of each (b, a) in the trace of an iteration
+// sets bit a of b's bitmap and clears N[a], C[a] and W[a] (the root keeps its
+// sums elsewhere).  It runs before the accumulate pass adds the visits.
+__global__ __launch_bounds__(kBlock) void k_claim_wide(PlanView P, int D) {
+  if (budget_spent(P)) return;
+  const TreeView& T = P.t;
+  const long long n = (long long)D * P.n_p;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const unsigned long long tk = T.tr_key[i];
+    if (tk == kEmptyKey) continue;
+    const unsigned long long body = tk & ~kTraceRec;
+    const int id = (int)(body >> kActBits);
+    const int rid = (tk & kTraceRec) ? id : record_of(T, id);
+    if (rid == 0) continue;
+    const int a = (int)(body & kActMask);
+    const uint32_t bit = 1u << (a & 31);
+    if (!(atomicOr(&rec_bits(T, rid)[a >> 5], bit) & bit)) {
+      rec_n(T, rid)[a] = 0;
+      rec_c(T, rid)[a] = 0ull;
+      rec_w(T, rid)[a] = 0ull;
+    }
+  }
+}
+
 __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm) {
   const TreeView& T = P.t;
   AggTable& G = sm.agg;
@@ -507,13 +535,7 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
           if (G.b[j]) atomicAdd(root_stripe(T, 1, a), G.b[j]);
         } else {
           const int a = (int)((k2 >> 1) & kActMask);
-          // Long rows clear W[a] at the first visit of (b, a) (not at
-          // creation); short rows add without waiting for the old count.
-          if (T.ra > kMaxA) {
-            if (atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]) == 0) rec_w(T, rid)[a] = 0ull;
-          } else {
-            atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
-          }
+          atomicAdd(&rec_n(T, rid)[a], (int)G.a[j]);
           if (G.b[j]) atomicAdd(&rec_c(T, rid)[a], G.b[j]);
         }
       }
@@ -853,32 +875,35 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
       const int b = __builtin_amdgcn_readfirstlane(__shfl(bl, __ffsll((long long)todo) - 1, 64));
       todo &= todo - 1;
       const float4* p4 = reinterpret_cast<const float4*>(rec_psi(T, b));
-      const int4* n4 = reinterpret_cast<const int4*>(rec_n(T, b));
+      const uint32_t* bits = rec_bits(T, b);
       const char* rec = reinterpret_cast<const char*>(rec_at(T, b));
       unsigned long long* wrow = rec_w(T, b);
       RecMeta* mt = rec_meta(T, b);
+      // Psi and the visited flags (the bitmap's nibble of each quad).
       float pf[4 * QPL];
-      int nf[4 * QPL];
+      uint32_t vb[QPL];
 #pragma unroll
       for (int i = 0; i < QPL; ++i) {
         const int q = lane + 64 * i;
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        int4 n = make_int4(0, 0, 0, 0);
+        uint32_t w = 0u;
         if (q < nq) {
           v = p4[q];
-          n = n4[q];
+          w = bits[q >> 3];
         }
         pf[4 * i] = v.x; pf[4 * i + 1] = v.y; pf[4 * i + 2] = v.z; pf[4 * i + 3] = v.w;
-        nf[4 * i] = n.x; nf[4 * i + 1] = n.y; nf[4 * i + 2] = n.z; nf[4 * i + 3] = n.w;
+        vb[i] = w;
       }
       // Read after the row: these uniform values are moved to scalar
       // registers at once, which waits for them.
       const float V0 = mt->V;
       const int N0 = mt->Nb;
       const unsigned long long par = mt->parent;
-      bool vis = false;                         // padding and absent quads hold 0
 #pragma unroll
-      for (int i = 0; i < 4 * QPL; ++i) vis = vis || nf[i] > 0;
+      for (int i = 0; i < QPL; ++i) vb[i] = (vb[i] >> (4 * ((lane + 64 * i) & 7))) & 15u;
+      bool vis = false;                         // padding is never visited
+#pragma unroll
+      for (int i = 0; i < QPL; ++i) vis = vis || vb[i] != 0u;
       float V;
       int N;
       const bool upd = __any(vis);
@@ -899,35 +924,39 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
         // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5), for visited
         // actions.  An unvisited action reads the metadata line instead (read
         // above), so the loads issue without branches.
-        const uint32_t c_off = 8u * (uint32_t)T.ra, w_off = 16u * (uint32_t)T.ra;
+        const uint32_t n_off = 4u * (uint32_t)T.ra, c_off = 8u * (uint32_t)T.ra,
+                       w_off = 16u * (uint32_t)T.ra;
         const uint32_t spare = 24u * (uint32_t)T.ra + (uint32_t)offsetof(RecMeta, parent);
         int nsum = 0, nn = 0;
 #pragma unroll
         for (int i0 = 0; i0 < QPL; i0 += 4) {
           unsigned long long cf[16], wf[16];
+          int nf[16];
 #pragma unroll
           for (int t = 0; t < 16; ++t) {
             const int i = 4 * i0 + t;
             const int j = 4 * (lane + 64 * (i >> 2)) + (i & 3);
-            const bool v = nf[i] > 0;
-            const uint32_t jb = 8u * (uint32_t)j;
-            cf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? c_off + jb : spare));
-            wf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? w_off + jb : spare));
+            const bool v = (vb[i >> 2] >> (i & 3)) & 1u;
+            const uint32_t j4 = 4u * (uint32_t)j, j8 = 8u * (uint32_t)j;
+            nf[t] = *reinterpret_cast<const int*>(rec + (v ? n_off + j4 : spare));
+            cf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? c_off + j8 : spare));
+            wf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? w_off + j8 : spare));
           }
 #pragma unroll
           for (int t = 0; t < 16; ++t) {
+            asm volatile("" : "+v"(nf[t]));
             asm volatile("" : "+v"(cf[t]));
             asm volatile("" : "+v"(wf[t]));
           }
 #pragma unroll
           for (int t = 0; t < 16; ++t) {
             const int i = 4 * i0 + t;
-            if (nf[i] > 0) {
+            if (((vb[i >> 2] >> (i & 3)) & 1u) && nf[t] > 0) {
               const float cv = from_fix(cf[t], inv);
               const float w = from_fix(wf[t], inv);
-              const float fn = (float)nf[i];
+              const float fn = (float)nf[t];
               pf[i] = (pf[i] - vc) + (cv / fn + gamma * (w / fn));
-              nsum += nf[i];
+              nsum += nf[t];
               ++nn;
               changed |= 1u << (i >> 2);
               if (wf[t]) clear |= 1ull << i;
@@ -1486,10 +1515,9 @@ __global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int 
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey, link = kEmptyKey;
     float r = 0.0f;
-    bool won = false, direct = false;
+    bool won = false;
     int obs = 0, a = 0;
     uint32_t h = 0;
-    const int rid_b = rid;
     if (alive) {
       const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
       if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
@@ -1498,10 +1526,10 @@ __global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int 
       tabular_step(P.m, s, a, w, sn, obs, r);
       s = sn;
       ++g;
-      direct = d >= kDirectLevel && rid >= 0;
-      if (!direct)
-        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
-                      : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      // Every visit goes to the trace: the first visit of (b, a) clears its
+      // columns in the claim pass, before any count is added.
+      tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
+                    : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
       link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
                       : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
       // AppendBeliefs by lane 0; the outcome goes to the whole wavefront.
@@ -1528,11 +1556,6 @@ __global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int 
     }
     if (ep_ok) {
       if (lane == 0) {
-        if (direct) {
-          if (atomicAdd(&rec_n(T, rid_b)[a], 1) == 0) rec_w(T, rid_b)[a] = 0ull;
-          const unsigned long long fx = to_fix(r, P.fix_scale);
-          if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
-        }
         const int t = t0 + d;
         T.tr_key[(size_t)d * n_p + ep] = tk;
         T.tr_val[(size_t)d * n_p + ep] = r;
@@ -1540,17 +1563,17 @@ __global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int 
         if (won) T.h_slot[h].id = rid;
       }
       if (won) {                                // the new record, by the wavefront
-        // Psi, N and C; W[a] is cleared by the first visit of (b, a) (no
-        // child can push into it before), which saves a third of the bytes.
+        // Psi, the metadata and a cleared bitmap; N, C and W of (b, a) are
+        // cleared by its first visit.
         uint4* q = reinterpret_cast<uint4*>(rec_at(T, rid));
         const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
-        const int ra = T.ra, nq = ra / 4, meta_q = 6 * ra / 4;
-        for (int i = lane; i < ra; i += 64)
-          q[i] = i < nq ? p0[i] : make_uint4(0u, 0u, 0u, 0u);
+        const int nq = T.ra / 4, meta_q = 6 * T.ra / 4, nbq = rec_bitmap_quads(T.ra);
+        for (int i = lane; i < nq; i += 64) q[i] = p0[i];
         if (lane == 0) {
           q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);
           q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));
         }
+        for (int i = lane; i < nbq; i += 64) q[meta_q + 2 + i] = make_uint4(0u, 0u, 0u, 0u);
       }
     }
   }
@@ -1718,6 +1741,12 @@ hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
+  if (P.t.ra > kMaxA) {
+    hipLaunchKernelGGL(k_claim_wide, dim3(blocks_for(std::min((long long)D * P.n_p, 1ll << 24))),
+                       dim3(kBlock), 0, s, P, D);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D);
   return hipGetLastError();
 }
@@ -1863,9 +1892,12 @@ __global__ __launch_bounds__(kBlock) void k_reroot_mark(RerootView V) {
         V.kept[r] = 1;
         nb = 1;
         const int* n = rec_n(V.src, r);
+        const uint32_t* bits = rec_bits(V.src, r);
+        const bool wide = V.src.ra > kMaxA;   // long rows: columns valid per bitmap
         for (int j = 0; j < V.A; ++j) {
-          nn += n[j] > 0 ? 1ull : 0ull;
-          nv += (unsigned long long)(n[j] > 0 ? n[j] : 0);
+          const int c = (!wide || ((bits[j >> 5] >> (j & 31)) & 1u)) ? n[j] : 0;
+          nn += c > 0 ? 1ull : 0ull;
+          nv += (unsigned long long)(c > 0 ? c : 0);
         }
       }
     }
@@ -1902,7 +1934,10 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
   for (int j = 0; j < V.src.rs / 16; ++j) b[j] = a[j];
   unsigned long long* c = rec_c(V.dst, nr);
   unsigned long long* w = rec_w(V.dst, nr);
+  const uint32_t* bits = rec_bits(V.dst, nr);
+  const bool wide = V.dst.ra > kMaxA;       // long rows: columns valid per bitmap
   for (int j = 0; j < V.dst.ra; ++j) {
+    if (wide && !((bits[j >> 5] >> (j & 31)) & 1u)) continue;
     if (V.rescale != 1.0 && c[j])
       c[j] = (unsigned long long)llrint((double)(long long)c[j] * V.rescale);
     w[j] = 0ull;
