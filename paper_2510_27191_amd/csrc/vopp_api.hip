@@ -326,6 +326,7 @@ size_t bytes_for(const WsSizes& z) {
   add(z.hcap * sizeof(HSlot));                       // table
   const size_t ar = (size_t)std::max(kMaxA, z.Apad);
   add(ar * 8); add(ar * 8); add(8);                  // root row and its CDF, V(root)
+  add(ar * 8);                                       // draw sums of the initial row
   add(ar * 4);                                       // initial preference row
   add((size_t)3 * z.Apad * kStripes * 8);            // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
@@ -365,6 +366,7 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.psi_root = c.take<double>(ar);
   t.psi0 = c.take<float>(ar);
   t.root_cdf = c.take<double>(ar);
+  t.psi0_cdf = c.take<unsigned long long>(ar);
   t.root_acc = c.take<unsigned long long>((size_t)3 * z.Apad * kStripes);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);

@@ -129,6 +129,8 @@ struct TreeView {
   float* psi0;                   // [ra] initial preference row ln pi0 / eta,
                                  // zero past |A|
   double* root_cdf;              // [nA] running sums of the root's softmax weights
+  unsigned long long* psi0_cdf;  // [nA] long rows: running sums of the integer
+                                 // draw weights of the initial row psi0
   unsigned long long* root_acc;  // [3][ra][kStripes]: N, C and W of the root's
                                  // action nodes, striped over blocks (every
                                  // episode passes through one of them)

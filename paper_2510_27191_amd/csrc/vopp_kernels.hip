@@ -198,10 +198,43 @@ struct SetupSmem {
   double buf[kBlock];
   double red[kBlock / 64];
   double bc;
+  unsigned long long part[kBlock];
 };
 __device__ double block_max64(double v, double* red);
 __device__ double block_ordered_sum(const double* x, int A, double m, double eta, double* cdf,
                                     double* buf, double* bc);
+
+__device__ __forceinline__ unsigned long long long_row_weight(float v, float m, float eta);
+
+// Running sums, in action order, of the integer draw weights of the initial
+// row psi0 (the weights of a long-row draw, for rows still equal to psi0: the
+// beliefs created in the current iteration).  Thread j sums a contiguous run
+// of actions; the runs' totals are scanned by one thread.
+__device__ void psi0_draw_sums(const TreeView& T, int A, float eta, int j, SetupSmem* ss) {
+  double mloc = -INFINITY;
+  for (int a = j; a < A; a += kBlock) mloc = fmax(mloc, (double)T.psi0[a]);
+  const float m = (float)block_max64(mloc, ss->red);
+  const int seg = (A + kBlock - 1) / kBlock;
+  const int lo = min(A, j * seg), hi = min(A, lo + seg);
+  unsigned long long sum = 0ull;
+  for (int a = lo; a < hi; ++a) sum += long_row_weight(T.psi0[a], m, eta);
+  ss->part[j] = sum;
+  __syncthreads();
+  if (j == 0) {
+    unsigned long long run = 0ull;
+    for (int i = 0; i < kBlock; ++i) {
+      const unsigned long long v = ss->part[i];
+      ss->part[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  unsigned long long run = ss->part[j];
+  for (int a = lo; a < hi; ++a) {
+    run += long_row_weight(T.psi0[a], m, eta);
+    T.psi0_cdf[a] = run;
+  }
+}
 
 __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
   const TreeView& T = P.t;
@@ -267,6 +300,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
       for (int a = j; a < P.m.nA; a += kBlock) mloc = fmax(mloc, T.psi_root[a]);
       const double m = block_max64(mloc, ss->red);
       block_ordered_sum(T.psi_root, P.m.nA, m, P.eta64, T.root_cdf, ss->buf, &ss->bc);
+      psi0_draw_sums(T, P.m.nA, P.eta, j, ss);
     }
     if (j == 0) {
       if (T.ra <= kMaxA) root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
@@ -1418,6 +1452,28 @@ __device__ __forceinline__ unsigned long long long_row_weight(float v, float m, 
   return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
 }
 
+// The long-row draw from running sums of its integer weights (A <= 4096): the
+// first a with t < cdf[a], t = u * total as in draw_long_row.  Lane l reads
+// the end of run l of ceil(A / 64) actions; the wavefront then reads the
+// chosen run.  Two rounds of loads, the same action as the scan.
+__device__ int draw_long_cdf(const unsigned long long* __restrict__ cdf, int A, uint32_t x0,
+                             int lane) {
+  const int step = (A + 63) / 64;
+  const unsigned long long tot = cdf[A - 1];
+  const int e = min((lane + 1) * step, A) - 1;
+  const bool run_ok = lane * step < A;
+  const unsigned long long end = run_ok ? cdf[e] : 0ull;
+  const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
+  const unsigned long long hit = __ballot(run_ok && t < end);
+  if (!hit) return A - 1;
+  const int r = __ffsll((long long)hit) - 1;
+  const int j = r * step + lane;
+  const bool ok = lane < step && j < A;
+  const unsigned long long v = ok ? cdf[j] : 0ull;
+  const unsigned long long hit2 = __ballot(ok && t < v);
+  return r * step + (__ffsll((long long)hit2) - 1);
+}
+
 constexpr int kLongChunks = kMaxAWide / 256;   // chunks of 256 actions in a row
 
 __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, uint32_t x0,
@@ -1448,16 +1504,16 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
     w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0ull;
     w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0ull;
   };
-  unsigned long long qs[kLongChunks];
+  uint32_t qs[kLongChunks];                     // a quad's sum is below 2^26
   unsigned long long tot = 0;
 #pragma unroll
   for (int c = 0; c < kLongChunks; ++c) {
-    qs[c] = 0ull;
+    qs[c] = 0u;
     const int q = c * 64 + lane;
     if (c < nc && q < nq) {
       unsigned long long w[4];
       quad(q, w);
-      qs[c] = w[0] + w[1] + w[2] + w[3];
+      qs[c] = (uint32_t)(w[0] + w[1] + w[2] + w[3]);
     }
     tot += qs[c];
   }
@@ -1467,7 +1523,7 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
 #pragma unroll
   for (int c = 0; c < kLongChunks; ++c) {
     if (c >= nc) break;
-    const unsigned long long incl = wave_incl_scan(qs[c]) + base;
+    const unsigned long long incl = wave_incl_scan((unsigned long long)qs[c]) + base;
     const unsigned long long hit = __ballot(c * 64 + lane < nq && t < incl);
     if (hit) {
       const int src = __ffsll((long long)hit) - 1;
@@ -1488,7 +1544,9 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
   return A - 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int D) {
+// Four wavefronts per SIMD (128 registers, a few spilled): each wavefront is
+// one episode's chain of dependent reads, so residency is what hides them.
+__global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
   if (budget_spent(P)) return;
   const TreeView& T = P.t;
@@ -1521,7 +1579,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_wide(PlanView P, int k, int 
     if (alive) {
       const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
       if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
-      else a = draw_long_row(fresh ? T.psi0 : rec_psi(T, rid), A, P.eta, w.x, lane);
+      else if (fresh) a = draw_long_cdf(T.psi0_cdf, A, w.x, lane);
+      else a = draw_long_row(rec_psi(T, rid), A, P.eta, w.x, lane);
       int sn;
       tabular_step(P.m, s, a, w, sn, obs, r);
       s = sn;
