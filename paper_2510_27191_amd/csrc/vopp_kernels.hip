@@ -147,6 +147,7 @@ struct Smem {
   AggTable agg;
   Ranges ranges;
   unsigned long long wave[kBlock / 64];
+  float psi0[kMaxA];        // the forward search's copy of the initial row
 };
 
 __device__ __forceinline__ void agg_clear(AggTable& T) {
@@ -320,11 +321,13 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
 // A new belief's record: Psi = ln pi0 / eta (the first term of Eq. 4; uniform
 // unless a reference policy is set), N = C = W = 0, its observation key and its
 // parent link.
-__device__ __forceinline__ void init_record(const PlanView& P, int id, int obs,
-                                            unsigned long long link) {
+// psi0s: the initial row staged in LDS (a copy from global memory would wait
+// for every store issued before it).
+__device__ __forceinline__ void init_record(const PlanView& P, const float* psi0s, int id,
+                                            int obs, unsigned long long link) {
   const TreeView& T = P.t;
   uint4* q = reinterpret_cast<uint4*>(rec_at(T, id));
-  const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
+  const uint4* p0 = reinterpret_cast<const uint4*>(psi0s);
   const int ra = T.ra;
   for (int j = 0; j < ra; j += 4) q[j >> 2] = p0[j >> 2];
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
@@ -336,8 +339,12 @@ __device__ __forceinline__ void init_record(const PlanView& P, int id, int obs,
 
 template <int AM>
 __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
-                            unsigned long long* red) {
+                            unsigned long long* red, float* psi0s) {
   const TreeView& T = P.t;
+  // The initial row in LDS, copied into new records (every thread of the
+  // block calls).
+  for (int i = threadIdx.x; i < T.ra; i += kBlock) psi0s[i] = T.psi0[i];
+  __syncthreads();
   const int t0 = T.step_base[k - 1];          // level step of level 0
   const int ep = blk * kBlock + threadIdx.x;
   const bool ep_ok = ep < P.n_p;
@@ -434,6 +441,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     if (alive && d + 1 < D) {
       w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
+      // One load from either row: a divergent pair of loads into the same
+      // registers would have to wait for each other.
       load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
       if (nav) z = nav_noise(P.m, w);
     }
@@ -450,7 +459,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
       T.list[(size_t)t * n_p + ep] = won ? sid : 0;
       if (won) {
         T.h_slot[h].id = rid;
-        init_record(P, rid, obs, link);
+        init_record(P, psi0s, rid, obs, link);
       }
     }
   }
@@ -1678,8 +1687,9 @@ __global__ __launch_bounds__(kBlock) void k_setup(PlanView P) {
 template <int AM>
 __global__ __launch_bounds__(kBlock) void k_forward(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
+  __shared__ float psi0s[kMaxA];
   if (budget_spent(P)) return;
-  dev_forward<AM>(P, k, D, blockIdx.x, red);
+  dev_forward<AM>(P, k, D, blockIdx.x, red, psi0s);
 }
 __global__ __launch_bounds__(kBlock) void k_accum(PlanView P, int D) {
   __shared__ Smem sm;
@@ -1738,10 +1748,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
     case kPhaseSetup: dev_setup(P, blk, it.nblk, nullptr); break;   // |A| <= 16
     case kPhaseForward:
       if (Apad <= 4) {
-        dev_forward<4>(P, it.a0, it.a1, blk, sm.wave);
+        dev_forward<4>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
       } else if constexpr (AMAX >= 8) {
-        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk, sm.wave);
-        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk, sm.wave);
+        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
+        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
       }
       break;
     case kPhaseAccum: dev_accum(P, it.a0, blk, it.nblk, sm); break;
