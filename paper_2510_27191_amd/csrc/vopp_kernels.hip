@@ -619,9 +619,6 @@ __device__ __forceinline__ unsigned long long resolve_link(const TreeView& T, Re
   }
   return par;
 }
-__device__ __forceinline__ unsigned long long parent_link(const TreeView& T, RecMeta* mt) {
-  return resolve_link(T, mt, mt->parent);
-}
 
 // Record of position ep of level step t, or -1 if no belief was inserted there.
 __device__ __forceinline__ int record_at(const PlanView& P, int t, int ep) {
@@ -1099,70 +1096,122 @@ __device__ double block_ordered_sum(const double* x, int A, double m, double eta
   return carry;
 }
 
-// The root row (|A| > kMaxA) in double precision, by one block: the striped
-// action-node sums are folded into the root record, then every sum over the
-// actions is taken in action order (the serial definition's order) from LDS.
+// Running sums, in the order of block_ordered_sum, of exp(eta (x - m)) for a
+// row whose entry j = i*kBlock + threadIdx.x is x[i] of the calling thread
+// (held in registers); with cdf set they are stored.  Every thread calls;
+// all get the total.
+template <int PER>
+__device__ double block_ordered_sum_regs(const double (&x)[PER], int A, double m, double eta,
+                                         double* cdf, double* buf) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double carry = 0.0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int base = i * kBlock;
+    if (base >= A) break;                       // uniform
+    const int j = base + (int)threadIdx.x;
+    double v = j < A ? exp(eta * (x[i] - m)) : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double o = __shfl_up(v, off, 64);
+      if (lane >= off) v += o;
+    }
+    if (lane == 63) buf[wv] = v;
+    __syncthreads();
+    double before = carry;
+    for (int w = 0; w < wv; ++w) before += buf[w];
+    double total = carry;
+    for (int w = 0; w < kBlock / 64; ++w) total += buf[w];
+    if (cdf && j < A) cdf[j] = before + v;
+    carry = total;
+    __syncthreads();
+  }
+  return carry;
+}
+
+// The root row (|A| > kMaxA) in double precision, by one block.  Thread t
+// holds actions t, t + kBlock, ... of the row and of the root's sums (one
+// stripe for long rows) in registers: one batch of loads, the update and its
+// sums (in the order of block_ordered_sum), then the stores, so that no load
+// waits behind a store.
 __device__ void dev_backup_root_wide(const PlanView& P, int k, double* buf) {
+  constexpr int PER = kMaxAWide / kBlock;
   const TreeView& T = P.t;
   const int A = P.m.nA;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double eta = P.eta64;
   __shared__ double red[kBlock / 64];
-  __shared__ double bc;
   __shared__ unsigned long long cnt[2];
   if (wv == 0) root_gate(P, k, lane);
   if (threadIdx.x == 0) { cnt[0] = 0ull; cnt[1] = 0ull; }
-  // The root's sums (one stripe for long rows), one action per thread: N and
-  // C into the root record, W into its W column.
-  for (int j = threadIdx.x; j < A; j += kBlock) {
-    unsigned long long* pw = &T.root_acc[((size_t)2 * T.ra + j) * kStripes];
-    rec_n(T, 0)[j] = (int)T.root_acc[((size_t)0 * T.ra + j) * kStripes];
-    rec_c(T, 0)[j] = T.root_acc[((size_t)1 * T.ra + j) * kStripes];
-    rec_w(T, 0)[j] = *pw;
-    *pw = 0ull;
-  }
-  __syncthreads();
-  auto block_max = [&](double v) { return block_max64(v, red); };
-  auto ordered = [&](const double* x, double m, double* cdf) {
-    return block_ordered_sum(x, A, m, eta, cdf, buf, &bc);
-  };
   double* psi = T.psi_root;
+  double pv[PER];
+  int nv[PER];
+  unsigned long long cv[PER], wv64[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = i * kBlock + (int)threadIdx.x;
+    pv[i] = -INFINITY;
+    nv[i] = 0;
+    cv[i] = 0ull;
+    wv64[i] = 0ull;
+    if (j < A) {
+      pv[i] = psi[j];
+      nv[i] = (int)T.root_acc[((size_t)0 * T.ra + j) * kStripes];
+      cv[i] = T.root_acc[((size_t)1 * T.ra + j) * kStripes];
+      wv64[i] = T.root_acc[((size_t)2 * T.ra + j) * kStripes];
+    }
+  }
   double mloc = -INFINITY;
   unsigned long long nodes = 0, nsum = 0;
-  for (int j = threadIdx.x; j < A; j += kBlock) {
-    mloc = fmax(mloc, psi[j]);
-    const int n = rec_n(T, 0)[j];
-    nodes += n > 0 ? 1ull : 0ull;
-    nsum += (unsigned long long)(n > 0 ? n : 0);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    mloc = fmax(mloc, pv[i]);
+    nodes += nv[i] > 0 ? 1ull : 0ull;
+    nsum += (unsigned long long)(nv[i] > 0 ? nv[i] : 0);
   }
   nodes = wave_sum(nodes);
   nsum = wave_sum(nsum);
+  __syncthreads();                              // cnt cleared
   if (lane == 0) {
     atomicAdd(&cnt[0], nodes);
     atomicAdd(&cnt[1], nsum);
   }
-  const double m = block_max(mloc);
-  if (cnt[0] == 0ull) return;                   // uniform: no action node yet
-  // V_curr = L_eta Psi before the update (Eq. 3).
-  const double vc = m + log(ordered(psi, m, nullptr)) / eta;
-  // Psi <- Psi - V_curr + Q for the actions with an action node (Eq. 5).
-  double m2 = -INFINITY;
-  for (int j = threadIdx.x; j < A; j += kBlock) {
-    const int n = rec_n(T, 0)[j];
-    double p = psi[j];
-    if (n > 0) {
-      const double c = (double)(long long)rec_c(T, 0)[j] * P.fix_inv64;
-      const double w = (double)(long long)rec_w(T, 0)[j] * P.fix_inv64;
-      p = (p - vc) + (c / (double)n + P.m.gamma64 * (w / (double)n));
-      psi[j] = p;
+  const double m = block_max64(mloc, red);
+  const bool any = cnt[0] != 0ull;              // uniform: an action node exists
+  double vc = 0.0, mm = 0.0, run = 0.0;
+  if (any) {
+    // V_curr = L_eta Psi before the update (Eq. 3).
+    vc = m + log(block_ordered_sum_regs<PER>(pv, A, m, eta, nullptr, buf)) / eta;
+    // Psi <- Psi - V_curr + Q for the actions with an action node (Eq. 5).
+    double m2 = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (nv[i] > 0) {
+        const double c = (double)(long long)cv[i] * P.fix_inv64;
+        const double w = (double)(long long)wv64[i] * P.fix_inv64;
+        pv[i] = (pv[i] - vc) + (c / (double)nv[i] + P.m.gamma64 * (w / (double)nv[i]));
+      }
+      m2 = fmax(m2, pv[i]);
     }
-    m2 = fmax(m2, p);
+    mm = block_max64(m2, red);
+    // V = L_eta Psi after the update, and the running sums of the root draw.
+    run = block_ordered_sum_regs<PER>(pv, A, mm, eta, T.root_cdf, buf);
   }
-  __syncthreads();
-  const double mm = block_max(m2);
-  // V = L_eta Psi after the update, and the running sums of the root draw.
-  const double run = ordered(psi, mm, T.root_cdf);
-  if (threadIdx.x == 0) {
+  // The root record's columns (N, C, W) and the updated row; W's stripe is
+  // cleared for the next iteration.
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = i * kBlock + (int)threadIdx.x;
+    if (j < A) {
+      rec_n(T, 0)[j] = nv[i];
+      rec_c(T, 0)[j] = cv[i];
+      rec_w(T, 0)[j] = wv64[i];
+      T.root_acc[((size_t)2 * T.ra + j) * kStripes] = 0ull;
+      if (any && nv[i] > 0) psi[j] = pv[i];
+    }
+  }
+  if (any && threadIdx.x == 0) {
     const double v = mm + log(run) / eta;
     T.v_root[0] = v;
     RecMeta* mt = rec_meta(T, 0);
