@@ -158,3 +158,47 @@ def test_wide_anytime_and_reroot(V, orc):
         for w in (A_ws, B_ws, C_ws):
             w.close()
         pom.close()
+
+
+def test_wide_anytime_stops_early_and_equals_plain_plan(V):
+    # 625 actions: an anytime plan stopped after one iteration, and one
+    # stopped about a third of the way, equal the plain plan at the realised
+    # K' bit for bit (the claim pass and every later phase of an iteration
+    # that does not run return at once).  The fixed-point shift is at its
+    # cap for every K here, so the two plans sum on the same grid.
+    inst = I.mars_like(4, 128, 625, reward_scale=0.05)
+    bel = I.tabular_belief(inst)
+    kmax, depth = 8, 3
+    pom = V.Pomdp.from_instance(inst)
+    b = V.belief_tensor(inst, bel)
+    prm = V.params(1024, seed=5)
+    ws = V.Workspace(pom, prm, kmax, depth)
+
+    def plain(K):
+        r = V.plan(pom, b, b.numel(), K, depth, prm, ws=ws)
+        return r, V.tree_dump(ws, 625, r.n_beliefs, r.n_actions)
+
+    def anytime(ms):
+        r, k = V.plan_anytime(pom, b, b.numel(), kmax, depth, ms, prm, ws=ws)
+        return r, k, V.tree_dump(ws, 625, r.n_beliefs, r.n_actions)
+
+    def same(a, ta, c, tc):
+        assert a.action == c.action and a.v_root == c.v_root
+        assert np.array_equal(a.values, c.values)
+        assert (a.particle_steps, a.n_beliefs, a.n_actions) == \
+            (c.particle_steps, c.n_beliefs, c.n_actions)
+        for key in ta:
+            assert np.array_equal(ta[key], tc[key]), key
+
+    try:
+        full, kf, _ = anytime(1e6)
+        assert kf == kmax
+        r, k, t = anytime(1e-6)
+        assert k == 1
+        same(r, t, *plain(1))
+        r, k, t = anytime(max(full.device_ms / 3.0, 0.05))
+        assert 1 <= k <= kmax
+        same(r, t, *plain(k))
+    finally:
+        ws.close()
+        pom.close()
