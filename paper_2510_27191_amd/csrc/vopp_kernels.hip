@@ -1510,42 +1510,84 @@ __device__ __forceinline__ unsigned long long long_row_weight(float v, float m, 
   return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
 }
 
+// Long-row episodes run on half a wavefront (kHalf = 32 lanes), so that a
+// wavefront carries two independent episodes: each is a chain of dependent
+// reads, and two chains per wavefront hide twice as much of their latency.
+// The helpers below reduce, scan and vote within the caller's half (lane is
+// the lane within the half).
+constexpr int kHalf = 32;
+
+__device__ __forceinline__ float half_maxf(float v) {
+#pragma unroll
+  for (int off = kHalf / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kHalf));
+  return v;
+}
+__device__ __forceinline__ unsigned long long half_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = kHalf / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kHalf);
+  return v;
+}
+__device__ __forceinline__ unsigned long long half_incl_scan(unsigned long long v, int lane) {
+#pragma unroll
+  for (int off = 1; off < kHalf; off <<= 1) {
+    const unsigned long long n = __shfl_up(v, off, kHalf);
+    if (lane >= off) v += n;
+  }
+  return v;
+}
+// Votes of the caller's half, bit l for lane l of the half.
+__device__ __forceinline__ uint32_t half_ballot(bool p) {
+  return (uint32_t)(__ballot(p) >> (threadIdx.x & kHalf));
+}
+
 // The long-row draw from running sums of its integer weights (A <= 4096): the
 // first a with t < cdf[a], t = u * total as in draw_long_row.  Lane l reads
-// the end of run l of ceil(A / 64) actions; the wavefront then reads the
-// chosen run.  Two rounds of loads, the same action as the scan.
+// the end of run l of ceil(A / 32) actions; the half then reads the chosen
+// run (at most 128 entries, four per lane, in order).  Two rounds of loads,
+// the same action as the scan.
 __device__ int draw_long_cdf(const unsigned long long* __restrict__ cdf, int A, uint32_t x0,
                              int lane) {
-  const int step = (A + 63) / 64;
+  const int step = (A + kHalf - 1) / kHalf;
   const unsigned long long tot = cdf[A - 1];
   const int e = min((lane + 1) * step, A) - 1;
   const bool run_ok = lane * step < A;
   const unsigned long long end = run_ok ? cdf[e] : 0ull;
   const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
-  const unsigned long long hit = __ballot(run_ok && t < end);
+  const uint32_t hit = half_ballot(run_ok && t < end);
   if (!hit) return A - 1;
-  const int r = __ffsll((long long)hit) - 1;
-  const int j = r * step + lane;
-  const bool ok = lane < step && j < A;
-  const unsigned long long v = ok ? cdf[j] : 0ull;
-  const unsigned long long hit2 = __ballot(ok && t < v);
-  return r * step + (__ffsll((long long)hit2) - 1);
+  const int r = __ffs(hit) - 1;
+  const int lo = r * step, hi = min(lo + step, A);
+  unsigned long long v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = lo + u * kHalf + lane;
+    v[u] = j < hi ? cdf[j] : 0ull;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = lo + u * kHalf + lane;
+    const uint32_t h2 = half_ballot(j < hi && t < v[u]);
+    if (h2) return lo + u * kHalf + (__ffs(h2) - 1);
+  }
+  return A - 1;
 }
 
-constexpr int kLongChunks = kMaxAWide / 256;   // chunks of 256 actions in a row
+constexpr int kLongChunks = kMaxAWide / (4 * kHalf);   // chunks of 128 actions
 
+// qs: this half's LDS area of kLongChunks * kHalf quad sums.
 __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, uint32_t x0,
-                             int lane) {
-  // Lane l holds the quads 4l, 4l + 256, ... (the row is padded to a
-  // multiple of 4; padding is masked off).  Each weight is evaluated once:
-  // the lane keeps its quad sum of every chunk, the wavefront scans those
-  // once the total is known, and only the chosen quad is evaluated again.
+                             int lane, uint32_t* qs) {
+  // Lane l of the half holds the quads l, l + 32, ... (the row is padded to
+  // a multiple of 4; padding is masked off).  Each weight is evaluated once:
+  // the lane keeps its quad sum of every chunk (in LDS, for registers), the
+  // half scans those once the total is known, and only the chosen quad is
+  // evaluated again.
   const float4* r4 = reinterpret_cast<const float4*>(row);
   const int nq = (A + 3) / 4;
-  const int nc = (nq + 63) / 64;
+  const int nc = (nq + kHalf - 1) / kHalf;
   float m = -INFINITY;
 #pragma unroll 4
-  for (int q = lane; q < nq; q += 64) {
+  for (int q = lane; q < nq; q += kHalf) {
     const float4 v = r4[q];
     const int j = 4 * q;
     m = fmaxf(m, v.x);
@@ -1553,7 +1595,7 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
     if (j + 2 < A) m = fmaxf(m, v.z);
     if (j + 3 < A) m = fmaxf(m, v.w);
   }
-  m = wave_maxf(m);
+  m = half_maxf(m);
   auto quad = [&](int q, unsigned long long (&w)[4]) {
     const float4 v = r4[q];
     const int j = 4 * q;
@@ -1562,54 +1604,53 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
     w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0ull;
     w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0ull;
   };
-  uint32_t qs[kLongChunks];                     // a quad's sum is below 2^26
-  unsigned long long tot = 0;
-#pragma unroll
-  for (int c = 0; c < kLongChunks; ++c) {
-    qs[c] = 0u;
-    const int q = c * 64 + lane;
-    if (c < nc && q < nq) {
+  unsigned long long tot = 0;                   // a quad's sum is below 2^26
+  for (int c = 0; c < nc; ++c) {
+    const int q = c * kHalf + lane;
+    uint32_t sq = 0u;
+    if (q < nq) {
       unsigned long long w[4];
       quad(q, w);
-      qs[c] = (uint32_t)(w[0] + w[1] + w[2] + w[3]);
+      sq = (uint32_t)(w[0] + w[1] + w[2] + w[3]);
     }
-    tot += qs[c];
+    qs[c * kHalf + lane] = sq;
+    tot += sq;
   }
-  tot = wave_sum(tot);
+  tot = half_sum(tot);
   const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
   unsigned long long base = 0;
-#pragma unroll
-  for (int c = 0; c < kLongChunks; ++c) {
-    if (c >= nc) break;
-    const unsigned long long incl = wave_incl_scan((unsigned long long)qs[c]) + base;
-    const unsigned long long hit = __ballot(c * 64 + lane < nq && t < incl);
+  for (int c = 0; c < nc; ++c) {
+    const uint32_t sq = qs[c * kHalf + lane];
+    const unsigned long long incl = half_incl_scan((unsigned long long)sq, lane) + base;
+    const uint32_t hit = half_ballot(c * kHalf + lane < nq && t < incl);
     if (hit) {
-      const int src = __ffsll((long long)hit) - 1;
+      const int src = __ffs(hit) - 1;
       int pick = 3;                             // within the chosen quad
       if (lane == src) {
         unsigned long long w[4];
-        quad(c * 64 + lane, w);
-        unsigned long long run = incl - qs[c];
+        quad(c * kHalf + lane, w);
+        unsigned long long run = incl - sq;
         for (int u = 0; u < 4; ++u) {
           run += w[u];
           if (t < run) { pick = u; break; }
         }
       }
-      return 4 * (c * 64 + src) + __shfl(pick, src, 64);
+      return 4 * (c * kHalf + src) + __shfl(pick, src, kHalf);
     }
-    base = __shfl(incl, 63, 64);
+    base = __shfl(incl, kHalf - 1, kHalf);
   }
   return A - 1;
 }
 
-// Four wavefronts per SIMD (128 registers, a few spilled): each wavefront is
-// one episode's chain of dependent reads, so residency is what hides them.
+// Four wavefronts per SIMD (128 registers, a few spilled): each episode is a
+// chain of dependent reads, so residency is what hides them.
 __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, int D) {
   __shared__ unsigned long long red[kBlock / 64];
+  __shared__ uint32_t qsum[kBlock / kHalf][kLongChunks * kHalf];
   if (budget_spent(P)) return;
   const TreeView& T = P.t;
-  const int lane = threadIdx.x & 63;
-  const int ep = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);   // uniform per wave
+  const int lane = threadIdx.x & (kHalf - 1);
+  const int ep = blockIdx.x * (kBlock / kHalf) + (threadIdx.x / kHalf);   // uniform per half
   const bool ep_ok = ep < P.n_p;
   const int t0 = T.step_base[k - 1];
   const int A = P.m.nA;
@@ -1638,7 +1679,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
       const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
       if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
       else if (fresh) a = draw_long_cdf(T.psi0_cdf, A, w.x, lane);
-      else a = draw_long_row(rec_psi(T, rid), A, P.eta, w.x, lane);
+      else a = draw_long_row(rec_psi(T, rid), A, P.eta, w.x, lane, qsum[threadIdx.x / kHalf]);
       int sn;
       tabular_step(P.m, s, a, w, sn, obs, r);
       s = sn;
@@ -1649,7 +1690,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
                     : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
       link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
                       : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
-      // AppendBeliefs by lane 0; the outcome goes to the whole wavefront.
+      // AppendBeliefs by lane 0 of the half; the outcome goes to the half.
       int fr = 0, id = -1, wn = 0;
       if (lane == 0) {
         bool b_won = false, b_fr = false;
@@ -1657,10 +1698,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
         wn = b_won;
         fr = b_fr;
       }
-      h = __shfl(h, 0, 64);
-      wn = __shfl(wn, 0, 64);
-      fr = __shfl(fr, 0, 64);
-      id = __shfl(id, 0, 64);
+      h = __shfl(h, 0, kHalf);
+      wn = __shfl(wn, 0, kHalf);
+      fr = __shfl(fr, 0, kHalf);
+      id = __shfl(id, 0, kHalf);
       won = wn != 0;
       if (h == ~0u) {
         if (lane == 0) atomicOr((unsigned int*)&T.counters[1], 2u);
@@ -1679,18 +1720,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
         T.list[(size_t)t * n_p + ep] = won ? sid : 0;
         if (won) T.h_slot[h].id = rid;
       }
-      if (won) {                                // the new record, by the wavefront
+      if (won) {                                // the new record, by the half
         // Psi, the metadata and a cleared bitmap; N, C and W of (b, a) are
         // cleared by its first visit.
         uint4* q = reinterpret_cast<uint4*>(rec_at(T, rid));
         const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
         const int nq = T.ra / 4, meta_q = 6 * T.ra / 4, nbq = rec_bitmap_quads(T.ra);
-        for (int i = lane; i < nq; i += 64) q[i] = p0[i];
+        for (int i = lane; i < nq; i += kHalf) q[i] = p0[i];
         if (lane == 0) {
           q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);
           q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));
         }
-        for (int i = lane; i < nbq; i += 64) q[meta_q + 2 + i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int i = lane; i < nbq; i += kHalf) q[meta_q + 2 + i] = make_uint4(0u, 0u, 0u, 0u);
       }
     }
   }
@@ -1854,7 +1895,7 @@ hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
   else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
   else
-    hipLaunchKernelGGL(k_forward_wide, dim3((P.n_p + kBlock / 64 - 1) / (kBlock / 64)), b, 0, s,
+    hipLaunchKernelGGL(k_forward_wide, dim3((P.n_p + kBlock / kHalf - 1) / (kBlock / kHalf)), b, 0, s,
                        P, k, D);
   return hipGetLastError();
 }

@@ -57,8 +57,11 @@ def test_first_iteration_full_size(V, orc, name):
     assert_parity(res, tree, o, inst["nA"])
 
 
+# 65 actions: the shortest long row; 1500, 3025 and 4096: the sweeps that hold
+# 8, 12 and 16 quads of the row per lane.
 @pytest.mark.parametrize("nS,A,n_p,K,depth", [(256, 625, 1024, 3, 3), (128, 3025, 768, 3, 3),
-                                             (256, 625, 2048, 4, 4)])
+                                             (256, 625, 2048, 4, 4), (128, 65, 1024, 3, 3),
+                                             (64, 1500, 768, 3, 3), (64, 4096, 512, 3, 3)])
 def test_reduced_plan(V, orc, nS, A, n_p, K, depth):
     inst = I.mars_like(1, nS, A, reward_scale=0.05)
     bel = I.tabular_belief(inst)
