@@ -66,8 +66,9 @@ typedef struct vopp_pomdp vopp_pomdp;
  * 2^(26 - b) with b = max(6, ceil(log2 nA)) (belief keys hold the action and
  * observation in 26 bits): nO <= 2^20 up to 64 actions, 2^16 for 625, 2^14
  * for 3025.  Models with more than 64 actions keep preference rows in memory
- * (one wavefront per belief in the backup sweeps); batched and served plans
- * take at most 16 actions.
+ * (one wavefront per belief in the backup sweeps, half a wavefront per
+ * episode in the forward search); batched and served plans take at most 16
+ * actions.
  * Sampling uses integer thresholds rint(cum/total * 2^31) per row. */
 typedef struct {
   int32_t nS, nA, nO;

@@ -859,8 +859,8 @@ __device__ __forceinline__ void root_gate(const PlanView& P, int k, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Sweeps for long action rows (|A| > kMaxA): one wavefront per belief, lane j
-// owning actions j, j + 64, ...; the row stays in memory.
+// Sweeps for long action rows (|A| > kMaxA): one wavefront per belief; lane l
+// holds the quads l, l + 64, ... of the row.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_max64(double v) {
 #pragma unroll
@@ -1498,13 +1498,14 @@ __device__ void dev_pf_resample(const PlanView& P, int t, int blk) {
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Forward search for long action rows (|A| > kMaxA, tabular models): one
-// wavefront per episode.  The episode's state is the same in every lane; the
-// lanes share the softmax draw (each owns actions j = lane, lane + 64, ...),
-// the record initialisation, and lane 0 does the episode's table probe and
-// its scalar writes.  The draw scales the single-precision weights by 2^24 to
-// integers, so the running sums are exact whatever the order of addition:
-// an inclusive wave scan per chunk of 64 actions finds the first running sum
-// above t = ((x0 >> 8) * total) >> 24.
+// half wavefront per episode.  The episode's state is the same in every lane
+// of the half; the lanes share the softmax draw (lane l owns the quads l,
+// l + 32, ... of the row), the record initialisation, and lane 0 of the half
+// does the episode's table probe and its scalar writes.  The draw scales the
+// single-precision weights by 2^24 to integers, so the running sums are
+// exact whatever the order of addition: an inclusive scan over the half per
+// chunk of 128 actions finds the first running sum above
+// t = ((x0 >> 8) * total) >> 24.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long long_row_weight(float v, float m, float eta) {
   return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
