@@ -93,9 +93,9 @@ def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it
 # was taken on (hash below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "10aec5d31dea35a1",
-    "backup_level": {"nav2d": 48.69e6, "sparse4096": 198.44e6},
-    "forward": {"nav2d": 135.65e6, "sparse4096": 726.67e6},
+    "sources_sha256_16": "5b8626943d689100",
+    "backup_level": {"nav2d": 48.67e6, "sparse4096": 199.94e6},
+    "forward": {"nav2d": 135.65e6, "sparse4096": 728.36e6},
 }
 
 
