@@ -406,7 +406,9 @@ def main():
                     choices=["nav2d", "sparse4096", "tabular16", "mars625", "mars3025"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-event-profile", action="store_true",
-                    help="skip the per-kernel event brackets in the timed region")
+                    help="skip the event-bracketed plans (kernel shares in the last "
+                         "warm-up plan, the dominant kernel's timing after the timed "
+                         "region); the roofline is then left out")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-instance batched vs plain comparison")
     ap.add_argument("--no-serve", action="store_true",
