@@ -35,8 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of each kernel kind over one plan: every field the kernel
 # must touch in HBM-resident tree, table or trace arrays, counted once (model
 # tables are cache resident and not counted).  ra = |A| rounded up to a
-# multiple of 4; a belief record holds 24*ra + 32 used bytes.  The kernel
-# table of the design doc derives each term.
+# multiple of 4; a belief record holds 24*ra + 32 used bytes.
 #   forward, per particle-step: preference row 4|A| + table slot 16 + N 8 and
 #     C 16 (atomic read + write) + trace word and value 12; per new belief:
 #     key insert 8 + record index 4 + list entry 4 + record 24*ra + 32; per
@@ -47,12 +46,9 @@ HBM_PEAK_GBS = 8000.0
 #     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16.
 #   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
 #     written, push 16.
-# With more than 64 actions a new record is written without its W column
-# (16*ra + 32) and W[a] is cleared at the action node's first visit (8), and
-# the level sweep reads only what it uses: per
-# belief the N and preference rows 8*ra, the row written 4*ra, the tail 32
-# read and V, N_b 8 written, the push 16, and per action node C and W read
-# 16 and W cleared 8 (nodes_per_belief on average).
+# With more than 64 actions a record also holds a bitmap of its valid action
+# columns; the long-row terms are given where they are computed below
+# (nodes_per_belief: action nodes per belief on average).
 def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
     ra = (nA + 3) // 4 * 4
     rec = 24 * ra + 32
@@ -438,7 +434,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the "
-                          "planner has no multi-GPU path (see DESIGN.md)",
+                          "planner has no multi-GPU path (one GPU plans one "
+                          "instance; many instances go to one GPU each)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
