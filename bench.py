@@ -434,8 +434,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the "
-                          "planner has no multi-GPU path (one GPU plans one "
-                          "instance; many instances go to one GPU each)",
+                          "planner has no multi-GPU path (independent instances "
+                          "would be shared out across GPUs by HBM footprint)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
