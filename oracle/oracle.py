@@ -57,7 +57,7 @@ class OrcParams(C.Structure):
                 ("depth", C.c_int32), ("schedule", C.c_int32),
                 ("eta", C.c_double), ("seed", C.c_uint64),
                 ("step", C.c_uint32), ("tau", C.c_double),
-                ("trace", C.c_int32), ("mutate", C.c_int32),
+                ("tau_abs", C.c_double), ("trace", C.c_int32), ("mutate", C.c_int32),
                 ("pi0", C.c_void_p), ("start", C.c_void_p)]
 
 
@@ -78,6 +78,9 @@ def load():
     lib.orc_result_info.argtypes = [vp, vp, vp, vp]
     lib.orc_result_tree.argtypes = [vp] * 11
     lib.orc_result_trace.argtypes = [vp] * 4
+    lib.orc_result_draws.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+    lib.orc_nav_obs_weight.argtypes = [C.POINTER(OrcNav), C.c_float, C.c_float, C.c_int32]
+    lib.orc_nav_obs_weight.restype = C.c_uint64
     lib.orc_result_free.argtypes = [vp]
     lib.orc_reroot.restype = vp
     lib.orc_reroot.argtypes = [vp, C.c_int32, C.c_int32]
@@ -86,7 +89,7 @@ def load():
     lib.orc_pick.argtypes = [vp, C.c_int32, C.c_uint32]
     lib.orc_pick.restype = C.c_int32
     lib.orc_sample_action.argtypes = [vp, C.c_int32, C.c_double, C.c_uint32,
-                                      C.c_int32, vp]
+                                      C.c_double, C.c_double, vp, vp]
     lib.orc_sample_action.restype = C.c_int32
     lib.orc_nav_step.argtypes = [C.POINTER(OrcNav), C.c_float, C.c_float,
                                  C.c_int32, C.c_uint32, C.c_uint32] + [vp] * 5
@@ -167,6 +170,7 @@ class OracleResult:
     a_C: np.ndarray
     a_N: np.ndarray
     trace: dict | None = None
+    draws: dict | None = None
     handle: "Handle | None" = None
 
 
@@ -212,13 +216,24 @@ def reroot(result, a, o, A):
     return hd, out
 
 
+def step_base(budget, depth, schedule):
+    """First level step of each iteration: [0, D_1, D_1 + D_2, ...] (K + 1)."""
+    out = [0]
+    for k in range(1, budget + 1):
+        out.append(out[-1] + (depth if schedule == 1 else min(k, depth)))
+    return np.asarray(out, np.int32)
+
+
 def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
-         schedule=0, step=0, tau=2.0 ** -16, trace=False, mutate=0, pi0=None,
-         start=None, keep=False):
+         schedule=0, step=0, tau=2.0 ** -12, tau_abs=0.0, trace=False,
+         draws=False, mutate=0, pi0=None, start=None, keep=False):
     """Run one serial planning step and return the full tree.  pi0: reference
     policy weights over the actions (positive; normalised), or None: uniform.
     start: a Handle from ``reroot`` to plan from its tree.  keep: keep the
-    result's handle (``.handle``) for re-rooting."""
+    result's handle (``.handle``) for re-rooting.  tau, tau_abs: near-tie
+    screen of the draws (|t - P_j| <= tau * P_last + tau_abs).  trace: the
+    per-draw rows; draws: the same as dense arrays by (level step, episode)
+    (``act`` -1 where no draw; ``flags`` bit 0 drawn, 1 terminal, 2 near tie)."""
     lib = load()
     keep = _Keep()
     pi = None
@@ -227,7 +242,7 @@ def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
         assert pi.shape == (inst["nA"],) and np.all(pi > 0)
         keep.arrs.append(pi)
     prm = OrcParams(n_particles, budget, depth, schedule, eta, seed, step,
-                    tau, 1 if trace else 0, mutate,
+                    tau, tau_abs, 1 if (trace or draws) else 0, mutate,
                     None if pi is None else pi.ctypes.data,
                     None if start is None else start.h)
     if inst["kind"] == "tabular":
@@ -253,11 +268,19 @@ def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
             tr = dict(k=ints[:, 0], d=ints[:, 1], ep=ints[:, 2], b=ints[:, 3],
                       a=ints[:, 4], obs=ints[:, 5], term=ints[:, 6],
                       an=ints[:, 7], r=r, margin=mg)
+        dr = None
+        if draws:
+            sb = step_base(budget, depth, schedule)
+            n = int(sb[-1]) * n_particles
+            dr = dict(act=np.full(n, -1, np.int16), obs=np.zeros(n, np.int32),
+                      flags=np.zeros(n, np.uint8), step_base=sb)
+            lib.orc_result_draws(h, _ptr(sb), n_particles, _ptr(dr["act"]),
+                                 _ptr(dr["obs"]), _ptr(dr["flags"]))
         return OracleResult(action=int(info[2]), v_root=float(vr[0]),
                             psi_root=out["psi"][0].copy(),
                             particle_steps=int(info[3]), n_draws=int(info[4]),
                             near_ties=int(info[5]), min_margin=float(mm[0]),
-                            trace=tr, handle=hd if keep else None, **out)
+                            trace=tr, draws=dr, handle=hd if keep else None, **out)
     finally:
         if not keep:
             del hd
@@ -287,13 +310,23 @@ def pick(thr, x):
     return int(lib.orc_pick(_ptr(thr), thr.size, int(x) & 0xFFFFFFFF))
 
 
-def sample_action(psi, eta, x0, root):
+def sample_action(psi, eta, x0, tau=0.0, tau_abs=0.0):
+    """Eq. (6) draw: (action, margin, near tie under the screen)."""
     lib = load()
     psi = _c32(psi, np.float64)
     mg = np.zeros(1, np.float64)
+    nr = np.zeros(1, np.int32)
     a = lib.orc_sample_action(_ptr(psi), psi.size, eta, int(x0) & 0xFFFFFFFF,
-                              1 if root else 0, _ptr(mg))
-    return int(a), float(mg[0])
+                              float(tau), float(tau_abs), _ptr(mg), _ptr(nr))
+    return int(a), float(mg[0]), bool(nr[0])
+
+
+def nav_obs_weight(inst, x, y, o):
+    """Navigation likelihood of observation key o at (x, y), units of 2^-24."""
+    lib = load()
+    keep = _Keep()
+    m = nav_struct(inst, keep)
+    return int(lib.orc_nav_obs_weight(C.byref(m), float(x), float(y), int(o)))
 
 
 def nav_step(inst, x, y, a, w1, w2):

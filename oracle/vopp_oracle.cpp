@@ -49,17 +49,15 @@
  *     Tags: ROOT = 1, STEP = 2.  A STEP block gives word 0 to the action
  *     draw and words 1, 2 to the model.
  *   - Root state draw: index = (x0 * M) >> 32 over the M belief particles.
- *   - Action draw (Eq. 6): w_j = exp(eta (Psi_j - max Psi)), P_j their
- *     running sums, t = u * P_last with u = (x0 >> 8) * 2^-24, action = first
- *     j with t < P_j (clamped to |A|-1).  Because floating point decides an
- *     integer here, the decision is taken in the precision the GPU kernel
- *     uses: single precision at non-root beliefs, double at the root.  At a
- *     non-root belief with more than 64 actions the single-precision weights
- *     are scaled by 2^24 and truncated to integers W_j, and the action is the
- *     first j whose integer running sum exceeds ((x0 >> 8) * sum W) >> 24;
- *     the sums are then exact in any order of addition.  The
- *     oracle also measures, in double precision, how far t lies from the
- *     nearest CDF boundary (the margin) and counts draws closer than tau.
+ *   - Action draw (Eq. 6), the same rule at every belief: weights
+ *     w_j = exp(eta (Psi_j - max Psi)) in double precision, P_j their running
+ *     sums in action order, t = u * P_last with u = (x0 >> 8) * 2^-24, action
+ *     = first j with t < P_j (clamped to |A|-1).  A row whose preferences are
+ *     all equal therefore gives floor(u |A|) exactly.  The oracle also reports
+ *     how close t lies to the nearest interior boundary P_j: a draw is a near
+ *     tie when some |t - P_j| <= tau * P_last + tau_abs (both passed in by the
+ *     caller; max weight = 1).  Any planner that keeps its preferences in
+ *     another precision may decide such a draw either way.
  *   - Tabular G: thresholds thr_j = rint(cum_j / total * 2^31) from the
  *     sequential double sum of the fp32 row (last = 2^31); outcome = first j
  *     with (x >> 1) < thr_j.  Successor from word 1, observation from word 2
@@ -187,7 +185,8 @@ typedef struct {
   double eta;
   uint64_t seed;
   uint32_t step;
-  double tau;      // margins below tau are counted as near ties
+  double tau;      // near-tie screen: |t - P_j| <= tau * P_last + tau_abs
+  double tau_abs;
   int32_t trace;   // keep a per-draw trace
   int32_t mutate;  // 0: none.  >0 plants a known mistake (pin sensitivity)
   const double* pi0;  // [A] reference policy weights (> 0), or NULL: uniform
@@ -491,7 +490,7 @@ double lse(const double* x, int n, double eta) {
 }
 
 struct TraceRow {
-  int32_t k, d, ep, b, a, obs, term, an;
+  int32_t k, d, ep, b, a, obs, term, an, near;
   float r;
   double margin;
 };
@@ -507,71 +506,37 @@ struct Result {
   std::vector<TraceRow> trace;
 };
 
-// Rows longer than this draw with integer weights (see the header).
-constexpr int kLongRow = 64;
-
-// Action draw of Eq. (6) in the GPU's decision precision, plus the margin of
-// the exact (double) draw to its nearest CDF boundary.
-int sample_action(const double* psi, int A, double eta, uint32_t x0, bool root,
-                  double* margin) {
+// Action draw of Eq. (6) in double precision.  *margin: distance of t from
+// the nearest interior boundary, relative to P_last (1 for a flat row, whose
+// draw floor(u |A|) is exact in any precision); *near: some interior boundary
+// lies within tau * P_last + tau_abs of t.
+int sample_action(const double* psi, int A, double eta, uint32_t x0, double tau,
+                  double tau_abs, double* margin, bool* near) {
   const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
-  // Margin in double precision.  A row whose entries are all equal is drawn
-  // exactly on both sides (every weight is exp(0) = 1), so it has no margin.
+  double m = psi[0];
   bool flat = true;
-  for (int j = 1; j < A; ++j) flat = flat && (psi[j] == psi[0]);
-  if (flat) {
-    *margin = 1.0;
-  } else {
-    double m = psi[0];
-    for (int j = 1; j < A; ++j) m = std::max(m, psi[j]);
-    std::vector<double> P(A);
-    double run = 0.0;
-    for (int j = 0; j < A; ++j) { run += std::exp(eta * (psi[j] - m)); P[j] = run; }
-    double t = u * P[A - 1];
-    double best = 1.0;
-    for (int j = 0; j + 1 < A; ++j)
-      best = std::min(best, std::fabs(t - P[j]) / P[A - 1]);
-    *margin = best;
+  for (int j = 1; j < A; ++j) {
+    m = std::max(m, psi[j]);
+    flat = flat && (psi[j] == psi[0]);
   }
-  if (root) {
-    double m = psi[0];
-    for (int j = 1; j < A; ++j) m = std::max(m, psi[j]);
-    double run = 0.0;
-    std::vector<double> P(A);
-    for (int j = 0; j < A; ++j) { run += std::exp(eta * (psi[j] - m)); P[j] = run; }
-    double t = u * P[A - 1];
-    for (int j = 0; j < A; ++j)
-      if (t < P[j]) return j;
-    return A - 1;
-  }
-  const float uf = (float)(x0 >> 8) * (1.0f / 16777216.0f);
-  const float ef = (float)eta;
-  std::vector<float> f(A), P(A);
-  float m = (float)psi[0];
-  for (int j = 0; j < A; ++j) { f[j] = (float)psi[j]; m = std::max(m, f[j]); }
-  if (A > kLongRow) {
-    // Long rows: single-precision weights scaled to 24-bit integers, so the
-    // running sums are exact and do not depend on the order of addition.
-    std::vector<uint64_t> W(A);
-    uint64_t tot = 0;
-    for (int j = 0; j < A; ++j) {
-      W[j] = (uint64_t)(uint32_t)(expf(ef * (f[j] - m)) * 16777216.0f);
-      tot += W[j];
-    }
-    const uint64_t ti = ((uint64_t)(x0 >> 8) * tot) >> 24;
-    uint64_t acc = 0;
-    for (int j = 0; j < A; ++j) {
-      acc += W[j];
-      if (ti < acc) return j;
-    }
-    return A - 1;
-  }
-  float run = 0.0f;
-  for (int j = 0; j < A; ++j) { run += expf(ef * (f[j] - m)); P[j] = run; }
-  float t = uf * P[A - 1];
+  std::vector<double> P(A);
+  double run = 0.0;
+  for (int j = 0; j < A; ++j) { run += std::exp(eta * (psi[j] - m)); P[j] = run; }
+  const double t = u * P[A - 1];
+  int a = A - 1;
   for (int j = 0; j < A; ++j)
-    if (t < P[j]) return j;
-  return A - 1;
+    if (t < P[j]) { a = j; break; }
+  *margin = 1.0;
+  *near = false;
+  if (!flat) {
+    const double lim = tau * P[A - 1] + tau_abs;
+    for (int j = 0; j + 1 < A; ++j) {
+      const double dist = std::fabs(t - P[j]);
+      *margin = std::min(*margin, dist / P[A - 1]);
+      if (dist <= lim) *near = true;
+    }
+  }
+  return a;
 }
 
 struct Particle { int32_t ep; State st; int32_t b; };
@@ -584,8 +549,6 @@ Result* plan(const Model& model, int A, const State* belief, int M,
   const double eta = prm->eta;
   const double gamma = model.gamma;
   const Tree* start = prm->start ? &((const Result*)prm->start)->tree : nullptr;
-  // A kept root's preference row was a non-root row before (single precision
-  // in the GPU's records), so its draws are screened like non-root draws.
   const bool kept_root = start && !start->b_parent.empty();
   if (kept_root) {
     T = *start;                                // plan from the kept subtree
@@ -615,11 +578,11 @@ Result* plan(const Model& model, int A, const State* belief, int M,
         Words x = draw(prm->seed, (uint32_t)P.ep, TAG_STEP, (uint32_t)d,
                        (uint32_t)k, prm->step);
         double margin = 1.0;
-        int a = sample_action(&T.psi[(size_t)P.b * A], A, eta, x.w[0],
-                              P.b == 0, &margin);
+        bool near = false;
+        int a = sample_action(&T.psi[(size_t)P.b * A], A, eta, x.w[0], prm->tau,
+                              prm->tau_abs, &margin, &near);
         res->n_draws++;
-        // The root row is double precision on both sides.
-        if (margin < (P.b == 0 && !kept_root ? 1e-12 : prm->tau)) res->near_ties++;
+        if (near) res->near_ties++;
         res->min_margin = std::min(res->min_margin, margin);
         Outcome o = model.step(P.st, a, x);
         res->particle_steps++;
@@ -633,7 +596,7 @@ Result* plan(const Model& model, int A, const State* belief, int M,
         }
         if (prm->trace)
           res->trace.push_back(TraceRow{k, d, P.ep, P.b, a, o.obs,
-                                        o.term ? 1 : 0, an, o.r, margin});
+                                        o.term ? 1 : 0, an, near ? 1 : 0, o.r, margin});
       }
       live.swap(next);
     }
@@ -765,6 +728,20 @@ void orc_result_trace(const void* h, int32_t* ints, float* r, double* margin) {
   }
 }
 
+// The per-draw trace as dense arrays indexed by (level step, episode): level
+// step t = step_base[k-1] + d is level d of iteration k.  act [steps*n_p]
+// (-1 where no draw), obs, flags: bit 0 drawn, bit 1 terminal, bit 2 near tie.
+void orc_result_draws(const void* h, const int32_t* step_base, int32_t n_p, int16_t* act,
+                      int32_t* obs, uint8_t* flags) {
+  const Result* res = (const Result*)h;
+  for (const TraceRow& t : res->trace) {
+    const size_t i = (size_t)(step_base[t.k - 1] + t.d) * (size_t)n_p + (size_t)t.ep;
+    act[i] = (int16_t)t.a;
+    obs[i] = t.obs;
+    flags[i] = (uint8_t)(1u | (t.term ? 2u : 0u) | (t.near ? 4u : 0u));
+  }
+}
+
 void orc_result_free(void* h) { delete (Result*)h; }
 
 // The tree of a finished plan re-rooted at (a, o); a result handle holding
@@ -792,9 +769,19 @@ int32_t orc_pick(const uint32_t* thr, int32_t n, uint32_t x) {
   return pick(thr, n, x);
 }
 
-int32_t orc_sample_action(const double* psi, int32_t A, double eta,
-                          uint32_t x0, int32_t root, double* margin) {
-  return sample_action(psi, A, eta, x0, root != 0, margin);
+int32_t orc_sample_action(const double* psi, int32_t A, double eta, uint32_t x0,
+                          double tau, double tau_abs, double* margin, int32_t* near) {
+  bool nr = false;
+  const int a = sample_action(psi, A, eta, x0, tau, tau_abs, margin, &nr);
+  if (near) *near = nr ? 1 : 0;
+  return a;
+}
+
+// Likelihood of observation key o at navigation position (x, y), in units of
+// 2^-24 (the count of noise-index pairs whose observation lands in o's cell).
+uint64_t orc_nav_obs_weight(const orc_nav* m, float x, float y, int32_t o) {
+  NavModel model(m);
+  return model.obs_weight(x, y, o);
 }
 
 // One navigation model step, for the fp32 arithmetic pins.

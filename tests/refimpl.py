@@ -71,13 +71,10 @@ def pick(thr, x):
 
 
 def uniform_row_action(x0, A):
-    """Action drawn from a uniform preference row, in single precision."""
-    u = np.float32((int(x0) >> 8)) * np.float32(1.0 / 16777216.0)
-    t = np.float32(u * np.float32(A))
-    for j in range(A):
-        if t < np.float32(j + 1):
-            return j
-    return A - 1
+    """Action drawn from a uniform preference row by Eq. (6): the running sums
+    are 1, 2, ..., |A| and t = u |A| with u = (x0 >> 8) 2^-24, so the first j
+    with t < j + 1 is floor(u |A|), computed here in integers."""
+    return min(((int(x0) >> 8) * A) >> 24, A - 1)
 
 
 def root_probs(M):

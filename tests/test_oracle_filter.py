@@ -104,3 +104,104 @@ def test_nav_cell_counts_cover_the_table():
         assert sum(cells.values()) == 4096
         for k, c in list(cells.items())[:3]:
             assert R.nav_cell_count(mdl, v, sd, k) == c
+
+
+# --- navigation likelihood (the SIR weight of the navigation model) -----------
+
+def test_nav_likelihood_sums_to_one_over_cells(orc):
+    # Every (x-noise, y-noise) index pair of the observation lands in exactly
+    # one grid cell, so the likelihood counts over all cells sum to 4096^2 at
+    # any position: near the clamped border of the grid too.
+    nav = I.nav2d(0, 4)
+    small = dict(nav, key_lo=2, key_n=12)       # cells [1, 7) per axis, clamped
+    for inst, pos in ((nav, (5.0, 5.0)), (small, (0.3, 9.7)), (small, (6.0, 3.2))):
+        n = inst["key_n"]
+        tot = sum(orc.nav_obs_weight(inst, pos[0], pos[1], o) for o in range(n * n))
+        assert tot == 4096 * 4096
+
+
+def _axis_cells(inst, v):
+    """Grid cell per axis of fp32 values v (floor, clamp), as the model keys
+    its observations."""
+    f = np.float32
+    c = np.floor(v * f(inst["inv_bin"])).astype(np.float32)
+    c = np.clip(c, f(inst["key_lo"]), f(inst["key_lo"] + inst["key_n"] - 1))
+    return c.astype(np.int64) - inst["key_lo"]
+
+
+def _posterior_one_axis(inst, pos, a, o):
+    """Bayes posterior of the moved position along the axis that moves freely,
+    for a particle at pos pushed into a wall by action a (so the other axis is
+    clamped to the wall whatever its noise): enumerate the 4096 motion-noise
+    values of the free axis and, for each, the 4096 x 4096 observation-noise
+    pairs, as the model draws them (fp32 throughout)."""
+    f = np.float32
+    g = np.asarray(inst["gauss"], np.float32)
+    lo, hi = f(inst["lo"]), f(inst["hi"])
+    sm = f(inst["sigma_move"])
+    step = f(inst["step"])
+    x0, y0 = f(pos[0]), f(pos[1])
+    dx = {0: f(0), 1: step, 2: f(0), 3: -step}[a]
+    dy = {0: step, 1: f(0), 2: -step, 3: f(0)}[a]
+    nx = np.clip((x0 + dx) + sm * g, lo, hi).astype(np.float32)   # x-noise index i
+    ny = np.clip((y0 + dy) + sm * g, lo, hi).astype(np.float32)   # y-noise index i'
+    free_x = a in (0, 2)
+    if free_x:
+        assert np.all(ny == ny[0])
+        xs, ys = nx, np.full(4096, ny[0], np.float32)
+    else:
+        assert np.all(nx == nx[0])
+        xs, ys = np.full(4096, nx[0], np.float32), ny
+    sd = (f(inst["sigma_obs0"]) +
+          f(inst["sigma_obs_slope"]) * np.abs(xs - f(inst["obs_center_x"]))).astype(np.float32)
+    kn = inst["key_n"]
+    kx, ky = o // kn, o % kn
+    like = np.zeros(4096)
+    for i in range(4096):
+        ox = (xs[i] + (sd[i] * g).astype(np.float32)).astype(np.float32)
+        oy = (ys[i] + (sd[i] * g).astype(np.float32)).astype(np.float32)
+        like[i] = (np.count_nonzero(_axis_cells(inst, ox) == kx) *
+                   np.count_nonzero(_axis_cells(inst, oy) == ky))
+    return (xs if free_x else ys), like / like.sum()
+
+
+@pytest.mark.parametrize("pos,a", [((4.3, 10.0), 0), ((10.0, 6.1), 1)])
+def test_nav_resampling_follows_bayes_posterior(orc, pos, a):
+    # Particles at one position pushed into a wall: the moved position varies
+    # along one axis only, and its posterior given the observation is the
+    # prior over the 4096 motion-noise values times the likelihood of the
+    # observed cell, enumerated over the observation noise.  One resampled
+    # particle per filter run (independent runs by seed) must follow it
+    # (chi-square over 8 equal-mass bins; self-normalised weights over n = 48
+    # particles bias each bin by about 1/n of its mass, below the test's
+    # resolution).
+    inst = I.nav2d(1, 4)
+    n, runs = 48, 1500
+    free, post = None, None
+    # The observation: the cell of the unperturbed move.
+    f = np.float32
+    tgt = (f(min(max(pos[0] + (1.0 if a == 1 else -1.0 if a == 3 else 0.0), 0.0), 10.0)),
+           f(min(max(pos[1] + (1.0 if a == 0 else -1.0 if a == 2 else 0.0), 0.0), 10.0)))
+    o = int(_axis_cells(inst, np.array([tgt[0]], np.float32))[0] * inst["key_n"] +
+            _axis_cells(inst, np.array([tgt[1]], np.float32))[0])
+    free, post = _posterior_one_axis(inst, pos, a, o)
+    # Bin edges at the posterior's octiles over the sorted values.
+    order = np.argsort(free, kind="stable")
+    cdf = np.cumsum(post[order])
+    edges = [free[order][np.searchsorted(cdf, q)] for q in np.arange(1, 8) / 8]
+    def bin_of(v):
+        return int(np.searchsorted(np.asarray(edges, np.float32), np.float32(v), side="right"))
+    mass = np.zeros(8)
+    for v, p in zip(free, post):
+        mass[bin_of(v)] += p
+    cnt = np.zeros(8)
+    bx = np.full(n, pos[0], np.float32)
+    by = np.full(n, pos[1], np.float32)
+    for r in range(runs):
+        (nx, ny), tot = orc.belief_update(inst, (bx, by), a, o, seed=1000 + r, step=r % 7)
+        assert tot > 0
+        cnt[bin_of(nx[0] if a in (0, 2) else ny[0])] += 1
+    m = mass > 0
+    chi2 = (((cnt[m] - runs * mass[m]) ** 2) / (runs * mass[m])).sum()
+    from scipy import stats
+    assert stats.chi2.sf(chi2, df=int(m.sum()) - 1) > 1e-4, (cnt, runs * mass)

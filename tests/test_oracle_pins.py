@@ -92,27 +92,38 @@ def test_root_draw_counts_closed_form():
 # --- action sampling (Eq. 6) ---------------------------------------------------
 
 def test_uniform_row_draw_is_floor_u_times_A(orc):
-    # With every preference equal, the softmax is uniform and the draw is
-    # floor(u |A|) for u = (x0 >> 8) 2^-24, up to the single-precision
-    # rounding of u*|A| at the non-root beliefs.
+    # With every preference equal, the softmax of Eq. (6) is uniform and the
+    # inverse-CDF draw is floor(u |A|) for u = (x0 >> 8) 2^-24, at every
+    # belief; such a draw is never a near tie.
     rng = np.random.default_rng(1)
     xs = list(rng.integers(0, 2 ** 32, size=3000)) + [0, 0xFFFFFFFF, 0x80000000]
-    for A in (2, 3, 4, 5, 6, 8, 64):
+    for A in (1, 2, 3, 4, 5, 6, 8, 64):
         psi = np.full(A, -math.log(A))
         for x in xs:
-            a_root, _ = orc.sample_action(psi, 1.0, int(x), True)
-            a_leaf, _ = orc.sample_action(psi, 1.0, int(x), False)
-            exact = min(((int(x) >> 8) * A) >> 24, A - 1)
-            assert a_root == exact
-            assert a_leaf == R.uniform_row_action(int(x), A)
-    # The one fp32 rounding case found by hand for |A| = 6: u*6 = 5 - 2^-23
-    # rounds up to 5, so the single-precision draw is 5 where exact is 4.
+            a, margin, near = orc.sample_action(psi, 1.0, int(x), 2.0 ** -12, 1e-6)
+            assert a == R.uniform_row_action(int(x), A) == ((int(x) >> 8) * A) >> 24
+            assert margin == 1.0 and not near
+    # u |A| = 5 - 2^-23 for |A| = 6 lies just below the boundary at 5: the
+    # exact draw is 4 (a single-precision product would round it up to 5).
     k = (5 * 2 ** 23 - 1) // 3
     x = k << 8
     assert ((x >> 8) * 6) >> 24 == 4
-    assert R.uniform_row_action(x, 6) == 5
-    assert orc.sample_action(np.zeros(6), 1.0, x, False)[0] == 5
-    assert orc.sample_action(np.zeros(6), 1.0, x, True)[0] == 4
+    assert orc.sample_action(np.zeros(6), 1.0, x)[0] == 4
+
+
+def test_two_action_draw_closed_form(orc):
+    # Psi = (0, ln 3 / eta): weights (1/3, 1), so action 0 is drawn exactly
+    # when u < 1/4, i.e. x0 >> 8 < 2^22.  Draws next to that boundary are
+    # near ties under the screen; draws far from it are not.
+    for eta in (0.5, 1.0, 2.0):
+        psi = np.array([0.0, math.log(3.0) / eta])
+        for q, want in ((0, 0), (1, 0), (2 ** 22 - 1, 0), (2 ** 22 + 1, 1),
+                        (2 ** 23, 1), (2 ** 24 - 1, 1)):
+            a, margin, near = orc.sample_action(psi, eta, q << 8, 2.0 ** -12, 0.0)
+            assert a == want
+            assert near == (q in (2 ** 22 - 1, 2 ** 22 + 1))
+            exact = abs(q / 2.0 ** 24 * 4.0 / 3.0 - 1.0 / 3.0) / (4.0 / 3.0)
+            assert margin == pytest.approx(exact, rel=1e-9, abs=1e-15)
 
 
 def test_softmax_draw_frequencies(orc):
@@ -125,7 +136,7 @@ def test_softmax_draw_frequencies(orc):
     n = 20000
     cnt = np.zeros(5)
     for x in rng.integers(0, 2 ** 32, size=n):
-        cnt[orc.sample_action(psi, eta, int(x), False)[0]] += 1
+        cnt[orc.sample_action(psi, eta, int(x))[0]] += 1
     chi2 = (((cnt - n * p) ** 2) / (n * p)).sum()
     assert chi2 < 20.0          # p ~ 5e-4 for 4 degrees of freedom
 

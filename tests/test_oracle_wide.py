@@ -14,33 +14,39 @@ from tests import refimpl as R
 
 @pytest.mark.parametrize("A", [625, 3025])
 def test_flat_row_draw(orc, A):
-    # Every weight is exp(0) = 1: at the root the running sums are the
-    # integers 1..A in double precision, elsewhere the integer weights are all
-    # 2^24; either way the draw is floor(u * A) with u = (x0 >> 8) / 2^24.
+    # Every weight is exp(0) = 1, the running sums are the integers 1..A, and
+    # the draw is floor(u * A) with u = (x0 >> 8) / 2^24.
     rng = np.random.default_rng(A)
     eta = 1.0
     row = np.full(A, -np.log(A) / eta)
     for x0 in rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64):
         x0 = int(x0)
         want = ((x0 >> 8) * A) >> 24
-        assert orc.sample_action(row, eta, x0, False)[0] == want
-        assert orc.sample_action(row, eta, x0, True)[0] == want
+        a, margin, near = orc.sample_action(row, eta, x0, 2.0 ** -12, 1e-4)
+        assert a == want and margin == 1.0 and not near
 
 
-def test_long_row_integer_weights(orc):
-    # A hand-made long row: two actions hold all but a sliver of the mass, so
-    # the truncated weights are known exactly and the boundaries sit at
-    # integer multiples that u = (x0 >> 8) / 2^24 can hit exactly.
+def test_long_row_exact_draw(orc):
+    # A hand-made long row: two actions hold all but exp(-40) of the mass
+    # each; the other 98 weigh exp(-40) ~ 4e-18.  By Eq. (6), t = u * P_last
+    # with P_last = 2 + 98 e^-40, so any u >= 2^-24 below 1/2 draws 17 and any
+    # u above 1/2 draws 63.  u = 0 gives t = 0 < P_0 = e^-40: action 0, a draw
+    # that sits on a boundary and is screened as a near tie.
     A, eta = 100, 1.0
-    row = np.full(A, -40.0)          # exp(-40) * 2^24 < 1: weight 0
-    row[17] = row[63] = 0.0          # weight 2^24 each; total 2^25, t = 2q
-    for q in (0, 1, 2 ** 22, 2 ** 23 - 1, 2 ** 23, 2 ** 23 + 1, 2 ** 24 - 1):
-        want = 17 if 2 * q < 2 ** 24 else 63
-        assert orc.sample_action(row, eta, q << 8, False)[0] == want
+    row = np.full(A, -40.0)
+    row[17] = row[63] = 0.0
+    for q in (1, 2, 2 ** 22, 2 ** 23 - 1, 2 ** 23 + 1, 2 ** 24 - 1):
+        a, _, near = orc.sample_action(row, eta, q << 8, 2.0 ** -12, 1e-5)
+        assert a == (17 if q < 2 ** 23 else 63)
+        # (u near 0 or 1 lies next to the boundaries that the light actions
+        # pile up at 0 and P_last: near ties as well)
+        if q in (2 ** 22, 2 ** 23 - 1, 2 ** 23 + 1):
+            assert near == (q != 2 ** 22)
+    a, _, near = orc.sample_action(row, eta, 0, 2.0 ** -12, 1e-5)
+    assert a == 0 and near
 
 
-@pytest.mark.parametrize("root", [False, True])
-def test_softmax_draw_frequencies_625(orc, root):
+def test_softmax_draw_frequencies_625(orc):
     rng = np.random.default_rng(9)
     A, eta, n = 625, 1.0, 120000
     row = rng.normal(0.0, 1.5, size=A)
@@ -48,7 +54,7 @@ def test_softmax_draw_frequencies_625(orc, root):
     p /= p.sum()
     counts = np.zeros(A)
     for x0 in rng.integers(0, 2 ** 32, size=n, dtype=np.uint64):
-        counts[orc.sample_action(row, eta, int(x0), root)[0]] += 1
+        counts[orc.sample_action(row, eta, int(x0))[0]] += 1
     # Bins: the 40 likeliest actions one by one, the rest pooled.
     order = np.argsort(-p)
     top = order[:40]
