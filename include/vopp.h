@@ -8,9 +8,10 @@
  * generative model G, AppendActions, FilterTerminals, AppendBeliefs) to the
  * iteration's depth, and the bottom-up preference backup of Alg. 3 (Q = C/N +
  * gamma W, Psi <- Psi - L_eta Psi + Q from Eq. 5, V = L_eta Psi from Eq. 3);
- * then the root action with the largest preference.  The tree is the tensor
- * store of Sec. III-C (belief rows, action-node rows, preference rows), kept
- * in HBM in structure-of-arrays form.
+ * then the root action with the largest preference.  The tree holds the
+ * tensors of Sec. III-C (belief rows, action-node rows, preference rows) as
+ * one record per belief in HBM: its preference row, the visit counts and
+ * reward sums of its action nodes, and its value, visit count and parent.
  *
  * Conventions for every entry point:
  *   - Every function returns a vopp_status; nothing throws across the ABI.
@@ -143,11 +144,19 @@ typedef struct {
   uint32_t step;
 } vopp_params;
 
+/* near_ties: action draws (Eq. 6) whose position t = u * P_last lies within
+ * 2^-16 * P_last of a neighbouring boundary P_j of the running sums, in the
+ * kernel's own arithmetic.  It counts draws from rows that a backup has
+ * updated (the root from the second iteration on, rows read from a record
+ * whose entries are not all equal); draws from the initial row are exact and
+ * do not count.  A planner that keeps its preferences in another precision
+ * may decide such a draw the other way. */
 typedef struct {
   int64_t particle_steps;   /* generative-model calls made by the plan     */
   int64_t n_beliefs;        /* beliefs of the tree (root included)         */
   int64_t n_actions;        /* action nodes (b, a) visited at least once   */
   double device_ms;         /* device time of the plan, HIP events          */
+  int64_t near_ties;        /* near-tie action draws (see above)           */
 } vopp_stats;
 
 /* A workspace holds one plan's tree and per-episode trace in HBM, sized for
@@ -186,6 +195,30 @@ vopp_status vopp_plan(const vopp_pomdp* pomdp, const void* belief_particles,
                       const vopp_params* params, vopp_workspace* ws,
                       void* stream, int32_t* action, double* values,
                       double* v_root, vopp_stats* stats);
+
+/* vopp_plan that also exports every action draw of the forward search
+ * (Alg. 2, one draw per live episode per level), for parity checks and
+ * debugging.  draw_act and draw_obs are DEVICE arrays of trace_len entries,
+ * at least n_steps * n_particles with n_steps = D_1 + ... + D_K (a re-rooted
+ * plan's kept steps not counted).  Entry t * n_particles + ep, for level step
+ * t = D_1 + ... + D_{k-1} + d (level d of iteration k) and episode ep, gets
+ * the action the episode drew there and the observation key G returned for
+ * it (also on the step that terminated it), or -1 in both once the episode
+ * has terminated.  force_act (DEVICE, may be NULL), same indexing: an entry
+ * in [0, nA) replaces the kernel's decision at that draw by that action; any
+ * other entry (-1) leaves it.  draw_act always receives the kernel's own decision.
+ * This is a test hook: a parity check forces the draws that a reference
+ * planner in another precision reports as near ties to that planner's
+ * decision, so the rest of the two trees can be compared bit for bit.
+ * Other arguments and outputs as for vopp_plan; the export adds two stores
+ * (and the force one load) per draw.  VOPP_E_INVALID for null output arrays
+ * or a short trace_len. */
+vopp_status vopp_plan_trace(const vopp_pomdp* pomdp, const void* belief_particles,
+                            int32_t n_belief, int32_t budget, int32_t depth,
+                            const vopp_params* params, vopp_workspace* ws, void* stream,
+                            int32_t* action, double* values, double* v_root,
+                            vopp_stats* stats, int16_t* draw_act, int32_t* draw_obs,
+                            const int16_t* force_act, int64_t trace_len);
 
 /* Anytime planning step: Alg. 1 with its wall-clock budget.  Iterations run
  * while the planning time is not used up: after each iteration the device

@@ -57,7 +57,8 @@ class OrcParams(C.Structure):
                 ("depth", C.c_int32), ("schedule", C.c_int32),
                 ("eta", C.c_double), ("seed", C.c_uint64),
                 ("step", C.c_uint32), ("tau", C.c_double),
-                ("tau_abs", C.c_double), ("trace", C.c_int32), ("mutate", C.c_int32),
+                ("tau_abs", C.c_double), ("tau_psi", C.c_double),
+                ("trace", C.c_int32), ("mutate", C.c_int32),
                 ("pi0", C.c_void_p), ("start", C.c_void_p)]
 
 
@@ -89,7 +90,7 @@ def load():
     lib.orc_pick.argtypes = [vp, C.c_int32, C.c_uint32]
     lib.orc_pick.restype = C.c_int32
     lib.orc_sample_action.argtypes = [vp, C.c_int32, C.c_double, C.c_uint32,
-                                      C.c_double, C.c_double, vp, vp]
+                                      C.c_double, C.c_double, C.c_double, vp, vp]
     lib.orc_sample_action.restype = C.c_int32
     lib.orc_nav_step.argtypes = [C.POINTER(OrcNav), C.c_float, C.c_float,
                                  C.c_int32, C.c_uint32, C.c_uint32] + [vp] * 5
@@ -225,32 +226,33 @@ def step_base(budget, depth, schedule):
 
 
 def plan(inst, belief, n_particles, budget, depth, eta=1.0, seed=1,
-         schedule=0, step=0, tau=2.0 ** -12, tau_abs=0.0, trace=False,
+         schedule=0, step=0, tau=2.0 ** -12, tau_abs=0.0, tau_psi=0.0, trace=False,
          draws=False, mutate=0, pi0=None, start=None, keep=False):
     """Run one serial planning step and return the full tree.  pi0: reference
     policy weights over the actions (positive; normalised), or None: uniform.
     start: a Handle from ``reroot`` to plan from its tree.  keep: keep the
-    result's handle (``.handle``) for re-rooting.  tau, tau_abs: near-tie
-    screen of the draws (|t - P_j| <= tau * P_last + tau_abs).  trace: the
+    result's handle (``.handle``) for re-rooting.  tau, tau_abs, tau_psi:
+    near-tie screen of the draws (|t - P_j| <= (tau + tau_psi * eta *
+    max |Psi|) * P_last + tau_abs).  trace: the
     per-draw rows; draws: the same as dense arrays by (level step, episode)
     (``act`` -1 where no draw; ``flags`` bit 0 drawn, 1 terminal, 2 near tie)."""
     lib = load()
-    keep = _Keep()
+    hold = _Keep()
     pi = None
     if pi0 is not None:
         pi = np.ascontiguousarray(pi0, np.float64)
         assert pi.shape == (inst["nA"],) and np.all(pi > 0)
-        keep.arrs.append(pi)
+        hold.arrs.append(pi)
     prm = OrcParams(n_particles, budget, depth, schedule, eta, seed, step,
-                    tau, tau_abs, 1 if (trace or draws) else 0, mutate,
+                    tau, tau_abs, tau_psi, 1 if (trace or draws) else 0, mutate,
                     None if pi is None else pi.ctypes.data,
                     None if start is None else start.h)
     if inst["kind"] == "tabular":
-        m = tabular_struct(inst, keep)
+        m = tabular_struct(inst, hold)
         bel = _c32(belief, np.int32)
         h = lib.orc_plan_tabular(C.byref(m), _ptr(bel), bel.size, C.byref(prm))
     else:
-        m = nav_struct(inst, keep)
+        m = nav_struct(inst, hold)
         bx = _c32(belief[0], np.float32)
         by = _c32(belief[1], np.float32)
         h = lib.orc_plan_nav(C.byref(m), _ptr(bx), _ptr(by), bx.size,
@@ -310,14 +312,15 @@ def pick(thr, x):
     return int(lib.orc_pick(_ptr(thr), thr.size, int(x) & 0xFFFFFFFF))
 
 
-def sample_action(psi, eta, x0, tau=0.0, tau_abs=0.0):
+def sample_action(psi, eta, x0, tau=0.0, tau_abs=0.0, tau_psi=0.0):
     """Eq. (6) draw: (action, margin, near tie under the screen)."""
     lib = load()
     psi = _c32(psi, np.float64)
     mg = np.zeros(1, np.float64)
     nr = np.zeros(1, np.int32)
     a = lib.orc_sample_action(_ptr(psi), psi.size, eta, int(x0) & 0xFFFFFFFF,
-                              float(tau), float(tau_abs), _ptr(mg), _ptr(nr))
+                              float(tau), float(tau_abs), float(tau_psi), _ptr(mg),
+                              _ptr(nr))
     return int(a), float(mg[0]), bool(nr[0])
 
 

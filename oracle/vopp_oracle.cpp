@@ -55,9 +55,10 @@
  *     = first j with t < P_j (clamped to |A|-1).  A row whose preferences are
  *     all equal therefore gives floor(u |A|) exactly.  The oracle also reports
  *     how close t lies to the nearest interior boundary P_j: a draw is a near
- *     tie when some |t - P_j| <= tau * P_last + tau_abs (both passed in by the
- *     caller; max weight = 1).  Any planner that keeps its preferences in
- *     another precision may decide such a draw either way.
+ *     tie when some |t - P_j| <= (tau + tau_psi * eta * max_j |Psi_j|) *
+ *     P_last + tau_abs (all three passed in by the caller; max weight = 1).
+ *     Any planner that keeps its preferences in another precision may decide
+ *     such a draw either way.
  *   - Tabular G: thresholds thr_j = rint(cum_j / total * 2^31) from the
  *     sequential double sum of the fp32 row (last = 2^31); outcome = first j
  *     with (x >> 1) < thr_j.  Successor from word 1, observation from word 2
@@ -185,8 +186,9 @@ typedef struct {
   double eta;
   uint64_t seed;
   uint32_t step;
-  double tau;      // near-tie screen: |t - P_j| <= tau * P_last + tau_abs
-  double tau_abs;
+  double tau;      // near-tie screen: |t - P_j| <= lim with
+  double tau_abs;  // lim = (tau + tau_psi * eta * max_j |Psi_j|) * P_last + tau_abs
+  double tau_psi;
   int32_t trace;   // keep a per-draw trace
   int32_t mutate;  // 0: none.  >0 plants a known mistake (pin sensitivity)
   const double* pi0;  // [A] reference policy weights (> 0), or NULL: uniform
@@ -509,14 +511,20 @@ struct Result {
 // Action draw of Eq. (6) in double precision.  *margin: distance of t from
 // the nearest interior boundary, relative to P_last (1 for a flat row, whose
 // draw floor(u |A|) is exact in any precision); *near: some interior boundary
-// lies within tau * P_last + tau_abs of t.
+// lies within lim = (tau + tau_psi * eta * max_j |Psi_j|) * P_last + tau_abs
+// of t.  The tau_psi term scales with the row's magnitude: a planner that
+// keeps preferences in a precision with relative rounding e perturbs every
+// weight exp(eta (Psi_j - max)) by a relative amount of order
+// eta * e * max |Psi|, and so every running sum by that much of P_last.
 int sample_action(const double* psi, int A, double eta, uint32_t x0, double tau,
-                  double tau_abs, double* margin, bool* near) {
+                  double tau_abs, double tau_psi, double* margin, bool* near) {
   const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
   double m = psi[0];
+  double mag = std::fabs(psi[0]);
   bool flat = true;
   for (int j = 1; j < A; ++j) {
     m = std::max(m, psi[j]);
+    mag = std::max(mag, std::fabs(psi[j]));
     flat = flat && (psi[j] == psi[0]);
   }
   std::vector<double> P(A);
@@ -529,7 +537,7 @@ int sample_action(const double* psi, int A, double eta, uint32_t x0, double tau,
   *margin = 1.0;
   *near = false;
   if (!flat) {
-    const double lim = tau * P[A - 1] + tau_abs;
+    const double lim = (tau + tau_psi * eta * mag) * P[A - 1] + tau_abs;
     for (int j = 0; j + 1 < A; ++j) {
       const double dist = std::fabs(t - P[j]);
       *margin = std::min(*margin, dist / P[A - 1]);
@@ -580,7 +588,7 @@ Result* plan(const Model& model, int A, const State* belief, int M,
         double margin = 1.0;
         bool near = false;
         int a = sample_action(&T.psi[(size_t)P.b * A], A, eta, x.w[0], prm->tau,
-                              prm->tau_abs, &margin, &near);
+                              prm->tau_abs, prm->tau_psi, &margin, &near);
         res->n_draws++;
         if (near) res->near_ties++;
         res->min_margin = std::min(res->min_margin, margin);
@@ -770,9 +778,10 @@ int32_t orc_pick(const uint32_t* thr, int32_t n, uint32_t x) {
 }
 
 int32_t orc_sample_action(const double* psi, int32_t A, double eta, uint32_t x0,
-                          double tau, double tau_abs, double* margin, int32_t* near) {
+                          double tau, double tau_abs, double tau_psi, double* margin,
+                          int32_t* near) {
   bool nr = false;
-  const int a = sample_action(psi, A, eta, x0, tau, tau_abs, margin, &nr);
+  const int a = sample_action(psi, A, eta, x0, tau, tau_abs, tau_psi, margin, &nr);
   if (near) *near = nr ? 1 : 0;
   return a;
 }

@@ -326,11 +326,11 @@ size_t bytes_for(const WsSizes& z) {
   add(z.hcap * sizeof(HSlot));                       // table
   const size_t ar = (size_t)std::max(kMaxA, z.Apad);
   add(ar * 8); add(ar * 8); add(8);                  // root row and its CDF, V(root)
-  add(ar * 8);                                       // draw sums of the initial row
+  add(ar * 8);                                       // running sums of the initial row
   add(ar * 4);                                       // initial preference row
   add((size_t)3 * z.Apad * kStripes * 8);            // striped root action nodes
   add((size_t)z.steps * z.n_p * 4);                  // level-step lists
-  add(64); add(5 * kStripes * 8); add(32); add((z.K + 1) * 4);
+  add(64); add(kStatRows * kStripes * 8); add(32); add((z.K + 1) * 4);
   add(2 * (kMaxDepth + 1) * 4);                      // kept-subtree steps by depth
   add((size_t)(z.depth + 1) * z.n_p * 8);            // trace words
   add((size_t)(z.depth + 1) * z.n_p * 4);            // trace values
@@ -366,12 +366,12 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.psi_root = c.take<double>(ar);
   t.psi0 = c.take<float>(ar);
   t.root_cdf = c.take<double>(ar);
-  t.psi0_cdf = c.take<unsigned long long>(ar);
+  t.psi0_cdf64 = c.take<double>(ar);
   t.root_acc = c.take<unsigned long long>((size_t)3 * z.Apad * kStripes);
   t.v_root = c.take<double>(1);
   t.list = c.take<int>((size_t)z.steps * z.n_p);
   t.counters = c.take<unsigned long long>(8);
-  t.stats = c.take<unsigned long long>(5 * kStripes);
+  t.stats = c.take<unsigned long long>(kStatRows * kStripes);
   t.gate = c.take<unsigned long long>(4);
   w->carry_rng_dev = c.take<int>(2 * (kMaxDepth + 1));
   t.carry_rng = w->carry_rng_dev;
@@ -660,13 +660,23 @@ vopp_status ensure_ws(const vopp_pomdp* p, vopp_workspace** ws, const vopp_param
 namespace vopp {
 // vopp_plan (time_ms = 0) and vopp_plan_anytime (time_ms > 0; budget is then
 // the iteration cap).
+// draw_act / draw_obs: the optional per-draw export (vopp_plan_trace).
 static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t n_belief,
                                int32_t budget, int32_t depth, const vopp_params* prm,
                                vopp_workspace* ws, void* stream, double time_ms,
                                int32_t* action, double* values, double* v_root,
-                               vopp_stats* stats, int32_t* iterations) {
+                               vopp_stats* stats, int32_t* iterations,
+                               int16_t* draw_act = nullptr, int32_t* draw_obs = nullptr,
+                               const int16_t* force_act = nullptr, int64_t trace_len = 0) {
   vopp_status st = check_params(p, prm, budget, depth);
   if (st != VOPP_OK) return st;
+  if ((draw_act == nullptr) != (draw_obs == nullptr))
+    return fail(VOPP_E_INVALID, "the draw trace needs both arrays");
+  if (draw_act &&
+      trace_len < (int64_t)sum_depths(budget, depth, prm->schedule) * prm->n_particles)
+    return fail(VOPP_E_INVALID, "draw trace holds %lld entries, the plan needs %lld",
+                (long long)trace_len,
+                (long long)sum_depths(budget, depth, prm->schedule) * prm->n_particles);
   if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
   if (!action) return fail(VOPP_E_INVALID, "null action pointer");
   int dev = -1;
@@ -695,6 +705,12 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
   if (ws->z.Apad < p->view.Apad) return fail(VOPP_E_INVALID, "workspace built for fewer actions");
   hipStream_t s = (hipStream_t)stream;
   PlanView P = make_view(p, ws, belief, n_belief, budget, depth, prm);
+  if (draw_act) {
+    P.t.dbg_act = draw_act;
+    P.t.dbg_obs = draw_obs;
+    P.t.dbg_force = force_act;
+    P.t.dbg_step0 = P.carry ? ws->carry.n_steps : 0;
+  }
   hipError_t e = hipSuccess;
   if (time_ms > 0.0) {
     int khz = 0;
@@ -777,6 +793,7 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
     stats->particle_steps = (int64_t)o[A + 2];
     stats->n_beliefs = (int64_t)nb;
     stats->n_actions = (int64_t)na;
+    stats->near_ties = (int64_t)o[A + 6];
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
     stats->device_ms = ms;
@@ -793,6 +810,18 @@ extern "C" vopp_status vopp_plan(const vopp_pomdp* p, const void* belief, int32_
   clear_error();
   return plan_common(p, belief, n_belief, budget, depth, prm, ws, stream, 0.0, action, values,
                      v_root, stats, nullptr);
+}
+
+extern "C" vopp_status vopp_plan_trace(const vopp_pomdp* p, const void* belief,
+                                       int32_t n_belief, int32_t budget, int32_t depth,
+                                       const vopp_params* prm, vopp_workspace* ws, void* stream,
+                                       int32_t* action, double* values, double* v_root,
+                                       vopp_stats* stats, int16_t* draw_act, int32_t* draw_obs,
+                                       const int16_t* force_act, int64_t trace_len) {
+  clear_error();
+  if (!draw_act || !draw_obs) return fail(VOPP_E_INVALID, "null draw trace");
+  return plan_common(p, belief, n_belief, budget, depth, prm, ws, stream, 0.0, action, values,
+                     v_root, stats, nullptr, draw_act, draw_obs, force_act, trace_len);
 }
 
 extern "C" vopp_status vopp_plan_anytime(const vopp_pomdp* p, const void* belief,

@@ -129,8 +129,10 @@ struct TreeView {
   float* psi0;                   // [ra] initial preference row ln pi0 / eta,
                                  // zero past |A|
   double* root_cdf;              // [nA] running sums of the root's softmax weights
-  unsigned long long* psi0_cdf;  // [nA] long rows: running sums of the integer
-                                 // draw weights of the initial row psi0
+  double* psi0_cdf64;            // [nA] running sums of the softmax weights of
+                                 // the initial row (double precision; the draws
+                                 // at beliefs created in the current iteration
+                                 // read them)
   unsigned long long* root_acc;  // [3][ra][kStripes]: N, C and W of the root's
                                  // action nodes, striped over blocks (every
                                  // episode passes through one of them)
@@ -140,9 +142,10 @@ struct TreeView {
   unsigned long long* counters;  // [1] error flags [2] beliefs of the last plan
                                  // [3] table dirty [5] last plan's level steps
                                  // [6] last plan's n_p
-  unsigned long long* stats;     // [5][kStripes] particle steps, then two banks
-                                 // of (action nodes, beliefs), striped over
-                                 // blocks so that no address takes many atomics
+  unsigned long long* stats;     // [6][kStripes] particle steps, then two banks
+                                 // of (action nodes, beliefs), then near-tie
+                                 // draws, striped over blocks so that no
+                                 // address takes many atomics
   unsigned long long* gate;      // [4] plans with a time budget: [0] start on
                                  // the wall clock, [1] stop flag, [2] iterations run
   const int* carry_rng;          // [kMaxDepth + 1][2] level steps of a kept
@@ -150,6 +153,16 @@ struct TreeView {
   const int* step_base;          // [K+1] first level step of each iteration
   unsigned long long* tr_key;    // [(depth + 1) * n_p] trace words
   float* tr_val;                 // reward (levels) or heuristic (leaf)
+  // Optional per-draw export (null unless a traced plan): for the plan's own
+  // level step t (0-based, kept-subtree steps not counted) and episode ep,
+  // entry t * n_p + ep holds the drawn action and the observation key, or -1
+  // where the episode drew nothing (it had terminated).
+  short* dbg_act;
+  int* dbg_obs;
+  // Optional forced draws, same indexing: an entry in [0, nA) replaces the
+  // kernel's decision at that draw (dbg_act still receives the kernel's own).
+  const short* dbg_force;
+  int dbg_step0;                 // level step of the plan's first own step
 };
 
 // Long rows (ra > kMaxA) add a bitmap of ra bits after RecMeta, padded to
@@ -194,6 +207,8 @@ struct EpisodeView {
 
 constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
 constexpr int kStripes = 64;                // stripes of each tree statistic
+constexpr int kStatRows = 6;                // rows of kStripes in TreeView::stats
+constexpr int kStatNear = 5;                // row of the near-tie draw count
 constexpr int kAccumCap = 4096;             // default block cap of the accumulate sweep
 
 // Particle-filter belief and true-environment state of a served episode.
@@ -253,7 +268,7 @@ __device__ __forceinline__ bool budget_spent(const PlanView& P) {
 
 // Result record written by the select phase (doubles): [0] action,
 // [1..A] root preferences, [A+1] V(root), [A+2] particle steps, [A+3] beliefs,
-// [A+4] action nodes, [A+5] input-error flags.
+// [A+4] action nodes, [A+5] input-error flags, [A+6] near-tie draws.
 constexpr int kOutStride = kMaxA + 8;
 
 // Phase kinds (same numbering as the ABI's VOPP_KERNEL_* kinds).
@@ -466,31 +481,46 @@ __device__ __forceinline__ float nav_heuristic(const NavParams& p, float x, floa
   return -(fabsf(x - p.goal_x) + fabsf(y - p.goal_y));
 }
 
-// Softmax draw of Eq. (6) in single precision over a row held in registers:
-// weights exp(eta (psi_j - max)), running sums P_j, t = u * P_last, first j
-// with t < P_j.  AM >= A is a compile-time bound so the row stays in registers.
+// Near-tie screen of the kernel's own draws: a draw counts as a near tie when
+// t lies within kTieRel * P_last of an interior boundary P_j next to it (the
+// running sums just below and above t).  Rows whose entries are all equal are
+// decided exactly and never count.
+constexpr double kTieRel = 1.0 / 65536.0;
+
+// Softmax draw of Eq. (6) over a row held in registers: single-precision
+// weights exp(eta (psi_j - max)), their running sums P_j and t = u * P_last
+// in double precision, action = first j with t < P_j.  The double sums of
+// single-precision weights are exact to far below the weights' own rounding,
+// and the product u * P_last is exact, so a row whose entries are all equal
+// (weights exactly 1, P_j = j + 1) gives floor(u |A|) exactly.  AM >= A is a
+// compile-time bound so the row stays in registers.
 template <int AM>
-__device__ __forceinline__ int draw_row32(float (&v)[AM], int A, float eta, uint32_t x0) {
+__device__ __forceinline__ int draw_row32(float (&v)[AM], int A, float eta, uint32_t x0,
+                                          bool& near) {
   float m = v[0];
+  bool flat = true;
 #pragma unroll
   for (int j = 1; j < AM; ++j)
-    if (j < A) m = fmaxf(m, v[j]);
-  float total = 0.0f;
+    if (j < A) { m = fmaxf(m, v[j]); flat = flat && v[j] == v[0]; }
+  double total = 0.0;
 #pragma unroll
   for (int j = 0; j < AM; ++j)
-    if (j < A) { v[j] = expf(eta * (v[j] - m)); total = total + v[j]; }
-  const float u = (float)(x0 >> 8) * (1.0f / 16777216.0f);
-  const float t = u * total;
-  float run = 0.0f;
+    if (j < A) { v[j] = expf(eta * (v[j] - m)); total = total + (double)v[j]; }
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double t = u * total;
+  double run = 0.0, below = 0.0, above = total;
   int a = A - 1;
   bool found = false;
 #pragma unroll
   for (int j = 0; j < AM; ++j) {
     if (j < A && !found) {
-      run = run + v[j];
-      if (t < run) { a = j; found = true; }
+      below = run;
+      run = run + (double)v[j];
+      if (t < run) { a = j; found = true; above = run; }
     }
   }
+  const double lim = kTieRel * total;
+  near = !flat && ((a > 0 && t - below <= lim) || (a < A - 1 && above - t <= lim));
   return a;
 }
 
@@ -541,6 +571,18 @@ __device__ __forceinline__ int draw_cdf64(const double* __restrict__ cdf, int A,
   for (int j = 0; j < A; ++j)
     if (t < cdf[j]) return j;
   return A - 1;
+}
+
+// Whether the draw of action a from running sums cdf lies within kTieRel *
+// P_last of one of its interior boundaries (cdf[a - 1] below, cdf[a] above).
+// flat: the row's entries are all equal (then the draw is exact).
+__device__ __forceinline__ bool near_tie64(const double* __restrict__ cdf, int A, uint32_t x0,
+                                           int a) {
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double tot = cdf[A - 1];
+  const double t = u * tot;
+  const double lim = kTieRel * tot;
+  return (a > 0 && t - cdf[a - 1] <= lim) || (a < A - 1 && cdf[a] - t <= lim);
 }
 
 // Fixed-point conversion of a value for the order-independent sums.

@@ -205,38 +205,6 @@ __device__ double block_max64(double v, double* red);
 __device__ double block_ordered_sum(const double* x, int A, double m, double eta, double* cdf,
                                     double* buf, double* bc);
 
-__device__ __forceinline__ unsigned long long long_row_weight(float v, float m, float eta);
-
-// Running sums, in action order, of the integer draw weights of the initial
-// row psi0 (the weights of a long-row draw, for rows still equal to psi0: the
-// beliefs created in the current iteration).  Thread j sums a contiguous run
-// of actions; the runs' totals are scanned by one thread.
-__device__ void psi0_draw_sums(const TreeView& T, int A, float eta, int j, SetupSmem* ss) {
-  double mloc = -INFINITY;
-  for (int a = j; a < A; a += kBlock) mloc = fmax(mloc, (double)T.psi0[a]);
-  const float m = (float)block_max64(mloc, ss->red);
-  const int seg = (A + kBlock - 1) / kBlock;
-  const int lo = min(A, j * seg), hi = min(A, lo + seg);
-  unsigned long long sum = 0ull;
-  for (int a = lo; a < hi; ++a) sum += long_row_weight(T.psi0[a], m, eta);
-  ss->part[j] = sum;
-  __syncthreads();
-  if (j == 0) {
-    unsigned long long run = 0ull;
-    for (int i = 0; i < kBlock; ++i) {
-      const unsigned long long v = ss->part[i];
-      ss->part[i] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  unsigned long long run = ss->part[j];
-  for (int a = lo; a < hi; ++a) {
-    run += long_row_weight(T.psi0[a], m, eta);
-    T.psi0_cdf[a] = run;
-  }
-}
-
 __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
   const TreeView& T = P.t;
   const unsigned long long n_prev = T.counters[2];
@@ -267,7 +235,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
       for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int j = threadIdx.x;
-    for (int i = j; i < 5 * kStripes; i += kBlock) T.stats[i] = 0ull;
+    for (int i = j; i < kStatRows * kStripes; i += kBlock) T.stats[i] = 0ull;
     if (j == 0) {
       T.gate[0] = (unsigned long long)wall_clock64();   // start of the plan
       T.gate[1] = 0ull;
@@ -301,10 +269,25 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
       for (int a = j; a < P.m.nA; a += kBlock) mloc = fmax(mloc, T.psi_root[a]);
       const double m = block_max64(mloc, ss->red);
       block_ordered_sum(T.psi_root, P.m.nA, m, P.eta64, T.root_cdf, ss->buf, &ss->bc);
-      psi0_draw_sums(T, P.m.nA, P.eta, j, ss);
+      // The initial row's running sums: eta * psi0 = ln pi0.
+      double m0 = -INFINITY;
+      for (int a = j; a < P.m.nA; a += kBlock) m0 = fmax(m0, P.m.logpi0[a]);
+      m0 = block_max64(m0, ss->red);
+      block_ordered_sum(P.m.logpi0, P.m.nA, m0, 1.0, T.psi0_cdf64, ss->buf, &ss->bc);
     }
     if (j == 0) {
-      if (T.ra <= kMaxA) root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
+      if (T.ra <= kMaxA) {
+        root_cdf(T.psi_root, P.m.nA, P.eta64, T.root_cdf);
+        // The initial row ln pi0 / eta in double precision: its running sums
+        // serve the draws at beliefs created in the current iteration.
+        double m = P.m.logpi0[0] / P.eta64;
+        for (int a = 1; a < P.m.nA; ++a) m = fmax(m, P.m.logpi0[a] / P.eta64);
+        double run = 0.0;
+        for (int a = 0; a < P.m.nA; ++a) {
+          run = run + exp(P.eta64 * (P.m.logpi0[a] / P.eta64 - m));
+          T.psi0_cdf64[a] = run;
+        }
+      }
       RecMeta* mt = rec_meta(T, 0);
       mt->obs = -1;
       mt->parent = kEmptyKey;
@@ -390,6 +373,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   for (int i = 0; i < 2 * kDiskRegs; ++i) dc.c[i] = 0.0f;
   if (nav) dc = load_disks(P.m);
   unsigned long long g = 0;   // generative-model calls of this episode
+  unsigned long long nt = 0;  // its near-tie draws
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey;
     float r = 0.0f;
@@ -398,9 +382,26 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     uint32_t h = 0;
     unsigned long long link = kEmptyKey;
     const int rid_b = rid;
+    const bool drew = alive;
+    int own = 0;                // the kernel's own decision (before a forced draw)
     if (alive) {
-      if (sid == 0) a = draw_cdf64(T.root_cdf, A, w.x);
-      else a = draw_row32<AM>(row, A, P.eta, w.x);
+      // Eq. (6): the root's running sums (double precision), those of the
+      // initial row for a belief created in this iteration, else the row.
+      bool tie = false;
+      if (sid == 0) {
+        a = draw_cdf64(T.root_cdf, A, w.x);
+        tie = (k > 1 || P.carry) && near_tie64(T.root_cdf, A, w.x, a);
+      } else if (fresh) {
+        a = draw_cdf64(T.psi0_cdf64, A, w.x);
+      } else {
+        a = draw_row32<AM>(row, A, P.eta, w.x, tie);
+      }
+      nt += tie ? 1u : 0u;
+      own = a;
+      if (T.dbg_force) {
+        const short f = T.dbg_force[(size_t)(t0 + d - T.dbg_step0) * n_p + ep];
+        if (f >= 0 && f < A) a = f;
+      }
       bool term = false;
       if (!nav) {
         int sn;
@@ -441,9 +442,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     }
     if (alive && d + 1 < D) {
       w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
-      // One load from either row: a divergent pair of loads into the same
-      // registers would have to wait for each other.
-      load_row<AM>(fresh ? T.psi0 : rec_psi(T, rid), A, row);
+      if (!fresh) load_row<AM>(rec_psi(T, rid), A, row);
       if (nav) z = nav_noise(P.m, w);
     }
     // Writes of level d.
@@ -460,6 +459,11 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
       if (won) {
         T.h_slot[h].id = rid;
         init_record(P, psi0s, rid, obs, link);
+      }
+      if (T.dbg_act) {
+        const size_t i = (size_t)(t - T.dbg_step0) * n_p + ep;
+        T.dbg_act[i] = drew ? (short)own : (short)-1;
+        T.dbg_obs[i] = drew ? obs : -1;
       }
     }
   }
@@ -485,8 +489,11 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     T.tr_key[(size_t)D * n_p + ep] = tk;
     T.tr_val[(size_t)D * n_p + ep] = hv;
   }
-  g = block_sum(g, red);
-  if (threadIdx.x == 0 && g) atomicAdd(&T.stats[blk % kStripes], g);
+  // Both counts in one word: a block makes fewer than 2^32 of each.
+  g = block_sum(g | (nt << 32), red);
+  if (threadIdx.x == 0 && (g & 0xffffffffull))
+    atomicAdd(&T.stats[blk % kStripes], g & 0xffffffffull);
+  if (threadIdx.x == 0 && (g >> 32)) atomicAdd(&T.stats[kStatNear * kStripes + blk % kStripes], g >> 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -1306,6 +1313,7 @@ __device__ void dev_select(const PlanView& P) {
   const unsigned long long steps = wave_sum(T.stats[lane]);
   const unsigned long long nodes = wave_sum(bank[lane]);
   const unsigned long long nb = 1 + wave_sum(bank[kStripes + lane]);
+  const unsigned long long near = wave_sum(T.stats[kStatNear * kStripes + lane]);
   const int A = P.m.nA;
   double* out = P.out;
   // Argmax with the lowest index on ties: each lane scans actions lane,
@@ -1331,6 +1339,7 @@ __device__ void dev_select(const PlanView& P) {
   out[A + 3] = (double)nb;
   out[A + 4] = (double)nodes;
   out[A + 5] = (double)T.counters[1];
+  out[A + 6] = (double)near;
   T.counters[2] = nb;
   T.counters[3] = 0ull;
   T.counters[5] = (unsigned long long)(P.timed ? T.step_base[k_last] : P.steps);
@@ -1501,14 +1510,17 @@ __device__ void dev_pf_resample(const PlanView& P, int t, int blk) {
 // half wavefront per episode.  The episode's state is the same in every lane
 // of the half; the lanes share the softmax draw (lane l owns the quads l,
 // l + 32, ... of the row), the record initialisation, and lane 0 of the half
-// does the episode's table probe and its scalar writes.  The draw scales the
-// single-precision weights by 2^24 to integers, so the running sums are
-// exact whatever the order of addition: an inclusive scan over the half per
-// chunk of 128 actions finds the first running sum above
-// t = ((x0 >> 8) * total) >> 24.
+// does the episode's table probe and its scalar writes.  The draw of Eq. (6)
+// takes single-precision weights exp(eta (psi_j - max)), sums each quad of
+// four in double precision and keeps it rounded once to single precision (in
+// LDS), and finds the first running sum above t = u * total by an inclusive
+// double-precision scan over the half per chunk of 128 actions.  Every
+// running sum is then within 2^-24 of itself (relative) of the sum of the
+// single-precision weights, and a row whose entries are all equal gives
+// floor(u |A|) exactly.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long long_row_weight(float v, float m, float eta) {
-  return (unsigned long long)(uint32_t)(expf(eta * (v - m)) * 16777216.0f);
+__device__ __forceinline__ float long_row_weight(float v, float m, float eta) {
+  return expf(eta * (v - m));
 }
 
 // Long-row episodes run on half a wavefront (kHalf = 32 lanes), so that a
@@ -1523,15 +1535,17 @@ __device__ __forceinline__ float half_maxf(float v) {
   for (int off = kHalf / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kHalf));
   return v;
 }
-__device__ __forceinline__ unsigned long long half_sum(unsigned long long v) {
+// Sum and inclusive scan over the half in double precision, in a fixed
+// order (the same for every call).
+__device__ __forceinline__ double half_sum64(double v) {
 #pragma unroll
   for (int off = kHalf / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kHalf);
   return v;
 }
-__device__ __forceinline__ unsigned long long half_incl_scan(unsigned long long v, int lane) {
+__device__ __forceinline__ double half_incl_scan64(double v, int lane) {
 #pragma unroll
   for (int off = 1; off < kHalf; off <<= 1) {
-    const unsigned long long n = __shfl_up(v, off, kHalf);
+    const double n = __shfl_up(v, off, kHalf);
     if (lane >= off) v += n;
   }
   return v;
@@ -1541,28 +1555,27 @@ __device__ __forceinline__ uint32_t half_ballot(bool p) {
   return (uint32_t)(__ballot(p) >> (threadIdx.x & kHalf));
 }
 
-// The long-row draw from running sums of its integer weights (A <= 4096): the
-// first a with t < cdf[a], t = u * total as in draw_long_row.  Lane l reads
-// the end of run l of ceil(A / 32) actions; the half then reads the chosen
-// run (at most 128 entries, four per lane, in order).  Two rounds of loads,
-// the same action as the scan.
-__device__ int draw_long_cdf(const unsigned long long* __restrict__ cdf, int A, uint32_t x0,
-                             int lane) {
+// The long-row draw from the double-precision running sums of a row's softmax
+// weights (A <= 4096): the first a with t < cdf[a], t = u * cdf[A - 1].  Lane
+// l reads the end of run l of ceil(A / 32) actions; the half then reads the
+// chosen run (at most 128 entries, four per lane, in order).  Two rounds of
+// loads.
+__device__ int draw_long_cdf(const double* __restrict__ cdf, int A, uint32_t x0, int lane) {
   const int step = (A + kHalf - 1) / kHalf;
-  const unsigned long long tot = cdf[A - 1];
+  const double tot = cdf[A - 1];
   const int e = min((lane + 1) * step, A) - 1;
   const bool run_ok = lane * step < A;
-  const unsigned long long end = run_ok ? cdf[e] : 0ull;
-  const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
+  const double end = run_ok ? cdf[e] : 0.0;
+  const double t = (double)(x0 >> 8) * (1.0 / 16777216.0) * tot;
   const uint32_t hit = half_ballot(run_ok && t < end);
   if (!hit) return A - 1;
   const int r = __ffs(hit) - 1;
   const int lo = r * step, hi = min(lo + step, A);
-  unsigned long long v[4];
+  double v[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = lo + u * kHalf + lane;
-    v[u] = j < hi ? cdf[j] : 0ull;
+    v[u] = j < hi ? cdf[j] : 0.0;
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -1575,9 +1588,11 @@ __device__ int draw_long_cdf(const unsigned long long* __restrict__ cdf, int A, 
 
 constexpr int kLongChunks = kMaxAWide / (4 * kHalf);   // chunks of 128 actions
 
-// qs: this half's LDS area of kLongChunks * kHalf quad sums.
+// qs: this half's LDS area of kLongChunks * kHalf quad sums (single-precision
+// bits).  near: t lies within kTieRel * total of a boundary next to it (rows
+// whose entries are all equal never count).
 __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, uint32_t x0,
-                             int lane, uint32_t* qs) {
+                             int lane, uint32_t* qs, bool& near) {
   // Lane l of the half holds the quads l, l + 32, ... (the row is padded to
   // a multiple of 4; padding is masked off).  Each weight is evaluated once:
   // the lane keeps its quad sum of every chunk (in LDS, for registers), the
@@ -1586,60 +1601,70 @@ __device__ int draw_long_row(const float* __restrict__ row, int A, float eta, ui
   const float4* r4 = reinterpret_cast<const float4*>(row);
   const int nq = (A + 3) / 4;
   const int nc = (nq + kHalf - 1) / kHalf;
-  float m = -INFINITY;
+  float m = -INFINITY, mn = INFINITY;
 #pragma unroll 4
   for (int q = lane; q < nq; q += kHalf) {
     const float4 v = r4[q];
     const int j = 4 * q;
     m = fmaxf(m, v.x);
-    if (j + 1 < A) m = fmaxf(m, v.y);
-    if (j + 2 < A) m = fmaxf(m, v.z);
-    if (j + 3 < A) m = fmaxf(m, v.w);
+    mn = fminf(mn, v.x);
+    if (j + 1 < A) { m = fmaxf(m, v.y); mn = fminf(mn, v.y); }
+    if (j + 2 < A) { m = fmaxf(m, v.z); mn = fminf(mn, v.z); }
+    if (j + 3 < A) { m = fmaxf(m, v.w); mn = fminf(mn, v.w); }
   }
   m = half_maxf(m);
-  auto quad = [&](int q, unsigned long long (&w)[4]) {
+  const bool flat = -half_maxf(-mn) == m;
+  auto quad = [&](int q, float (&w)[4]) {
     const float4 v = r4[q];
     const int j = 4 * q;
     w[0] = long_row_weight(v.x, m, eta);
-    w[1] = j + 1 < A ? long_row_weight(v.y, m, eta) : 0ull;
-    w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0ull;
-    w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0ull;
+    w[1] = j + 1 < A ? long_row_weight(v.y, m, eta) : 0.0f;
+    w[2] = j + 2 < A ? long_row_weight(v.z, m, eta) : 0.0f;
+    w[3] = j + 3 < A ? long_row_weight(v.w, m, eta) : 0.0f;
   };
-  unsigned long long tot = 0;                   // a quad's sum is below 2^26
+  double tot = 0.0;
   for (int c = 0; c < nc; ++c) {
     const int q = c * kHalf + lane;
-    uint32_t sq = 0u;
+    float sq = 0.0f;
     if (q < nq) {
-      unsigned long long w[4];
+      float w[4];
       quad(q, w);
-      sq = (uint32_t)(w[0] + w[1] + w[2] + w[3]);
+      sq = (float)((((double)w[0] + (double)w[1]) + (double)w[2]) + (double)w[3]);
     }
-    qs[c * kHalf + lane] = sq;
-    tot += sq;
+    qs[c * kHalf + lane] = __float_as_uint(sq);
+    tot += (double)sq;
   }
-  tot = half_sum(tot);
-  const unsigned long long t = ((unsigned long long)(x0 >> 8) * tot) >> 24;
-  unsigned long long base = 0;
+  tot = half_sum64(tot);
+  const double t = (double)(x0 >> 8) * (1.0 / 16777216.0) * tot;
+  double base = 0.0;
   for (int c = 0; c < nc; ++c) {
-    const uint32_t sq = qs[c * kHalf + lane];
-    const unsigned long long incl = half_incl_scan((unsigned long long)sq, lane) + base;
+    const double sq = (double)__uint_as_float(qs[c * kHalf + lane]);
+    const double incl = half_incl_scan64(sq, lane) + base;
     const uint32_t hit = half_ballot(c * kHalf + lane < nq && t < incl);
     if (hit) {
       const int src = __ffs(hit) - 1;
       int pick = 3;                             // within the chosen quad
+      int tie = 0;
       if (lane == src) {
-        unsigned long long w[4];
+        float w[4];
         quad(c * kHalf + lane, w);
-        unsigned long long run = incl - sq;
+        double run = incl - sq, below = run;
         for (int u = 0; u < 4; ++u) {
-          run += w[u];
+          below = run;
+          run += (double)w[u];
           if (t < run) { pick = u; break; }
         }
+        if (pick == 3) run = incl;              // the quad's rounded sum bounds it
+        const int a = 4 * (c * kHalf + lane) + pick;
+        const double lim = kTieRel * tot;
+        tie = !flat && ((a > 0 && t - below <= lim) || (a < A - 1 && run - t <= lim));
       }
+      near = __shfl(tie, src, kHalf) != 0;
       return 4 * (c * kHalf + src) + __shfl(pick, src, kHalf);
     }
     base = __shfl(incl, kHalf - 1, kHalf);
   }
+  near = false;
   return A - 1;
 }
 
@@ -1669,18 +1694,32 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
     }
     alive = true;
   }
-  unsigned long long g = 0;
+  unsigned long long g = 0, nt = 0;
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey, link = kEmptyKey;
     float r = 0.0f;
     bool won = false;
     int obs = 0, a = 0;
     uint32_t h = 0;
+    const bool drew = alive;
+    int own = 0;
     if (alive) {
       const U4 w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)d, (uint32_t)k);
-      if (sid == 0) a = draw_cdf64_bisect(T.root_cdf, A, w.x);
-      else if (fresh) a = draw_long_cdf(T.psi0_cdf, A, w.x, lane);
-      else a = draw_long_row(rec_psi(T, rid), A, P.eta, w.x, lane, qsum[threadIdx.x / kHalf]);
+      bool tie = false;
+      if (sid == 0) {
+        a = draw_cdf64_bisect(T.root_cdf, A, w.x);
+        tie = (k > 1 || P.carry) && near_tie64(T.root_cdf, A, w.x, a);
+      } else if (fresh) {
+        a = draw_long_cdf(T.psi0_cdf64, A, w.x, lane);
+      } else {
+        a = draw_long_row(rec_psi(T, rid), A, P.eta, w.x, lane, qsum[threadIdx.x / kHalf], tie);
+      }
+      nt += tie ? 1u : 0u;
+      own = a;
+      if (T.dbg_force) {
+        const short f = T.dbg_force[(size_t)(t0 + d - T.dbg_step0) * n_p + ep];
+        if (f >= 0 && f < A) a = f;
+      }
       int sn;
       tabular_step(P.m, s, a, w, sn, obs, r);
       s = sn;
@@ -1720,6 +1759,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
         T.tr_val[(size_t)d * n_p + ep] = r;
         T.list[(size_t)t * n_p + ep] = won ? sid : 0;
         if (won) T.h_slot[h].id = rid;
+        if (T.dbg_act) {
+          const size_t i = (size_t)(t - T.dbg_step0) * n_p + ep;
+          T.dbg_act[i] = drew ? (short)own : (short)-1;
+          T.dbg_obs[i] = drew ? obs : -1;
+        }
       }
       if (won) {                                // the new record, by the half
         // Psi, the metadata and a cleared bitmap; N, C and W of (b, a) are
@@ -1754,8 +1798,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
     T.tr_key[(size_t)D * n_p + ep] = tk;
     T.tr_val[(size_t)D * n_p + ep] = hv;
   }
-  g = block_sum(lane == 0 ? g : 0ull, red);
-  if (threadIdx.x == 0 && g) atomicAdd(&T.stats[blockIdx.x % kStripes], g);
+  g = block_sum(lane == 0 ? (g | (nt << 32)) : 0ull, red);
+  if (threadIdx.x == 0 && (g & 0xffffffffull))
+    atomicAdd(&T.stats[blockIdx.x % kStripes], g & 0xffffffffull);
+  if (threadIdx.x == 0 && (g >> 32))
+    atomicAdd(&T.stats[kStatNear * kStripes + blockIdx.x % kStripes], g >> 32);
 }
 
 __global__ void k_env(PlanView P, int t) { dev_env(P, t); }

@@ -77,7 +77,8 @@ class vopp_params(C.Structure):
 
 class vopp_stats(C.Structure):
     _fields_ = [("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
-                ("n_actions", C.c_int64), ("device_ms", C.c_double)]
+                ("n_actions", C.c_int64), ("device_ms", C.c_double),
+                ("near_ties", C.c_int64)]
 
 
 class vopp_request(C.Structure):
@@ -150,6 +151,10 @@ def lib():
     L.vopp_plan.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vopp_params), vp, vp,
                             C.POINTER(i32), vp, vp, C.POINTER(vopp_stats)]
     L.vopp_plan.restype = st
+    L.vopp_plan_trace.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vopp_params), vp, vp,
+                                  C.POINTER(i32), vp, vp, C.POINTER(vopp_stats), vp, vp,
+                                  vp, C.c_int64]
+    L.vopp_plan_trace.restype = st
     L.vopp_plan_anytime.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.POINTER(vopp_params),
                                     vp, vp, C.POINTER(i32), vp, vp, C.POINTER(vopp_stats),
                                     C.POINTER(i32)]
@@ -312,6 +317,7 @@ class PlanResult:
     n_beliefs: int
     n_actions: int
     device_ms: float
+    near_ties: int = 0
 
 
 def belief_tensor(inst, belief, device="cuda"):
@@ -339,7 +345,47 @@ def plan(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None):
                            C.c_void_p(stream.cuda_stream), C.byref(act), _p(vals),
                            _p(vroot), C.byref(st)))
     return PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
-                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
+                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
+                      int(st.near_ties))
+
+
+def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None,
+               force=None):
+    """vopp_plan_trace: returns (PlanResult, act, obs), with act (int16, the
+    kernel's own decisions) and obs (int32) of shape [level steps, n_particles]
+    on the host (-1 where an episode had terminated).  force: None, or an
+    int16 array of the same size whose entries >= 0 replace the kernel's
+    decision at that draw."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    steps = sum(depth if prm.schedule == 1 else min(k, depth) for k in range(1, budget + 1))
+    n = steps * prm.n_particles
+    act_d = torch.empty(n, dtype=torch.int16, device=belief_dev.device)
+    obs_d = torch.empty(n, dtype=torch.int32, device=belief_dev.device)
+    force_d = None
+    if force is not None:
+        f = np.ascontiguousarray(np.asarray(force, np.int16).reshape(-1))
+        if f.size != n:
+            raise ValueError(f"force holds {f.size} entries, the plan has {n} draws")
+        force_d = torch.as_tensor(f, device=belief_dev.device)
+    act = C.c_int32(-1)
+    vals = np.zeros(pomdp.nA, np.float64)
+    vroot = np.zeros(1, np.float64)
+    st = vopp_stats()
+    _check(lib().vopp_plan_trace(pomdp.handle, C.c_void_p(belief_dev.data_ptr()),
+                                 int(n_belief), int(budget), int(depth), C.byref(prm),
+                                 ws.handle if ws is not None else None,
+                                 C.c_void_p(stream.cuda_stream), C.byref(act), _p(vals),
+                                 _p(vroot), C.byref(st), C.c_void_p(act_d.data_ptr()),
+                                 C.c_void_p(obs_d.data_ptr()),
+                                 None if force_d is None else C.c_void_p(force_d.data_ptr()),
+                                 C.c_int64(n)))
+    res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
+                     int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
+                     int(st.near_ties))
+    shape = (steps, prm.n_particles)
+    return (res, act_d.cpu().numpy().reshape(shape), obs_d.cpu().numpy().reshape(shape))
 
 
 def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, ws=None,
@@ -360,7 +406,8 @@ def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, w
                                    C.c_void_p(stream.cuda_stream), C.byref(act), _p(vals),
                                    _p(vroot), C.byref(st), C.byref(iters)))
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
-                     int(st.n_beliefs), int(st.n_actions), float(st.device_ms))
+                     int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
+                     int(st.near_ties))
     return res, int(iters.value)
 
 

@@ -1,25 +1,25 @@
 """Parity of the HIP planner (through the C ABI) with the serial CPU oracle.
 
-Structure (every belief and action row, observation keys, visit counts) must
-match bit for bit; fp32 values must match the fp64 oracle within
-|gpu - oracle| <= 1e-4 * max(|oracle|, 1).  Action draws are decided by
-floating point, so bit-exact trees are asserted for plans whose oracle run
-reports no draw closer than tau = 2^-16 (relative) to a CDF boundary at a
-non-uniform preference row; such near ties are decided by rounding and may
-legitimately differ between the fp32 kernel and the fp64 oracle.  Iteration 1
-(all rows uniform) is exact by construction at any size.
+Every plan is checked draw by draw with the protocol of tests/drawcheck.py:
+the oracle (double precision) plans first and flags the draws that lie within
+its screen of a CDF boundary; the GPU plans with exactly those draws forced to
+the oracle's decision and exports its own decision at every draw.  Every
+unflagged draw and every observation key must be equal, and the trees must
+then match: structure (every belief and action row, observation keys, visit
+counts) bit for bit, fp32 values within |gpu - oracle| <= 1e-4 *
+max(|oracle|, 1).  Iteration 1 draws only from initial rows, which both sides
+decide exactly, so no draw there is ever flagged.  The benchmark shapes are
+held to the same bar at full size.
 """
 
 import numpy as np
 import pytest
 
 from paper_2510_27191_amd import instances as I
-from tests.treecanon import canonical_tree
+from tests.drawcheck import (REL, assert_tree_parity as assert_parity, close, forced_parity,
+                             oracle_plan, screen)
 
 pytestmark = pytest.mark.gpu
-
-TAU = 2.0 ** -16
-REL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -49,58 +49,9 @@ def run_gpu(V, inst, belief, n_p, K, depth, eta=1.0, seed=1, schedule=0, step=0,
     return res, tree
 
 
-def run_orc(orc, inst, belief, n_p, K, depth, eta=1.0, seed=1, schedule=0, step=0):
-    return orc.plan(inst, belief, n_p, K, depth, eta=eta, seed=seed,
-                    schedule=schedule, step=step, tau=TAU)
-
-
-def close(a, b, rel=REL):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    tol = rel * np.maximum(np.abs(b), 1.0)
-    bad = np.abs(a - b) > tol
-    return (not bad.any()), (np.max(np.abs(a - b) / tol) if a.size else 0.0)
-
-
-def assert_parity(res, tree, o, A):
-    # Structure: bit exact, rows compared in the canonical order.
-    assert res.n_beliefs == len(o.b_parent)
-    assert res.n_actions == len(o.a_parent)
-    assert res.particle_steps == o.particle_steps
-    oc = canonical_tree(o)
-    for k in ("b_parent", "b_obs", "b_depth", "a_parent", "a_act"):
-        assert np.array_equal(tree[k], oc[k]), k
-    assert np.array_equal(tree["a_N"], oc["a_N"])
-    assert np.array_equal(tree["b_N"], oc["b_N"])
-    # Values within tolerance.
-    ok, worst = close(tree["a_C"], oc["a_C"])
-    assert ok, ("a_C", worst)
-    ok, worst = close(tree["psi"][1:], oc["psi"][1:])
-    assert ok, ("psi", worst)
-    ok, worst = close(tree["b_V"][1:], oc["b_V"][1:])
-    assert ok, ("b_V", worst)
-    ok, worst = close(res.values, o.psi_root)
-    assert ok, ("root psi", worst)
-    ok, worst = close([res.v_root], [o.v_root])
-    assert ok, ("v_root", worst)
-    srt = np.sort(o.psi_root)[::-1]
-    if A > 1 and srt[0] - srt[1] > REL * max(abs(srt[0]), 1.0):
-        assert res.action == o.action
-    else:
-        assert res.action in np.nonzero(o.psi_root >= srt[0] - REL * max(abs(srt[0]), 1.0))[0]
-
-
-def clean_seeds(orc, inst, belief, n_p, K, depth, want, schedule=0, eta=1.0,
-                candidates=range(1, 40)):
-    out = []
-    for sd in candidates:
-        o = run_orc(orc, inst, belief, n_p, K, depth, eta=eta, seed=sd, schedule=schedule)
-        if o.near_ties == 0:
-            out.append((sd, o))
-            if len(out) == want:
-                break
-    assert out, "no seed without near ties"
-    return out
+def report(name, st):
+    print(f"[parity] {name}: draws {st['draws']} flagged {st['flagged']} "
+          f"followed {st['follow']}", flush=True)
 
 
 # --- tabular, |S|=16 |A|=3 |O|=4, n_p=1024, depth 4 -------------------------
@@ -108,26 +59,26 @@ def clean_seeds(orc, inst, belief, n_p, K, depth, want, schedule=0, eta=1.0,
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_tabular16_first_iteration_exact(V, orc, seed):
     inst, bel, p = I.workload("tabular16", seed=0)
-    o = run_orc(orc, inst, bel, 1024, 1, 4, seed=seed, schedule=1)
-    assert o.near_ties == 0
+    st = forced_parity(V, orc, inst, bel, 1024, 1, 4, seed=seed, schedule=1)
+    assert st["flagged"] == 0 and st["o"].near_ties == 0
     res, tree = run_gpu(V, inst, bel, 1024, 1, 4, seed=seed, schedule=1)
-    assert_parity(res, tree, o, 3)
+    assert_parity(res, tree, st["o"], 3)          # the plain entry point too
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
-def test_tabular16_full_plan(V, orc, schedule):
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tabular16_full_plan(V, orc, schedule, seed):
     inst, bel, p = I.workload("tabular16", seed=0)
-    for sd, o in clean_seeds(orc, inst, bel, 1024, 4, 4, 3, schedule=schedule):
-        res, tree = run_gpu(V, inst, bel, 1024, 4, 4, seed=sd, schedule=schedule)
-        assert_parity(res, tree, o, 3)
+    st = forced_parity(V, orc, inst, bel, 1024, 4, 4, seed=seed, schedule=schedule)
+    report(f"tabular16 K=4 schedule {schedule} seed {seed}", st)
 
 
-def test_tabular16_with_heuristic_and_eta(V, orc):
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tabular16_with_heuristic_and_eta(V, orc, seed):
     inst = I.tabular_dense(3, 16, 3, 4, with_heuristic=True)
     bel = I.tabular_belief(inst)
-    for sd, o in clean_seeds(orc, inst, bel, 1000, 5, 4, 2, eta=2.0):
-        res, tree = run_gpu(V, inst, bel, 1000, 5, 4, eta=2.0, seed=sd)
-        assert_parity(res, tree, o, 3)
+    st = forced_parity(V, orc, inst, bel, 1000, 5, 4, seed=seed, eta=2.0)
+    report(f"tabular16 eta=2 seed {seed}", st)
 
 
 # --- sparse tabular ------------------------------------------------------------
@@ -135,16 +86,14 @@ def test_tabular16_with_heuristic_and_eta(V, orc):
 def test_sparse_reduced_plan(V, orc):
     inst = I.tabular_sparse(1, 512, 8, 32, 8, with_heuristic=True)
     bel = I.tabular_belief(inst)
-    for sd, o in clean_seeds(orc, inst, bel, 3001, 5, 5, 1):
-        res, tree = run_gpu(V, inst, bel, 3001, 5, 5, seed=sd)
-        assert_parity(res, tree, o, 8)
+    st = forced_parity(V, orc, inst, bel, 3001, 5, 5, seed=1)
+    report("sparse512 K=5", st)
 
 
 def test_sparse4096_first_iteration_full_size(V, orc):
     inst, bel, p = I.workload("sparse4096", seed=0)
-    o = run_orc(orc, inst, bel, p["n_particles"], 1, 8, seed=5, schedule=1)
-    res, tree = run_gpu(V, inst, bel, p["n_particles"], 1, 8, seed=5, schedule=1)
-    assert_parity(res, tree, o, 8)
+    st = forced_parity(V, orc, inst, bel, p["n_particles"], 1, 8, seed=5, schedule=1)
+    assert st["flagged"] == 0
 
 
 # --- navigation --------------------------------------------------------------------
@@ -152,30 +101,24 @@ def test_sparse4096_first_iteration_full_size(V, orc):
 def test_nav_reduced_plan(V, orc):
     inst = I.nav2d(2, 8, heuristic=1)
     bel = I.nav_belief(3, 2000)
-    for sd, o in clean_seeds(orc, inst, bel, 2500, 5, 5, 1):
-        res, tree = run_gpu(V, inst, bel, 2500, 5, 5, seed=sd)
-        assert_parity(res, tree, o, 4)
+    st = forced_parity(V, orc, inst, bel, 2500, 5, 5, seed=1)
+    report("nav reduced K=5", st)
 
 
 def test_nav_terminals(V, orc):
     inst = I.nav2d(4, 6, heuristic=1)
     bel = I.nav_belief(5, 500, 7.6, 8.6)          # next to the goal
-    for sd, o in clean_seeds(orc, inst, bel, 777, 4, 4, 1):
-        res, tree = run_gpu(V, inst, bel, 777, 4, 4, seed=sd)
-        assert_parity(res, tree, o, 4)
-        assert res.particle_steps < 777 * (1 + 2 + 3 + 4)   # some episodes ended
+    st = forced_parity(V, orc, inst, bel, 777, 4, 4, seed=1)
+    assert st["res"].particle_steps < 777 * (1 + 2 + 3 + 4)   # some episodes ended
 
 
 def test_nav2d_first_iteration_full_size(V, orc):
     inst, bel, p = I.workload("nav2d", seed=0)
-    o = run_orc(orc, inst, bel, p["n_particles"], 1, 10, seed=2, schedule=1)
-    res, tree = run_gpu(V, inst, bel, p["n_particles"], 1, 10, seed=2, schedule=1)
-    assert_parity(res, tree, o, 4)
+    st = forced_parity(V, orc, inst, bel, p["n_particles"], 1, 10, seed=2, schedule=1)
+    assert st["flagged"] == 0
 
 
-# --- full-size plans as benchmarked: near ties are expected, so the check is
-# on the root values (averages over K*n_p episodes), tree-size agreement and
-# the invariants of the GPU tree itself. -------------------------------------
+# --- the benchmark shapes at full size, every iteration ---------------------------
 
 def gpu_invariants(res, tree, n_p, K, depth, schedule):
     Ds = [depth if schedule == 1 else min(k, depth) for k in range(1, K + 1)]
@@ -196,15 +139,63 @@ def gpu_invariants(res, tree, n_p, K, depth, schedule):
 
 @pytest.mark.parametrize("name", ["nav2d", "sparse4096"])
 def test_full_size_plan(V, orc, name):
+    """nav2d (n_p 65,536, K 10, depth 10) and sparse4096 (n_p 262,144, K 8,
+    depth 8) as benchmarked: every draw, the whole tree and every value."""
     inst, bel, p = I.workload(name, seed=0)
     n_p, K, depth = p["n_particles"], p["budget"], p["depth"]
-    o = run_orc(orc, inst, bel, n_p, K, depth, seed=1)
-    res, tree = run_gpu(V, inst, bel, n_p, K, depth, seed=1)
-    gpu_invariants(res, tree, n_p, K, depth, 0)
-    assert abs(res.n_beliefs - len(o.b_parent)) <= 1e-3 * len(o.b_parent)
-    assert abs(res.particle_steps - o.particle_steps) <= 1e-3 * o.particle_steps
-    ok, worst = close(res.values, o.psi_root, rel=1e-3)
-    assert ok, worst
+    st = forced_parity(V, orc, inst, bel, n_p, K, depth, seed=1)
+    report(f"{name} full size", st)
+    gpu_invariants(st["res"], st["tree"], n_p, K, depth, 0)
+
+
+# --- the per-draw export and its forcing hook ------------------------------------
+
+def test_trace_export_is_the_plan(V):
+    # vopp_plan_trace without forcing is vopp_plan plus the export: the same
+    # tree bit for bit; one draw per particle step; -1 after termination.
+    inst = I.nav2d(4, 6, heuristic=1)
+    bel = I.nav_belief(5, 500, 6.6, 8.6)
+    pom = V.Pomdp.from_instance(inst)
+    prm = V.params(1500, seed=3)
+    ws = V.Workspace(pom, prm, 4, 4)
+    try:
+        b = V.belief_tensor(inst, bel)
+        r0 = V.plan(pom, b, 500, 4, 4, prm, ws=ws)
+        t0 = V.tree_dump(ws, 4, r0.n_beliefs, r0.n_actions)
+        r1, act, obs = V.plan_trace(pom, b, 500, 4, 4, prm, ws=ws)
+        t1 = V.tree_dump(ws, 4, r1.n_beliefs, r1.n_actions)
+    finally:
+        ws.close()
+        pom.close()
+    for k in t0:
+        assert np.array_equal(t0[k], t1[k]), k
+    assert np.array_equal(r0.values, r1.values)
+    assert act.shape == (1 + 2 + 3 + 4, 1500)
+    assert int((act >= 0).sum()) == r1.particle_steps < act.size
+    assert np.array_equal(act < 0, obs < 0)
+    assert act.max() < 4
+
+
+def test_forced_draws_take_the_forced_action(V):
+    # Forcing every root draw of a one-iteration plan to action 2 leaves the
+    # root with one action node; the export still holds the kernel's own draws.
+    inst, bel, _ = I.workload("tabular16", seed=0)
+    pom = V.Pomdp.from_instance(inst)
+    prm = V.params(1024, seed=1, schedule=1)
+    ws = V.Workspace(pom, prm, 1, 3)
+    try:
+        b = V.belief_tensor(inst, bel)
+        force = np.full((3, 1024), -1, np.int16)
+        force[0] = 2
+        r, act, obs = V.plan_trace(pom, b, 16, 1, 3, prm, ws=ws, force=force)
+        tree = V.tree_dump(ws, 3, r.n_beliefs, r.n_actions)
+    finally:
+        ws.close()
+        pom.close()
+    root = tree["a_parent"] == 0
+    assert np.array_equal(tree["a_act"][root], [2])
+    assert tree["a_N"][root][0] == 1024
+    assert len(np.unique(act[0])) == 3             # the kernel's own root draws
 
 
 # --- edge cases -----------------------------------------------------------------------
@@ -213,36 +204,29 @@ def test_full_size_plan(V, orc, name):
 def test_ragged_particle_counts(V, orc, n_p):
     inst = I.tabular_dense(7, 9, 4, 3, with_heuristic=True)
     bel = I.tabular_belief(inst)
-    for sd, o in clean_seeds(orc, inst, bel, n_p, 3, 3, 1):
-        res, tree = run_gpu(V, inst, bel, n_p, 3, 3, seed=sd)
-        assert_parity(res, tree, o, 4)
+    forced_parity(V, orc, inst, bel, n_p, 3, 3, seed=1)
 
 
 @pytest.mark.parametrize("nA,nO", [(1, 3), (5, 1), (64, 2), (13, 7)])
 def test_action_and_observation_extremes(V, orc, nA, nO):
     inst = I.tabular_dense(11, 6, nA, nO, with_heuristic=True)
     bel = I.tabular_belief(inst)
-    for sd, o in clean_seeds(orc, inst, bel, 600, 3, 3, 1):
-        res, tree = run_gpu(V, inst, bel, 600, 3, 3, seed=sd)
-        assert_parity(res, tree, o, nA)
+    forced_parity(V, orc, inst, bel, 600, 3, 3, seed=1)
 
 
 def test_single_belief_particle_and_depth_one(V, orc):
     inst = I.tabular_dense(12, 8, 3, 4)
     bel = np.array([5], np.int32)
-    o = run_orc(orc, inst, bel, 300, 1, 1, seed=3)
-    res, tree = run_gpu(V, inst, bel, 300, 1, 1, seed=3)
-    assert_parity(res, tree, o, 3)
+    forced_parity(V, orc, inst, bel, 300, 1, 1, seed=3)
 
 
 def test_all_episodes_terminate_at_first_level(V, orc):
     inst = I.nav2d(4, 4, heuristic=1)
     inst = dict(inst, goal_r2=400.0)                # the goal covers the map
     bel = I.nav_belief(5, 64, 4.0, 6.0)
-    o = run_orc(orc, inst, bel, 500, 3, 3, seed=1)
-    res, tree = run_gpu(V, inst, bel, 500, 3, 3, seed=1)
+    st = forced_parity(V, orc, inst, bel, 500, 3, 3, seed=1)
+    o = st["o"]
     assert o.particle_steps == 3 * 500 and len(o.b_parent) == 1
-    assert_parity(res, tree, o, 4)
 
 
 def test_workspace_reuse_and_determinism(V, orc):

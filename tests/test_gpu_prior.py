@@ -1,17 +1,18 @@
 """Parity of the HIP planner with the oracle under a non-uniform reference
 policy pi0 (Sec. III-A, Eq. 4: every preference row starts at ln pi0 / eta).
 
-Same bar as the uniform parity tests: bit-exact structure on plans whose
-oracle run has no near-tie draw, values within 1e-4 relative.  With pi0 the
-first draws at a new belief already come from a non-uniform row, so those are
-covered by the near-tie screen as well.
+Same bar and protocol as the uniform parity tests (tests/drawcheck.py):
+every unflagged draw equal, bit-exact structure, values within 1e-4.  With
+pi0 the first draws at a new belief come from a non-uniform row; the kernels
+draw those from the initial row's double-precision running sums, as the
+oracle does.
 """
 
 import numpy as np
 import pytest
 
 from paper_2510_27191_amd import instances as I
-from tests.test_gpu_parity import TAU, assert_parity, close
+from tests.drawcheck import close, forced_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -42,26 +43,22 @@ def run_gpu(V, inst, belief, n_p, K, depth, pi0, seed=1, schedule=0, eta=1.0):
     return res, tree
 
 
-def clean_runs(orc, inst, belief, n_p, K, depth, pi0, want, schedule=0, eta=1.0):
-    out = []
-    for sd in range(1, 40):
-        o = orc.plan(inst, belief, n_p, K, depth, eta=eta, seed=sd, schedule=schedule,
-                     tau=TAU, pi0=pi0)
-        if o.near_ties == 0:
-            out.append((sd, o))
-            if len(out) == want:
-                break
-    assert out, "no seed without near ties"
-    return out
-
-
 @pytest.mark.parametrize("schedule", [0, 1])
-def test_tabular16_prior_plan(V, orc, schedule):
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tabular16_prior_plan(V, orc, schedule, seed):
     inst, bel, _ = I.workload("tabular16", seed=0)
     pi0 = np.array([0.6, 0.3, 0.1])
-    for sd, o in clean_runs(orc, inst, bel, 1024, 4, 4, pi0, 2, schedule=schedule):
-        res, tree = run_gpu(V, inst, bel, 1024, 4, 4, pi0, seed=sd, schedule=schedule)
-        assert_parity(res, tree, o, 3)
+    forced_parity(V, orc, inst, bel, 1024, 4, 4, seed=seed, schedule=schedule, pi0=pi0)
+
+
+def test_prior_first_iteration_is_exact(V, orc):
+    # Iteration 1 draws every non-root belief from the initial row's double
+    # running sums and the root from its double row: the GPU decides every
+    # draw as the oracle does, flagged or not.
+    inst, bel, _ = I.workload("sparse4096", seed=0)
+    pi0 = np.linspace(1.0, 3.0, inst["nA"])
+    st = forced_parity(V, orc, inst, bel, 65536, 1, 8, seed=2, schedule=1, pi0=pi0)
+    assert st["follow"] == 0
 
 
 def test_tabular_prior_eta(V, orc):
@@ -69,18 +66,14 @@ def test_tabular_prior_eta(V, orc):
     inst = I.tabular_dense(3, 24, 5, 6)
     bel = I.tabular_belief(inst)
     pi0 = np.array([1.0, 2.0, 3.0, 4.0, 5.0])         # unnormalised weights
-    for sd, o in clean_runs(orc, inst, bel, 1500, 3, 5, pi0, 1, eta=2.5):
-        res, tree = run_gpu(V, inst, bel, 1500, 3, 5, pi0, seed=sd, eta=2.5)
-        assert_parity(res, tree, o, 5)
+    forced_parity(V, orc, inst, bel, 1500, 3, 5, seed=1, eta=2.5, pi0=pi0)
 
 
 def test_nav_prior_plan(V, orc):
     inst = I.nav2d(2, 8, heuristic=1)
     bel = I.nav_belief(3, 2000)
     pi0 = np.array([0.1, 0.2, 0.3, 0.4])
-    for sd, o in clean_runs(orc, inst, bel, 2500, 5, 5, pi0, 1):
-        res, tree = run_gpu(V, inst, bel, 2500, 5, 5, pi0, seed=sd)
-        assert_parity(res, tree, o, 4)
+    forced_parity(V, orc, inst, bel, 2500, 5, 5, seed=1, pi0=pi0)
 
 
 def test_uniform_prior_is_the_default(V):

@@ -2,9 +2,9 @@
 
 A chain is: plan in workspace A, keep the subtree under (action, observation)
 in workspace B, plan from it in B (and optionally keep again into A and plan
-a third time).  Each plan of a chain is held to the uniform parity bar
-(bit-exact structure in canonical order, values within 1e-4) on seeds whose
-oracle runs have no near-tie draw; a kept root's draws are screened like
+a third time).  Each plan of a chain is held to the parity bar of
+tests/drawcheck.py (every unflagged draw equal, bit-exact structure in
+canonical order, values within 1e-4); a kept root's draws are screened like
 non-root draws, because the GPU keeps non-root rows in single precision.
 """
 
@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 from paper_2510_27191_amd import instances as I
-from tests.test_gpu_parity import TAU, assert_parity
+from tests.drawcheck import (assert_tree_parity as assert_parity, check_draws, gpu_forced_plan,
+                             oracle_plan)
 from tests.test_oracle_reroot import branches
 
 pytestmark = pytest.mark.gpu
@@ -28,54 +29,47 @@ def V():
     return vopp
 
 
-def clean_chain(orc, inst, bel, plans, A, tries=30):
-    """Seeds (one per plan) whose oracle chain has no near tie, with the
-    oracle results and the (action, observation) kept after each plan."""
-    for s1 in range(1, tries):
-        seeds, outs, keys, start = [], [], [], None
-        ok = True
-        for i, (n_p, K, depth) in enumerate(plans):
-            for sd in range(s1 * 100 + i * 10, s1 * 100 + i * 10 + 10):
-                o = orc.plan(inst, bel, n_p, K, depth, seed=sd, tau=TAU, start=start,
-                             keep=True)
-                if o.near_ties == 0:
-                    break
-            else:
-                ok = False
-                break
-            seeds.append(sd)
-            outs.append(o)
-            if i + 1 < len(plans):
-                a, ob = branches(o, A, 1)[0]
-                keys.append((a, ob))
-                start, _ = orc.reroot(o, a, ob, A)
-        if ok:
-            return seeds, outs, keys
-    pytest.fail("no seed chain without near ties")
-
-
-def run_chain(V, inst, bel, plans, seeds, keys, A):
+def forced_chain(V, orc, inst, bel, plans, A, seed0=1, schedule=0):
+    """A chain of plans (n_p, K, depth), each re-rooted on the oracle's most
+    visited branch of the previous plan, run by the oracle and then by the GPU
+    with the oracle's flagged draws forced (tests/drawcheck.py); every plan is
+    held to the parity bar.  Returns the oracle results, the branches and the
+    GPU's kept-belief counts."""
+    seeds = [seed0 + 100 * i for i in range(len(plans))]
+    outs, keys, start = [], [], None
+    for i, (n_p, K, depth) in enumerate(plans):
+        o = oracle_plan(orc, inst, bel, n_p, K, depth, seed=seeds[i], schedule=schedule,
+                        start=start, keep=True)
+        outs.append(o)
+        if i + 1 < len(plans):
+            a, ob = branches(o, A, 1)[0]
+            keys.append((a, ob))
+            start, _ = orc.reroot(o, a, ob, A)
     pom = V.Pomdp.from_instance(inst)
     b = V.belief_tensor(inst, bel)
     nb = b.numel() if inst["kind"] == "tabular" else b.numel() // 2
     n_p, K, depth = plans[0]
-    wss = [V.Workspace(pom, V.params(n_p, seed=seeds[0]), K, depth),
-           V.Workspace(pom, V.params(plans[1][0], seed=seeds[1]), plans[1][1], plans[1][2])]
-    out, kept = [], []
+    prm0 = V.params(n_p, seed=seeds[0], schedule=schedule)
+    prm1 = V.params(plans[1][0], seed=seeds[1], schedule=schedule)
+    wss = [V.Workspace(pom, prm0, K, depth), V.Workspace(pom, prm1, plans[1][1], plans[1][2])]
+    kept = []
     try:
         for i, (n_p, K, depth) in enumerate(plans):
             ws = wss[i % 2]
-            res = V.plan(pom, b, nb, K, depth, V.params(n_p, seed=seeds[i]), ws=ws)
-            out.append((res, V.tree_dump(ws, A, res.n_beliefs, res.n_actions)))
+            res, tree, act, obs = gpu_forced_plan(V, pom, ws, inst, b, nb, n_p, K, depth,
+                                                  outs[i], seed=seeds[i], schedule=schedule)
+            check_draws(outs[i], act, obs)
+            assert_parity(res, tree, outs[i], A)
             if i + 1 < len(plans):
                 nn, nK, nd = plans[i + 1]
                 kept.append(V.reroot(pom, ws, keys[i][0], keys[i][1],
-                                     V.params(nn, seed=seeds[i + 1]), nK, nd, wss[(i + 1) % 2]))
+                                     V.params(nn, seed=seeds[i + 1], schedule=schedule), nK,
+                                     nd, wss[(i + 1) % 2]))
     finally:
         for w in wss:
             w.close()
         pom.close()
-    return out, kept
+    return outs, keys, kept
 
 
 @pytest.mark.parametrize("plans", [
@@ -85,10 +79,7 @@ def run_chain(V, inst, bel, plans, seeds, keys, A):
 ])
 def test_tabular_chain(V, orc, plans):
     inst, bel, _ = I.workload("tabular16", seed=0)
-    seeds, outs, keys = clean_chain(orc, inst, bel, plans, 3)
-    res, kept = run_chain(V, inst, bel, plans, seeds, keys, 3)
-    for (r, t), o in zip(res, outs):
-        assert_parity(r, t, o, 3)
+    outs, keys, kept = forced_chain(V, orc, inst, bel, plans, 3)
     for i, k in enumerate(kept):
         _, tr = orc.reroot(outs[i], keys[i][0], keys[i][1], 3)
         assert k == len(tr["b_parent"])
@@ -97,43 +88,14 @@ def test_tabular_chain(V, orc, plans):
 def test_nav_chain(V, orc):
     inst = I.nav2d(4, 6, heuristic=1)
     bel = I.nav_belief(5, 500, 6.6, 8.6)          # near the goal: terminals
-    plans = [(1500, 4, 4), (1500, 3, 4)]
-    seeds, outs, keys = clean_chain(orc, inst, bel, plans, 4)
-    res, _ = run_chain(V, inst, bel, plans, seeds, keys, 4)
-    for (r, t), o in zip(res, outs):
-        assert_parity(r, t, o, 4)
+    forced_chain(V, orc, inst, bel, [(1500, 4, 4), (1500, 3, 4)], 4)
 
 
 def test_sparse_chain_fixed_schedule(V, orc):
     inst = I.tabular_sparse(3, 256, 5, 6, 4)
     bel = I.tabular_belief(inst)
-    plans = [(2000, 3, 3), (1000, 3, 3)]     # a different n_p for the second plan
-    for s1 in range(1, 30):
-        o1 = orc.plan(inst, bel, 2000, 3, 3, seed=s1, schedule=1, tau=TAU, keep=True)
-        if o1.near_ties:
-            continue
-        a, ob = branches(o1, 5, 1)[0]
-        h, _ = orc.reroot(o1, a, ob, 5)
-        o2 = orc.plan(inst, bel, 1000, 3, 3, seed=s1 + 500, schedule=1, tau=TAU, start=h)
-        if o2.near_ties == 0:
-            break
-    else:
-        pytest.fail("no clean seeds")
-    pom = V.Pomdp.from_instance(inst)
-    b = V.belief_tensor(inst, bel)
-    p1 = V.params(2000, seed=s1, schedule=1)
-    p2 = V.params(1000, seed=s1 + 500, schedule=1)
-    A_ws, B_ws = V.Workspace(pom, p1, 3, 3), V.Workspace(pom, p2, 3, 3)
-    try:
-        r1 = V.plan(pom, b, b.numel(), 3, 3, p1, ws=A_ws)
-        assert_parity(r1, V.tree_dump(A_ws, 5, r1.n_beliefs, r1.n_actions), o1, 5)
-        V.reroot(pom, A_ws, a, ob, p2, 3, 3, B_ws)
-        r2 = V.plan(pom, b, b.numel(), 3, 3, p2, ws=B_ws)
-        assert_parity(r2, V.tree_dump(B_ws, 5, r2.n_beliefs, r2.n_actions), o2, 5)
-    finally:
-        A_ws.close()
-        B_ws.close()
-        pom.close()
+    # a different n_p for the second plan
+    forced_chain(V, orc, inst, bel, [(2000, 3, 3), (1000, 3, 3)], 5, schedule=1)
 
 
 def test_missing_branch_gives_a_fresh_plan(V):

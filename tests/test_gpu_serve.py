@@ -118,3 +118,59 @@ def test_oversized_episode_rejected(V):
     assert e.value.status == V.VOPP_E_NOMEM
     srv.close()
     pom.close()
+
+
+def test_episode_chain_matches_oracle(V, orc):
+    # One tabular and one navigation episode of the mix, step by step against
+    # the oracle's own chain (plan, true-environment step, SIR belief update):
+    # every plan meets the parity bar of tests/drawcheck.py with no flagged
+    # draw decided differently, the environment gives the same observation,
+    # and the updated particles are equal bit for bit.  The served requests of
+    # the same episodes equal this plain chain (test above), so they meet the
+    # bar too.
+    import torch
+    from tests.drawcheck import (assert_tree_parity, check_draws, gpu_forced_plan,
+                                 oracle_plan)
+    eps = episodes(4)[:2]
+    served = serve(V, eps)
+    for ep, got in zip(eps, served):
+        inst = ep["inst"]
+        tab = inst["kind"] == "tabular"
+        pom = V.Pomdp.from_instance(inst)
+        parts = torch.as_tensor(V.particles_host(inst, ep["belief"]), device="cuda")
+        state = torch.tensor([ep["state"]] if tab else ep["state"],
+                             dtype=torch.int32 if tab else torch.float32, device="cuda")
+        o_parts = ep["belief"] if tab else (ep["belief"][0], ep["belief"][1])
+        o_state = ep["state"]
+        ws = V.Workspace(pom, V.params(ep["n_p"]), ep["budget"], ep["depth"])
+        try:
+            for t in range(ep["steps"]):
+                o = oracle_plan(orc, inst, o_parts, ep["n_p"], ep["budget"], ep["depth"],
+                                seed=ep["seed"], step=t)
+                r, tree, act, obs = gpu_forced_plan(V, pom, ws, inst, parts, ep["n_p"],
+                                                    ep["n_p"], ep["budget"], ep["depth"], o,
+                                                    seed=ep["seed"], step=t)
+                follow, _, _ = check_draws(o, act, obs)
+                assert follow == 0
+                assert_tree_parity(r, tree, o, inst["nA"])
+                assert r.action == o.action
+                assert got[t] == (r.action, r.v_root, r.particle_steps)
+                if t + 1 == ep["steps"]:
+                    break
+                o_state, o_obs, _, _ = orc.env_step(inst, o_state, o.action, ep["env_seed"], t)
+                g_obs, _, _ = V.env_step(pom, state, r.action, ep["env_seed"], t)
+                assert g_obs == o_obs
+                o_parts, _ = orc.belief_update(inst, o_parts, o.action, o_obs, ep["seed"], t)
+                V.belief_update(pom, parts, ep["n_p"], r.action, g_obs, ep["seed"], t)
+                host = parts.cpu().numpy()
+                if tab:
+                    assert np.array_equal(host, o_parts)
+                else:
+                    n = ep["n_p"]
+                    assert np.array_equal(host[:n].view(np.uint32),
+                                          np.asarray(o_parts[0], np.float32).view(np.uint32))
+                    assert np.array_equal(host[n:].view(np.uint32),
+                                          np.asarray(o_parts[1], np.float32).view(np.uint32))
+        finally:
+            ws.close()
+            pom.close()
