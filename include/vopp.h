@@ -220,6 +220,30 @@ vopp_status vopp_plan_trace(const vopp_pomdp* pomdp, const void* belief_particle
                             vopp_stats* stats, int16_t* draw_act, int32_t* draw_obs,
                             const int16_t* force_act, int64_t trace_len);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): vopp_plan
+ * without a workspace.  The tree lives in a static device array of
+ * VOPP_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends; the call allocates nothing (no hipMalloc, no pinned host
+ * memory, no events) and copies nothing from or to the host, so it can be
+ * captured in a graph.  It only enqueues the plan on `stream` and returns.
+ *   pomdp, belief_particles (DEVICE), n_belief, budget, depth, params: as
+ *     for vopp_plan; the plan's vopp_plan_footprint must not exceed
+ *     VOPP_NOALLOC_SCRATCH_BYTES, else VOPP_E_INVALID before any launch.
+ *   result (DEVICE, out): nA + 7 doubles, written when the stream reaches
+ *     the end of the plan: [0] action, [1 .. nA] root preferences, [nA+1]
+ *     V(root), [nA+2] particle steps, [nA+3] beliefs, [nA+4] action nodes,
+ *     [nA+5] error flags (1: a belief particle outside [0, nS); 2: internal
+ *     table overflow; 0 on success), [nA+6] near-tie draws.
+ * The result equals vopp_plan's bit for bit.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on one GPU (other streams or
+ * threads) race and give undefined results; calls in stream order do not.
+ * Every plan clears what it reads of the array first. */
+#define VOPP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vopp_status vopp_plan_noalloc(const vopp_pomdp* pomdp, const void* belief_particles,
+                              int32_t n_belief, int32_t budget, int32_t depth,
+                              const vopp_params* params, void* stream, double* result);
+
 /* Anytime planning step: Alg. 1 with its wall-clock budget.  Iterations run
  * while the planning time is not used up: after each iteration the device
  * compares its wall clock with the start of the plan's first kernel, and the

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -344,19 +345,11 @@ bool fits(const WsSizes& have, const WsSizes& need) {
          have.hcap >= need.hcap;
 }
 
-vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
-  vopp_workspace* w = new vopp_workspace();
-  w->z = z;
-  w->bytes = bytes_for(z);
-  (void)hipGetDevice(&w->device);
-  hipError_t e = hipMalloc(&w->arena, w->bytes);
-  if (e != hipSuccess) {
-    delete w;
-    return fail(VOPP_E_NOMEM, "hipMalloc(%zu bytes) for the workspace: %s", bytes_for(z),
-                hipGetErrorString(e));
-  }
-  Carver c(w->arena);
-  TreeView& t = w->tree;
+// Lays out the buffers of one plan's tree (sizes z) in device memory at base,
+// bytes_for(z) of it, in the order bytes_for counts them.
+void carve_tree(void* base, const WsSizes& z, TreeView& t, int** carry_rng, int** step_base,
+                double** out) {
+  Carver c(base);
   t.rec = c.take<unsigned char>((size_t)z.cap_b * z.rs);
   t.rs = z.rs;
   t.ra = z.Apad;
@@ -373,14 +366,28 @@ vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
   t.counters = c.take<unsigned long long>(8);
   t.stats = c.take<unsigned long long>(kStatRows * kStripes);
   t.gate = c.take<unsigned long long>(4);
-  w->carry_rng_dev = c.take<int>(2 * (kMaxDepth + 1));
-  t.carry_rng = w->carry_rng_dev;
-  int* step_base = c.take<int>(z.K + 1);
-  t.step_base = step_base;
-  w->step_base_dev = step_base;
+  *carry_rng = c.take<int>(2 * (kMaxDepth + 1));
+  t.carry_rng = *carry_rng;
+  *step_base = c.take<int>(z.K + 1);
+  t.step_base = *step_base;
   t.tr_key = c.take<unsigned long long>((size_t)(z.depth + 1) * z.n_p);
   t.tr_val = c.take<float>((size_t)(z.depth + 1) * z.n_p);
-  w->out_dev = c.take<double>(out_len(z));
+  *out = c.take<double>(out_len(z));
+}
+
+vopp_status ws_alloc(const WsSizes& z, vopp_workspace** out) {
+  vopp_workspace* w = new vopp_workspace();
+  w->z = z;
+  w->bytes = bytes_for(z);
+  (void)hipGetDevice(&w->device);
+  hipError_t e = hipMalloc(&w->arena, w->bytes);
+  if (e != hipSuccess) {
+    delete w;
+    return fail(VOPP_E_NOMEM, "hipMalloc(%zu bytes) for the workspace: %s", bytes_for(z),
+                hipGetErrorString(e));
+  }
+  TreeView& t = w->tree;
+  carve_tree(w->arena, z, t, &w->carry_rng_dev, &w->step_base_dev, &w->out_dev);
   e = hipHostMalloc((void**)&w->out_host, out_len(z) * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&w->step_host, (kMaxBudget + 8) * sizeof(int), hipHostMallocDefault);
@@ -503,7 +510,7 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
 }
 
 // Grid for a backup sweep over the beliefs of depth `dep` after iteration k.
-int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
+int backup_grid(const vopp_pomdp* p, int n_p, const int* D, int dep, int k,
                 int cap, int extra, bool wide) {
   (void)p;
   // One chunk of record positions per block over the level steps that hold
@@ -545,19 +552,21 @@ static vopp_status timed_gate(const vopp_workspace* w, hipStream_t s, int k, boo
 vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView& P,
                          hipStream_t s, int* n_steps_out) {
   const int K = P.K;
-  std::vector<int> D(K + 1, 0);
+  int D[kMaxBudget + 1] = {0};
   const int c0 = P.carry ? w->carry.n_steps : 0;   // a kept subtree's steps first
   int steps = c0;
-  w->step_host[0] = c0;
+  hipError_t e = hipSuccess;
+  if (!P.clear_all) w->step_host[0] = c0;
   for (int k = 1; k <= K; ++k) {
     D[k] = P.schedule == VOPP_SCHEDULE_FIXED ? P.depth : std::min(k, P.depth);
     steps += D[k];
-    w->step_host[k] = steps;
+    if (!P.clear_all) w->step_host[k] = steps;
   }
-  hipError_t e = hipMemcpyAsync(w->step_base_dev, w->step_host, (K + 1) * sizeof(int),
-                                hipMemcpyHostToDevice, s);
+  // Without a workspace (P.clear_all) the set-up kernel writes the schedule.
+  if (!P.clear_all)
+    e = hipMemcpyAsync(w->step_base_dev, w->step_host, (K + 1) * sizeof(int),
+                       hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "upload schedule");
-  const WsSizes& z = w->z;
   w->prof_used = 0;
   // Each launch below is bracketed by prof_begin/prof_end (no-ops unless
   // profiling is enabled on the workspace).
@@ -567,7 +576,7 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
     if (e == hipSuccess) e = (call);                        \
     if (e == hipSuccess) e = prof_end(w, s);                \
   } while (0)
-  if (w->hash_dirty) {
+  if (w->hash_dirty && !P.clear_all) {
     // A plan did not finish: the table state is unknown, clear it fully.
     e = hipMemcpyAsync(&w->tree.counters[3], &w->step_host[kMaxBudget + 1],
                        sizeof(unsigned long long), hipMemcpyHostToDevice, s);
@@ -822,6 +831,73 @@ extern "C" vopp_status vopp_plan_trace(const vopp_pomdp* p, const void* belief,
   if (!draw_act || !draw_obs) return fail(VOPP_E_INVALID, "null draw trace");
   return plan_common(p, belief, n_belief, budget, depth, prm, ws, stream, 0.0, action, values,
                      v_root, stats, nullptr, draw_act, draw_obs, force_act, trace_len);
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free plan: the tree lives in a file-scope device array of
+// VOPP_NOALLOC_SCRATCH_BYTES per GPU instead of a workspace.  In host code the
+// array's name only stands for the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress, taken once per device on the first call and
+// kept in scratch_ptr.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[VOPP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {nullptr};
+
+vopp_status scratch_of(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(VOPP_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    scratch_ptr[dev] = ptr;
+  }
+  *out = scratch_ptr[dev];
+  return VOPP_OK;
+}
+}  // namespace
+
+extern "C" vopp_status vopp_plan_noalloc(const vopp_pomdp* p, const void* belief,
+                                         int32_t n_belief, int32_t budget, int32_t depth,
+                                         const vopp_params* prm, void* stream, double* result) {
+  clear_error();
+  vopp_status st = check_params(p, prm, budget, depth);
+  if (st != VOPP_OK) return st;
+  if (!belief || n_belief < 1) return fail(VOPP_E_INVALID, "empty belief");
+  if (!result) return fail(VOPP_E_INVALID, "null result pointer");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device)
+    return fail(VOPP_E_INVALID, "model lives on device %d, current is %d", p->device, dev);
+  const WsSizes z = sizes_for(p, prm->n_particles, budget, depth, prm->schedule);
+  const size_t need = bytes_for(z);
+  if (need > (size_t)VOPP_NOALLOC_SCRATCH_BYTES)
+    return fail(VOPP_E_INVALID,
+                "the plan needs %zu bytes of tree memory; the allocation-free entry point "
+                "holds %zu (use vopp_plan with a workspace)",
+                need, (size_t)VOPP_NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  st = scratch_of(dev, &base);
+  if (st != VOPP_OK) return st;
+  // A workspace record over the scratch: no pinned buffers, events or
+  // profiling; nothing in it allocates.
+  vopp_workspace w;
+  w.z = z;
+  w.device = dev;
+  w.arena = base;
+  w.bytes = need;
+  double* unused_out = nullptr;
+  carve_tree(base, z, w.tree, &w.carry_rng_dev, &w.step_base_dev, &unused_out);
+  w.out_dev = result;
+  PlanView P = make_view(p, &w, belief, n_belief, budget, depth, prm);
+  P.clear_all = 1;
+  int steps = 0;
+  return enqueue_plan(p, &w, P, (hipStream_t)stream, &steps);
 }
 
 extern "C" vopp_status vopp_plan_anytime(const vopp_pomdp* p, const void* belief,

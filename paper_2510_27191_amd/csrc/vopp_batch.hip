@@ -58,9 +58,9 @@ std::vector<Phase> plan_phases(const vopp_pomdp* p, const PlanView& P, int accum
     ph.push_back({kPhaseForward, k, D[k], forward_blocks(P)});
     ph.push_back({kPhaseAccum, D[k], 0, accum_blocks(P, D[k], accum_cap)});
     t += D[k];
-    ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D, D[k], k, backup_cap)});
+    ph.push_back({kPhaseLeaf, D[k], k, backup_grid(p, P.n_p, D.data(), D[k], k, backup_cap)});
     for (int dep = D[k]; dep >= 2; --dep)
-      ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D, dep - 1, k, backup_cap)});
+      ph.push_back({kPhaseLevel, dep, k, backup_grid(p, P.n_p, D.data(), dep - 1, k, backup_cap)});
     ph.push_back({kPhaseRoot, k, 0, 1});
   }
   ph.push_back({kPhaseSelect, 0, 0, 1});

@@ -246,6 +246,10 @@ struct PlanView {
   // The plan starts from a kept subtree (tree re-rooting): its beliefs sit in
   // the level steps before the plan's own, listed by depth in t.carry_rng.
   int carry;
+  // Plans without a workspace (the allocation-free entry point): set-up clears
+  // the whole table (the memory holds whatever the last call left) and
+  // writes the schedule t.step_base itself (the host copies nothing).
+  int clear_all;
   FilterView f;            // served episodes only
 };
 

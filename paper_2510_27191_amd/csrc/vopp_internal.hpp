@@ -103,7 +103,7 @@ PlanView make_view(const vopp_pomdp* p, vopp_workspace* w, const void* belief,
                    int n_belief, int K, int depth, const vopp_params* prm);
 // Blocks of a backup sweep over the beliefs of depth dep after iteration k;
 // extra: level steps of a kept subtree holding that depth.
-int backup_grid(const vopp_pomdp* p, int n_p, const std::vector<int>& D, int dep, int k,
+int backup_grid(const vopp_pomdp* p, int n_p, const int* D, int dep, int k,
                 int cap, int extra = 0, bool wide = false);
 // Sizes of a plan; extra_steps: level steps of a kept subtree in front.
 WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,

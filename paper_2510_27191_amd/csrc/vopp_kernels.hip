@@ -209,7 +209,8 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
   const TreeView& T = P.t;
   const unsigned long long n_prev = T.counters[2];
   const size_t hcap = (size_t)T.h_mask + 1;
-  const bool full = T.counters[3] != 0ull || n_prev * 10ull >= (unsigned long long)hcap;
+  const bool full = P.clear_all || T.counters[3] != 0ull ||
+                    n_prev * 10ull >= (unsigned long long)hcap;
   const size_t tid = (size_t)blk * kBlock + threadIdx.x;
   const size_t stride = (size_t)nblk * kBlock;
   if (P.carry) {
@@ -236,6 +237,17 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
     __syncthreads();
     const int j = threadIdx.x;
     for (int i = j; i < kStatRows * kStripes; i += kBlock) T.stats[i] = 0ull;
+    if (j == 0 && P.clear_all) {
+      // The schedule D_k (no kept subtree on this path): first level step of
+      // each iteration.
+      int* sb = const_cast<int*>(T.step_base);
+      int run = 0;
+      for (int k = 1; k <= P.K; ++k) {
+        sb[k - 1] = run;
+        run += P.schedule == 1 ? P.depth : min(k, P.depth);
+      }
+      sb[P.K] = run;
+    }
     if (j == 0) {
       T.gate[0] = (unsigned long long)wall_clock64();   // start of the plan
       T.gate[1] = 0ull;

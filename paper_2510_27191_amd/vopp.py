@@ -155,6 +155,8 @@ def lib():
                                   C.POINTER(i32), vp, vp, C.POINTER(vopp_stats), vp, vp,
                                   vp, C.c_int64]
     L.vopp_plan_trace.restype = st
+    L.vopp_plan_noalloc.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vopp_params), vp, vp]
+    L.vopp_plan_noalloc.restype = st
     L.vopp_plan_anytime.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.POINTER(vopp_params),
                                     vp, vp, C.POINTER(i32), vp, vp, C.POINTER(vopp_stats),
                                     C.POINTER(i32)]
@@ -386,6 +388,25 @@ def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=
                      int(st.near_ties))
     shape = (steps, prm.n_particles)
     return (res, act_d.cpu().numpy().reshape(shape), obs_d.cpu().numpy().reshape(shape))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def plan_noalloc(pomdp, belief_dev, n_belief, budget, depth, prm, result_dev, stream=None):
+    """vopp_plan_noalloc: enqueue a plan whose tree lives in the library's
+    static device array; result_dev is a float64 device tensor of at least
+    nA + 7 entries (action, root preferences, V(root), particle steps,
+    beliefs, action nodes, error flags, near ties), written on the stream."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if result_dev.dtype != torch.float64 or result_dev.numel() < pomdp.nA + 7:
+        raise ValueError("result_dev must be a float64 device tensor of nA + 7 entries")
+    _check(lib().vopp_plan_noalloc(pomdp.handle, C.c_void_p(belief_dev.data_ptr()),
+                                   int(n_belief), int(budget), int(depth), C.byref(prm),
+                                   C.c_void_p(stream.cuda_stream),
+                                   C.c_void_p(result_dev.data_ptr())))
 
 
 def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, ws=None,
