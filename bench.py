@@ -32,55 +32,52 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes of each kernel kind over one plan: every field the kernel
-# must touch in HBM-resident tree, table or trace arrays, counted once (model
-# tables are cache resident and not counted).  ra = |A| rounded up to a
-# multiple of 4; a belief record holds 24*ra + 32 used bytes.
-#   forward, per particle-step: preference row 4|A| + table slot 16 + N 8 and
-#     C 16 (atomic read + write) + trace word and value 12; per new belief:
-#     key insert 8 + record index 4 + list entry 4 + record 24*ra + 32; per
-#     episode and iteration: leaf count 8 and sum 16, leaf trace 12.
-#   accumulate, per trace item: 8 (the value only where the word is set).
-#     The visits it folds are counted under forward.
-#   backup_level, per belief of the swept depth: record 24*ra + 32 read, row
-#     4*ra + V and N_b 8 written, W cleared 8|A|, push into the parent 16.
-#   backup_leaf, per belief of the deepest depth: record tail 32 read, 24
-#     written, push 16.
-# With more than 64 actions a record also holds a bitmap of its valid action
-# columns; the long-row terms are given where they are computed below
-# (nodes_per_belief: action nodes per belief on average).
-def plan_bytes(nA, n_p, K, depth, counts, particle_steps, nodes_per_belief=0.0):
+# The method's bytes per unit of work (the hot-path scope table's per-unit
+# figures), independent of this implementation's layout:
+#   forward, per particle step: read the episode's particle (state 12 B
+#     tabular, 16 B navigation), gather the preference row 4|A|, probe the
+#     (belief, action) child 4, probe the belief table 16, update N and C 12,
+#     write the next state and belief 8; per new action node 16; per new
+#     belief 12 + 8|A| for its row, initial preferences and child links, plus
+#     a 16 B table insert.
+#   backup, per node visit: a belief as a child 20 (read V, N_b and its
+#     parent 12, accumulate into the parent 8); an internal belief (one with
+#     an action node) 12|A| + 8 (read and write its preferences, read its
+#     child links, write V and N_b); an action node 20.
+# The level sweeps count their own visits (vopp_stats.sweep_*); the leaf sweep
+# visits every belief of the iteration's deepest depth as a child.
+def method_bytes(kind, nA, particle_steps, n_beliefs, n_actions, sweep, leaf_visits):
+    state = 16 if kind == "nav2d" else 12
+    visits, internal, nodes = sweep
+    return {
+        "forward": particle_steps * (state + 4 * nA + 4 + 16 + 12 + 8) + n_actions * 16
+                   + (n_beliefs - 1) * (12 + 8 * nA + 16),
+        "backup_level": 20 * visits + (12 * nA + 8) * internal + 20 * nodes,
+        "backup_leaf": 20 * leaf_visits,
+    }
+
+
+# Bytes the present layout moves for the same work (the overhead against the
+# method's bytes): a belief record holds 24*ra + 32 bytes (ra = |A| rounded up
+# to a multiple of 4); a level sweep reads each swept record whole, writes
+# its row and V, N_b, clears W of its visited actions and pushes into its
+# parent (16: the atomic's read and write).
+def layout_bytes_backup_level(nA, sweep):
     ra = (nA + 3) // 4 * 4
-    rec = 24 * ra + 32
+    visits, internal, nodes = sweep
+    return visits * (24 * ra + 32 + 16) + internal * (4 * ra + 8) + nodes * 8
+
+
+def leaf_sweep_visits(n_p, K, depth, counts):
+    """Beliefs the leaf sweeps visit over a plan (every belief of the
+    iteration's deepest depth), from the beliefs created per level step."""
     D = [min(k, depth) for k in range(1, K + 1)]
     t0 = np.concatenate([[0], np.cumsum(D)[:-1]]).astype(int)
-    new_b = int(np.sum(counts))
-    items = sum((d + 1) * n_p for d in D)
-
-    def beliefs_at(k, dep):       # beliefs of depth dep after iteration k (1-based)
-        return sum(int(counts[t0[kk] + dep - 1]) for kk in range(k) if D[kk] >= dep)
-
-    level = sum(beliefs_at(k, dep - 1) for k in range(1, K + 1)
-                for dep in range(2, D[k - 1] + 1))
-    leaf = sum(beliefs_at(k, D[k - 1]) for k in range(1, K + 1))
-    # Long rows write a new record's Psi, metadata and bitmap (4*ra + 32 +
-    # 16 per 128 actions); the first visit of an action node sets its bit and
-    # clears N, C and W (4 + 20), in the claim pass before the accumulate.
-    wide = nA > 64
-    nbq = (ra + 127) // 128
-    rec_new = rec if not wide else 4 * ra + 32 + 16 * nbq
-    claim = (sum(d * n_p for d in D) * 8 + new_b * nodes_per_belief * 24) if wide else 0
-    # A long-row sweep reads Psi, the bitmap and the metadata, then N, C and W
-    # of the visited actions (20), writes their Psi quads (16) and clears W
-    # (8), and pushes one word.
-    return {
-        "forward": particle_steps * (4 * nA + 16 + 24 + 12) + new_b * (8 + 4 + 4 + rec_new)
-                   + K * n_p * (24 + 12),
-        "accumulate": items * 8 + claim,
-        "backup_level": (level * (rec + 4 * ra + 8 + 8 * nA + 16) if not wide else
-                         level * (4 * ra + ra // 8 + 32 + 8 + nodes_per_belief * (20 + 16 + 8))),
-        "backup_leaf": leaf * (32 + 24 + 16),
-    }
+    total = 0
+    for k in range(1, K + 1):
+        dep = D[k - 1]
+        total += sum(int(counts[t0[kk] + dep - 1]) for kk in range(k) if D[kk] >= dep)
+    return total
 
 
 # Measured HBM traffic of the dominant kernel per launch (bytes), from the
@@ -128,7 +125,68 @@ def cpu_baseline(inst, bel, p, budget_s=12.0, max_plans=4):
                       f"serial, {t_total:.1f} s"}
 
 
-def bench_batch(V, I, reps=3, autotune=True):
+def _oracle_mix_worker(indices, barrier, queue):
+    """One host core of the parallel oracle baseline: plans the given
+    instances of the 256-instance mix serially (after every worker has built
+    its inputs) and reports (particle steps, seconds)."""
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as orc
+    from paper_2510_27191_amd import instances as I
+    mix = I.batch_mix(0)
+    barrier.wait()
+    t0 = time.perf_counter()
+    steps = 0
+    for i in indices:
+        inst, bel, p = mix[i]
+        r = orc.plan(inst, bel, p["n_particles"], p["budget"], p["depth"], eta=p["eta"],
+                     seed=p["seed"])
+        steps += r.particle_steps
+    queue.put((steps, time.perf_counter() - t0))
+
+
+def host_cores():
+    """Host cores this process may use (the GPU machine gives one GPU 16 of them,
+    whatever the machine has)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_mix_baseline(stride=16):
+    """The serial oracle over a bounded sample of the 256-instance mix (the
+    instances i with i % stride in {0, 1}: half tabular, half navigation),
+    one worker process per host core, instances dealt round robin.  Rate =
+    all particle steps / the slowest worker's planning time."""
+    import multiprocessing as mp
+    from paper_2510_27191_amd import instances as I
+    idx = [i for i in range(256) if i % stride in (0, 1)]
+    cores = min(host_cores(), len(idx))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    queue = ctx.Queue()
+    # Largest instances first, so the deal balances the workers.
+    mix = I.batch_mix(0)
+    work = sorted(idx, key=lambda i: -mix[i][2]["n_particles"] * mix[i][2]["depth"] ** 2)
+    procs = [ctx.Process(target=_oracle_mix_worker, args=(work[w::cores], barrier, queue))
+             for w in range(cores)]
+    for pr in procs:
+        pr.start()
+    got = [queue.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+    steps = sum(g[0] for g in got)
+    wall = max(g[1] for g in got)
+    return {"value": steps / wall, "unit": "particle-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(idx)} of the 256 instances (i mod {stride} in {{0, 1}}), "
+                      f"{steps} particle steps, one serial oracle process per core, "
+                      f"slowest worker {wall:.1f} s, "
+                      f"{sum(g[1] for g in got):.1f} s of CPU time in all"}
+
+
+def bench_batch(V, I, reps=3, autotune=True, cpu=True):
     """256 mixed instances: one batched hipGraph replay vs 256 plain calls."""
     import torch
     mix = I.batch_mix(0)
@@ -193,6 +251,8 @@ def bench_batch(V, I, reps=3, autotune=True):
     batch.close()
     for it in items:
         it[0].close()
+    if cpu:
+        out["cpu_baseline"] = oracle_mix_baseline()
     return out
 
 
@@ -393,6 +453,119 @@ def bench_serve(V, I, qps_list=(250, 1000, 2500), seconds=5.0, steps_per_episode
             "sweep": results}
 
 
+def bench_plain(V, I, name, steps, warmup, event_profile, cpu):
+    """Plain single-instance plans of one workload: throughput, latency, the
+    dominant kernel against the HBM roofline and the oracle on the host."""
+    import torch
+    inst, bel, p = I.workload(name, seed=0)
+    n_p, K, depth, eta = p["n_particles"], p["budget"], p["depth"], p["eta"]
+    pom = V.Pomdp.from_instance(inst)
+    prm = V.params(n_p, eta=eta, seed=1)
+    ws = V.Workspace(pom, prm, K, depth)
+    belt = V.belief_tensor(inst, bel)
+    n_bel = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
+    stream = torch.cuda.current_stream()
+    # Warm-up plans; the last one brackets every kernel kind with events to
+    # find the kind that dominates device time.
+    dom = None
+    warm_share = None
+    for i in range(warmup):
+        if event_profile and i == warmup - 1:
+            V.profile_reset(ws)
+            V.profile_enable(ws, None)
+        V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=100 + i),
+               ws=ws, stream=stream)
+    if event_profile and warmup > 0:
+        warm = V.profile_read(ws)
+        dom = max((k for k in warm if k != "setup"), key=lambda k: warm[k][0])
+        warm_total = sum(v[0] for v in warm.values())
+        warm_share = {k: v[0] / warm_total for k, v in warm.items() if v[1]}
+    # Timed region: plain plans, no event brackets.
+    V.profile_enable(ws, [])
+    torch.cuda.synchronize()
+    lat, dev_ms, results = [], [], []
+    total_steps = 0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        a = time.perf_counter()
+        r = V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
+                   ws=ws, stream=stream)
+        lat.append((time.perf_counter() - a) * 1e3)
+        dev_ms.append(r.device_ms)
+        results.append(r)
+        total_steps += r.particle_steps
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    counts = V.level_counts(ws)              # beliefs per level step, last plan
+    # The dominant kind's launches, bracketed with HIP events on the plan
+    # stream, over the same plans run again (each bracket costs about 2 us of
+    # device time, so the timed region carries none).
+    prof = None
+    if dom is not None:
+        V.profile_reset(ws)
+        V.profile_enable(ws, [dom])
+        for i in range(steps):
+            V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
+                   ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        prof = V.profile_read(ws)
+        V.profile_enable(ws, [])
+    out = {
+        "value": total_steps / elapsed,
+        "unit": "particle-steps/s",
+        "ms_per_step": elapsed * 1e3 / steps,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "device_p50": percentile(dev_ms, 50)},
+        "particle_steps_per_plan": total_steps / steps,
+        "near_ties_per_plan": float(np.mean([r.near_ties for r in results])),
+    }
+    if prof is not None:
+        kinds = {k: v for k, v in prof.items() if v[1] > 0}
+        out["kernel_share_warmup"] = warm_share
+        roof = {"kernel": dom, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": None}
+        # Method bytes summed over the timed plans (each plan's own tree).
+        leaf = leaf_sweep_visits(n_p, K, depth, counts)
+        per = [method_bytes(name, pom.nA, r.particle_steps, r.n_beliefs, r.n_actions,
+                            r.sweep, leaf) for r in results]
+        total = {k: sum(x[k] for x in per) for k in per[0]}
+        if dom in total:
+            ms, launches = kinds[dom]
+            achieved = total[dom] / (ms * 1e-3) / 1e9
+            roof.update(achieved=achieved, frac=achieved / HBM_PEAK_GBS,
+                        launches_per_plan=launches // steps,
+                        avg_launch_us=ms * 1e3 / launches,
+                        bytes_per_launch=total[dom] / launches,
+                        bytes_per_plan=total[dom] / steps,
+                        byte_model="the method's bytes per unit of work (per particle "
+                                   "step, new node, belief and action-node visit) "
+                                   "times the units each timed plan counted",
+                        timing="HIP events around each launch of the kernel on the plan "
+                               "stream, over the timed plans run again")
+            if dom == "backup_level":
+                sw = [sum(r.sweep[i] for r in results) / launches for i in range(3)]
+                roof["units_per_launch"] = {"belief_visits": sw[0],
+                                            "internal_belief_visits": sw[1],
+                                            "action_node_visits": sw[2]}
+                lay = sum(layout_bytes_backup_level(pom.nA, r.sweep) for r in results)
+                roof["layout_bytes_per_launch"] = lay / launches
+            tr = MEASURED_TRAFFIC.get(dom, {}).get(name)
+            if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
+                roof["traffic"] = tr
+                roof["traffic_GBs"] = tr / (ms * 1e-3 / launches) / 1e9
+                roof["traffic_over_method_bytes"] = tr / (total[dom] / launches)
+        else:
+            roof.update(achieved=None, frac=None,
+                        note=f"dominant kernel {dom} has no byte model")
+        out["roofline"] = roof
+    ws.close()
+    pom.close()
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, bel, p)
+    out["_inputs"] = (inst, bel, p)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +580,8 @@ def main():
                          "region); the roofline is then left out")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-instance batched vs plain comparison")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse4096 line that follows the nav2d headline")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served (continuous batching) vs plain comparison")
     ap.add_argument("--no-anytime", action="store_true",
@@ -446,129 +621,63 @@ def main():
     from paper_2510_27191_amd import instances as I
     from paper_2510_27191_amd import vopp as V
 
-    inst, bel, p = I.workload(args.workload, seed=0)
-    n_p, K, depth, eta = p["n_particles"], p["budget"], p["depth"], p["eta"]
-    pom = V.Pomdp.from_instance(inst)
-    prm = V.params(n_p, eta=eta, seed=1)
-    ws = V.Workspace(pom, prm, K, depth)
-    belt = V.belief_tensor(inst, bel)
-    n_bel = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
-    stream = torch.cuda.current_stream()
+    WORKLOADS = {
+        "nav2d": "continuous 2-D navigation POMDP, 8 obstacle disks, 0.5-grid "
+                 "observation keys, n_p=65536, depth 10, budget 10 iterations",
+        "sparse4096": "sparse tabular POMDP |S|=4096 |A|=8 |O|=32, 8 successors, "
+                      "n_p=262144, depth 8, budget 8 iterations",
+        "tabular16": "tabular POMDP |S|=16 |A|=3 |O|=4, n_p=1024, depth 4, budget 4",
+        "mars625": "MARS-shaped tabular POMDP |S|=2048 |A|=625 |O|=9, 4 successors, "
+                   "n_p=16384, depth 4, budget 4 iterations",
+        "mars3025": "MARS-shaped tabular POMDP |S|=512 |A|=3025 |O|=9, 4 successors, "
+                    "n_p=16384, depth 4, budget 4 iterations",
+    }
 
-    # Warm-up plans; the last ones bracket every kernel kind with events to
-    # find the kind that dominates device time.
-    dom = None
-    for i in range(args.warmup):
-        if not args.no_event_profile and i == args.warmup - 1:
-            V.profile_reset(ws)
-            V.profile_enable(ws, None)
-        V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=100 + i),
-               ws=ws, stream=stream)
-    if not args.no_event_profile and args.warmup > 0:
-        warm = V.profile_read(ws)
-        dom = max((k for k in warm if k != "setup"), key=lambda k: warm[k][0])
-        warm_total = sum(v[0] for v in warm.values())
-        warm_share = {k: v[0] / warm_total for k, v in warm.items() if v[1]}
+    def config_of(name, inst, p):
+        return {"workload": f"{name}: {WORKLOADS[name]}", "n_particles": p["n_particles"],
+                "budget": p["budget"], "depth": p["depth"], "eta": p["eta"],
+                "gamma": inst["gamma"], "schedule": "deepening",
+                "parallelism": "single GPU"}
 
-    # Timed region: plain plans, no event brackets.
-    V.profile_enable(ws, [])
-    torch.cuda.synchronize()
-    lat = []
-    dev_ms = []
-    steps = 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        a = time.perf_counter()
-        r = V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
-                   ws=ws, stream=stream)
-        lat.append((time.perf_counter() - a) * 1e3)
-        dev_ms.append(r.device_ms)
-        steps += r.particle_steps
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # The dominant kind's launches, bracketed with HIP events on the plan
-    # stream, over the same plans run again (each bracket costs about 2 us of
-    # device time, so the timed region carries none).
-    prof = None
-    if dom is not None:
-        V.profile_reset(ws)
-        V.profile_enable(ws, [dom])
-        for i in range(args.steps):
-            r = V.plan(pom, belt, n_bel, K, depth, V.params(n_p, eta=eta, seed=1000 + i),
-                       ws=ws, stream=stream)
-        torch.cuda.synchronize()
-        prof = V.profile_read(ws)
-        V.profile_enable(ws, [])
-
+    head = bench_plain(V, I, args.workload, args.steps, args.warmup,
+                       not args.no_event_profile, not args.no_cpu_baseline)
+    inst, bel, p = head.pop("_inputs")
     out = {
         "metric": "particle-steps/s at fixed budget; p50/p99 plan latency, batched vs plain",
-        "value": steps / elapsed,
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded instance generators; no dataset)",
-        "config": {"workload": f"{args.workload}: " + {
-            "nav2d": "continuous 2-D navigation POMDP, 8 obstacle disks, 0.5-grid "
-                     "observation keys, n_p=65536, depth 10, budget 10 iterations",
-            "sparse4096": "sparse tabular POMDP |S|=4096 |A|=8 |O|=32, 8 successors, "
-                          "n_p=262144, depth 8, budget 8 iterations",
-            "tabular16": "tabular POMDP |S|=16 |A|=3 |O|=4, n_p=1024, depth 4, budget 4",
-            "mars625": "MARS-shaped tabular POMDP |S|=2048 |A|=625 |O|=9, 4 successors, "
-                       "n_p=16384, depth 4, budget 4 iterations",
-            "mars3025": "MARS-shaped tabular POMDP |S|=512 |A|=3025 |O|=9, 4 successors, "
-                        "n_p=16384, depth 4, budget 4 iterations",
-        }[args.workload], "n_particles": n_p, "budget": K, "depth": depth,
-            "eta": eta, "gamma": inst["gamma"], "schedule": "deepening",
-            "parallelism": "single GPU"},
-        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
-                       "device_p50": percentile(dev_ms, 50)},
-        "particle_steps_per_plan": steps / args.steps,
+        "config": config_of(args.workload, inst, p),
     }
-    if prof is not None:
-        kinds = {k: v for k, v in prof.items() if v[1] > 0}
-        out["kernel_share_warmup"] = warm_share
-        roof = {"kernel": dom, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "traffic": None}
-        model = plan_bytes(pom.nA, n_p, K, depth, V.level_counts(ws), r.particle_steps,
-                           r.n_actions / max(r.n_beliefs, 1))
-        if dom in model:
-            ms, launches = kinds[dom]
-            per_plan_ms = ms / args.steps
-            achieved = model[dom] / (per_plan_ms * 1e-3) / 1e9
-            roof.update(achieved=achieved, frac=achieved / HBM_PEAK_GBS,
-                        launches_per_plan=launches // args.steps,
-                        avg_launch_us=ms * 1e3 / launches,
-                        bytes_per_launch=model[dom] * args.steps / launches,
-                        bytes_per_plan=model[dom],
-                        byte_model="algorithmic bytes of the last timed plan's tree",
-                        timing="HIP events around each launch of the kernel on the plan "
-                               "stream, over the timed plans run again")
-            tr = MEASURED_TRAFFIC.get(dom, {}).get(args.workload)
-            if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
-                roof["traffic"] = tr
-                roof["traffic_GBs"] = tr / (ms * 1e-3 / launches) / 1e9
-        else:
-            roof.update(achieved=None, frac=None,
-                        note=f"dominant kernel {dom} has no byte model")
-        out["roofline"] = roof
-    ws.close()
+    out.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
+    # The large sparse tabular workload as its own line (same fields).
+    if args.workload == "nav2d" and not args.no_sparse:
+        sub = bench_plain(V, I, "sparse4096", args.steps, args.warmup,
+                          not args.no_event_profile, not args.no_cpu_baseline)
+        s_inst, _, s_p = sub.pop("_inputs")
+        sub["config"] = config_of("sparse4096", s_inst, s_p)
+        out["sparse4096"] = sub
+    n_p, K, depth, eta = p["n_particles"], p["budget"], p["depth"], p["eta"]
+    pom = V.Pomdp.from_instance(inst)
+    belt = V.belief_tensor(inst, bel)
+    n_bel = belt.numel() if inst["kind"] == "tabular" else belt.numel() // 2
     if not args.no_anytime:
         out["anytime"] = bench_anytime(V, pom, belt, n_bel, n_p, depth, eta)
     if not args.no_reroot:
         out["reroot"] = bench_reroot(V, inst, pom, belt, n_bel, n_p, K, depth, eta)
     pom.close()
     if not args.no_batch:
-        out["batched_vs_plain"] = bench_batch(V, I)
+        out["batched_vs_plain"] = bench_batch(V, I, cpu=not args.no_cpu_baseline)
     if not args.no_serve:
         out["served_vs_plain"] = bench_serve(V, I, seconds=args.serve_seconds)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, bel, p)
     print(json.dumps(out), flush=True)
 
 

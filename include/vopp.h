@@ -157,6 +157,13 @@ typedef struct {
   int64_t n_actions;        /* action nodes (b, a) visited at least once   */
   double device_ms;         /* device time of the plan, HIP events          */
   int64_t near_ties;        /* near-tie action draws (see above)           */
+  /* Work of the depth sweeps of the backup (Alg. 3, the loop over d = D..2,
+   * summed over every iteration; the leaf sweep is not included): belief
+   * visits, the visits of beliefs with at least one action node (those
+   * update their preference row), and action-node visits. */
+  int64_t sweep_visits;
+  int64_t sweep_internal;
+  int64_t sweep_nodes;
 } vopp_stats;
 
 /* A workspace holds one plan's tree and per-episode trace in HBM, sized for
@@ -230,11 +237,12 @@ vopp_status vopp_plan_trace(const vopp_pomdp* pomdp, const void* belief_particle
  *   pomdp, belief_particles (DEVICE), n_belief, budget, depth, params: as
  *     for vopp_plan; the plan's vopp_plan_footprint must not exceed
  *     VOPP_NOALLOC_SCRATCH_BYTES, else VOPP_E_INVALID before any launch.
- *   result (DEVICE, out): nA + 7 doubles, written when the stream reaches
+ *   result (DEVICE, out): nA + 10 doubles, written when the stream reaches
  *     the end of the plan: [0] action, [1 .. nA] root preferences, [nA+1]
  *     V(root), [nA+2] particle steps, [nA+3] beliefs, [nA+4] action nodes,
  *     [nA+5] error flags (1: a belief particle outside [0, nS); 2: internal
- *     table overflow; 0 on success), [nA+6] near-tie draws.
+ *     table overflow; 0 on success), [nA+6] near-tie draws, [nA+7 .. nA+9]
+ *     the sweep counts of vopp_stats.
  * The result equals vopp_plan's bit for bit.  Every call on one GPU uses
  * that GPU's one array: calls that overlap on one GPU (other streams or
  * threads) race and give undefined results; calls in stream order do not.

@@ -318,7 +318,7 @@ WsSizes sizes_for(const vopp_pomdp* p, int n_p, int K, int depth, int schedule,
 
 // Doubles of a workspace's result record: action, |A| root preferences, V,
 // counts and flags.
-size_t out_len(const WsSizes& z) { return (size_t)std::max(kOutStride, z.Apad + 8); }
+size_t out_len(const WsSizes& z) { return (size_t)std::max(kOutStride, z.Apad + 12); }
 
 size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
@@ -803,6 +803,9 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
     stats->n_beliefs = (int64_t)nb;
     stats->n_actions = (int64_t)na;
     stats->near_ties = (int64_t)o[A + 6];
+    stats->sweep_visits = (int64_t)o[A + 7];
+    stats->sweep_internal = (int64_t)o[A + 8];
+    stats->sweep_nodes = (int64_t)o[A + 9];
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
     stats->device_ms = ms;

@@ -142,10 +142,10 @@ struct TreeView {
   unsigned long long* counters;  // [1] error flags [2] beliefs of the last plan
                                  // [3] table dirty [5] last plan's level steps
                                  // [6] last plan's n_p
-  unsigned long long* stats;     // [6][kStripes] particle steps, then two banks
-                                 // of (action nodes, beliefs), then near-tie
-                                 // draws, striped over blocks so that no
-                                 // address takes many atomics
+  unsigned long long* stats;     // [kStatRows][kStripes] particle steps, then two
+                                 // banks of (action nodes, beliefs), near-tie
+                                 // draws and the sweeps' work, striped over
+                                 // blocks so that no address takes many atomics
   unsigned long long* gate;      // [4] plans with a time budget: [0] start on
                                  // the wall clock, [1] stop flag, [2] iterations run
   const int* carry_rng;          // [kMaxDepth + 1][2] level steps of a kept
@@ -207,8 +207,11 @@ struct EpisodeView {
 
 constexpr int kBackupCap = 2048;            // default block cap of a backup sweep
 constexpr int kStripes = 64;                // stripes of each tree statistic
-constexpr int kStatRows = 6;                // rows of kStripes in TreeView::stats
+constexpr int kStatRows = 9;                // rows of kStripes in TreeView::stats
 constexpr int kStatNear = 5;                // row of the near-tie draw count
+constexpr int kStatSweep = 6;               // rows 6, 7, 8: the level sweeps' belief
+                                            // visits, internal-belief visits and
+                                            // action-node visits over the plan
 constexpr int kAccumCap = 4096;             // default block cap of the accumulate sweep
 
 // Particle-filter belief and true-environment state of a served episode.
@@ -272,8 +275,9 @@ __device__ __forceinline__ bool budget_spent(const PlanView& P) {
 
 // Result record written by the select phase (doubles): [0] action,
 // [1..A] root preferences, [A+1] V(root), [A+2] particle steps, [A+3] beliefs,
-// [A+4] action nodes, [A+5] input-error flags, [A+6] near-tie draws.
-constexpr int kOutStride = kMaxA + 8;
+// [A+4] action nodes, [A+5] input-error flags, [A+6] near-tie draws,
+// [A+7 .. A+9] the level sweeps' belief, internal-belief and action-node visits.
+constexpr int kOutStride = kMaxA + 12;
 
 // Phase kinds (same numbering as the ABI's VOPP_KERNEL_* kinds).
 enum : int {

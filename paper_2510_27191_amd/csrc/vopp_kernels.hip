@@ -737,6 +737,7 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
   const int A = P.m.nA;
   const float gamma = P.m.gamma, eta = P.eta, inv = P.fix_inv;
   unsigned long long nodes = 0, beliefs = 0;  // tree statistics (last iteration)
+  unsigned long long internal = 0;            // beliefs with an action node
   const int per = (P.n_p + kBlock - 1) / kBlock;
   for (int c = blk; c < R.n * per; c += nblk) {
     const int r = c / per;
@@ -837,6 +838,7 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
           if (j < A && n[j] > 0 && wf[j]) wrow[j] = 0ull;
         mt->V = V;
         mt->Nb = N;
+        ++internal;
       } else {
         V = V0;
         N = N0;
@@ -848,12 +850,20 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
     }
     push_values(P, sm.agg, dep - 1 < kPushDirectDepth, parent, V, N);
   }
-  if (counts_tree(P, k)) {
-    unsigned long long* bank = stat_bank(P, k);
-    nodes = block_sum(nodes, sm.wave);
-    if (threadIdx.x == 0 && nodes) atomicAdd(&bank[blk % kStripes], nodes);
-    beliefs = block_sum(beliefs, sm.wave);
-    if (threadIdx.x == 0 && beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
+  // The sweep's work over the plan (every iteration), then the tree
+  // statistics (the last iteration).  A block visits fewer than 2^32 beliefs.
+  const unsigned long long vi = block_sum(beliefs | (internal << 32), sm.wave);
+  const unsigned long long nd = block_sum(nodes, sm.wave);
+  if (threadIdx.x == 0) {
+    unsigned long long* sw = P.t.stats + (size_t)kStatSweep * kStripes + blk % kStripes;
+    if (vi & 0xffffffffull) atomicAdd(sw, vi & 0xffffffffull);
+    if (vi >> 32) atomicAdd(sw + kStripes, vi >> 32);
+    if (nd) atomicAdd(sw + 2 * kStripes, nd);
+    if (counts_tree(P, k)) {
+      unsigned long long* bank = stat_bank(P, k);
+      if (nd) atomicAdd(&bank[blk % kStripes], nd);
+      if (vi & 0xffffffffull) atomicAdd(&bank[kStripes + blk % kStripes], vi & 0xffffffffull);
+    }
   }
 }
 
@@ -920,6 +930,7 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
   const int lane = threadIdx.x & 63;
   const int waves = kBlock / 64;
   unsigned long long nodes = 0, beliefs = 0;  // tree statistics (lane 0 counts)
+  unsigned long long internal = 0;            // beliefs with an action node
   // Each wavefront takes kWideChunk positions of one level step at a time and
   // visits the beliefs among them one after the other.
   const int per = (P.n_p + kWideChunk - 1) / kWideChunk;
@@ -1035,6 +1046,7 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
         V = m2 + logf(wave_sumf(se2)) / eta;
         N = (int)wave_sum((unsigned long long)nsum);
         nodes += wave_sum((unsigned long long)nn);
+        ++internal;
       } else {
         V = V0;
         N = N0;
@@ -1066,10 +1078,16 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
       }
     }
   }
-  if (counts_tree(P, k) && lane == 0) {
-    unsigned long long* bank = stat_bank(P, k);
-    if (nodes) atomicAdd(&bank[blk % kStripes], nodes);
-    if (beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
+  if (lane == 0) {
+    unsigned long long* sw = T.stats + (size_t)kStatSweep * kStripes + blk % kStripes;
+    if (beliefs) atomicAdd(sw, beliefs);
+    if (internal) atomicAdd(sw + kStripes, internal);
+    if (nodes) atomicAdd(sw + 2 * kStripes, nodes);
+    if (counts_tree(P, k)) {
+      unsigned long long* bank = stat_bank(P, k);
+      if (nodes) atomicAdd(&bank[blk % kStripes], nodes);
+      if (beliefs) atomicAdd(&bank[kStripes + blk % kStripes], beliefs);
+    }
   }
 }
 
@@ -1326,6 +1344,9 @@ __device__ void dev_select(const PlanView& P) {
   const unsigned long long nodes = wave_sum(bank[lane]);
   const unsigned long long nb = 1 + wave_sum(bank[kStripes + lane]);
   const unsigned long long near = wave_sum(T.stats[kStatNear * kStripes + lane]);
+  const unsigned long long sw_v = wave_sum(T.stats[kStatSweep * kStripes + lane]);
+  const unsigned long long sw_i = wave_sum(T.stats[(kStatSweep + 1) * kStripes + lane]);
+  const unsigned long long sw_n = wave_sum(T.stats[(kStatSweep + 2) * kStripes + lane]);
   const int A = P.m.nA;
   double* out = P.out;
   // Argmax with the lowest index on ties: each lane scans actions lane,
@@ -1352,6 +1373,9 @@ __device__ void dev_select(const PlanView& P) {
   out[A + 4] = (double)nodes;
   out[A + 5] = (double)T.counters[1];
   out[A + 6] = (double)near;
+  out[A + 7] = (double)sw_v;
+  out[A + 8] = (double)sw_i;
+  out[A + 9] = (double)sw_n;
   T.counters[2] = nb;
   T.counters[3] = 0ull;
   T.counters[5] = (unsigned long long)(P.timed ? T.step_base[k_last] : P.steps);

@@ -78,7 +78,8 @@ class vopp_params(C.Structure):
 class vopp_stats(C.Structure):
     _fields_ = [("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
                 ("n_actions", C.c_int64), ("device_ms", C.c_double),
-                ("near_ties", C.c_int64)]
+                ("near_ties", C.c_int64), ("sweep_visits", C.c_int64),
+                ("sweep_internal", C.c_int64), ("sweep_nodes", C.c_int64)]
 
 
 class vopp_request(C.Structure):
@@ -320,6 +321,11 @@ class PlanResult:
     n_actions: int
     device_ms: float
     near_ties: int = 0
+    sweep: tuple = (0, 0, 0)      # level sweeps: belief, internal, action-node visits
+
+
+def _sweep(st):
+    return (int(st.sweep_visits), int(st.sweep_internal), int(st.sweep_nodes))
 
 
 def belief_tensor(inst, belief, device="cuda"):
@@ -348,7 +354,7 @@ def plan(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None):
                            _p(vroot), C.byref(st)))
     return PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                       int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                      int(st.near_ties))
+                      int(st.near_ties), _sweep(st))
 
 
 def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None,
@@ -385,7 +391,7 @@ def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=
                                  C.c_int64(n)))
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                     int(st.near_ties))
+                     int(st.near_ties), _sweep(st))
     shape = (steps, prm.n_particles)
     return (res, act_d.cpu().numpy().reshape(shape), obs_d.cpu().numpy().reshape(shape))
 
@@ -396,13 +402,14 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 def plan_noalloc(pomdp, belief_dev, n_belief, budget, depth, prm, result_dev, stream=None):
     """vopp_plan_noalloc: enqueue a plan whose tree lives in the library's
     static device array; result_dev is a float64 device tensor of at least
-    nA + 7 entries (action, root preferences, V(root), particle steps,
-    beliefs, action nodes, error flags, near ties), written on the stream."""
+    nA + 10 entries (action, root preferences, V(root), particle steps,
+    beliefs, action nodes, error flags, near ties, sweep counts), written on
+    the stream."""
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
-    if result_dev.dtype != torch.float64 or result_dev.numel() < pomdp.nA + 7:
-        raise ValueError("result_dev must be a float64 device tensor of nA + 7 entries")
+    if result_dev.dtype != torch.float64 or result_dev.numel() < pomdp.nA + 10:
+        raise ValueError("result_dev must be a float64 device tensor of nA + 10 entries")
     _check(lib().vopp_plan_noalloc(pomdp.handle, C.c_void_p(belief_dev.data_ptr()),
                                    int(n_belief), int(budget), int(depth), C.byref(prm),
                                    C.c_void_p(stream.cuda_stream),
@@ -428,7 +435,7 @@ def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, w
                                    _p(vroot), C.byref(st), C.byref(iters)))
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                     int(st.near_ties))
+                     int(st.near_ties), _sweep(st))
     return res, int(iters.value)
 
 

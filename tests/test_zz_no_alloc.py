@@ -30,7 +30,7 @@ def plain(V, pom, bel, nb, K, depth, prm):
 
 def noalloc(V, pom, bel, nb, K, depth, prm):
     import torch
-    out = torch.full((pom.nA + 7,), -7.0, dtype=torch.float64, device="cuda")
+    out = torch.full((pom.nA + 10,), -7.0, dtype=torch.float64, device="cuda")
     V.plan_noalloc(pom, bel, nb, K, depth, prm, out)
     torch.cuda.synchronize()
     return out.cpu().numpy()
@@ -44,6 +44,7 @@ def same(r, o, A):
         (r.particle_steps, r.n_beliefs, r.n_actions)
     assert int(o[A + 5]) == 0
     assert int(o[A + 6]) == r.near_ties
+    assert tuple(int(x) for x in o[A + 7:A + 10]) == r.sweep
 
 
 @pytest.mark.parametrize("kind", ["nav", "tabular"])
@@ -76,7 +77,7 @@ def test_noalloc_rejects_plans_beyond_the_scratch(V):
     try:
         prm = V.params(p["n_particles"], seed=1)
         assert V.footprint(pom, prm, 10, 10) > V.NOALLOC_SCRATCH_BYTES
-        out = torch.zeros(pom.nA + 7, dtype=torch.float64, device="cuda")
+        out = torch.zeros(pom.nA + 10, dtype=torch.float64, device="cuda")
         belt = V.belief_tensor(inst, bel)
         with pytest.raises(V.VoppError) as e:
             V.plan_noalloc(pom, belt, belt.numel() // 2, 10, 10, prm, out)
