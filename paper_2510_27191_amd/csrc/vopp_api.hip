@@ -323,7 +323,10 @@ size_t out_len(const WsSizes& z) { return (size_t)std::max(kOutStride, z.Apad + 
 size_t bytes_for(const WsSizes& z) {
   size_t b = 0;
   auto add = [&](size_t n) { b += align_up(n, 256); };
-  add((size_t)z.cap_b * z.rs);                       // belief records
+  const size_t cb = (size_t)z.cap_b;                 // the belief field arrays
+  add(cb * z.Apad * 4); add(cb * z.Apad * 4); add(cb * z.Apad * 8); add(cb * z.Apad * 8);
+  add(cb * sizeof(BeliefHot)); add(cb * sizeof(BeliefLeaf));
+  add(cb * (size_t)rec_bitmap_words(z.Apad) * 4);
   add(z.hcap * sizeof(HSlot));                       // table
   const size_t ar = (size_t)std::max(kMaxA, z.Apad);
   add(ar * 8); add(ar * 8); add(8);                  // root row and its CDF, V(root)
@@ -350,9 +353,16 @@ bool fits(const WsSizes& have, const WsSizes& need) {
 void carve_tree(void* base, const WsSizes& z, TreeView& t, int** carry_rng, int** step_base,
                 double** out) {
   Carver c(base);
-  t.rec = c.take<unsigned char>((size_t)z.cap_b * z.rs);
-  t.rs = z.rs;
+  const size_t cb = (size_t)z.cap_b;
   t.ra = z.Apad;
+  t.bw = rec_bitmap_words(z.Apad);
+  t.psi = c.take<float>(cb * z.Apad);
+  t.nv = c.take<int>(cb * z.Apad);
+  t.cv = c.take<unsigned long long>(cb * z.Apad);
+  t.wv = c.take<unsigned long long>(cb * z.Apad);
+  t.hot = c.take<BeliefHot>(cb);
+  t.leaf = c.take<BeliefLeaf>(cb);
+  t.bits = c.take<uint32_t>(cb * (size_t)t.bw);
   t.h_slot = c.take<HSlot>(z.hcap);
   t.h_mask = (uint32_t)(z.hcap - 1);
   const size_t ar = (size_t)std::max(kMaxA, z.Apad);
@@ -923,7 +933,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   clear_error();
   if (!w) return fail(VOPP_E_INVALID, "null workspace");
   if (w->n_prev_beliefs <= 0) return fail(VOPP_E_INVALID, "no plan has run in this workspace");
-  const int A = w->last_A, ra = w->tree.ra, rs = w->tree.rs;
+  const int A = w->last_A, ra = w->tree.ra, rs = dump_bytes(w->tree.ra);
   const int steps = w->last_steps, n_p = w->last_n_p;
   hipError_t e = hipDeviceSynchronize();
   auto cp = [&](void* dst, const void* src, size_t bytes) {
@@ -959,20 +969,24 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
   if (ids_dev) (void)hipFree(ids_dev);
   if (rec_dev) (void)hipFree(rec_dev);
   if (e != hipSuccess) return hip_fail(e, "tree dump");
+  // The packed copy of each belief (layout in vopp_device.hpp).
+  struct Tail { float V; int Nb; int obs; int pad; unsigned long long parent; };
   auto meta = [&](size_t i) {
-    return reinterpret_cast<const RecMeta*>(rec.data() + i * rs + 24 * ra);
+    return reinterpret_cast<const Tail*>(rec.data() + i * rs + dump_tail_off(ra));
   };
-  auto nrow = [&](size_t i) { return reinterpret_cast<const int*>(rec.data() + i * rs + 4 * ra); };
+  auto nrow = [&](size_t i) {
+    return reinterpret_cast<const int*>(rec.data() + i * rs + dump_n_off(ra));
+  };
   auto crow = [&](size_t i) {
-    return reinterpret_cast<const long long*>(rec.data() + i * rs + 8 * ra);
+    return reinterpret_cast<const long long*>(rec.data() + i * rs + dump_c_off(ra));
   };
   auto prow = [&](size_t i) { return reinterpret_cast<const float*>(rec.data() + i * rs); };
-  // Long rows: a record other than the root's holds (b, a) only where bit a
+  // Long rows: a belief other than the root holds (b, a) only where bit a
   // of its bitmap is set.
   auto valid = [&](size_t i, int a) {
     if (ra <= kMaxA || ids[i] == 0) return true;
-    const uint32_t* bits = reinterpret_cast<const uint32_t*>(rec.data() + i * rs + 24 * ra +
-                                                             sizeof(RecMeta));
+    const uint32_t* bits =
+        reinterpret_cast<const uint32_t*>(rec.data() + i * rs + dump_bits_off(ra));
     return ((bits[a >> 5] >> (a & 31)) & 1u) != 0;
   };
   // Canonical order: by depth, then (parent's position, action, observation);
@@ -1023,7 +1037,7 @@ extern "C" vopp_status vopp_tree_dump(vopp_workspace* w, int32_t* b_parent, int3
                 w->n_prev_actions);
   for (size_t q = 0; q < nb; ++q) {
     const size_t i = order[q];
-    const RecMeta* m = meta(i);
+    const Tail* m = meta(i);
     int par = -1;
     if (q > 0) {
       const int pq = pos_of[(int)(m->parent >> kActBits)];

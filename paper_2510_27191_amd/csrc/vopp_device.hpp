@@ -99,30 +99,42 @@ struct ModelView {
   double gamma64;
 };
 
-// Tail of a belief record.
-struct RecMeta {
+// Per-belief fields besides the preference row and the action-node columns:
+// the part every backup visit reads (hot) and the part only the leaf updates,
+// the observation key and the tree dump use.
+struct BeliefHot {
   float V;                   // L_eta Psi (internal) or mean heuristic (leaf)
   int Nb;                    // visit count N_b
+  unsigned long long parent; // (parent id << kActBits) | action; ~0 for the root
+};
+struct BeliefLeaf {
   int leaf_cnt;              // this iteration's leaf visits (0 between iterations)
   int obs;                   // observation key (-1 for the root)
   unsigned long long leaf_h; // this iteration's heuristic sum (fixed point)
-  unsigned long long parent; // (parent id << kActBits) | action; ~0 for the root
 };
 
-// The tree store in HBM.  Each belief owns one record of rs bytes (a multiple
-// of the 128-byte cache line); with ra = |A| rounded up to a multiple of 4 it
-// holds
-//   Psi[ra] f32 | N[ra] i32 | C[ra] i64 | W[ra] i64 | RecMeta
+// The tree store in HBM: one array per field, indexed by belief id.  With
+// ra = |A| rounded up to a multiple of 4, belief id owns
+//   psi[id*ra ..] f32, n[id*ra ..] i32, c[id*ra ..] i64, w[id*ra ..] i64,
+//   hot[id], leaf[id]
 // where N, C (cumulative reward) and W (sum of V*N_b over the child beliefs)
 // are the action nodes (b, a) of tensor A, stored with their parent belief.
-// C, W and the leaf sums are 64-bit two's-complement fixed point.  Record 0 is
+// C, W and the leaf sums are 64-bit two's-complement fixed point.  Belief 0 is
 // the root (its preference row is kept in double precision in psi_root); the
-// beliefs created by level step t occupy records 1 + t*n_p + [0, n_p), where
-// list[t*n_p + ep] says which positions are used, so one depth of the tree is
-// a few contiguous runs of records.
+// beliefs created by level step t are ids 1 + t*n_p + [0, n_p), where
+// list[t*n_p + ep] says which ids are used.  One depth of the tree is thus a
+// few contiguous runs of ids, and a backup sweep that gives consecutive ids to
+// consecutive lanes reads each field with full cache lines.
 struct TreeView {
-  unsigned char* rec;            // [(1 + steps * n_p) * rs]
-  int rs, ra;
+  float* psi;                    // [cap * ra]
+  int* nv;                       // [cap * ra]
+  unsigned long long* cv;        // [cap * ra]
+  unsigned long long* wv;        // [cap * ra]
+  BeliefHot* hot;                // [cap]
+  BeliefLeaf* leaf;              // [cap]
+  uint32_t* bits;                // [cap * bw] long rows only (see below)
+  int ra;
+  int bw;                        // bitmap words per belief (0 up to kMaxA actions)
   HSlot* h_slot;                 // [h_mask + 1] open-addressing table
   uint32_t h_mask;
   double* psi_root;              // [nA]
@@ -165,38 +177,47 @@ struct TreeView {
   int dbg_step0;                 // level step of the plan's first own step
 };
 
-// Long rows (ra > kMaxA) add a bitmap of ra bits after RecMeta, padded to
-// 16-byte quads: in a record other than the root's, N[a], C[a] and W[a] hold
+// Long rows (ra > kMaxA) add a bitmap of ra bits per belief, padded to
+// 16-byte quads: for a belief other than the root, N[a], C[a] and W[a] hold
 // values only where bit a is set (set, and the three cleared, by the first
-// visit of (b, a)); elsewhere they are whatever the memory held.  A new record
-// then writes Psi, its metadata and the bitmap, not three quarters of its
-// bytes.  The root's columns are all valid.
+// visit of (b, a)); elsewhere they are whatever the memory held.  A new belief
+// then writes Psi, its tails and the bitmap, not three quarters of its bytes.
+// The root's columns are all valid.
 __host__ __device__ inline int rec_bitmap_quads(int ra) { return (ra + 127) / 128; }
-__host__ __device__ inline int rec_bytes(int ra) {
-  int used = 24 * ra + (int)sizeof(RecMeta);
-  if (ra > kMaxA) used += 16 * rec_bitmap_quads(ra);
-  return (used + 127) / 128 * 128;
+__host__ __device__ inline int rec_bitmap_words(int ra) {
+  return ra > kMaxA ? 4 * rec_bitmap_quads(ra) : 0;
 }
-__device__ __forceinline__ unsigned char* rec_at(const TreeView& t, int id) {
-  return t.rec + (size_t)id * (size_t)t.rs;
+// Bytes one belief owns across the field arrays.
+__host__ __device__ inline int rec_bytes(int ra) {
+  return 24 * ra + (int)(sizeof(BeliefHot) + sizeof(BeliefLeaf)) + 4 * rec_bitmap_words(ra);
 }
 __device__ __forceinline__ float* rec_psi(const TreeView& t, int id) {
-  return reinterpret_cast<float*>(rec_at(t, id));
+  return t.psi + (size_t)id * (size_t)t.ra;
 }
 __device__ __forceinline__ int* rec_n(const TreeView& t, int id) {
-  return reinterpret_cast<int*>(rec_at(t, id) + 4 * t.ra);
+  return t.nv + (size_t)id * (size_t)t.ra;
 }
 __device__ __forceinline__ unsigned long long* rec_c(const TreeView& t, int id) {
-  return reinterpret_cast<unsigned long long*>(rec_at(t, id) + 8 * t.ra);
+  return t.cv + (size_t)id * (size_t)t.ra;
 }
 __device__ __forceinline__ unsigned long long* rec_w(const TreeView& t, int id) {
-  return reinterpret_cast<unsigned long long*>(rec_at(t, id) + 16 * t.ra);
+  return t.wv + (size_t)id * (size_t)t.ra;
 }
-__device__ __forceinline__ RecMeta* rec_meta(const TreeView& t, int id) {
-  return reinterpret_cast<RecMeta*>(rec_at(t, id) + 24 * t.ra);
-}
+__device__ __forceinline__ BeliefHot* rec_hot(const TreeView& t, int id) { return t.hot + id; }
+__device__ __forceinline__ BeliefLeaf* rec_leaf(const TreeView& t, int id) { return t.leaf + id; }
 __device__ __forceinline__ uint32_t* rec_bits(const TreeView& t, int id) {
-  return reinterpret_cast<uint32_t*>(rec_at(t, id) + 24 * t.ra + sizeof(RecMeta));
+  return t.bits + (size_t)id * (size_t)t.bw;
+}
+
+// The tree dump's packed copy of one belief (gathered on the device, parsed
+// on the host): Psi[ra] f32 | N[ra] i32 | C[ra] i64 | V f32 | N_b i32 | obs
+// i32 | pad | parent u64 | bitmap (long rows).
+__host__ __device__ inline int dump_n_off(int ra) { return 4 * ra; }
+__host__ __device__ inline int dump_c_off(int ra) { return 8 * ra; }
+__host__ __device__ inline int dump_tail_off(int ra) { return 16 * ra; }
+__host__ __device__ inline int dump_bits_off(int ra) { return 16 * ra + 24; }
+__host__ __device__ inline int dump_bytes(int ra) {
+  return (dump_bits_off(ra) + 4 * rec_bitmap_words(ra) + 15) / 16 * 16;
 }
 
 // The root belief of a plan.

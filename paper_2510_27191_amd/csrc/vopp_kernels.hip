@@ -231,9 +231,19 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
   for (size_t i = tid; i < (size_t)3 * T.ra * kStripes; i += stride)
     if (!(P.carry && i % kStripes == 0 && i < (size_t)2 * T.ra * kStripes)) T.root_acc[i] = 0ull;
   if (blk == 0) {
-    uint4* r = reinterpret_cast<uint4*>(T.rec);
-    if (!P.carry)
-      for (int i = threadIdx.x; i < T.rs / 16; i += kBlock) r[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (!P.carry) {                             // a fresh root: every field of belief 0
+      for (int i = threadIdx.x; i < T.ra; i += kBlock) {
+        rec_psi(T, 0)[i] = 0.0f;
+        rec_n(T, 0)[i] = 0;
+        rec_c(T, 0)[i] = 0ull;
+        rec_w(T, 0)[i] = 0ull;
+      }
+      for (int i = threadIdx.x; i < T.bw; i += kBlock) rec_bits(T, 0)[i] = 0u;
+      if (threadIdx.x == 0) {
+        *rec_hot(T, 0) = BeliefHot{0.0f, 0, kEmptyKey};
+        *rec_leaf(T, 0) = BeliefLeaf{0, -1, 0ull};
+      }
+    }
     __syncthreads();
     const int j = threadIdx.x;
     for (int i = j; i < kStatRows * kStripes; i += kBlock) T.stats[i] = 0ull;
@@ -300,10 +310,9 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
           T.psi0_cdf64[a] = run;
         }
       }
-      RecMeta* mt = rec_meta(T, 0);
-      mt->obs = -1;
-      mt->parent = kEmptyKey;
-      T.v_root[0] = P.carry ? (double)mt->V : 0.0;
+      rec_leaf(T, 0)->obs = -1;
+      rec_hot(T, 0)->parent = kEmptyKey;
+      T.v_root[0] = P.carry ? (double)rec_hot(T, 0)->V : 0.0;
       T.counters[1] = 0ull;
     }
   }
@@ -321,15 +330,23 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
 __device__ __forceinline__ void init_record(const PlanView& P, const float* psi0s, int id,
                                             int obs, unsigned long long link) {
   const TreeView& T = P.t;
-  uint4* q = reinterpret_cast<uint4*>(rec_at(T, id));
-  const uint4* p0 = reinterpret_cast<const uint4*>(psi0s);
   const int ra = T.ra;
-  for (int j = 0; j < ra; j += 4) q[j >> 2] = p0[j >> 2];
-  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-  const int meta_q = 6 * ra / 4;                // N, C and W take 5*ra/4 quads
-  for (int i = ra / 4; i < meta_q; ++i) q[i] = z;
-  q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);            // V, N_b, leaf_cnt, obs
-  q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));  // leaf_h, parent
+  float4* pq = reinterpret_cast<float4*>(rec_psi(T, id));
+  int4* nq = reinterpret_cast<int4*>(rec_n(T, id));
+  ulonglong2* cq = reinterpret_cast<ulonglong2*>(rec_c(T, id));
+  ulonglong2* wq = reinterpret_cast<ulonglong2*>(rec_w(T, id));
+  const float4* p0 = reinterpret_cast<const float4*>(psi0s);
+  const ulonglong2 z2 = make_ulonglong2(0ull, 0ull);
+  for (int j = 0; j < ra / 4; ++j) {
+    pq[j] = p0[j];
+    nq[j] = make_int4(0, 0, 0, 0);
+    cq[2 * j] = z2;
+    cq[2 * j + 1] = z2;
+    wq[2 * j] = z2;
+    wq[2 * j + 1] = z2;
+  }
+  *rec_hot(T, id) = BeliefHot{0.0f, 0, link};
+  *rec_leaf(T, id) = BeliefLeaf{0, obs, 0ull};
 }
 
 template <int AM>
@@ -489,10 +506,10 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
         hv = nav_heuristic(P.m.nav, x, y);
       }
       if (D >= kDirectLevel && rid >= 0) {
-        RecMeta* mt = rec_meta(T, rid);
-        atomicAdd(&mt->leaf_cnt, 1);
+        BeliefLeaf* lf = rec_leaf(T, rid);
+        atomicAdd(&lf->leaf_cnt, 1);
         const unsigned long long fx = to_fix(hv, P.fix_scale);
-        if (fx) atomicAdd(&mt->leaf_h, fx);
+        if (fx) atomicAdd(&lf->leaf_h, fx);
       } else {
         tk = rid >= 0 ? ((unsigned long long)(uint32_t)rid | kTraceRec)
                       : (unsigned long long)(uint32_t)sid;
@@ -588,9 +605,9 @@ __device__ void dev_accum(const PlanView& P, int D, int blk, int nblk, Smem& sm)
         if (k2 == kEmptyKey) continue;
         const int rid = (int)(k2 >> (kActBits + 1));
         if (k2 & 1ull) {
-          RecMeta* mt = rec_meta(T, rid);
-          atomicAdd(&mt->leaf_cnt, (int)G.a[j]);
-          if (G.b[j]) atomicAdd(&mt->leaf_h, G.b[j]);
+          BeliefLeaf* lf = rec_leaf(T, rid);
+          atomicAdd(&lf->leaf_cnt, (int)G.a[j]);
+          if (G.b[j]) atomicAdd(&lf->leaf_h, G.b[j]);
         } else if (rid == 0) {
           const int a = (int)((k2 >> 1) & kActMask);
           atomicAdd(root_stripe(T, 0, a), G.a[j]);
@@ -629,7 +646,7 @@ __device__ __forceinline__ void load_ranges(const PlanView& P, int dep, int k, R
 
 // The parent link of a record, resolved to (record << kActBits) | a (written
 // back); par is the stored link, read by the caller.
-__device__ __forceinline__ unsigned long long resolve_link(const TreeView& T, RecMeta* mt,
+__device__ __forceinline__ unsigned long long resolve_link(const TreeView& T, BeliefHot* mt,
                                                           unsigned long long par) {
   if (par != kEmptyKey && (par & kLinkSlot)) {
     const int psid = (int)((par & ~kLinkSlot) >> kActBits);
@@ -700,9 +717,10 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
     if (b > 0) {
       // Every field is read before the first store: on CDNA a wait for a
       // load also waits for the stores issued before it.
-      RecMeta* mt = rec_meta(P.t, b);
-      const int c = mt->leaf_cnt;
-      const unsigned long long hs = mt->leaf_h;
+      BeliefHot* mt = rec_hot(P.t, b);
+      BeliefLeaf* lf = rec_leaf(P.t, b);
+      const int c = lf->leaf_cnt;
+      const unsigned long long hs = lf->leaf_h;
       const float V0 = mt->V;
       const int N0 = mt->Nb;
       const unsigned long long par = mt->parent;
@@ -711,8 +729,8 @@ __device__ void dev_backup_leaf(const PlanView& P, int dep, int k, int blk, int 
         N = c;
         mt->V = V;
         mt->Nb = N;
-        mt->leaf_cnt = 0;
-        if (hs) mt->leaf_h = 0ull;
+        lf->leaf_cnt = 0;
+        if (hs) lf->leaf_h = 0ull;
       } else {
         V = V0;
         N = N0;
@@ -751,15 +769,16 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
       const int* nrow = rec_n(P.t, b);
       unsigned long long* crow = rec_c(P.t, b);
       unsigned long long* wrow = rec_w(P.t, b);
-      RecMeta* mt = rec_meta(P.t, b);
+      BeliefHot* mt = rec_hot(P.t, b);
       // The whole record (its link and stored value included) is read in one
       // batch, before its first store: a wait for a load also waits for the
       // stores issued before it.  (Reading
       // Psi, C and W only after the counts show a visited action costs one
       // more round trip, which measured slower than the extra bytes.)
-      const float V0 = mt->V;
-      const int N0 = mt->Nb;
-      const unsigned long long par = mt->parent;
+      const uint4 hq = *reinterpret_cast<const uint4*>(mt);   // V, N_b, parent
+      const float V0 = __uint_as_float(hq.x);
+      const int N0 = (int)hq.y;
+      const unsigned long long par = ((unsigned long long)hq.w << 32) | hq.z;
       int n[AM];
       float psi[AM];
       unsigned long long cf[AM], wf[AM];
@@ -946,9 +965,10 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
       todo &= todo - 1;
       const float4* p4 = reinterpret_cast<const float4*>(rec_psi(T, b));
       const uint32_t* bits = rec_bits(T, b);
-      const char* rec = reinterpret_cast<const char*>(rec_at(T, b));
+      const int* nrow = rec_n(T, b);
+      const unsigned long long* crow = rec_c(T, b);
       unsigned long long* wrow = rec_w(T, b);
-      RecMeta* mt = rec_meta(T, b);
+      BeliefHot* mt = rec_hot(T, b);
       // Psi and the visited flags (the bitmap's nibble of each quad).
       float pf[4 * QPL];
       uint32_t vb[QPL];
@@ -992,11 +1012,10 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
           if (4 * (lane + 64 * (i >> 2)) + (i & 3) < A) se = se + expf(eta * (pf[i] - m));
         const float vc = m + logf(wave_sumf(se)) / eta;
         // Psi <- Psi - V_curr + Q, Q = C/N + gamma W/N (Eq. 5), for visited
-        // actions.  An unvisited action reads the metadata line instead (read
-        // above), so the loads issue without branches.
-        const uint32_t n_off = 4u * (uint32_t)T.ra, c_off = 8u * (uint32_t)T.ra,
-                       w_off = 16u * (uint32_t)T.ra;
-        const uint32_t spare = 24u * (uint32_t)T.ra + (uint32_t)offsetof(RecMeta, parent);
+        // actions.  An unvisited action reads the belief's hot fields instead
+        // (read above), so the loads issue without branches.
+        const int* spare_n = reinterpret_cast<const int*>(mt);
+        const unsigned long long* spare_l = &mt->parent;
         int nsum = 0, nn = 0;
 #pragma unroll
         for (int i0 = 0; i0 < QPL; i0 += 4) {
@@ -1007,10 +1026,9 @@ __device__ void dev_backup_level_wide(const PlanView& P, int dep, int k, int blk
             const int i = 4 * i0 + t;
             const int j = 4 * (lane + 64 * (i >> 2)) + (i & 3);
             const bool v = (vb[i >> 2] >> (i & 3)) & 1u;
-            const uint32_t j4 = 4u * (uint32_t)j, j8 = 8u * (uint32_t)j;
-            nf[t] = *reinterpret_cast<const int*>(rec + (v ? n_off + j4 : spare));
-            cf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? c_off + j8 : spare));
-            wf[t] = *reinterpret_cast<const unsigned long long*>(rec + (v ? w_off + j8 : spare));
+            nf[t] = *(v ? nrow + j : spare_n);
+            cf[t] = *(v ? crow + j : spare_l);
+            wf[t] = *(v ? wrow + j : spare_l);
           }
 #pragma unroll
           for (int t = 0; t < 16; ++t) {
@@ -1251,7 +1269,7 @@ __device__ void dev_backup_root_wide(const PlanView& P, int k, double* buf) {
   if (any && threadIdx.x == 0) {
     const double v = mm + log(run) / eta;
     T.v_root[0] = v;
-    RecMeta* mt = rec_meta(T, 0);
+    BeliefHot* mt = rec_hot(T, 0);
     mt->V = (float)v;
     mt->Nb = (int)cnt[1];
     if (counts_tree(P, k)) atomicAdd(&stat_bank(P, k)[0], cnt[0]);
@@ -1325,7 +1343,7 @@ __device__ void dev_backup_root(const PlanView& P, int k) {
   if (lane != 0) return;
   const double v = m2 + log(run) / eta;
   P.t.v_root[0] = v;
-  RecMeta* mt = rec_meta(P.t, 0);
+  BeliefHot* mt = rec_hot(P.t, 0);
   mt->V = (float)v;
   mt->Nb = (int)nsum;
 }
@@ -1804,15 +1822,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
       if (won) {                                // the new record, by the half
         // Psi, the metadata and a cleared bitmap; N, C and W of (b, a) are
         // cleared by its first visit.
-        uint4* q = reinterpret_cast<uint4*>(rec_at(T, rid));
+        uint4* q = reinterpret_cast<uint4*>(rec_psi(T, rid));
         const uint4* p0 = reinterpret_cast<const uint4*>(T.psi0);
-        const int nq = T.ra / 4, meta_q = 6 * T.ra / 4, nbq = rec_bitmap_quads(T.ra);
+        const int nq = T.ra / 4, nbq = rec_bitmap_quads(T.ra);
         for (int i = lane; i < nq; i += kHalf) q[i] = p0[i];
         if (lane == 0) {
-          q[meta_q] = make_uint4(0u, 0u, 0u, (uint32_t)obs);
-          q[meta_q + 1] = make_uint4(0u, 0u, (uint32_t)link, (uint32_t)(link >> 32));
+          *rec_hot(T, rid) = BeliefHot{0.0f, 0, link};
+          *rec_leaf(T, rid) = BeliefLeaf{0, obs, 0ull};
         }
-        for (int i = lane; i < nbq; i += kHalf) q[meta_q + 2 + i] = make_uint4(0u, 0u, 0u, 0u);
+        uint4* bq = reinterpret_cast<uint4*>(rec_bits(T, rid));
+        for (int i = lane; i < nbq; i += kHalf) bq[i] = make_uint4(0u, 0u, 0u, 0u);
       }
     }
   }
@@ -1822,10 +1841,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forward_wide(PlanView P, int k, i
     if (alive) {
       if (P.m.H) hv = P.m.H[s];
       if (D >= kDirectLevel && rid >= 0) {
-        RecMeta* mt = rec_meta(T, rid);
-        atomicAdd(&mt->leaf_cnt, 1);
+        BeliefLeaf* lf = rec_leaf(T, rid);
+        atomicAdd(&lf->leaf_cnt, 1);
         const unsigned long long fx = to_fix(hv, P.fix_scale);
-        if (fx) atomicAdd(&mt->leaf_h, fx);
+        if (fx) atomicAdd(&lf->leaf_h, fx);
       } else {
         tk = rid >= 0 ? ((unsigned long long)(uint32_t)rid | kTraceRec)
                       : (unsigned long long)(uint32_t)sid;
@@ -2039,21 +2058,39 @@ hipError_t launch_pf(const PlanView& P, int t, hipStream_t s) {
   hipLaunchKernelGGL(k_pf_resample, g, b, 0, s, P, t);
   return hipGetLastError();
 }
+// The tree dump: belief ids[i]'s fields packed at out + i * dump_bytes(ra)
+// (layout in vopp_device.hpp), one thread per belief.
 __global__ __launch_bounds__(kBlock) void k_gather(TreeView t, const int* ids, int n,
                                                    unsigned char* out) {
-  const int q = t.rs / 16;
-  const long long total = (long long)n * q;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+  const int ra = t.ra;
+  const size_t db = (size_t)dump_bytes(ra);
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (long long)gridDim.x * kBlock) {
-    const long long b = i / q;
-    const int j = (int)(i - b * q);
-    reinterpret_cast<uint4*>(out)[i] = reinterpret_cast<const uint4*>(rec_at(t, ids[b]))[j];
+    const int id = ids[i];
+    unsigned char* o = out + (size_t)i * db;
+    float* po = reinterpret_cast<float*>(o);
+    int* no = reinterpret_cast<int*>(o + dump_n_off(ra));
+    unsigned long long* co = reinterpret_cast<unsigned long long*>(o + dump_c_off(ra));
+    for (int j = 0; j < ra; ++j) {
+      po[j] = rec_psi(t, id)[j];
+      no[j] = rec_n(t, id)[j];
+      co[j] = rec_c(t, id)[j];
+    }
+    const BeliefHot h = *rec_hot(t, id);
+    const BeliefLeaf l = *rec_leaf(t, id);
+    unsigned char* tl = o + dump_tail_off(ra);
+    *reinterpret_cast<float*>(tl) = h.V;
+    *reinterpret_cast<int*>(tl + 4) = h.Nb;
+    *reinterpret_cast<int*>(tl + 8) = l.obs;
+    *reinterpret_cast<int*>(tl + 12) = 0;
+    *reinterpret_cast<unsigned long long*>(tl + 16) = h.parent;
+    uint32_t* bo = reinterpret_cast<uint32_t*>(o + dump_bits_off(ra));
+    for (int j = 0; j < t.bw; ++j) bo[j] = rec_bits(t, id)[j];
   }
 }
 hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char* out,
                          hipStream_t s) {
-  const long long total = (long long)n * (t.rs / 16);
-  const int g = (int)std::max(1ll, std::min((total + kBlock - 1) / kBlock, 4096ll));
+  const int g = (int)std::max(1ll, std::min(((long long)n + kBlock - 1) / kBlock, 4096ll));
   hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, s, t, ids, n, out);
   return hipGetLastError();
 }
@@ -2108,7 +2145,7 @@ __device__ __forceinline__ int reroot_record(const RerootView& V, long long i) {
 
 // The parent link (record << kActBits | action) of a source record, resolved.
 __device__ __forceinline__ unsigned long long reroot_parent(const TreeView& T, int r) {
-  unsigned long long par = rec_meta(T, r)->parent;
+  unsigned long long par = rec_hot(T, r)->parent;
   if (par != kEmptyKey && (par & kLinkSlot)) {
     const int psid = (int)((par & ~kLinkSlot) >> kActBits);
     par = ((unsigned long long)(uint32_t)record_of(T, psid) << kActBits) | (par & kActMask);
@@ -2172,9 +2209,18 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
     nr = (int)(1 + t * V.dst_n_p + (long long)(q % (unsigned long long)V.dst_n_p));
   }
   V.new_id[r] = nr;
-  const uint4* a = reinterpret_cast<const uint4*>(rec_at(V.src, r));
-  uint4* b = reinterpret_cast<uint4*>(rec_at(V.dst, nr));
-  for (int j = 0; j < V.src.rs / 16; ++j) b[j] = a[j];
+  {                                           // every field of the belief
+    const int ra = V.src.ra;
+    for (int j = 0; j < ra; ++j) {
+      rec_psi(V.dst, nr)[j] = rec_psi(V.src, r)[j];
+      rec_n(V.dst, nr)[j] = rec_n(V.src, r)[j];
+      rec_c(V.dst, nr)[j] = rec_c(V.src, r)[j];
+      rec_w(V.dst, nr)[j] = rec_w(V.src, r)[j];
+    }
+    for (int j = 0; j < V.src.bw; ++j) rec_bits(V.dst, nr)[j] = rec_bits(V.src, r)[j];
+    *rec_hot(V.dst, nr) = *rec_hot(V.src, r);
+    *rec_leaf(V.dst, nr) = *rec_leaf(V.src, r);
+  }
   unsigned long long* c = rec_c(V.dst, nr);
   unsigned long long* w = rec_w(V.dst, nr);
   const uint32_t* bits = rec_bits(V.dst, nr);
@@ -2185,11 +2231,12 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
       c[j] = (unsigned long long)llrint((double)(long long)c[j] * V.rescale);
     w[j] = 0ull;
   }
-  RecMeta* mt = rec_meta(V.dst, nr);
-  mt->leaf_cnt = 0;
-  mt->leaf_h = 0ull;
+  BeliefHot* mt = rec_hot(V.dst, nr);
+  BeliefLeaf* lf = rec_leaf(V.dst, nr);
+  lf->leaf_cnt = 0;
+  lf->leaf_h = 0ull;
   if (d_new == 0) {
-    mt->obs = -1;
+    lf->obs = -1;
     mt->parent = kEmptyKey;
     return;
   }
@@ -2197,7 +2244,7 @@ __global__ __launch_bounds__(kBlock) void k_reroot_copy(RerootView V) {
   const int a_par = (int)(par & kActMask);
   const int np = V.new_id[(int)(par >> kActBits)];
   const int psid = np == 0 ? 0 : V.dst.list[np - 1];
-  const unsigned long long key = belief_key(psid, a_par, mt->obs, V.obs_bits);
+  const unsigned long long key = belief_key(psid, a_par, lf->obs, V.obs_bits);
   bool won = false, fresh = false;
   int id = -1;
   const uint32_t h = probe(V.dst, key, kCarryStamp, won, fresh, id);
