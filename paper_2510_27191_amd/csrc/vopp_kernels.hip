@@ -770,48 +770,38 @@ __device__ void dev_backup_level(const PlanView& P, int dep, int k, int blk, int
       unsigned long long* crow = rec_c(P.t, b);
       unsigned long long* wrow = rec_w(P.t, b);
       BeliefHot* mt = rec_hot(P.t, b);
-      // The whole record (its link and stored value included) is read in one
-      // batch, before its first store: a wait for a load also waits for the
-      // stores issued before it.  (Reading
-      // Psi, C and W only after the counts show a visited action costs one
-      // more round trip, which measured slower than the extra bytes.)
+      // Two rounds of loads, both before the belief's first store (a wait for
+      // a load also waits for the stores issued before it): the hot fields
+      // and the visit counts, then -- for a belief with an action node -- its
+      // preference row and the C and W of its visited actions only.
       const uint4 hq = *reinterpret_cast<const uint4*>(mt);   // V, N_b, parent
-      const float V0 = __uint_as_float(hq.x);
-      const int N0 = (int)hq.y;
-      const unsigned long long par = ((unsigned long long)hq.w << 32) | hq.z;
       int n[AM];
-      float psi[AM];
-      unsigned long long cf[AM], wf[AM];
 #pragma unroll
       for (int j = 0; j < AM; j += 4) {
         int4 c = make_int4(0, 0, 0, 0);
-        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        ulonglong2 c0 = make_ulonglong2(0ull, 0ull), c1 = c0, w0 = c0, w1 = c0;
-        if (j < A) {
-          c = *reinterpret_cast<const int4*>(nrow + j);
-          q = *reinterpret_cast<const float4*>(prow + j);
-          c0 = reinterpret_cast<const ulonglong2*>(crow + j)[0];
-          c1 = reinterpret_cast<const ulonglong2*>(crow + j)[1];
-          w0 = reinterpret_cast<const ulonglong2*>(wrow + j)[0];
-          w1 = reinterpret_cast<const ulonglong2*>(wrow + j)[1];
-        }
+        if (j < A) c = *reinterpret_cast<const int4*>(nrow + j);
         n[j] = c.x; n[j + 1] = c.y; n[j + 2] = c.z; n[j + 3] = c.w;
-        psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
-        cf[j] = c0.x; cf[j + 1] = c0.y; cf[j + 2] = c1.x; cf[j + 3] = c1.y;
-        wf[j] = w0.x; wf[j + 1] = w0.y; wf[j + 2] = w1.x; wf[j + 3] = w1.y;
       }
-      // Held here: the compiler would otherwise sink these loads into the
-      // branch below, behind the wait for the counts.
+      const float V0 = __uint_as_float(hq.x);
+      const int N0 = (int)hq.y;
+      const unsigned long long par = ((unsigned long long)hq.w << 32) | hq.z;
+      float psi[AM];
+      unsigned long long cf[AM], wf[AM];
 #pragma unroll
-      for (int j = 0; j < AM; ++j) {
-        asm volatile("" : "+v"(psi[j]));
-        asm volatile("" : "+v"(cf[j]));
-        asm volatile("" : "+v"(wf[j]));
-      }
+      for (int j = 0; j < AM; ++j) { psi[j] = 0.0f; cf[j] = 0ull; wf[j] = 0ull; }
       bool any = false;
 #pragma unroll
       for (int j = 0; j < AM; ++j) any = any || (j < A && n[j] > 0);
       if (any) {
+#pragma unroll
+        for (int j = 0; j < AM; j += 4) {
+          float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          if (j < A) q = *reinterpret_cast<const float4*>(prow + j);
+          psi[j] = q.x; psi[j + 1] = q.y; psi[j + 2] = q.z; psi[j + 3] = q.w;
+        }
+#pragma unroll
+        for (int j = 0; j < AM; ++j)
+          if (j < A && n[j] > 0) { cf[j] = crow[j]; wf[j] = wrow[j]; }
         // V_curr = L_eta Psi (Eq. 3) before the update.
         float m = psi[0];
 #pragma unroll
