@@ -215,20 +215,38 @@ def bench_batch(V, I, reps=3, autotune=True, cpu=True):
         plain_s.append(time.perf_counter() - t0)
     plain_ref = [V.plan(pom, belt, nb, K, depth, prm, stream=stream)
                  for pom, belt, nb, K, depth, prm in items]
-    # Batched: the whole batch as one graph launch.
+    # Batched: the whole batch as one persistent launch (autotuned), and the
+    # per-phase launch sequence as a graph for comparison.
     batch = V.Batch(items)
     tuning = batch.autotune(reps=1) if autotune else None
-    batch.run()
+    batch.run(mode=V.BATCH_PERSISTENT)
     batch_s, batch_dev = [], []
     res = None
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, ms = batch.run(use_graph=True)
+        res, ms = batch.run(mode=V.BATCH_PERSISTENT)
         batch_s.append(time.perf_counter() - t0)
         batch_dev.append(ms)
-    identical = all(a.action == b.action and np.array_equal(a.values, b.values)
-                    and a.n_beliefs == b.n_beliefs for a, b in zip(res, plain_ref))
+    # The per-phase launch sequence with its own block caps (256 blocks per
+    # accumulate or backup sweep of an instance).
+    batch_ph = V.Batch(items, tuning=(256, 256, 0, 1, 4))
+    batch_ph.run(mode=V.BATCH_GRAPH)
+    phase_s, phase_dev = [], []
+    res_phase = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res_phase, ms = batch_ph.run(mode=V.BATCH_GRAPH)
+        phase_s.append(time.perf_counter() - t0)
+        phase_dev.append(ms)
+    n_launches = batch_ph.num_launches
+    batch_ph.close()
+
+    def same_all(rs):
+        return all(a.action == b.action and np.array_equal(a.values, b.values)
+                   and a.n_beliefs == b.n_beliefs for a, b in zip(rs, plain_ref))
+    identical = same_all(res) and same_all(res_phase)
     bsteps = sum(r.particle_steps for r in res)
     out = {
         "workload": "256 mixed instances: tabular (|S| log-uniform 64-4096, |A| 3-8, "
@@ -240,13 +258,18 @@ def bench_batch(V, I, reps=3, autotune=True, cpu=True):
                              "ms_per_batch": min(plain_s) * 1e3,
                              "plan_latency_ms": {"p50": percentile(plain_lat, 50),
                                                  "p99": percentile(plain_lat, 99)}},
-        "batched_graph": {"value": bsteps / min(batch_s), "unit": "particle-steps/s",
-                          "ms_per_batch": min(batch_s) * 1e3,
-                          "device_ms_per_batch": min(batch_dev),
-                          "launches": batch.num_launches},
+        "batched_persistent": {"value": bsteps / min(batch_s), "unit": "particle-steps/s",
+                               "ms_per_batch": min(batch_s) * 1e3,
+                               "device_ms_per_batch": min(batch_dev),
+                               "launches": 1},
+        "batched_per_phase_graph": {"value": bsteps / min(phase_s), "unit": "particle-steps/s",
+                                    "ms_per_batch": min(phase_s) * 1e3,
+                                    "device_ms_per_batch": min(phase_dev),
+                                    "launches": n_launches},
         "speedup": min(plain_s) / min(batch_s),
         "results_identical_to_plain": bool(identical),
-        "tuning": {"accum_cap": tuning[0], "backup_cap": tuning[1]} if tuning else None,
+        "tuning": {"blocks_per_cu": tuning[2], "forward_group": tuning[3],
+                   "sweep_group": tuning[4]} if tuning else None,
     }
     batch.close()
     for it in items:

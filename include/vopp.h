@@ -386,21 +386,42 @@ typedef struct {
   double values[VOPP_MAX_ACTIONS];
 } vopp_result;
 
-/* Launch-shape knobs of a batch.  accum_cap: most blocks of one instance's
- * accumulate sweep (the sweep loops over the trace when capped); backup_cap:
- * most blocks of one backup sweep of one instance. */
+/* Launch-shape knobs of a batch.  accum_cap: most tiles (blocks) of one
+ * instance's accumulate sweep (a tile loops over its share of the trace);
+ * backup_cap: most tiles of one backup sweep of one instance (both in the
+ * per-phase launches).  The persistent launch sizes
+ * its tiles by work instead: sweep_group chunks of 256 record positions (or
+ * trace items, or table slots of the set-up) per sweep tile, forward_group
+ * blocks of 256 episodes per forward tile (both >= 1), and runs blocks_per_cu
+ * blocks per compute unit (0: as many as fit). */
 typedef struct {
   int32_t accum_cap;
   int32_t backup_cap;
+  int32_t blocks_per_cu;
+  int32_t forward_group;
+  int32_t sweep_group;
 } vopp_tuning;
+
+/* Modes of vopp_batch_run. */
+enum {
+  VOPP_BATCH_EAGER = 0,       /* per-phase launches issued one by one         */
+  VOPP_BATCH_GRAPH = 1,       /* the per-phase launches as one hipGraph      */
+  VOPP_BATCH_PERSISTENT = 2   /* one persistent launch over a device queue   */
+};
 
 typedef struct vopp_batch vopp_batch;
 
 /* Create a batch of n requests: one workspace per request (owned by the
- * batch), a per-phase schedule in which launch g runs the g-th phase of every
- * instance that has one (each block of the launch serves one phase of one
- * instance), and that launch sequence captured in one hipGraph.  All models
- * must have |A| <= 16.  tuning may be NULL (defaults). */
+ * batch), and two ways to run it (Sec. III: the vectorised planner applied to
+ * many instances at once):
+ *   - the persistent launch: one kernel sized to the blocks the GPU holds at
+ *     once, whose blocks take (instance, phase, tile) items from a device
+ *     queue; each instance has its own phase counter, so every instance moves
+ *     to its next phase as soon as its previous one is done; the queue reset
+ *     and the kernel are captured in one hipGraph;
+ *   - per-phase launches: launch g runs the g-th phase of every instance that
+ *     has one, captured in a second hipGraph or issued eagerly.
+ * All models must have |A| <= 16.  tuning may be NULL (defaults). */
 vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
                               const vopp_tuning* tuning, vopp_batch** out);
 /* Bytes of device memory the batch's workspaces need. */
@@ -408,14 +429,17 @@ size_t vopp_batch_footprint(const vopp_request* reqs, int32_t n);
 /* Replace request i's belief particles, seed and real step (same sizes). */
 vopp_status vopp_batch_set_request(vopp_batch* b, int32_t i, const void* belief_particles,
                                    int32_t n_belief, uint64_t seed, uint32_t step);
-/* Run every request once.  use_graph != 0 replays the captured hipGraph;
- * 0 issues the same launches one by one.  The batch runs on its own stream,
- * ordered after the work already queued on `stream`.  results[n] (host, out);
- * device_ms (host, out, may be NULL): device time of the batch. */
-vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_graph,
+/* Run every request once in the given mode (VOPP_BATCH_*; VOPP_E_INVALID
+ * for another value).  The batch runs on its own stream, ordered after the
+ * work already queued on `stream`.  results[n] (host, out); device_ms (host,
+ * out, may be NULL): device time of the batch.  Every mode gives the same
+ * results bit for bit. */
+vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t mode,
                            vopp_result* results, double* device_ms);
-/* Try launch shapes on this batch (reps timed runs each), keep the fastest,
- * re-capture the graph, and report it in chosen (may be NULL).  Every tried
+/* The autotuner: time the persistent launch of this batch (reps timed runs
+ * each) over its tile sizes (sweep_group in {1, 2, 4, 8}, forward_group in
+ * {1, 4}) and blocks per CU (all that fit, or one), keep the fastest,
+ * re-capture the graphs, and report it in chosen (may be NULL).  Every tried
  * shape must give bit-identical results, else VOPP_E_INTERNAL. */
 vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t reps,
                                 vopp_tuning* chosen);

@@ -1,13 +1,19 @@
 // vopp_batch.hip -- batched planning: many independent instances advanced
-// together, one phase per launch, the launch sequence captured in a hipGraph.
+// together.
 //
 // Each instance's plan is a fixed list of phases (set-up; per iteration the
 // forward search, the accumulate sweep, the leaf sweep, one sweep per depth,
-// the root; finally select).  Launch g of the batch runs the g-th
-// phase of every instance that still has one: the launch's blocks are split
-// into BatchItems, each block serving one phase of one instance.  Instances
-// share no state, so each result is the same as that of a plain vopp_plan
-// call with the same inputs.
+// the root; finally select), each split into tiles (one block's share).
+//   - Persistent launch (the default): one kernel whose blocks take tiles
+//     from a device queue; every instance moves through its own phases as
+//     soon as its previous phase's tiles are done, so short and long
+//     instances do not wait for each other.  Captured with the queue reset in
+//     one hipGraph.
+//   - Per-phase launches (for comparison): launch g runs the g-th phase of
+//     every instance that still has one; the sequence is captured in a
+//     hipGraph or issued eagerly.
+// Instances share no state, so each result is the same as that of a plain
+// vopp_plan call with the same inputs, in every mode and for every tuning.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,11 +42,21 @@ struct vopp_batch {
   double* out_dev = nullptr;
   double* out_host = nullptr;            // pinned
   int amax = 4;
-  vopp_tuning tuning{kAccumCap, kBackupCap};
+  vopp_tuning tuning{kAccumCap, kBackupCap, 0, 1, 4};
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;             // the per-phase launch sequence
   hipGraphExec_t exec = nullptr;
+  // The persistent launch: every instance's phases, its queue state, and the
+  // graph of (queue reset, persistent kernel).
+  BatchItem* ph_dev = nullptr;
+  int* ph_off_dev = nullptr;
+  unsigned long long* word_dev = nullptr;
+  unsigned int* done_dev = nullptr;       // [n] then the finished counter
+  int n_cu = 0;
+  int persist_blocks = 0;
+  hipGraph_t pgraph = nullptr;
+  hipGraphExec_t pexec = nullptr;
 };
 
 namespace vopp {
@@ -74,8 +90,23 @@ namespace {
 void release_graph(vopp_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->pexec) (void)hipGraphExecDestroy(b->pexec);
+  if (b->pgraph) (void)hipGraphDestroy(b->pgraph);
   b->exec = nullptr;
   b->graph = nullptr;
+  b->pexec = nullptr;
+  b->pgraph = nullptr;
+}
+
+PersistView persist_view(const vopp_batch* b) {
+  PersistView V;
+  V.word = b->word_dev;
+  V.done = b->done_dev;
+  V.finished = b->done_dev + b->n;
+  V.phases = b->ph_dev;
+  V.ph_off = b->ph_off_dev;
+  V.n = b->n;
+  return V;
 }
 
 // Build views and the launch schedule for the current tuning; upload them.
@@ -117,7 +148,54 @@ vopp_status build_schedule(vopp_batch* b) {
     b->launch_items.push_back(cnt);
     b->launch_blocks.push_back(blocks);
   }
+  // The persistent launch's queue: each instance's phases in order, with
+  // tiles sized by work: a sweep tile covers sweep_group chunks of record
+  // positions (or trace items), a forward tile forward_group blocks of
+  // episodes, so the phases of large instances get many tiles and those of
+  // small ones few.
+  std::vector<BatchItem> ph;
+  std::vector<int> ph_off(1, 0);
+  const int big = 1 << 30;
+  for (int i = 0; i < n; ++i) {
+    const vopp_request& r = b->reqs[i];
+    for (const Phase& f0 : plan_phases(r.pomdp, b->views[i], big, big)) {
+      Phase f = f0;
+      if (f.kind == kPhaseAccum || f.kind == kPhaseLeaf || f.kind == kPhaseLevel) {
+        const int g = std::max(1, b->tuning.sweep_group);
+        f.nblk = (f.nblk + g - 1) / g;
+      }
+      BatchItem it;
+      it.inst = i;
+      it.kind = f.kind;
+      it.a0 = f.a0;
+      it.a1 = f.a1;
+      it.blk0 = 0;
+      it.nblk = f.nblk;
+      if (f.kind == kPhaseForward) {        // fewer, larger forward tiles
+        const int g = std::max(1, b->tuning.forward_group);
+        it.blk0 = f.nblk;
+        it.nblk = (f.nblk + g - 1) / g;
+      } else if (f.kind == kPhaseSetup) {   // set-up strides over its table fill
+        const int g = std::max(1, b->tuning.sweep_group);
+        it.nblk = (f.nblk + g - 1) / g;
+      }
+      ph.push_back(it);
+    }
+    ph_off.push_back((int)ph.size());
+  }
+  const int per_cu = persistent_blocks_per_cu(b->amax);
+  const int want = b->tuning.blocks_per_cu > 0 ? std::min(b->tuning.blocks_per_cu, per_cu) : per_cu;
+  b->persist_blocks = std::max(1, want * b->n_cu);
   hipError_t e = hipSuccess;
+  if (b->ph_dev) (void)hipFree(b->ph_dev);
+  b->ph_dev = nullptr;
+  e = hipMalloc(&b->ph_dev, ph.size() * sizeof(BatchItem));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->ph_dev, ph.data(), ph.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->ph_off_dev, ph_off.data(), ph_off.size() * sizeof(int),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch queue upload");
   if (b->items_dev) (void)hipFree(b->items_dev);
   b->items_dev = nullptr;
   e = hipMalloc(&b->items_dev, b->items.size() * sizeof(BatchItem));
@@ -147,6 +225,16 @@ vopp_status capture(vopp_batch* b) {
   if (e2 != hipSuccess) return hip_fail(e2, "batched launch during capture");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  // The persistent launch: the queue reset (a kernel, not a memset node) and
+  // the persistent kernel, one graph.
+  e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  e2 = launch_persistent(b->views_dev, persist_view(b), b->persist_blocks, b->amax, b->stream);
+  e = hipStreamEndCapture(b->stream, &b->pgraph);
+  if (e2 != hipSuccess) return hip_fail(e2, "persistent launch during capture");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->pexec, b->pgraph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   return VOPP_OK;
 }
@@ -188,6 +276,10 @@ extern "C" void vopp_batch_free(vopp_batch* b) {
   for (vopp_workspace* w : b->ws) vopp_workspace_free(w);
   if (b->views_dev) (void)hipFree(b->views_dev);
   if (b->items_dev) (void)hipFree(b->items_dev);
+  if (b->ph_dev) (void)hipFree(b->ph_dev);
+  if (b->ph_off_dev) (void)hipFree(b->ph_off_dev);
+  if (b->word_dev) (void)hipFree(b->word_dev);
+  if (b->done_dev) (void)hipFree(b->done_dev);
   if (b->out_dev) (void)hipFree(b->out_dev);
   if (b->out_host) (void)hipHostFree(b->out_host);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
@@ -218,7 +310,9 @@ extern "C" vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
       return fail(VOPP_E_INVALID, "request %d: batched plans support |A| <= 16", i);
     amax = std::max(amax, r.pomdp->view.Apad);
   }
-  if (tuning && (tuning->accum_cap < 1 || tuning->backup_cap < 1))
+  if (tuning && (tuning->accum_cap < 1 || tuning->backup_cap < 1 ||
+                 tuning->blocks_per_cu < 0 || tuning->forward_group < 1 ||
+                 tuning->sweep_group < 1))
     return fail(VOPP_E_INVALID, "bad tuning");
   vopp_batch* b = new vopp_batch();
   b->n = n;
@@ -248,7 +342,12 @@ extern "C" vopp_status vopp_batch_create(const vopp_request* reqs, int32_t n,
       return hip_fail(e, "batch schedule");
     }
   }
-  hipError_t e = hipMalloc(&b->views_dev, n * sizeof(PlanView));
+  hipError_t e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess && b->n_cu < 1) b->n_cu = 1;
+  if (e == hipSuccess) e = hipMalloc(&b->views_dev, n * sizeof(PlanView));
+  if (e == hipSuccess) e = hipMalloc(&b->ph_off_dev, (size_t)(n + 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&b->word_dev, (size_t)n * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&b->done_dev, (size_t)(n + 1) * sizeof(unsigned int));
   if (e == hipSuccess) e = hipMalloc(&b->out_dev, (size_t)n * kOutStride * sizeof(double));
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&b->out_host, (size_t)n * kOutStride * sizeof(double),
@@ -292,15 +391,18 @@ extern "C" vopp_status vopp_batch_set_request(vopp_batch* b, int32_t i, const vo
   return VOPP_OK;
 }
 
-extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t use_graph,
+extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t mode,
                                       vopp_result* results, double* device_ms) {
   clear_error();
   if (!b || !results) return fail(VOPP_E_INVALID, "null argument");
+  if (mode != VOPP_BATCH_EAGER && mode != VOPP_BATCH_GRAPH && mode != VOPP_BATCH_PERSISTENT)
+    return fail(VOPP_E_INVALID, "unknown batch mode %d", mode);
   hipError_t e = hipEventRecord(b->ev_in, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
   if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
   if (e == hipSuccess) {
-    if (use_graph && b->exec) e = hipGraphLaunch(b->exec, b->stream);
+    if (mode == VOPP_BATCH_PERSISTENT) e = hipGraphLaunch(b->pexec, b->stream);
+    else if (mode == VOPP_BATCH_GRAPH) e = hipGraphLaunch(b->exec, b->stream);
     else e = enqueue_launches(b, b->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(b->ev1, b->stream);
@@ -337,39 +439,49 @@ extern "C" vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t 
   clear_error();
   if (!b) return fail(VOPP_E_INVALID, "null batch");
   if (reps < 1) reps = 1;
-  const int acc_cands[] = {256, 1024, 4096};
-  const int cap_cands[] = {256, 1024, 4096};
+  // Tile sizes of the persistent launch -- chunks of 256 record positions or
+  // trace items per sweep tile, blocks of 256 episodes per forward tile --
+  // and persistent blocks per CU.
+  const int sweep_cands[] = {1, 2, 4, 8};
+  const int fwd_cands[] = {1, 4};
+  const int per_cu = persistent_blocks_per_cu(b->amax);
+  std::vector<int> cu_cands{per_cu};
+  if (per_cu > 1) cu_cands.push_back(1);
   std::vector<vopp_result> ref(b->n), cur(b->n);
   bool have_ref = false;
   double best_ms = 1e30;
   vopp_tuning best = b->tuning;
-  for (int rc : acc_cands) {
-    for (int cc : cap_cands) {
-      b->tuning.accum_cap = rc;
-      b->tuning.backup_cap = cc;
-      vopp_status st = build_schedule(b);
-      if (st == VOPP_OK) st = capture(b);
-      if (st != VOPP_OK) return st;
-      double ms_min = 1e30;
-      for (int r = 0; r < reps + 1; ++r) {
-        double ms = 0.0;
-        st = vopp_batch_run(b, stream, 1, cur.data(), &ms);
+  for (int sg : sweep_cands) {
+    for (int fg : fwd_cands) {
+      for (int bc : cu_cands) {
+        b->tuning.sweep_group = sg;
+        b->tuning.forward_group = fg;
+        b->tuning.blocks_per_cu = bc;
+        vopp_status st = build_schedule(b);
+        if (st == VOPP_OK) st = capture(b);
         if (st != VOPP_OK) return st;
-        if (r > 0) ms_min = std::min(ms_min, ms);      // the first run warms up
-      }
-      // The launch shape must not change any result.
-      if (!have_ref) {
-        ref = cur;
-        have_ref = true;
-      } else {
-        for (int i = 0; i < b->n; ++i)
-          if (std::memcmp(&ref[i], &cur[i], sizeof(vopp_result)) != 0)
-            return fail(VOPP_E_INTERNAL, "tuning (%d, %d) changed the result of request %d",
-                        rc, cc, i);
-      }
-      if (ms_min < best_ms) {
-        best_ms = ms_min;
-        best = b->tuning;
+        double ms_min = 1e30;
+        for (int r = 0; r < reps + 1; ++r) {
+          double ms = 0.0;
+          st = vopp_batch_run(b, stream, VOPP_BATCH_PERSISTENT, cur.data(), &ms);
+          if (st != VOPP_OK) return st;
+          if (r > 0) ms_min = std::min(ms_min, ms);      // the first run warms up
+        }
+        // The launch shape must not change any result.
+        if (!have_ref) {
+          ref = cur;
+          have_ref = true;
+        } else {
+          for (int i = 0; i < b->n; ++i)
+            if (std::memcmp(&ref[i], &cur[i], sizeof(vopp_result)) != 0)
+              return fail(VOPP_E_INTERNAL,
+                          "tuning (%d, %d, %d) changed the result of request %d", sg, fg,
+                          bc, i);
+        }
+        if (ms_min < best_ms) {
+          best_ms = ms_min;
+          best = b->tuning;
+        }
       }
     }
   }
@@ -386,7 +498,7 @@ extern "C" vopp_status vopp_plan_batch(const vopp_request* reqs, int32_t n, void
   vopp_batch* b = nullptr;
   vopp_status st = vopp_batch_create(reqs, n, nullptr, &b);
   if (st != VOPP_OK) return st;
-  st = vopp_batch_run(b, stream, 1, results, nullptr);
+  st = vopp_batch_run(b, stream, VOPP_BATCH_PERSISTENT, results, nullptr);
   vopp_batch_free(b);
   return st;
 }

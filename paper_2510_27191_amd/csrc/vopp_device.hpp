@@ -314,6 +314,19 @@ struct BatchItem {
   int inst, kind, a0, a1, blk0, nblk;
 };
 
+// The persistent batched launch: a work queue over every instance's phase
+// list.  word[i] = (current phase << 32) | tiles of it taken; done[i] = tiles
+// of the current phase finished; finished = instances past their last phase.
+struct PersistView {
+  unsigned long long* word;
+  unsigned int* done;
+  unsigned int* finished;
+  const BatchItem* phases;     // every instance's phases, concatenated (a forward
+                               // phase: blk0 = its blocks of episodes, nblk = tiles)
+  const int* ph_off;           // [n + 1] first phase of each instance
+  int n;
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds; each multiplies words 0
 // and 2 by the two round constants, mixes the high halves with the key and the

@@ -1911,21 +1911,10 @@ __global__ void k_select(PlanView P) { dev_select(P); }
 // Batched kernel: block -> (instance, phase) through the item list, sorted by
 // first block.  AMAX bounds the padded action count of the batch.
 // ---------------------------------------------------------------------------
+// One phase item of one instance, as block blk of its nblk (LDS in sm).
 template <int AMAX>
-__global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ views,
-                                                  const BatchItem* __restrict__ items,
-                                                  int n_items) {
-  __shared__ Smem sm;
-  const int g = blockIdx.x;
-  int lo = 0, hi = n_items - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].blk0 <= g) lo = mid; else hi = mid - 1;
-  }
-  const BatchItem it = items[lo];
-  const int blk = g - it.blk0;
-  if (blk >= it.nblk) return;          // uniform per block
-  const PlanView& P = views[it.inst];
+__device__ __forceinline__ void run_item(const PlanView& P, const BatchItem& it, int blk,
+                                         Smem& sm) {
   const int Apad = P.m.Apad;
   switch (it.kind) {
     case kPhaseSetup: dev_setup(P, blk, it.nblk, nullptr); break;   // |A| <= 16
@@ -1954,6 +1943,136 @@ __global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ v
     case kPhasePFScan: dev_pf_scan(P, sm); break;
     case kPhasePFResample: dev_pf_resample(P, it.a0, blk); break;
     default: break;
+  }
+}
+
+template <int AMAX>
+__global__ __launch_bounds__(kBlock) void k_batch(const PlanView* __restrict__ views,
+                                                  const BatchItem* __restrict__ items,
+                                                  int n_items) {
+  __shared__ Smem sm;
+  const int g = blockIdx.x;
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].blk0 <= g) lo = mid; else hi = mid - 1;
+  }
+  const BatchItem it = items[lo];
+  const int blk = g - it.blk0;
+  if (blk >= it.nblk) return;          // uniform per block
+  run_item<AMAX>(views[it.inst], it, blk, sm);
+}
+
+// The persistent batched launch.  Every block loops: take a tile (one block's
+// share) of some instance's current phase from the queue, run it, and report
+// it finished; the last finisher of a phase moves its instance to the next
+// phase.  Taking a tile is one atomic add on the instance's word, whose old
+// value names the phase and the tile together, so a block never runs a tile
+// of a phase that has not started.  Memory order: each finisher releases its
+// block's writes (agent scope) before it counts; the last finisher publishes
+// the next phase with a release; a taker acquires after the add.  A block
+// that finds no tile sleeps briefly and looks again; it returns once every
+// instance is past its last phase.  Tiles never wait on anything, so every
+// taken tile finishes and the queue drains whatever the residency.
+__global__ void k_persist_reset(PersistView V) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < V.n) {
+    V.word[i] = 0ull;
+    V.done[i] = 0u;
+  }
+  if (i == 0) *V.finished = 0u;
+}
+
+template <int AMAX>
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(const PlanView* __restrict__ views,
+                                                             PersistView V) {
+  __shared__ Smem sm;
+  __shared__ int take[3];
+  int cur = (int)(blockIdx.x % (unsigned)V.n);
+  for (;;) {
+    if (threadIdx.x < 64) {
+      // Wavefront 0 looks for a tile: its lanes read 64 instances' words at
+      // once (this block's last instance first, then the others in turn), and
+      // the instances with a tile left are tried in that order, one atomic
+      // add each, until one yields a tile.
+      const int lane = (int)threadIdx.x;
+      int inst = -1, ph = 0, tile = 0;
+      for (int base = 0; base < V.n && inst < 0; base += 64) {
+        const int q = base + lane;
+        int i = 0;
+        bool avail = false;
+        if (q < V.n) {
+          i = cur + q < V.n ? cur + q : cur + q - V.n;
+          const int np = V.ph_off[i + 1] - V.ph_off[i];
+          const unsigned long long w =
+              __hip_atomic_load(&V.word[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int g = (int)(w >> 32);
+          avail = g < np && (unsigned)w < (unsigned)V.phases[V.ph_off[i] + g].nblk;
+        }
+        unsigned long long m = __ballot(avail);
+        while (m && inst < 0) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          int got = 0, g2 = 0, t2 = 0;
+          if (lane == src) {
+            const unsigned long long o = atomicAdd(&V.word[i], 1ull);
+            g2 = (int)(o >> 32);
+            t2 = (int)(unsigned)o;
+            const int np = V.ph_off[i + 1] - V.ph_off[i];
+            got = g2 < np && (unsigned)t2 < (unsigned)V.phases[V.ph_off[i] + g2].nblk;
+          }
+          if (__shfl(got, src, 64)) {
+            inst = __shfl(i, src, 64);
+            ph = __shfl(g2, src, 64);
+            tile = __shfl(t2, src, 64);
+          }
+        }
+      }
+      if (lane == 0) {
+        if (inst >= 0) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        } else if (__hip_atomic_load(V.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                   (unsigned)V.n) {
+          inst = -2;
+        }
+        take[0] = inst;
+        take[1] = ph;
+        take[2] = tile;
+      }
+    }
+    __syncthreads();
+    const int inst = take[0], ph = take[1], tile = take[2];
+    __syncthreads();
+    if (inst == -2) return;
+    if (inst == -1) {
+      __builtin_amdgcn_s_sleep(8);
+      continue;
+    }
+    cur = inst;
+    const BatchItem it = V.phases[V.ph_off[inst] + ph];
+    if (it.kind == kPhaseForward) {
+      // A forward tile runs several of the phase's blocks of episodes
+      // (blk0 of them in all, nblk tiles).
+      for (int sub = tile; sub < it.blk0; sub += it.nblk) {
+        run_item<AMAX>(views[inst], it, sub, sm);
+        __syncthreads();
+      }
+    } else {
+      run_item<AMAX>(views[inst], it, tile, sm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned d = atomicAdd(&V.done[inst], 1u) + 1u;
+      if (d == (unsigned)it.nblk) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(&V.done[inst], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int np = V.ph_off[inst + 1] - V.ph_off[inst];
+        __hip_atomic_exchange(&V.word[inst], (unsigned long long)(ph + 1) << 32,
+                              __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (ph + 1 == np) atomicAdd(V.finished, 1u);
+      }
+    }
   }
 }
 
@@ -2276,6 +2395,28 @@ hipError_t launch_fill16(void* p, size_t n, uint4 v, hipStream_t s) {
   const int g = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 8192);
   hipLaunchKernelGGL(k_fill16, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<uint4*>(p), n, v);
   return hipGetLastError();
+}
+
+hipError_t launch_persistent(const PlanView* views, const PersistView& V, int n_blocks,
+                             int amax, hipStream_t s) {
+  hipLaunchKernelGGL(k_persist_reset, dim3((V.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, V);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g(n_blocks), b(kBlock);
+  if (amax <= 4) hipLaunchKernelGGL(k_batch_persistent<4>, g, b, 0, s, views, V);
+  else if (amax <= 8) hipLaunchKernelGGL(k_batch_persistent<8>, g, b, 0, s, views, V);
+  else hipLaunchKernelGGL(k_batch_persistent<16>, g, b, 0, s, views, V);
+  return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int amax) {
+  const void* f = amax <= 4 ? (const void*)k_batch_persistent<4>
+                 : amax <= 8 ? (const void*)k_batch_persistent<8>
+                             : (const void*)k_batch_persistent<16>;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0) != hipSuccess || n < 1)
+    n = 1;
+  return n;
 }
 
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,

@@ -53,6 +53,11 @@ hipError_t launch_reroot_copy(const RerootView& V, hipStream_t s);
 // Fill n 16-byte words at p with v.
 hipError_t launch_fill16(void* p, size_t n, uint4 v, hipStream_t s);
 
+// The persistent batched launch (one reset kernel, then n_blocks blocks that
+// drain V's queue); the most blocks of it one CU holds at once.
+hipError_t launch_persistent(const PlanView* views, const PersistView& V, int n_blocks,
+                             int amax, hipStream_t s);
+int persistent_blocks_per_cu(int amax);
 // One batched launch: n_blocks blocks over n_items phase items (device arrays).
 hipError_t launch_batch(const PlanView* views, const BatchItem* items, int n_items,
                         int n_blocks, int amax, hipStream_t s);

@@ -95,7 +95,12 @@ class vopp_result(C.Structure):
 
 
 class vopp_tuning(C.Structure):
-    _fields_ = [("accum_cap", C.c_int32), ("backup_cap", C.c_int32)]
+    _fields_ = [("accum_cap", C.c_int32), ("backup_cap", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("forward_group", C.c_int32),
+                ("sweep_group", C.c_int32)]
+
+
+BATCH_EAGER, BATCH_GRAPH, BATCH_PERSISTENT = 0, 1, 2
 
 
 class vopp_server_config(C.Structure):
@@ -523,6 +528,8 @@ class Batch:
         self.reqs = make_requests(self.items)
         self.nAs = [it[0].nA for it in self.items]
         h = C.c_void_p()
+        if tuning is not None and len(tuning) < 5:
+            tuning = tuple(tuning) + (0, 1, 4)[len(tuning) - 2:]
         tu = None if tuning is None else C.byref(vopp_tuning(*tuning))
         _check(lib().vopp_batch_create(C.cast(self.reqs, C.c_void_p), len(self.items), tu,
                                        C.byref(h)))
@@ -541,14 +548,18 @@ class Batch:
                                             int(n_belief), int(seed) & (2 ** 64 - 1),
                                             int(step) & 0xFFFFFFFF))
 
-    def run(self, use_graph=True, stream=None):
+    def run(self, use_graph=True, stream=None, mode=None):
+        """mode: BATCH_PERSISTENT (default), BATCH_GRAPH or BATCH_EAGER; the
+        older use_graph=False means BATCH_EAGER."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
+        if mode is None:
+            mode = BATCH_PERSISTENT if use_graph else BATCH_EAGER
         arr = (vopp_result * len(self.items))()
         ms = np.zeros(1, np.float64)
         _check(lib().vopp_batch_run(self.handle, C.c_void_p(stream.cuda_stream),
-                                    1 if use_graph else 0, C.cast(arr, C.c_void_p), _p(ms)))
+                                    int(mode), C.cast(arr, C.c_void_p), _p(ms)))
         return _results(arr, self.nAs), float(ms[0])
 
     def autotune(self, reps=2, stream=None):
@@ -558,7 +569,8 @@ class Batch:
         tu = vopp_tuning()
         _check(lib().vopp_batch_autotune(self.handle, C.c_void_p(stream.cuda_stream),
                                          int(reps), C.byref(tu)))
-        return (int(tu.accum_cap), int(tu.backup_cap))
+        return (int(tu.accum_cap), int(tu.backup_cap), int(tu.blocks_per_cu),
+                int(tu.forward_group), int(tu.sweep_group))
 
     def close(self):
         if self.handle:
