@@ -366,7 +366,7 @@ def serve_trace(seed, qps, seconds, steps_per_episode):
 
 
 def bench_serve(V, I, qps_list=(250, 1000, 2500), seconds=5.0, steps_per_episode=50,
-                deadline_ms=50.0, plain_max_qps=1000):
+                deadline_ms=50.0, plain_max_qps=1000, phases_per_tick=32):
     """Continuous-batching server vs plain one-request-at-a-time planning on
     the same arrival trace of episodes drawn from the 256-instance mix."""
     import torch
@@ -400,7 +400,8 @@ def bench_serve(V, I, qps_list=(250, 1000, 2500), seconds=5.0, steps_per_episode
         starts = serve_trace(17, qps, seconds, steps_per_episode)
         eps = [episode(j) for j in range(len(starts))]
         # Served: continuous batching.
-        srv = V.Server(hbm_budget_bytes=64 << 30, max_active=512, max_inflight=3)
+        srv = V.Server(hbm_budget_bytes=64 << 30, max_active=512, max_inflight=3,
+                       phases_per_tick=phases_per_tick)
         lat, steps = [], 0
         t0 = time.perf_counter()
         nxt = 0
@@ -471,8 +472,10 @@ def bench_serve(V, I, qps_list=(250, 1000, 2500), seconds=5.0, steps_per_episode
         p.close()
     return {"workload": f"episodes drawn from the 256-instance mix, {steps_per_episode} "
                         f"steps each, Poisson episode starts for {seconds:.0f} s, belief "
-                        "particles and trees resident, 64 GiB HBM admission budget, "
+                        "particles and tree workspaces resident (each step plans a fresh "
+                        "tree), 64 GiB HBM admission budget, "
                         f"{deadline_ms:.0f} ms per-step deadline",
+            "phases_per_tick": phases_per_tick,
             "sweep": results}
 
 

@@ -457,12 +457,16 @@ vopp_status vopp_plan_batch(const vopp_request* reqs, int32_t n, void* stream,
 
 /* hbm_budget_bytes: admission limit on the summed footprint (workspace and
  * particle buffers) of the active episodes.  max_active: most episodes
- * resident at once (<= 4096).  max_inflight: launches queued ahead on the
- * device (1..8). */
+ * resident at once (<= 4096).  max_inflight: ticks queued ahead on the device
+ * (1..8).  phases_per_tick: launches one tick queues back to back (0..64; 0
+ * or 1: one), each advancing every active request by one phase; more per tick
+ * means fewer host round trips per request, fewer means new requests join
+ * sooner. */
 typedef struct {
   uint64_t hbm_budget_bytes;
   int32_t max_active;
   int32_t max_inflight;
+  int32_t phases_per_tick;
 } vopp_server_config;
 
 /* One episode: a model, its initial belief particles (HOST array, n_particles
@@ -504,8 +508,8 @@ typedef struct vopp_server vopp_server;
 vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_server** out);
 /* Queue an episode for admission; its id is returned in *episode. */
 vopp_status vopp_server_submit(vopp_server* s, const vopp_episode_desc* ep, int32_t* episode);
-/* Admit what fits, issue at most one batched launch that advances every
- * active request by one phase, and collect finished requests.  *pending
+/* Admit what fits, issue up to phases_per_tick batched launches that each
+ * advance every active request by one phase, and collect finished requests.  *pending
  * (may be NULL) = queued + active episodes after the call. */
 vopp_status vopp_server_tick(vopp_server* s, int32_t* pending);
 /* Move up to max finished requests into out; returns how many. */

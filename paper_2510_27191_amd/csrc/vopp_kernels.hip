@@ -2156,16 +2156,17 @@ hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {
   hipLaunchKernelGGL(k_env, dim3(1), dim3(64), 0, s, P, t);
   return hipGetLastError();
 }
-hipError_t launch_pf(const PlanView& P, int t, hipStream_t s) {
+hipError_t launch_pf_part(const PlanView& P, int part, int t, hipStream_t s) {
   const dim3 g(blocks_for(P.f.M)), b(kBlock);
-  hipLaunchKernelGGL(k_pf_weight, g, b, 0, s, P, t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pf_scan, dim3(1), b, 0, s, P);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pf_resample, g, b, 0, s, P, t);
+  if (part == 0) hipLaunchKernelGGL(k_pf_weight, g, b, 0, s, P, t);
+  else if (part == 1) hipLaunchKernelGGL(k_pf_scan, dim3(1), b, 0, s, P);
+  else hipLaunchKernelGGL(k_pf_resample, g, b, 0, s, P, t);
   return hipGetLastError();
+}
+hipError_t launch_pf(const PlanView& P, int t, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_pf_part(P, part, t, s);
+  return e;
 }
 // The tree dump: belief ids[i]'s fields packed at out + i * dump_bytes(ra)
 // (layout in vopp_device.hpp), one thread per belief.

@@ -20,6 +20,8 @@ hipError_t launch_select(const PlanView& P, hipStream_t s);
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s);
 // SIR update of P.f: weight, scan, resample (three launches).
 hipError_t launch_pf(const PlanView& P, int t, hipStream_t s);
+// One of the three: 0 weight, 1 scan, 2 resample.
+hipError_t launch_pf_part(const PlanView& P, int part, int t, hipStream_t s);
 // Copy the records of beliefs ids[0..n) (device) to out[n * rs] (device).
 hipError_t launch_gather(const TreeView& t, const int* ids, int n, unsigned char* out,
                          hipStream_t s);

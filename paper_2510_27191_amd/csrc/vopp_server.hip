@@ -6,8 +6,8 @@
 //   t > 0:  execute the previous action in the simulated true environment,
 //           then the SIR belief update (weight, scan, resample);
 //   always: the planning step (set-up ... select) on the updated particles.
-// Every tick issues at most one k_batch launch that advances each active
-// request by one phase.  Requests that arrive while others run simply join
+// Every tick issues up to phases_per_tick k_batch launches back to back, each
+// advancing every active request by one phase.  Requests that arrive while others run simply join
 // the next tick: new episodes are admitted as soon as a slot and HBM (the
 // configured budget, counted over the resident footprints) are free, and an
 // episode's next request is issued as soon as the server has seen the result
@@ -31,6 +31,7 @@ using namespace vopp;
 namespace {
 
 constexpr int kMaxInflight = 8;
+constexpr int kMaxPhasesPerTick = 64;
 
 // Device resources of one resident episode (reused through a pool).
 struct Resources {
@@ -278,6 +279,8 @@ extern "C" vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_se
     return fail(VOPP_E_INVALID, "max_active must be in [1, 4096]");
   if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxInflight)
     return fail(VOPP_E_INVALID, "max_inflight must be in [1, %d]", kMaxInflight);
+  if (cfg->phases_per_tick < 0 || cfg->phases_per_tick > kMaxPhasesPerTick)
+    return fail(VOPP_E_INVALID, "phases_per_tick must be in [0, %d]", kMaxPhasesPerTick);
   vopp_server* s = new vopp_server();
   s->cfg = *cfg;
   (void)hipGetDevice(&s->device);
@@ -289,10 +292,12 @@ extern "C" vopp_status vopp_server_create(const vopp_server_config* cfg, vopp_se
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&s->views_host, na * sizeof(PlanView), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&s->out_dev, na * kOutStride * sizeof(double));
+  const size_t per_tick = (size_t)std::max(1, cfg->phases_per_tick);
   for (int k = 0; k <= cfg->max_inflight && e == hipSuccess; ++k) {
-    e = hipMalloc(&s->items_dev[k], na * sizeof(BatchItem));
+    e = hipMalloc(&s->items_dev[k], na * per_tick * sizeof(BatchItem));
     if (e == hipSuccess)
-      e = hipHostMalloc((void**)&s->items_host[k], na * sizeof(BatchItem), hipHostMallocDefault);
+      e = hipHostMalloc((void**)&s->items_host[k], na * per_tick * sizeof(BatchItem),
+                        hipHostMallocDefault);
     if (e == hipSuccess)
       e = hipHostMalloc((void**)&s->out_host[k], na * kOutStride * sizeof(double),
                         hipHostMallocDefault);
@@ -395,38 +400,111 @@ extern "C" vopp_status vopp_server_tick(vopp_server* s, int32_t* pending) {
     if (st != VOPP_OK) return st;
     ++active;
   }
-  // 3. One launch: the next phase of every active request.
+  // 3. Up to phases_per_tick launches, queued back to back: launch g runs the
+  // next phase of every active request that has one and has not reached its
+  // select in an earlier launch of this tick.
   const int k = s->ring;
+  const int per_tick = std::max(1, s->cfg.phases_per_tick);
+  const size_t na = s->slot_ep.size();
   BatchItem* items = s->items_host[k];
   TickRec tk;
-  int n = 0, blocks = 0, amax = 4;
+  std::vector<int> lo, cnt, nblocks;
+  int total = 0, amax = 4;
   hipError_t err = hipSuccess;
-  for (int slot = 0; slot < (int)s->slot_ep.size(); ++slot) {
+  // One request with phases to run: its phases go to the single-plan kernels
+  // (no batch dispatch), as many as a tick takes.
+  int pending_slot = -1, n_pending = 0;
+  for (int slot = 0; slot < (int)na; ++slot) {
     const int id = s->slot_ep[slot];
     if (id < 0) continue;
+    const Episode& e = s->eps[id];
+    if (!e.waiting && e.next < e.phases.size()) {
+      ++n_pending;
+      pending_slot = slot;
+    }
+  }
+  if (n_pending == 1) {
+    const int id = s->slot_ep[pending_slot];
     Episode& e = s->eps[id];
-    if (e.waiting || e.next >= e.phases.size()) continue;
     if (e.new_view) {
-      err = hipMemcpyAsync(s->views_dev + slot, s->views_host + slot, sizeof(PlanView),
-                           hipMemcpyHostToDevice, s->stream);
+      err = hipMemcpyAsync(s->views_dev + pending_slot, s->views_host + pending_slot,
+                           sizeof(PlanView), hipMemcpyHostToDevice, s->stream);
       if (err != hipSuccess) return hip_fail(err, "view upload");
       e.new_view = false;
     }
-    const Phase& f = e.phases[e.next++];
-    items[n] = BatchItem{slot, f.kind, f.a0, f.a1, blocks, f.nblk};
-    blocks += f.nblk;
-    ++n;
-    amax = std::max(amax, e.d.pomdp->view.Apad);
-    if (f.kind == kPhaseSelect) {
-      e.waiting = true;
-      tk.selects.push_back(id);
+    const PlanView& P = s->views_host[pending_slot];
+    for (int g = 0; g < per_tick && !e.waiting && e.next < e.phases.size() && err == hipSuccess;
+         ++g) {
+      const Phase& f = e.phases[e.next++];
+      switch (f.kind) {
+        case kPhaseSetup: err = launch_setup(P, s->stream); break;
+        case kPhaseForward: err = launch_forward(P, f.a0, f.a1, s->stream); break;
+        case kPhaseAccum: err = launch_accum(P, f.a0, f.nblk, s->stream); break;
+        case kPhaseLeaf: err = launch_backup_leaf(P, f.a0, f.a1, f.nblk, s->stream); break;
+        case kPhaseLevel: err = launch_backup_level(P, f.a0, f.a1, f.nblk, s->stream); break;
+        case kPhaseRoot: err = launch_backup_root(P, f.a0, s->stream); break;
+        case kPhaseEnv: err = launch_env(P, f.a0, s->stream); break;
+        case kPhasePFWeight: err = launch_pf_part(P, 0, f.a0, s->stream); break;
+        case kPhasePFScan: err = launch_pf_part(P, 1, f.a0, s->stream); break;
+        case kPhasePFResample: err = launch_pf_part(P, 2, f.a0, s->stream); break;
+        case kPhaseSelect:
+          err = launch_select(P, s->stream);
+          e.waiting = true;
+          tk.selects.push_back(id);
+          break;
+        default: break;
+      }
     }
+    if (err == hipSuccess && !tk.selects.empty())
+      err = hipMemcpyAsync(s->out_host[k], s->out_dev,
+                           s->slot_ep.size() * kOutStride * sizeof(double),
+                           hipMemcpyDeviceToHost, s->stream);
+    if (err == hipSuccess) err = hipEventRecord(s->ev[k], s->stream);
+    if (err != hipSuccess) return hip_fail(err, "server launch");
+    tk.ev = s->ev[k];
+    tk.ring = k;
+    s->inflight.push_back(tk);
+    s->ring = (s->ring + 1) % (s->cfg.max_inflight + 1);
+    n_pending = -1;                         // issued
   }
-  if (n > 0) {
-    err = hipMemcpyAsync(s->items_dev[k], items, n * sizeof(BatchItem), hipMemcpyHostToDevice,
-                         s->stream);
-    if (err == hipSuccess) err = launch_batch(s->views_dev, s->items_dev[k], n, blocks, amax,
-                                              s->stream);
+  for (int g = 0; g < per_tick && n_pending >= 0; ++g) {
+    int n = 0, blocks = 0;
+    BatchItem* it = items + (size_t)g * na;
+    for (int slot = 0; slot < (int)na; ++slot) {
+      const int id = s->slot_ep[slot];
+      if (id < 0) continue;
+      Episode& e = s->eps[id];
+      if (e.waiting || e.next >= e.phases.size()) continue;
+      if (e.new_view) {
+        err = hipMemcpyAsync(s->views_dev + slot, s->views_host + slot, sizeof(PlanView),
+                             hipMemcpyHostToDevice, s->stream);
+        if (err != hipSuccess) return hip_fail(err, "view upload");
+        e.new_view = false;
+      }
+      const Phase& f = e.phases[e.next++];
+      it[n] = BatchItem{slot, f.kind, f.a0, f.a1, blocks, f.nblk};
+      blocks += f.nblk;
+      ++n;
+      amax = std::max(amax, e.d.pomdp->view.Apad);
+      if (f.kind == kPhaseSelect) {
+        e.waiting = true;
+        tk.selects.push_back(id);
+      }
+    }
+    if (n == 0) break;
+    lo.push_back(g);
+    cnt.push_back(n);
+    nblocks.push_back(blocks);
+    total = g + 1;
+  }
+  if (n_pending < 0) {
+    // issued above
+  } else if (total > 0) {
+    err = hipMemcpyAsync(s->items_dev[k], items, (size_t)total * na * sizeof(BatchItem),
+                         hipMemcpyHostToDevice, s->stream);
+    for (size_t g = 0; g < lo.size() && err == hipSuccess; ++g)
+      err = launch_batch(s->views_dev, s->items_dev[k] + (size_t)lo[g] * na, cnt[g],
+                         nblocks[g], amax, s->stream);
     if (err == hipSuccess && !tk.selects.empty())
       err = hipMemcpyAsync(s->out_host[k], s->out_dev,
                            s->slot_ep.size() * kOutStride * sizeof(double),

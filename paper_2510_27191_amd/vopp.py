@@ -105,7 +105,7 @@ BATCH_EAGER, BATCH_GRAPH, BATCH_PERSISTENT = 0, 1, 2
 
 class vopp_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_active", C.c_int32),
-                ("max_inflight", C.c_int32)]
+                ("max_inflight", C.c_int32), ("phases_per_tick", C.c_int32)]
 
 
 class vopp_episode_desc(C.Structure):
@@ -623,9 +623,11 @@ def particles_host(inst, belief):
 class Server:
     """vopp_server: continuous batching of many episodes' planning steps."""
 
-    def __init__(self, hbm_budget_bytes=64 << 30, max_active=256, max_inflight=3):
+    def __init__(self, hbm_budget_bytes=64 << 30, max_active=256, max_inflight=3,
+                 phases_per_tick=1):
         h = C.c_void_p()
-        cfg = vopp_server_config(int(hbm_budget_bytes), int(max_active), int(max_inflight))
+        cfg = vopp_server_config(int(hbm_budget_bytes), int(max_active), int(max_inflight),
+                                 int(phases_per_tick))
         _check(lib().vopp_server_create(C.byref(cfg), C.byref(h)))
         self.handle = h
         self.kinds = {}

@@ -64,8 +64,9 @@ def plain_episode(V, ep):
     return out
 
 
-def serve(V, eps, max_active=64, budget=64 << 30):
-    srv = V.Server(hbm_budget_bytes=budget, max_active=max_active)
+def serve(V, eps, max_active=64, budget=64 << 30, phases_per_tick=1):
+    srv = V.Server(hbm_budget_bytes=budget, max_active=max_active,
+                   phases_per_tick=phases_per_tick)
     poms = [V.Pomdp.from_instance(ep["inst"]) for ep in eps]
     ids = []
     for pom, ep in zip(poms, eps):
@@ -91,6 +92,9 @@ def test_served_mix_equals_alone_and_plain(V):
         assert got == plain_episode(V, ep)
     alone = serve(V, eps[3:4])
     assert alone[0] == mixed[3]
+    # Several phases per tick: the same results.
+    for ppt in (5, 64):
+        assert serve(V, eps, phases_per_tick=ppt) == mixed
 
 
 def test_admission_by_budget_and_slots(V):
