@@ -10,8 +10,8 @@ K = 10 iterations, 8 obstacle disks, observations keyed on a 0.5 grid.  Inputs
 Prints one JSON line:
   value        particle-steps/s (generative-model calls per second, whole job)
   latency_ms   p50 / p99 of the per-plan wall time (host call to result)
-  roofline     achieved algorithmic GB/s of the dominant kernel (HIP events on
-               the plan's stream) against the 8 TB/s HBM peak
+  roofline     achieved algorithmic GB/s of the dominant kernel (its launches'
+               own start and end timestamps) against the 8 TB/s HBM peak
   cpu_baseline the serial CPU oracle timed on a bounded sample of the workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -58,14 +58,17 @@ def method_bytes(kind, nA, particle_steps, n_beliefs, n_actions, sweep, leaf_vis
 
 
 # Bytes the present layout moves for the same work (the overhead against the
-# method's bytes): a belief record holds 24*ra + 32 bytes (ra = |A| rounded up
-# to a multiple of 4); a level sweep reads each swept record whole, writes
-# its row and V, N_b, clears W of its visited actions and pushes into its
-# parent (16: the atomic's read and write).
+# method's bytes).  The tree is one array per field indexed by belief id (ra =
+# |A| rounded up to a multiple of 4).  A level sweep visit reads the position's
+# list entry (4), the belief's hot fields {V, N_b, parent} (16) and its visit
+# counts (4*ra), and pushes into its parent's W (16: the atomic's read and
+# write); a belief with an action node also reads and writes its preference
+# row (8*ra) and writes V and N_b (8); each action node reads C and W (16) and
+# clears W (8).
 def layout_bytes_backup_level(nA, sweep):
     ra = (nA + 3) // 4 * 4
     visits, internal, nodes = sweep
-    return visits * (24 * ra + 32 + 16) + internal * (4 * ra + 8) + nodes * 8
+    return visits * (4 + 16 + 4 * ra + 16) + internal * (8 * ra + 8) + nodes * 24
 
 
 def leaf_sweep_visits(n_p, K, depth, counts):
@@ -80,15 +83,22 @@ def leaf_sweep_visits(n_p, K, depth, counts):
     return total
 
 
-# Measured HBM traffic of the dominant kernel per launch (bytes), from the
+# Measured HBM traffic of the dominant kernels per launch (bytes), from the
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
-# profiles/planning_step_hbm_traffic.md, scaled by a plain-copy calibration
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources it
-# was taken on (hash below); otherwise `traffic` is reported as null.
+# profiles/planning_step_hbm_traffic.md.  "copy": each counter scaled by what it
+# reads for a plain device copy of known size (FETCH_SIZE x 2.0, WRITE_SIZE x
+# 1.0).  "gather": FETCH_SIZE unscaled, which is what the counter reads for
+# random 16-byte reads (128 B per access, one cache line), the access pattern of
+# these kernels.  Valid only for the kernel sources they were taken on (hash
+# below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "5b8626943d689100",
-    "backup_level": {"nav2d": 48.67e6, "sparse4096": 199.94e6},
-    "forward": {"nav2d": 135.65e6, "sparse4096": 728.36e6},
+    "sources_sha256_16": "d6d45a94f01650e6",
+    "backup_level": {"nav2d": 3.907e+07, "sparse4096": 1.293e+08},
+    "forward": {"nav2d": 1.304e+08, "sparse4096": 6.915e+08},
+    "gather_scale": {
+        "backup_level": {"nav2d": 2.688e+07, "sparse4096": 8.173e+07},
+        "forward": {"nav2d": 1.068e+08, "sparse4096": 4.935e+08},
+    },
 }
 
 
@@ -215,33 +225,26 @@ def bench_batch(V, I, reps=3, autotune=True, cpu=True):
         plain_s.append(time.perf_counter() - t0)
     plain_ref = [V.plan(pom, belt, nb, K, depth, prm, stream=stream)
                  for pom, belt, nb, K, depth, prm in items]
-    # Batched: the whole batch as one persistent launch (autotuned), and the
-    # per-phase launch sequence as a graph for comparison.
+    # Batched: the autotuner times the persistent launch over its tile sizes
+    # and the per-phase graph over its block caps; each mode is then timed
+    # at its own best tuning, and the faster is the batch's figure.
     batch = V.Batch(items)
     tuning = batch.autotune(reps=1) if autotune else None
-    batch.run(mode=V.BATCH_PERSISTENT)
-    batch_s, batch_dev = [], []
-    res = None
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res, ms = batch.run(mode=V.BATCH_PERSISTENT)
-        batch_s.append(time.perf_counter() - t0)
-        batch_dev.append(ms)
-    # The per-phase launch sequence with its own block caps (256 blocks per
-    # accumulate or backup sweep of an instance).
-    batch_ph = V.Batch(items, tuning=(256, 256, 0, 1, 4))
-    batch_ph.run(mode=V.BATCH_GRAPH)
-    phase_s, phase_dev = [], []
-    res_phase = None
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res_phase, ms = batch_ph.run(mode=V.BATCH_GRAPH)
-        phase_s.append(time.perf_counter() - t0)
-        phase_dev.append(ms)
-    n_launches = batch_ph.num_launches
-    batch_ph.close()
+
+    def timed(mode):
+        batch.run(mode=mode)
+        wall, dev, r = [], [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r, ms = batch.run(mode=mode)
+            wall.append(time.perf_counter() - t0)
+            dev.append(ms)
+        return r, wall, dev
+    res, batch_s, batch_dev = timed(V.BATCH_PERSISTENT)
+    res_phase, phase_s, phase_dev = timed(V.BATCH_GRAPH)
+    n_launches = batch.num_launches
+    auto_mode = batch.auto_mode
 
     def same_all(rs):
         return all(a.action == b.action and np.array_equal(a.values, b.values)
@@ -266,9 +269,12 @@ def bench_batch(V, I, reps=3, autotune=True, cpu=True):
                                     "ms_per_batch": min(phase_s) * 1e3,
                                     "device_ms_per_batch": min(phase_dev),
                                     "launches": n_launches},
-        "speedup": min(plain_s) / min(batch_s),
+        "autotuned_mode": {V.BATCH_GRAPH: "per_phase_graph",
+                           V.BATCH_PERSISTENT: "persistent"}.get(auto_mode),
+        "speedup": min(plain_s) / min(min(batch_s), min(phase_s)),
         "results_identical_to_plain": bool(identical),
-        "tuning": {"blocks_per_cu": tuning[2], "forward_group": tuning[3],
+        "tuning": {"accum_cap": tuning[0], "backup_cap": tuning[1],
+                   "blocks_per_cu": tuning[2], "forward_group": tuning[3],
                    "sweep_group": tuning[4]} if tuning else None,
     }
     batch.close()
@@ -523,9 +529,9 @@ def bench_plain(V, I, name, steps, warmup, event_profile, cpu):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     counts = V.level_counts(ws)              # beliefs per level step, last plan
-    # The dominant kind's launches, bracketed with HIP events on the plan
-    # stream, over the same plans run again (each bracket costs about 2 us of
-    # device time, so the timed region carries none).
+    # The dominant kind's launches timed by their own dispatch (start and end
+    # events taken by hipExtLaunchKernel on the plan stream), over the same
+    # plans run again, so that the timed region carries no profiling.
     prof = None
     if dom is not None:
         V.profile_reset(ws)
@@ -566,8 +572,9 @@ def bench_plain(V, I, name, steps, warmup, event_profile, cpu):
                         byte_model="the method's bytes per unit of work (per particle "
                                    "step, new node, belief and action-node visit) "
                                    "times the units each timed plan counted",
-                        timing="HIP events around each launch of the kernel on the plan "
-                               "stream, over the timed plans run again")
+                        timing="start and end timestamps of each launch's own dispatch "
+                               "(HIP events taken by hipExtLaunchKernel on the plan stream), "
+                               "over the timed plans run again")
             if dom == "backup_level":
                 sw = [sum(r.sweep[i] for r in results) / launches for i in range(3)]
                 roof["units_per_launch"] = {"belief_visits": sw[0],
@@ -578,8 +585,13 @@ def bench_plain(V, I, name, steps, warmup, event_profile, cpu):
             tr = MEASURED_TRAFFIC.get(dom, {}).get(name)
             if tr is not None and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]:
                 roof["traffic"] = tr
+                roof["traffic_calibration"] = "plain device copy (FETCH_SIZE x 2, WRITE_SIZE x 1)"
                 roof["traffic_GBs"] = tr / (ms * 1e-3 / launches) / 1e9
                 roof["traffic_over_method_bytes"] = tr / (total[dom] / launches)
+                tg = MEASURED_TRAFFIC["gather_scale"].get(dom, {}).get(name)
+                if tg is not None:
+                    roof["traffic_gather_calibration"] = tg
+                    roof["traffic_gather_over_method_bytes"] = tg / (total[dom] / launches)
         else:
             roof.update(achieved=None, frac=None,
                         note=f"dominant kernel {dom} has no byte model")
@@ -618,7 +630,28 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to "
                          "calibrate HBM traffic counters, then exit")
+    ap.add_argument("--gather-calibration", type=int, default=0, metavar="MROWS",
+                    help="only gather MROWS million random 16-byte rows of a 1 GiB "
+                         "table (5 times), a scattered-access calibration of the "
+                         "traffic counters, then exit")
     args = ap.parse_args()
+
+    if args.gather_calibration:
+        import torch
+        rows = (1 << 30) // 16
+        n = args.gather_calibration * 1000000
+        table = torch.ones((rows, 4), dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        idx = torch.randint(0, rows, (n,), device="cuda", generator=g)
+        out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(5):
+            torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_calibration_rows": n, "row_bytes": 16,
+                          "table_bytes": rows * 16, "gathers": 5}), flush=True)
+        return
 
     if args.copy_calibration:
         import torch

@@ -9,9 +9,10 @@
  * iteration's depth, and the bottom-up preference backup of Alg. 3 (Q = C/N +
  * gamma W, Psi <- Psi - L_eta Psi + Q from Eq. 5, V = L_eta Psi from Eq. 3);
  * then the root action with the largest preference.  The tree holds the
- * tensors of Sec. III-C (belief rows, action-node rows, preference rows) as
- * one record per belief in HBM: its preference row, the visit counts and
- * reward sums of its action nodes, and its value, visit count and parent.
+ * tensors of Sec. III-C (belief rows, action-node rows, preference rows) in
+ * HBM as one array per belief field, indexed by belief id: the preference
+ * row, the visit counts, reward sums and child-value sums of the belief's
+ * action nodes, and its value, visit count and parent.
  *
  * Conventions for every entry point:
  *   - Every function returns a vopp_status; nothing throws across the ABI.
@@ -406,7 +407,10 @@ typedef struct {
 enum {
   VOPP_BATCH_EAGER = 0,       /* per-phase launches issued one by one         */
   VOPP_BATCH_GRAPH = 1,       /* the per-phase launches as one hipGraph      */
-  VOPP_BATCH_PERSISTENT = 2   /* one persistent launch over a device queue   */
+  VOPP_BATCH_PERSISTENT = 2,  /* one persistent launch over a device queue   */
+  VOPP_BATCH_AUTO = 3         /* the faster of GRAPH and PERSISTENT as the last
+                                 vopp_batch_autotune measured it (PERSISTENT
+                                 before any autotuning)                       */
 };
 
 typedef struct vopp_batch vopp_batch;
@@ -436,15 +440,21 @@ vopp_status vopp_batch_set_request(vopp_batch* b, int32_t i, const void* belief_
  * results bit for bit. */
 vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t mode,
                            vopp_result* results, double* device_ms);
-/* The autotuner: time the persistent launch of this batch (reps timed runs
- * each) over its tile sizes (sweep_group in {1, 2, 4, 8}, forward_group in
- * {1, 4}) and blocks per CU (all that fit, or one), keep the fastest,
- * re-capture the graphs, and report it in chosen (may be NULL).  Every tried
- * shape must give bit-identical results, else VOPP_E_INTERNAL. */
+/* The autotuner (reps timed runs per shape, after one warm-up run): time the
+ * persistent launch of this batch over its tile sizes (sweep_group in
+ * {1, 2, 4, 8}, forward_group in {1, 4}) and blocks per CU (all that fit, or
+ * one), then the per-phase graph over its block caps (accum_cap and
+ * backup_cap 256 each, or the plain plan's caps); keep the fastest of each,
+ * re-capture both graphs, report the tuning in chosen (may be NULL), and let
+ * VOPP_BATCH_AUTO run the faster mode from then on.  Every tried shape must
+ * give bit-identical results, else VOPP_E_INTERNAL. */
 vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t reps,
                                 vopp_tuning* chosen);
 /* Number of batched launches (phases of the longest instance). */
 int32_t vopp_batch_num_launches(const vopp_batch* b);
+/* The mode VOPP_BATCH_AUTO runs (VOPP_BATCH_GRAPH or VOPP_BATCH_PERSISTENT);
+ * -1 for a null batch. */
+int32_t vopp_batch_auto_mode(const vopp_batch* b);
 void vopp_batch_free(vopp_batch* b);
 
 /* One-shot form: create, run once, free. */
@@ -536,12 +546,14 @@ enum {
   VOPP_KERNEL_KINDS = 7
 };
 
-/* kind_mask != 0: every later vopp_plan in `ws` brackets each launch of the
- * kernel kinds whose bit (1 << kind) is set with a pair of HIP events on its
- * stream and adds the elapsed time to per-kind totals (-1 = all kinds).
- * kind_mask == 0 stops it.  Totals are kept until vopp_profile_reset.  Each
- * bracket costs a few microseconds of device time, so bracket only the kinds
- * being measured. */
+/* kind_mask != 0: every later vopp_plan in `ws` times each launch of the
+ * kernel kinds whose bit (1 << kind) is set by the start and end timestamps
+ * of its own dispatch (a pair of HIP events that hipExtLaunchKernel takes on
+ * the plan's stream; the accumulate kind spans its claim pass too) and adds
+ * the elapsed time to per-kind totals (-1 = all kinds).  kind_mask == 0 stops
+ * it.  Totals are kept until vopp_profile_reset.  Timed launches are
+ * dispatched with their events attached, which costs a little device time,
+ * so time only the kinds being measured. */
 vopp_status vopp_profile_enable(vopp_workspace* ws, int32_t kind_mask);
 vopp_status vopp_profile_reset(vopp_workspace* ws);
 /* ms[VOPP_KERNEL_KINDS] (host, out): summed kernel milliseconds per kind;

@@ -579,12 +579,16 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   if (e != hipSuccess) return hip_fail(e, "upload schedule");
   w->prof_used = 0;
   // Each launch below is bracketed by prof_begin/prof_end (no-ops unless
-  // profiling is enabled on the workspace).
+  // profiling is enabled on the workspace); prof_end runs whenever prof_begin
+  // did, so no bracket stays open past its launch.
 #define VOPP_TIMED(kind, call)                              \
   do {                                                      \
-    if (e == hipSuccess) e = prof_begin(w, kind, s);        \
-    if (e == hipSuccess) e = (call);                        \
-    if (e == hipSuccess) e = prof_end(w, s);                \
+    if (e == hipSuccess) {                                  \
+      e = prof_begin(w, kind, s);                           \
+      if (e == hipSuccess) e = (call);                      \
+      const hipError_t e_end = prof_end(w, s);              \
+      if (e == hipSuccess) e = e_end;                       \
+    }                                                       \
   } while (0)
   if (w->hash_dirty && !P.clear_all) {
     // A plan did not finish: the table state is unknown, clear it fully.
@@ -627,24 +631,40 @@ vopp_status enqueue_plan(const vopp_pomdp* p, vopp_workspace* w, const PlanView&
   return VOPP_OK;
 }
 
+// A bracket's events are the start and end timestamps of its launches' own
+// dispatches (launch_timing), the times a kernel trace reports, not markers
+// recorded on the stream around them.
 hipError_t prof_begin(vopp_workspace* w, int kind, hipStream_t s) {
+  (void)s;
   w->prof_open = w->prof_on && ((w->prof_mask >> kind) & 1u);
   if (!w->prof_open) return hipSuccess;
   while (w->prof_events.size() < w->prof_used + 2) {
     hipEvent_t ev;
     hipError_t e = hipEventCreate(&ev);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      w->prof_open = false;
+      return e;
+    }
     w->prof_events.push_back(ev);
   }
   if (w->prof_kinds.size() < w->prof_used / 2 + 1) w->prof_kinds.resize(w->prof_used / 2 + 1);
   w->prof_kinds[w->prof_used / 2] = kind;
-  return hipEventRecord(w->prof_events[w->prof_used], s);
+  launch_timing() = LaunchTiming{w->prof_events[w->prof_used], w->prof_events[w->prof_used + 1],
+                                 false};
+  return hipSuccess;
 }
 
 hipError_t prof_end(vopp_workspace* w, hipStream_t s) {
   if (!w->prof_open) return hipSuccess;
   w->prof_open = false;
-  hipError_t e = hipEventRecord(w->prof_events[w->prof_used + 1], s);
+  const bool used = launch_timing().used;
+  launch_timing() = LaunchTiming{};
+  hipError_t e = hipSuccess;
+  if (!used) {
+    // Nothing was launched: an empty bracket.
+    e = hipEventRecord(w->prof_events[w->prof_used], s);
+    if (e == hipSuccess) e = hipEventRecord(w->prof_events[w->prof_used + 1], s);
+  }
   w->prof_used += 2;
   return e;
 }

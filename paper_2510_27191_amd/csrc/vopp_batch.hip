@@ -4,14 +4,17 @@
 // Each instance's plan is a fixed list of phases (set-up; per iteration the
 // forward search, the accumulate sweep, the leaf sweep, one sweep per depth,
 // the root; finally select), each split into tiles (one block's share).
-//   - Persistent launch (the default): one kernel whose blocks take tiles
+//   - Persistent launch: one kernel whose blocks take tiles
 //     from a device queue; every instance moves through its own phases as
 //     soon as its previous phase's tiles are done, so short and long
 //     instances do not wait for each other.  Captured with the queue reset in
 //     one hipGraph.
-//   - Per-phase launches (for comparison): launch g runs the g-th phase of
-//     every instance that still has one; the sequence is captured in a
-//     hipGraph or issued eagerly.
+//   - Per-phase launches: launch g runs the g-th phase of every instance
+//     that still has one; the sequence is captured in a hipGraph or issued
+//     eagerly.
+// The autotuner times both (the persistent launch over its tile sizes, the
+// per-phase graph over its block caps) and VOPP_BATCH_AUTO then runs the
+// faster; before any autotuning it runs the persistent launch.
 // Instances share no state, so each result is the same as that of a plain
 // vopp_plan call with the same inputs, in every mode and for every tuning.
 #include <hip/hip_runtime.h>
@@ -55,6 +58,7 @@ struct vopp_batch {
   unsigned int* done_dev = nullptr;       // [n] then the finished counter
   int n_cu = 0;
   int persist_blocks = 0;
+  int auto_mode = VOPP_BATCH_PERSISTENT;  // what VOPP_BATCH_AUTO runs
   hipGraph_t pgraph = nullptr;
   hipGraphExec_t pexec = nullptr;
 };
@@ -395,8 +399,10 @@ extern "C" vopp_status vopp_batch_run(vopp_batch* b, void* stream, int32_t mode,
                                       vopp_result* results, double* device_ms) {
   clear_error();
   if (!b || !results) return fail(VOPP_E_INVALID, "null argument");
-  if (mode != VOPP_BATCH_EAGER && mode != VOPP_BATCH_GRAPH && mode != VOPP_BATCH_PERSISTENT)
+  if (mode != VOPP_BATCH_EAGER && mode != VOPP_BATCH_GRAPH && mode != VOPP_BATCH_PERSISTENT &&
+      mode != VOPP_BATCH_AUTO)
     return fail(VOPP_E_INVALID, "unknown batch mode %d", mode);
+  if (mode == VOPP_BATCH_AUTO) mode = b->auto_mode;
   hipError_t e = hipEventRecord(b->ev_in, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
   if (e == hipSuccess) e = hipEventRecord(b->ev0, b->stream);
@@ -434,22 +440,55 @@ extern "C" int32_t vopp_batch_num_launches(const vopp_batch* b) {
   return b ? (int32_t)b->launch_items.size() : 0;
 }
 
+extern "C" int32_t vopp_batch_auto_mode(const vopp_batch* b) {
+  return b ? (int32_t)b->auto_mode : -1;
+}
+
+// Times `mode` on the batch's present schedule: the best of reps runs after
+// one warm-up run.  Every run must reproduce ref (or sets it when have_ref is
+// false): a launch shape or mode never changes a result.
+static vopp_status time_mode(vopp_batch* b, void* stream, int32_t mode, int reps,
+                             std::vector<vopp_result>& ref, bool& have_ref, double* best_ms) {
+  std::vector<vopp_result> cur(b->n);
+  double ms_min = 1e30;
+  for (int r = 0; r < reps + 1; ++r) {
+    double ms = 0.0;
+    vopp_status st = vopp_batch_run(b, stream, mode, cur.data(), &ms);
+    if (st != VOPP_OK) return st;
+    if (r > 0) ms_min = std::min(ms_min, ms);
+  }
+  if (!have_ref) {
+    ref = cur;
+    have_ref = true;
+  } else {
+    for (int i = 0; i < b->n; ++i)
+      if (std::memcmp(&ref[i], &cur[i], sizeof(vopp_result)) != 0)
+        return fail(VOPP_E_INTERNAL,
+                    "tuning (%d, %d, %d, %d, %d) in mode %d changed the result of request %d",
+                    b->tuning.accum_cap, b->tuning.backup_cap, b->tuning.blocks_per_cu,
+                    b->tuning.forward_group, b->tuning.sweep_group, mode, i);
+  }
+  *best_ms = ms_min;
+  return VOPP_OK;
+}
+
 extern "C" vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t reps,
                                            vopp_tuning* chosen) {
   clear_error();
   if (!b) return fail(VOPP_E_INVALID, "null batch");
   if (reps < 1) reps = 1;
-  // Tile sizes of the persistent launch -- chunks of 256 record positions or
-  // trace items per sweep tile, blocks of 256 episodes per forward tile --
-  // and persistent blocks per CU.
+  std::vector<vopp_result> ref(b->n);
+  bool have_ref = false;
+  vopp_status st = VOPP_OK;
+  // 1. The persistent launch: tile sizes -- chunks of 256 belief positions or
+  //    trace items per sweep tile, blocks of 256 episodes per forward tile --
+  //    and persistent blocks per CU.  Its phases ignore the block caps.
   const int sweep_cands[] = {1, 2, 4, 8};
   const int fwd_cands[] = {1, 4};
   const int per_cu = persistent_blocks_per_cu(b->amax);
   std::vector<int> cu_cands{per_cu};
   if (per_cu > 1) cu_cands.push_back(1);
-  std::vector<vopp_result> ref(b->n), cur(b->n);
-  bool have_ref = false;
-  double best_ms = 1e30;
+  double best_persist = 1e30;
   vopp_tuning best = b->tuning;
   for (int sg : sweep_cands) {
     for (int fg : fwd_cands) {
@@ -457,36 +496,41 @@ extern "C" vopp_status vopp_batch_autotune(vopp_batch* b, void* stream, int32_t 
         b->tuning.sweep_group = sg;
         b->tuning.forward_group = fg;
         b->tuning.blocks_per_cu = bc;
-        vopp_status st = build_schedule(b);
+        st = build_schedule(b);
         if (st == VOPP_OK) st = capture(b);
+        double ms = 0.0;
+        if (st == VOPP_OK) st = time_mode(b, stream, VOPP_BATCH_PERSISTENT, reps, ref, have_ref, &ms);
         if (st != VOPP_OK) return st;
-        double ms_min = 1e30;
-        for (int r = 0; r < reps + 1; ++r) {
-          double ms = 0.0;
-          st = vopp_batch_run(b, stream, VOPP_BATCH_PERSISTENT, cur.data(), &ms);
-          if (st != VOPP_OK) return st;
-          if (r > 0) ms_min = std::min(ms_min, ms);      // the first run warms up
-        }
-        // The launch shape must not change any result.
-        if (!have_ref) {
-          ref = cur;
-          have_ref = true;
-        } else {
-          for (int i = 0; i < b->n; ++i)
-            if (std::memcmp(&ref[i], &cur[i], sizeof(vopp_result)) != 0)
-              return fail(VOPP_E_INTERNAL,
-                          "tuning (%d, %d, %d) changed the result of request %d", sg, fg,
-                          bc, i);
-        }
-        if (ms_min < best_ms) {
-          best_ms = ms_min;
+        if (ms < best_persist) {
+          best_persist = ms;
           best = b->tuning;
         }
       }
     }
   }
+  // 2. The per-phase graph: blocks per accumulate and backup sweep of an
+  //    instance (few blocks let more instances share a launch; many let a
+  //    large instance fill the GPU).
+  const int cap_cands[][2] = {{256, 256}, {kAccumCap, kBackupCap}};
+  double best_phase = 1e30;
+  for (const auto& cc : cap_cands) {
+    b->tuning = best;
+    b->tuning.accum_cap = cc[0];
+    b->tuning.backup_cap = cc[1];
+    st = build_schedule(b);
+    if (st == VOPP_OK) st = capture(b);
+    double ms = 0.0;
+    if (st == VOPP_OK) st = time_mode(b, stream, VOPP_BATCH_GRAPH, reps, ref, have_ref, &ms);
+    if (st != VOPP_OK) return st;
+    if (ms < best_phase) {
+      best_phase = ms;
+      best.accum_cap = cc[0];
+      best.backup_cap = cc[1];
+    }
+  }
   b->tuning = best;
-  vopp_status st = build_schedule(b);
+  b->auto_mode = best_phase < best_persist ? VOPP_BATCH_GRAPH : VOPP_BATCH_PERSISTENT;
+  st = build_schedule(b);
   if (st == VOPP_OK) st = capture(b);
   if (st != VOPP_OK) return st;
   if (chosen) *chosen = best;

@@ -29,6 +29,8 @@
 // per phase; the batched path launches k_batch, whose blocks each run one
 // phase of one instance of a batch (BatchItem), so one launch advances every
 // instance of the batch by one phase.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "vopp_device.hpp"
@@ -2094,62 +2096,82 @@ int accum_blocks(const PlanView& P, int D, int cap) {
   return (int)std::max(1ll, std::min(g, (long long)cap));
 }
 
+LaunchTiming& launch_timing() {
+  static thread_local LaunchTiming t;
+  return t;
+}
+
+// A plan kernel's launch, timed by its own dispatch when a profiling bracket
+// is open on this thread (launch_timing).
+template <typename... KArgs, typename... Args>
+static void plan_launch(void (*kernel)(KArgs...), dim3 g, dim3 b, uint32_t shm, hipStream_t s,
+                        Args... args) {
+  LaunchTiming& t = launch_timing();
+  if (t.stop) {
+    hipExtLaunchKernelGGL(kernel, g, b, shm, s, t.start, t.stop, 0u, args...);
+    t.start = nullptr;
+    t.used = true;
+  } else {
+    hipLaunchKernelGGL(kernel, g, b, shm, s, args...);
+  }
+}
+
 hipError_t launch_setup(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, P);
+  plan_launch(k_setup, dim3(setup_blocks(P)), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_forward(const PlanView& P, int k, int D, hipStream_t s) {
   const dim3 g(forward_blocks(P)), b(kBlock);
   const int Ap = P.m.Apad;
-  if (Ap <= 4) hipLaunchKernelGGL(k_forward<4>, g, b, 0, s, P, k, D);
-  else if (Ap <= 8) hipLaunchKernelGGL(k_forward<8>, g, b, 0, s, P, k, D);
-  else if (Ap <= 16) hipLaunchKernelGGL(k_forward<16>, g, b, 0, s, P, k, D);
-  else if (Ap <= 32) hipLaunchKernelGGL(k_forward<32>, g, b, 0, s, P, k, D);
-  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_forward<64>, g, b, 0, s, P, k, D);
+  if (Ap <= 4) plan_launch(k_forward<4>, g, b, 0, s, P, k, D);
+  else if (Ap <= 8) plan_launch(k_forward<8>, g, b, 0, s, P, k, D);
+  else if (Ap <= 16) plan_launch(k_forward<16>, g, b, 0, s, P, k, D);
+  else if (Ap <= 32) plan_launch(k_forward<32>, g, b, 0, s, P, k, D);
+  else if (Ap <= kMaxA) plan_launch(k_forward<64>, g, b, 0, s, P, k, D);
   else
-    hipLaunchKernelGGL(k_forward_wide, dim3((P.n_p + kBlock / kHalf - 1) / (kBlock / kHalf)), b, 0, s,
-                       P, k, D);
+    plan_launch(k_forward_wide, dim3((P.n_p + kBlock / kHalf - 1) / (kBlock / kHalf)), b, 0, s,
+                P, k, D);
   return hipGetLastError();
 }
 hipError_t launch_accum(const PlanView& P, int D, int grid, hipStream_t s) {
   if (P.t.ra > kMaxA) {
-    hipLaunchKernelGGL(k_claim_wide, dim3(blocks_for(std::min((long long)D * P.n_p, 1ll << 24))),
-                       dim3(kBlock), 0, s, P, D);
+    plan_launch(k_claim_wide, dim3(blocks_for(std::min((long long)D * P.n_p, 1ll << 24))),
+                dim3(kBlock), 0, s, P, D);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D);
+  plan_launch(k_accum, dim3(grid), dim3(kBlock), 0, s, P, D);
   return hipGetLastError();
 }
 hipError_t launch_backup_leaf(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_backup_leaf, dim3(grid), dim3(kBlock), 0, s, P, dep, k);
+  plan_launch(k_backup_leaf, dim3(grid), dim3(kBlock), 0, s, P, dep, k);
   return hipGetLastError();
 }
 hipError_t launch_backup_level(const PlanView& P, int dep, int k, int grid, hipStream_t s) {
   const dim3 g(grid), b(kBlock);
   const int Ap = P.m.Apad;
-  if (Ap <= 4) hipLaunchKernelGGL(k_backup_level<4>, g, b, 0, s, P, dep, k);
-  else if (Ap <= 8) hipLaunchKernelGGL(k_backup_level<8>, g, b, 0, s, P, dep, k);
-  else if (Ap <= 16) hipLaunchKernelGGL(k_backup_level<16>, g, b, 0, s, P, dep, k);
-  else if (Ap <= 32) hipLaunchKernelGGL(k_backup_level<32>, g, b, 0, s, P, dep, k);
-  else if (Ap <= kMaxA) hipLaunchKernelGGL(k_backup_level<64>, g, b, 0, s, P, dep, k);
+  if (Ap <= 4) plan_launch(k_backup_level<4>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 8) plan_launch(k_backup_level<8>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 16) plan_launch(k_backup_level<16>, g, b, 0, s, P, dep, k);
+  else if (Ap <= 32) plan_launch(k_backup_level<32>, g, b, 0, s, P, dep, k);
+  else if (Ap <= kMaxA) plan_launch(k_backup_level<64>, g, b, 0, s, P, dep, k);
   else {
     // Quads of the row per lane: rows of up to 1024, 2048, 3072, 4096 actions.
     const int qpl = (Ap / 4 + 63) / 64;
-    if (qpl <= 4) hipLaunchKernelGGL(k_backup_level_wide<4>, g, b, 0, s, P, dep, k);
-    else if (qpl <= 8) hipLaunchKernelGGL(k_backup_level_wide<8>, g, b, 0, s, P, dep, k);
-    else if (qpl <= 12) hipLaunchKernelGGL(k_backup_level_wide<12>, g, b, 0, s, P, dep, k);
-    else hipLaunchKernelGGL(k_backup_level_wide<16>, g, b, 0, s, P, dep, k);
+    if (qpl <= 4) plan_launch(k_backup_level_wide<4>, g, b, 0, s, P, dep, k);
+    else if (qpl <= 8) plan_launch(k_backup_level_wide<8>, g, b, 0, s, P, dep, k);
+    else if (qpl <= 12) plan_launch(k_backup_level_wide<12>, g, b, 0, s, P, dep, k);
+    else plan_launch(k_backup_level_wide<16>, g, b, 0, s, P, dep, k);
   }
   return hipGetLastError();
 }
 hipError_t launch_backup_root(const PlanView& P, int k, hipStream_t s) {
-  if (P.m.Apad > kMaxA) hipLaunchKernelGGL(k_backup_root_wide, dim3(1), dim3(kBlock), 0, s, P, k);
-  else hipLaunchKernelGGL(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
+  if (P.m.Apad > kMaxA) plan_launch(k_backup_root_wide, dim3(1), dim3(kBlock), 0, s, P, k);
+  else plan_launch(k_backup_root, dim3(1), dim3(64), 0, s, P, k);
   return hipGetLastError();
 }
 hipError_t launch_select(const PlanView& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, P);
+  plan_launch(k_select, dim3(1), dim3(64), 0, s, P);
   return hipGetLastError();
 }
 hipError_t launch_env(const PlanView& P, int t, hipStream_t s) {

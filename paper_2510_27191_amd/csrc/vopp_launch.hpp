@@ -6,6 +6,20 @@
 
 namespace vopp {
 
+// Events that the calling thread's next plan-kernel launches (launch_setup
+// ... launch_select) take as the start and end timestamps of their own
+// dispatch (hipExtLaunchKernel), rather than stream markers around it.  The
+// first launch takes `start`, every launch takes `stop`, so a bracket over
+// two launches spans both.  `used` says whether any launch took them.  Only
+// the plan's per-kernel profiling sets them, between its bracket's begin and
+// end.
+struct LaunchTiming {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  bool used = false;
+};
+LaunchTiming& launch_timing();
+
 int setup_blocks(const PlanView& P);
 int forward_blocks(const PlanView& P);
 // Blocks of a sweep over the trace of an iteration with D levels (at most cap).

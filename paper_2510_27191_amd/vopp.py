@@ -34,7 +34,7 @@ EXPORTS = (
     "vopp_tree_dump", "vopp_level_counts", "vopp_profile_enable", "vopp_profile_reset",
     "vopp_profile_read", "vopp_batch_create", "vopp_batch_footprint",
     "vopp_batch_set_request", "vopp_batch_run", "vopp_batch_autotune",
-    "vopp_batch_num_launches", "vopp_batch_free", "vopp_plan_batch",
+    "vopp_batch_num_launches", "vopp_batch_auto_mode", "vopp_batch_free", "vopp_plan_batch",
     "vopp_env_step", "vopp_belief_update", "vopp_server_create",
     "vopp_server_submit", "vopp_server_tick", "vopp_server_poll",
     "vopp_server_episode_state", "vopp_server_free",
@@ -100,7 +100,7 @@ class vopp_tuning(C.Structure):
                 ("sweep_group", C.c_int32)]
 
 
-BATCH_EAGER, BATCH_GRAPH, BATCH_PERSISTENT = 0, 1, 2
+BATCH_EAGER, BATCH_GRAPH, BATCH_PERSISTENT, BATCH_AUTO = 0, 1, 2, 3
 
 
 class vopp_server_config(C.Structure):
@@ -192,6 +192,8 @@ def lib():
     L.vopp_batch_autotune.restype = st
     L.vopp_batch_num_launches.argtypes = [vp]
     L.vopp_batch_num_launches.restype = i32
+    L.vopp_batch_auto_mode.argtypes = [vp]
+    L.vopp_batch_auto_mode.restype = i32
     L.vopp_batch_free.argtypes = [vp]
     L.vopp_batch_free.restype = None
     L.vopp_plan_batch.argtypes = [vp, i32, vp, vp]
@@ -542,6 +544,11 @@ class Batch:
     def num_launches(self):
         return int(lib().vopp_batch_num_launches(self.handle))
 
+    @property
+    def auto_mode(self):
+        """The mode BATCH_AUTO runs (BATCH_GRAPH or BATCH_PERSISTENT)."""
+        return int(lib().vopp_batch_auto_mode(self.handle))
+
     def set_request(self, i, belief_dev, n_belief, seed, step=0):
         _check(lib().vopp_batch_set_request(self.handle, int(i),
                                             C.c_void_p(belief_dev.data_ptr()),
@@ -549,13 +556,14 @@ class Batch:
                                             int(step) & 0xFFFFFFFF))
 
     def run(self, use_graph=True, stream=None, mode=None):
-        """mode: BATCH_PERSISTENT (default), BATCH_GRAPH or BATCH_EAGER; the
-        older use_graph=False means BATCH_EAGER."""
+        """mode: BATCH_AUTO (default: the faster mode of the last autotune,
+        else the persistent launch), BATCH_PERSISTENT, BATCH_GRAPH or
+        BATCH_EAGER; the older use_graph=False means BATCH_EAGER."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
         if mode is None:
-            mode = BATCH_PERSISTENT if use_graph else BATCH_EAGER
+            mode = BATCH_AUTO if use_graph else BATCH_EAGER
         arr = (vopp_result * len(self.items))()
         ms = np.zeros(1, np.float64)
         _check(lib().vopp_batch_run(self.handle, C.c_void_p(stream.cuda_stream),

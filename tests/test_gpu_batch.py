@@ -176,11 +176,16 @@ def test_autotune_keeps_results(V):
     items, keep = build(V, small_mix(4, 8))
     ref = plain(V, items)
     batch = V.Batch(items)
+    assert batch.auto_mode == V.BATCH_PERSISTENT
     chosen = batch.autotune(reps=1)
     assert chosen[2] >= 0 and chosen[3] in (1, 4) and chosen[4] in (1, 2, 4, 8)
-    res, _ = batch.run()
-    for a, b in zip(res, ref):
-        same(a, b)
+    # Block caps of the per-phase graph: 256 each, or the plain plan's.
+    assert (chosen[0], chosen[1]) in ((256, 256), (4096, 2048))
+    assert batch.auto_mode in (V.BATCH_GRAPH, V.BATCH_PERSISTENT)
+    for mode in (V.BATCH_AUTO, V.BATCH_GRAPH, V.BATCH_PERSISTENT):
+        res, _ = batch.run(mode=mode)
+        for a, b in zip(res, ref):
+            same(a, b)
     batch.close()
 
 
