@@ -615,6 +615,28 @@ __device__ __forceinline__ int draw_cdf64(const double* __restrict__ cdf, int A,
   return A - 1;
 }
 
+// draw_cdf64 over running sums held in registers (AM >= A of them): the
+// same comparisons in the same order.
+template <int AM>
+__device__ __forceinline__ int draw_cdf64_regs(const double (&cdf)[AM], int A, uint32_t x0) {
+  double last = cdf[0];
+#pragma unroll
+  for (int j = 1; j < AM; ++j)
+    if (j == A - 1) last = cdf[j];
+  const double u = (double)(x0 >> 8) * (1.0 / 16777216.0);
+  const double t = u * last;
+  int a = A - 1;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < AM; ++j) {
+    if (!found && j < A && t < cdf[j]) {
+      a = j;
+      found = true;
+    }
+  }
+  return a;
+}
+
 // Whether the draw of action a from running sums cdf lies within kTieRel *
 // P_last of one of its interior boundaries (cdf[a - 1] below, cdf[a] above).
 // flat: the row's entries are all equal (then the draw is exact).

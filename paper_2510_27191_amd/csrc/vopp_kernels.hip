@@ -113,6 +113,62 @@ __device__ __forceinline__ uint32_t probe(const TreeView& t, unsigned long long 
   return ~0u;
 }
 
+// The first line of a key's probe sequence (its 8 slots, one batch of
+// loads) and the key's slot order in it.
+struct Bucket {
+  uint4 v[8];
+  uint32_t base, rot;
+};
+__device__ __forceinline__ void bucket_read(const TreeView& t, unsigned long long key,
+                                            Bucket& b) {
+  const unsigned long long hk = mix64(key);
+  b.base = (uint32_t)hk & t.h_mask & ~7u;
+  b.rot = (uint32_t)(hk >> 40) & 7u;
+  const uint4* ln = reinterpret_cast<const uint4*>(&t.h_slot[b.base]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b.v[j] = ln[j];
+}
+
+// probe() split for the forward search, on the first line already read:
+//   1: the key is there (won false; fresh and id as probe() sets them);
+//   2: an empty slot comes first in the key's order; the insert's
+//      compare-and-swap is issued and its old value returned in `seen`,
+//      not waited for (the caller settles it later with settle_insert);
+//   0: the line is full (the caller falls back to probe()).
+__device__ __forceinline__ int probe_line(const TreeView& t, const Bucket& b,
+                                          unsigned long long key, unsigned long long stamp,
+                                          uint32_t& slot, bool& fresh, int& id,
+                                          unsigned long long& seen) {
+  uint32_t best = 8;
+  int at = -1;
+  bool empty = false;
+  unsigned long long cur_at = kEmptyKey;
+  int rid = -1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned long long cur = ((unsigned long long)b.v[j].y << 32) | b.v[j].x;
+    const uint32_t pos = ((uint32_t)j - b.rot) & 7u;
+    if ((cur == kEmptyKey || (cur & ~kStampMask) == key) && pos < best) {
+      best = pos;
+      at = j;
+      empty = cur == kEmptyKey;
+      cur_at = cur;
+      rid = (int)b.v[j].z;
+    }
+  }
+  if (at < 0) return 0;
+  slot = b.base + (uint32_t)at;
+  if (empty) {
+    seen = atomicCAS(&t.h_slot[slot].key, kEmptyKey, key | stamp);
+    fresh = true;
+    id = -1;
+    return 2;
+  }
+  fresh = (cur_at & kStampMask) == stamp;
+  id = fresh ? -1 : rid;
+  return 1;
+}
+
 // Key of belief (parent slot id b, action a, observation obs); the
 // observation takes the low ob bits, the action the next 26 - ob.
 __device__ __forceinline__ unsigned long long belief_key(int b, int a, int obs, int ob) {
@@ -403,16 +459,61 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
 #pragma unroll
   for (int i = 0; i < 2 * kDiskRegs; ++i) dc.c[i] = 0.0f;
   if (nav) dc = load_disks(P.m);
+  // The running sums of the initial row in registers for short rows, so that
+  // a draw at a belief created in this iteration issues no memory access.
+  constexpr int kCdfRegs = AM <= 8 ? AM : 1;
+  double cdf0[kCdfRegs];
+#pragma unroll
+  for (int j = 0; j < kCdfRegs; ++j) cdf0[j] = (AM <= 8 && j < A) ? T.psi0_cdf64[j] : 0.0;
   unsigned long long g = 0;   // generative-model calls of this episode
   unsigned long long nt = 0;  // its near-tie draws
+  // An insert whose compare-and-swap is still in flight: the episode goes on
+  // as if it had won the slot (a belief created in this iteration, Psi
+  // initial, whichever episode inserted it) and settles it at the next level
+  // or after the last one.  Only if another key took the slot does the next
+  // level's key change; it is then formed again.  The insert's writes (list
+  // entry, slot's record index, the new record) wait for the settlement.
+  bool pend = false;
+  uint32_t pend_slot = 0;
+  unsigned long long pend_key = 0, pend_seen = 0, pend_link = 0;
+  int pend_t = 0, pend_obs = 0;
+  // Settles the pending insert: sets sid and rid of the belief the episode
+  // stands on; returns false if the table is full.
+  auto settle = [&]() -> bool {
+    pend = false;
+    bool won = pend_seen == kEmptyKey;
+    int rid_new = -1;
+    uint32_t slot = pend_slot;
+    if (!won && (pend_seen & ~kStampMask) != pend_key) {
+      // Another key took the slot: find or insert the key again (a belief of
+      // this iteration either way, so the draws made on it stand).
+      bool fr;
+      int id;
+      slot = probe(T, pend_key, stamp, won, fr, id);
+      if (slot == ~0u) {
+        atomicOr((unsigned int*)&T.counters[1], 2u);
+        if (ep_ok) T.list[(size_t)pend_t * n_p + ep] = 0;
+        return false;
+      }
+    }
+    if (won) rid_new = 1 + pend_t * P.n_p + ep;   // the inserter's own record
+    sid = (int)slot + 1;
+    rid = rid_new;
+    fresh = true;
+    T.list[(size_t)pend_t * n_p + ep] = won ? sid : 0;
+    if (won) {
+      T.h_slot[slot].id = rid_new;
+      init_record(P, psi0s, rid_new, pend_obs, pend_link);
+    }
+    return true;
+  };
   for (int d = 0; d < D; ++d) {
     unsigned long long tk = kEmptyKey;
     float r = 0.0f;
-    bool won = false, direct = false;
+    bool direct = false, insert_now = false, won_now = false;
     int obs = 0, a = 0;
     uint32_t h = 0;
     unsigned long long link = kEmptyKey;
-    const int rid_b = rid;
     const bool drew = alive;
     int own = 0;                // the kernel's own decision (before a forced draw)
     if (alive) {
@@ -423,7 +524,8 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
         a = draw_cdf64(T.root_cdf, A, w.x);
         tie = (k > 1 || P.carry) && near_tie64(T.root_cdf, A, w.x, a);
       } else if (fresh) {
-        a = draw_cdf64(T.psi0_cdf64, A, w.x);
+        if constexpr (AM <= 8) a = draw_cdf64_regs<AM>(cdf0, A, w.x);
+        else a = draw_cdf64(T.psi0_cdf64, A, w.x);
       } else {
         a = draw_row32<AM>(row, A, P.eta, w.x, tie);
       }
@@ -445,49 +547,85 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
         y = ny;
       }
       ++g;
+      // The next level's noise, issued before this level's insert.
+      const U4 wn = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
+      if (nav && !term && d + 1 < D) z = nav_noise(P.m, wn);
+      // AppendBeliefs, first line: read with the previous insert in flight.
+      Bucket bk;
+      unsigned long long key = 0;
+      if (!term) {
+        key = belief_key(sid, a, obs, P.m.obs_bits);
+        bucket_read(T, key, bk);
+      }
+      bool full = false;
+      if (pend) {
+        const uint32_t sid_guess = (uint32_t)sid;
+        if (!settle()) {
+          full = true;                          // the table is full: stop
+        } else if (!term && (uint32_t)sid != sid_guess) {
+          key = belief_key(sid, a, obs, P.m.obs_bits);
+          bucket_read(T, key, bk);
+        }
+      }
       // AppendActions: visit count and reward sum of (b, a), counted below
       // when b's record is known, else left to the accumulate pass.
-      direct = d >= kDirectLevel && rid >= 0;
-      if (!direct)
+      direct = !full && d >= kDirectLevel && rid >= 0;
+      if (!direct && !full)
         tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
                       : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
       link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
                       : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
-      if (term) {
+      const int rid_b = rid;
+      if (term || full) {
         alive = false;                          // FilterTerminals
       } else {
         // AppendBeliefs: find or insert (b, a, o).
-        const unsigned long long key = belief_key(sid, a, obs, P.m.obs_bits);
-        bool fr;
-        int id;
-        h = probe(T, key, stamp, won, fr, id);
-        if (h == ~0u) {                         // table full: stop and report
-          atomicOr((unsigned int*)&T.counters[1], 2u);
-          alive = false;
-        } else {
+        bool fr = false;
+        int id = -1;
+        unsigned long long seen = 0;
+        const int got = probe_line(T, bk, key, stamp, h, fr, id, seen);
+        if (got == 2) {
+          pend = true;
+          pend_slot = h;
+          pend_key = key;
+          pend_seen = seen;
+          pend_link = link;
+          pend_t = t0 + d;
+          pend_obs = obs;
           sid = (int)h + 1;
-          fresh = fr;
-          rid = won ? 1 + (t0 + d) * P.n_p + ep : id;   // the inserter's own record
+          fresh = true;
+          rid = -1;
+        } else {
+          bool won = false;
+          if (got == 0) h = probe(T, key, stamp, won, fr, id);   // the line is full
+          if (h == ~0u) {                       // table full: stop and report
+            atomicOr((unsigned int*)&T.counters[1], 2u);
+            alive = false;
+          } else {
+            sid = (int)h + 1;
+            fresh = fr;
+            rid = won ? 1 + (t0 + d) * P.n_p + ep : id;   // the inserter's own record
+            won_now = won;
+          }
         }
+        insert_now = pend;
       }
-    }
-    if (alive && d + 1 < D) {
-      w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
-      if (!fresh) load_row<AM>(rec_psi(T, rid), A, row);
-      if (nav) z = nav_noise(P.m, w);
-    }
-    // Writes of level d.
-    if (direct) {
-      atomicAdd(&rec_n(T, rid_b)[a], 1);
-      const unsigned long long fx = to_fix(r, P.fix_scale);
-      if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
+      // The next level's row (an existing belief's; a new one's is Psi0).
+      w = wn;
+      if (alive && d + 1 < D && !fresh) load_row<AM>(rec_psi(T, rid), A, row);
+      // Writes of level d.
+      if (direct) {
+        atomicAdd(&rec_n(T, rid_b)[a], 1);
+        const unsigned long long fx = to_fix(r, P.fix_scale);
+        if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
+      }
     }
     if (ep_ok) {
       const int t = t0 + d;
       T.tr_key[(size_t)d * n_p + ep] = tk;
       T.tr_val[(size_t)d * n_p + ep] = r;
-      T.list[(size_t)t * n_p + ep] = won ? sid : 0;
-      if (won) {
+      if (!insert_now) T.list[(size_t)t * n_p + ep] = won_now ? sid : 0;
+      if (won_now) {
         T.h_slot[h].id = rid;
         init_record(P, psi0s, rid, obs, link);
       }
@@ -498,6 +636,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
       }
     }
   }
+  if (pend && !settle()) alive = false;
   if (ep_ok) {
     unsigned long long tk = kEmptyKey;
     float hv = 0.0f;                            // ValueHeuristic of the leaf state
