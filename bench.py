@@ -92,12 +92,12 @@ def leaf_sweep_visits(n_p, K, depth, counts):
 # these kernels.  Valid only for the kernel sources they were taken on (hash
 # below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "d6d45a94f01650e6",
-    "backup_level": {"nav2d": 3.907e+07, "sparse4096": 1.293e+08},
-    "forward": {"nav2d": 1.304e+08, "sparse4096": 6.915e+08},
+    "sources_sha256_16": "0c5f691ec843ce23",
+    "backup_level": {"nav2d": 3.91e+07, "sparse4096": 1.294e+08},
+    "forward": {"nav2d": 1.309e+08, "sparse4096": 6.831e+08},
     "gather_scale": {
-        "backup_level": {"nav2d": 2.688e+07, "sparse4096": 8.173e+07},
-        "forward": {"nav2d": 1.068e+08, "sparse4096": 4.935e+08},
+        "backup_level": {"nav2d": 2.69e+07, "sparse4096": 8.178e+07},
+        "forward": {"nav2d": 1.072e+08, "sparse4096": 4.899e+08},
     },
 }
 

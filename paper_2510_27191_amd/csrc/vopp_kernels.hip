@@ -666,6 +666,187 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
   if (threadIdx.x == 0 && (g >> 32)) atomicAdd(&T.stats[kStatNear * kStripes + blk % kStripes], g >> 32);
 }
 
+// The forward search of the batched kernels: the same decisions, draws and
+// writes as dev_forward, with each insert settled before the next level.  A
+// batched kernel holds the registers of its largest phase, and carrying an
+// unsettled insert across levels (dev_forward) would cost it half its
+// wavefronts per SIMD.
+template <int AM>
+__device__ void dev_forward_inorder(const PlanView& P, int k, int D, int blk,
+                                    unsigned long long* red, float* psi0s) {
+  const TreeView& T = P.t;
+  // The initial row in LDS, copied into new records (every thread of the
+  // block calls).
+  for (int i = threadIdx.x; i < T.ra; i += kBlock) psi0s[i] = T.psi0[i];
+  __syncthreads();
+  const int t0 = T.step_base[k - 1];          // level step of level 0
+  const int ep = blk * kBlock + threadIdx.x;
+  const bool ep_ok = ep < P.n_p;
+  const int A = P.m.nA;
+  const bool nav = P.m.kind != kTabular;
+  const size_t n_p = (size_t)P.n_p;
+  const unsigned long long stamp = (unsigned long long)(k - 1) << kStampShift;
+  int s = 0;
+  float x = 0.0f, y = 0.0f;
+  int sid = 0;                // current belief's slot id (0: root)
+  int rid = 0;                // its record, -1 if another episode inserted it
+                              // during this iteration
+  bool fresh = false;         // inserted during this iteration (Psi initial)
+  bool alive = false;
+  if (ep_ok) {
+    // Alg. 1: the episode starts at the root with a state drawn from the
+    // belief particles.
+    const U4 w = draw(P, (uint32_t)ep, kTagRoot, 0, (uint32_t)k);
+    const uint32_t idx = __umulhi(w.x, (uint32_t)P.e.n_belief);
+    if (!nav) {
+      s = ((const int*)P.e.belief)[idx];
+      if ((unsigned)s >= (unsigned)P.m.nS) {   // caller's particle out of range
+        atomicOr((unsigned int*)&T.counters[1], 1u);
+        s = 0;
+      }
+    } else {
+      const float* bf = (const float*)P.e.belief;
+      x = bf[idx];
+      y = bf[P.e.n_belief + idx];
+    }
+    alive = true;
+  }
+  // Inputs of the next level, read ahead of the previous level's writes: a
+  // wait for a load also waits for every memory operation issued before it.
+  U4 w = draw(P, (uint32_t)ep, kTagStep, 0u, (uint32_t)k);
+  float row[AM];
+#pragma unroll
+  for (int j = 0; j < AM; ++j) row[j] = 0.0f;
+  NavNoise z{0.0f, 0.0f, 0.0f, 0.0f};
+  if (alive && nav) z = nav_noise(P.m, w);
+  DiskCache dc;
+#pragma unroll
+  for (int i = 0; i < 2 * kDiskRegs; ++i) dc.c[i] = 0.0f;
+  if (nav) dc = load_disks(P.m);
+  unsigned long long g = 0;   // generative-model calls of this episode
+  unsigned long long nt = 0;  // its near-tie draws
+  for (int d = 0; d < D; ++d) {
+    unsigned long long tk = kEmptyKey;
+    float r = 0.0f;
+    bool won = false, direct = false;
+    int obs = 0, a = 0;
+    uint32_t h = 0;
+    unsigned long long link = kEmptyKey;
+    const int rid_b = rid;
+    const bool drew = alive;
+    int own = 0;                // the kernel's own decision (before a forced draw)
+    if (alive) {
+      // Eq. (6): the root's running sums (double precision), those of the
+      // initial row for a belief created in this iteration, else the row.
+      bool tie = false;
+      if (sid == 0) {
+        a = draw_cdf64(T.root_cdf, A, w.x);
+        tie = (k > 1 || P.carry) && near_tie64(T.root_cdf, A, w.x, a);
+      } else if (fresh) {
+        a = draw_cdf64(T.psi0_cdf64, A, w.x);
+      } else {
+        a = draw_row32<AM>(row, A, P.eta, w.x, tie);
+      }
+      nt += tie ? 1u : 0u;
+      own = a;
+      if (T.dbg_force) {
+        const short f = T.dbg_force[(size_t)(t0 + d - T.dbg_step0) * n_p + ep];
+        if (f >= 0 && f < A) a = f;
+      }
+      bool term = false;
+      if (!nav) {
+        int sn;
+        tabular_step(P.m, s, a, w, sn, obs, r);
+        s = sn;
+      } else {
+        float nx, ny;
+        nav_step_z(P.m, dc, x, y, a, z, nx, ny, obs, r, term);
+        x = nx;
+        y = ny;
+      }
+      ++g;
+      // AppendActions: visit count and reward sum of (b, a), counted below
+      // when b's record is known, else left to the accumulate pass.
+      direct = d >= kDirectLevel && rid >= 0;
+      if (!direct)
+        tk = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a | kTraceRec)
+                      : (((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      link = rid >= 0 ? (((unsigned long long)(uint32_t)rid << kActBits) | (uint32_t)a)
+                      : (kLinkSlot | ((unsigned long long)(uint32_t)sid << kActBits) | (uint32_t)a);
+      if (term) {
+        alive = false;                          // FilterTerminals
+      } else {
+        // AppendBeliefs: find or insert (b, a, o).
+        const unsigned long long key = belief_key(sid, a, obs, P.m.obs_bits);
+        bool fr;
+        int id;
+        h = probe(T, key, stamp, won, fr, id);
+        if (h == ~0u) {                         // table full: stop and report
+          atomicOr((unsigned int*)&T.counters[1], 2u);
+          alive = false;
+        } else {
+          sid = (int)h + 1;
+          fresh = fr;
+          rid = won ? 1 + (t0 + d) * P.n_p + ep : id;   // the inserter's own record
+        }
+      }
+    }
+    if (alive && d + 1 < D) {
+      w = draw(P, (uint32_t)ep, kTagStep, (uint32_t)(d + 1), (uint32_t)k);
+      if (!fresh) load_row<AM>(rec_psi(T, rid), A, row);
+      if (nav) z = nav_noise(P.m, w);
+    }
+    // Writes of level d.
+    if (direct) {
+      atomicAdd(&rec_n(T, rid_b)[a], 1);
+      const unsigned long long fx = to_fix(r, P.fix_scale);
+      if (fx) atomicAdd(&rec_c(T, rid_b)[a], fx);
+    }
+    if (ep_ok) {
+      const int t = t0 + d;
+      T.tr_key[(size_t)d * n_p + ep] = tk;
+      T.tr_val[(size_t)d * n_p + ep] = r;
+      T.list[(size_t)t * n_p + ep] = won ? sid : 0;
+      if (won) {
+        T.h_slot[h].id = rid;
+        init_record(P, psi0s, rid, obs, link);
+      }
+      if (T.dbg_act) {
+        const size_t i = (size_t)(t - T.dbg_step0) * n_p + ep;
+        T.dbg_act[i] = drew ? (short)own : (short)-1;
+        T.dbg_obs[i] = drew ? obs : -1;
+      }
+    }
+  }
+  if (ep_ok) {
+    unsigned long long tk = kEmptyKey;
+    float hv = 0.0f;                            // ValueHeuristic of the leaf state
+    if (alive) {
+      if (!nav) {
+        if (P.m.H) hv = P.m.H[s];
+      } else {
+        hv = nav_heuristic(P.m.nav, x, y);
+      }
+      if (D >= kDirectLevel && rid >= 0) {
+        BeliefLeaf* lf = rec_leaf(T, rid);
+        atomicAdd(&lf->leaf_cnt, 1);
+        const unsigned long long fx = to_fix(hv, P.fix_scale);
+        if (fx) atomicAdd(&lf->leaf_h, fx);
+      } else {
+        tk = rid >= 0 ? ((unsigned long long)(uint32_t)rid | kTraceRec)
+                      : (unsigned long long)(uint32_t)sid;
+      }
+    }
+    T.tr_key[(size_t)D * n_p + ep] = tk;
+    T.tr_val[(size_t)D * n_p + ep] = hv;
+  }
+  // Both counts in one word: a block makes fewer than 2^32 of each.
+  g = block_sum(g | (nt << 32), red);
+  if (threadIdx.x == 0 && (g & 0xffffffffull))
+    atomicAdd(&T.stats[blk % kStripes], g & 0xffffffffull);
+  if (threadIdx.x == 0 && (g >> 32)) atomicAdd(&T.stats[kStatNear * kStripes + blk % kStripes], g >> 32);
+}
+
 // ---------------------------------------------------------------------------
 // Phase: fold the trace of an iteration with D levels into the records.
 // Aggregation keys: (record << (kActBits + 1)) | (a << 1) for action nodes,
@@ -2061,10 +2242,10 @@ __device__ __forceinline__ void run_item(const PlanView& P, const BatchItem& it,
     case kPhaseSetup: dev_setup(P, blk, it.nblk, nullptr); break;   // |A| <= 16
     case kPhaseForward:
       if (Apad <= 4) {
-        dev_forward<4>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
+        dev_forward_inorder<4>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
       } else if constexpr (AMAX >= 8) {
-        if (Apad <= 8) dev_forward<8>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
-        else if constexpr (AMAX >= 16) dev_forward<16>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
+        if (Apad <= 8) dev_forward_inorder<8>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
+        else if constexpr (AMAX >= 16) dev_forward_inorder<16>(P, it.a0, it.a1, blk, sm.wave, sm.psi0);
       }
       break;
     case kPhaseAccum: dev_accum(P, it.a0, blk, it.nblk, sm); break;
