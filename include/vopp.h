@@ -148,8 +148,8 @@ typedef struct {
 /* near_ties: action draws (Eq. 6) whose position t = u * P_last lies within
  * 2^-16 * P_last of a neighbouring boundary P_j of the running sums, in the
  * kernel's own arithmetic.  It counts draws from rows that a backup has
- * updated (the root from the second iteration on, rows read from a record
- * whose entries are not all equal); draws from the initial row are exact and
+ * updated (the root from the second iteration on, rows of a belief whose
+ * entries are not all equal); draws from the initial row are exact and
  * do not count.  A planner that keeps its preferences in another precision
  * may decide such a draw the other way. */
 typedef struct {
@@ -165,6 +165,10 @@ typedef struct {
   int64_t sweep_visits;
   int64_t sweep_internal;
   int64_t sweep_nodes;
+  /* Inserts of new beliefs in the forward search whose slot another key
+   * took first, so that the episode probed for its key again (its next
+   * level's key formed again).  A count of insert races, not an error. */
+  int64_t insert_reprobes;
 } vopp_stats;
 
 /* A workspace holds one plan's tree and per-episode trace in HBM, sized for

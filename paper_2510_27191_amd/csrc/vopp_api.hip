@@ -836,6 +836,7 @@ static vopp_status plan_common(const vopp_pomdp* p, const void* belief, int32_t 
     stats->sweep_visits = (int64_t)o[A + 7];
     stats->sweep_internal = (int64_t)o[A + 8];
     stats->sweep_nodes = (int64_t)o[A + 9];
+    stats->insert_reprobes = (int64_t)o[A + 10];
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
     stats->device_ms = ms;

@@ -260,7 +260,7 @@ struct PlanView {
   double fix_inv64;
   int K, depth, schedule;
   int steps;               // level steps of the plan (sum of D_k)
-  double* out;             // max(kOutStride, ra + 8) doubles: the plan's result
+  double* out;             // max(kOutStride, ra + 12) doubles: the plan's result
   // Time budget (anytime plan): 0 = run all K iterations.  Otherwise the
   // iterations after the first run only while fewer than budget_ticks
   // wall-clock ticks have passed since set-up; K is then the cap.

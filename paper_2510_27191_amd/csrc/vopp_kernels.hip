@@ -372,6 +372,7 @@ __device__ void dev_setup(const PlanView& P, int blk, int nblk, SetupSmem* ss) {
       rec_hot(T, 0)->parent = kEmptyKey;
       T.v_root[0] = P.carry ? (double)rec_hot(T, 0)->V : 0.0;
       T.counters[1] = 0ull;
+      T.counters[4] = 0ull;
     }
   }
 }
@@ -487,6 +488,7 @@ __device__ void dev_forward(const PlanView& P, int k, int D, int blk,
     if (!won && (pend_seen & ~kStampMask) != pend_key) {
       // Another key took the slot: find or insert the key again (a belief of
       // this iteration either way, so the draws made on it stand).
+      atomicAdd(&T.counters[4], 1ull);
       bool fr;
       int id;
       slot = probe(T, pend_key, stamp, won, fr, id);
@@ -1706,6 +1708,8 @@ __device__ void dev_select(const PlanView& P) {
   out[A + 7] = (double)sw_v;
   out[A + 8] = (double)sw_i;
   out[A + 9] = (double)sw_n;
+  // The allocation-free entry point's result holds |A| + 10 values.
+  if (!P.clear_all) out[A + 10] = (double)T.counters[4];
   T.counters[2] = nb;
   T.counters[3] = 0ull;
   T.counters[5] = (unsigned long long)(P.timed ? T.step_base[k_last] : P.steps);

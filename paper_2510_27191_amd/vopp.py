@@ -79,7 +79,8 @@ class vopp_stats(C.Structure):
     _fields_ = [("particle_steps", C.c_int64), ("n_beliefs", C.c_int64),
                 ("n_actions", C.c_int64), ("device_ms", C.c_double),
                 ("near_ties", C.c_int64), ("sweep_visits", C.c_int64),
-                ("sweep_internal", C.c_int64), ("sweep_nodes", C.c_int64)]
+                ("sweep_internal", C.c_int64), ("sweep_nodes", C.c_int64),
+                ("insert_reprobes", C.c_int64)]
 
 
 class vopp_request(C.Structure):
@@ -329,6 +330,7 @@ class PlanResult:
     device_ms: float
     near_ties: int = 0
     sweep: tuple = (0, 0, 0)      # level sweeps: belief, internal, action-node visits
+    insert_reprobes: int = 0      # inserts whose slot another key took first
 
 
 def _sweep(st):
@@ -361,7 +363,7 @@ def plan(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None):
                            _p(vroot), C.byref(st)))
     return PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                       int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                      int(st.near_ties), _sweep(st))
+                      int(st.near_ties), _sweep(st), int(st.insert_reprobes))
 
 
 def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=None,
@@ -398,7 +400,7 @@ def plan_trace(pomdp, belief_dev, n_belief, budget, depth, prm, ws=None, stream=
                                  C.c_int64(n)))
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                     int(st.near_ties), _sweep(st))
+                     int(st.near_ties), _sweep(st), int(st.insert_reprobes))
     shape = (steps, prm.n_particles)
     return (res, act_d.cpu().numpy().reshape(shape), obs_d.cpu().numpy().reshape(shape))
 
@@ -442,7 +444,7 @@ def plan_anytime(pomdp, belief_dev, n_belief, max_budget, depth, time_ms, prm, w
                                    _p(vroot), C.byref(st), C.byref(iters)))
     res = PlanResult(int(act.value), vals, float(vroot[0]), int(st.particle_steps),
                      int(st.n_beliefs), int(st.n_actions), float(st.device_ms),
-                     int(st.near_ties), _sweep(st))
+                     int(st.near_ties), _sweep(st), int(st.insert_reprobes))
     return res, int(iters.value)
 
 

@@ -146,6 +146,11 @@ def test_full_size_plan(V, orc, name):
     st = forced_parity(V, orc, inst, bel, n_p, K, depth, seed=1)
     report(f"{name} full size", st)
     gpu_invariants(st["res"], st["tree"], n_p, K, depth, 0)
+    # Inserts whose slot another key took first (the forward kernel probes
+    # again and forms the next key again): at these sizes they happen, so the
+    # parity above covers that path.
+    print(f"[{name}] insert re-probes {st['res'].insert_reprobes}", flush=True)
+    assert st["res"].insert_reprobes > 0
 
 
 # --- the per-draw export and its forcing hook ------------------------------------
