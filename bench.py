@@ -92,12 +92,12 @@ def leaf_sweep_visits(n_p, K, depth, counts):
 # these kernels.  Valid only for the kernel sources they were taken on (hash
 # below); otherwise `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "0c5f691ec843ce23",
+    "sources_sha256_16": "ea77e652ac2a13d4",
     "backup_level": {"nav2d": 3.91e+07, "sparse4096": 1.294e+08},
-    "forward": {"nav2d": 1.309e+08, "sparse4096": 6.831e+08},
+    "forward": {"nav2d": 1.31e+08, "sparse4096": 6.829e+08},
     "gather_scale": {
-        "backup_level": {"nav2d": 2.69e+07, "sparse4096": 8.178e+07},
-        "forward": {"nav2d": 1.072e+08, "sparse4096": 4.899e+08},
+        "backup_level": {"nav2d": 2.69e+07, "sparse4096": 8.177e+07},
+        "forward": {"nav2d": 1.073e+08, "sparse4096": 4.898e+08},
     },
 }
 
