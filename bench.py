@@ -286,7 +286,7 @@ def bench_batch(V, I, reps=3, autotune=True, cpu=True):
 
 
 def bench_anytime(V, pom, belt, n_bel, n_p, depth, eta, budgets_ms=(10.0, 30.0, 100.0),
-                  k_max=64, reps=3):
+                  k_max=128, reps=3):
     """Anytime planning (Alg. 1's wall-clock budget) on the same workload:
     iterations reached, particle steps and the overshoot past the budget."""
     prm = V.params(n_p, eta=eta, seed=1)
